@@ -1,0 +1,117 @@
+/*
+ * Plain FP64 CPU oracle for the MHDuet method-of-lines right-hand side.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the HIP library; it is
+ * not a code path of the library.  Only tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py may load it.  It shares no source with the HIP
+ * path (no common headers, helpers or constant generators).
+ *
+ * Everything is written pointwise, in plain loops, in double precision, in the
+ * order of the equations of the paper (arXiv:2510.13965):
+ *   Sec. 2.1  CCZ4 evolution equations, Ricci split, Laplacian of the lapse,
+ *             matter projections, gauge (1+log, Gamma-freezing shift)
+ *   Sec. 2.2  GRMHD balance laws with divergence cleaning, cons/prim
+ *             definitions, hybrid piecewise-polytropic EoS
+ *   Sec. 3.1  Runge-Kutta (Table I, explicit RK4)
+ *   Sec. 3.2  4th-order centred, upwind and Kreiss-Oliger operators
+ *   Sec. 3.3  Lax-Friedrichs flux splitting + MP5 reconstruction
+ *   App. B    fast-magnetosonic speed bound
+ *   App. D    conserved-to-primitive recovery (two Brent solves) and error policy
+ *
+ * Storage: structure of arrays, field-major, x fastest, contiguous:
+ *   idx(i,j,k) = i + Nx*(j + Ny*k), Nx = nx+2ng, ...; field f at f*Nx*Ny*Nz.
+ * Field order (evolved U): gt_xx,gt_xy,gt_xz,gt_yy,gt_yz,gt_zz (0-5),
+ *   At_xx..At_zz (6-11), chi (12), Khat (13), Theta (14), Ghat^x,y,z (15-17),
+ *   alpha (18), beta^x,y,z (19-21), Dbar (22), DYebar (23), taubar (24),
+ *   Sbar_x,y,z (25-27), Bbar^x,y,z (28-30), phibar (31).
+ * Primitive P: rho, eps, p, v^x, v^y, v^z, W, Ye (0-7).
+ */
+#ifndef ORC_H
+#define ORC_H
+
+#include <stdint.h>
+
+#define ORC_NST 22
+#define ORC_NMHD 10
+#define ORC_NU 32
+#define ORC_NP 8
+
+/* con2prim flag bits */
+#define ORC_F_ATMO 1u
+#define ORC_F_EPS_LO 2u
+#define ORC_F_EPS_HI 4u
+#define ORC_F_VEL_LIMIT 8u
+#define ORC_F_YE_RESET 16u
+#define ORC_F_FALLBACK 32u
+#define ORC_F_NOT_CONVERGED 64u
+#define ORC_F_FATAL 128u
+
+typedef struct {
+  int n[3];      /* interior points per axis */
+  int ng;        /* ghost width (3) */
+  double dx[3];  /* spacing */
+} orc_grid;
+
+typedef struct {
+  int npieces;          /* cold pieces, 1..4; a single piece with K=0 is the ideal gas */
+  double K[4];          /* K_i */
+  double Gamma[4];      /* Gamma_i */
+  double rho_b[3];      /* piece boundaries rho_i */
+  double a[4];          /* a_i */
+  double Gamma_th;      /* thermal index */
+  double rho_atm, rho_min, rho_max, eps_max, W_max, rho_low, alpha_bh, h0;
+  double ye_min, ye_max, ye_atm;
+} orc_eos;
+
+typedef struct {
+  double kappa_z, kappa_c, kappa_2, eta;
+  double beta0[3];
+  double sigma_ko, c_b, kappa_b, alpha_mp5, f_beta;
+  int f_alpha_kind;     /* 0: f_alpha = 1 (1+log); 1: f_alpha = alpha/2 (harmonic) */
+  int evolve_st;        /* CCZ4 block on/off */
+  int evolve_mhd;       /* GRMHD block on/off */
+  int couple_matter;    /* matter terms in the CCZ4 block on/off */
+} orc_par;
+
+/* ---- EoS (Sec. 2.2, hybrid piecewise polytrope + thermal ideal gas) ---- */
+void orc_eos_init_pwp(orc_eos* e, int npieces, double K0, const double* Gamma,
+                      const double* rho_b, double Gamma_th);
+double orc_eps_cold(const orc_eos* e, double rho);
+double orc_press(const orc_eos* e, double rho, double eps);
+double orc_cs2(const orc_eos* e, double rho, double eps);
+
+/* ---- finite-difference operators of Sec. 3.2 at one point ---- */
+double orc_d1(const double* u, int64_t p, int64_t s, double h);
+double orc_d2(const double* u, int64_t p, int64_t s, double h);
+double orc_d11(const double* u, int64_t p, int64_t s1, int64_t s2, double h1, double h2);
+double orc_dup(const double* u, int64_t p, int64_t s, double h, double beta);
+double orc_ko(const double* u, int64_t p, int64_t s, double h, double sigma);
+double orc_mp5(const double* f5, double alpha);
+
+/* ---- cons <-> prim (Sec. 2.2 definitions, App. D recovery) ---- */
+/* eps_mode 0: P[eps] is the specific internal energy;
+ *          1: P[eps] is the thermal part, eps_cold(rho) is added and written back. */
+void orc_prim2con(const orc_grid* g, const orc_eos* e, double* U, double* P,
+                  const double* EM, int eps_mode);
+int64_t orc_con2prim(const orc_grid* g, const orc_eos* e, double* U, double* P,
+                     uint8_t* flags, double* mu);
+/* one-point recovery on undensitized conserved data, for pins */
+unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3],
+                       const double gdn[6], const double gup[6], double alpha,
+                       double prim[8], double mu[2], int* iters);
+
+/* ---- right-hand side ---- */
+void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e,
+             const double* U, const double* P, double* rhs, double* max_speed);
+
+/* ---- Runge-Kutta stage (Table I, explicit RK4, low-storage form) ---- */
+void orc_rk4_stage(int stage, double dt, int64_t n, const double* Un,
+                   const double* k, double* acc, double* Unext);
+void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt,
+                            const double* Un, const double* k, double* acc,
+                            double* Unext);
+
+/* ---- ghost fill ---- */
+void orc_fill_periodic(const orc_grid* g, double* U, int nfields);
+
+#endif

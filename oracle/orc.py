@@ -1,0 +1,185 @@
+"""ctypes binding of the FP64 CPU oracle (test infrastructure only).
+
+Only tests/, __graft_entry__.smoke() and the cpu_baseline leg of bench.py may
+import this module.  Arrays are numpy float64, C-contiguous, laid out as
+(field, z, y, x) over the padded patch.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+
+class Grid(C.Structure):
+    _fields_ = [("n", C.c_int * 3), ("ng", C.c_int), ("dx", C.c_double * 3)]
+
+
+class Eos(C.Structure):
+    _fields_ = [("npieces", C.c_int), ("K", C.c_double * 4), ("Gamma", C.c_double * 4),
+                ("rho_b", C.c_double * 3), ("a", C.c_double * 4), ("Gamma_th", C.c_double),
+                ("rho_atm", C.c_double), ("rho_min", C.c_double), ("rho_max", C.c_double),
+                ("eps_max", C.c_double), ("W_max", C.c_double), ("rho_low", C.c_double),
+                ("alpha_bh", C.c_double), ("h0", C.c_double), ("ye_min", C.c_double),
+                ("ye_max", C.c_double), ("ye_atm", C.c_double)]
+
+
+class Par(C.Structure):
+    _fields_ = [("kappa_z", C.c_double), ("kappa_c", C.c_double), ("kappa_2", C.c_double),
+                ("eta", C.c_double), ("beta0", C.c_double * 3), ("sigma_ko", C.c_double),
+                ("c_b", C.c_double), ("kappa_b", C.c_double), ("alpha_mp5", C.c_double),
+                ("f_beta", C.c_double), ("f_alpha_kind", C.c_int), ("evolve_st", C.c_int),
+                ("evolve_mhd", C.c_int), ("couple_matter", C.c_int)]
+
+
+_dp = C.POINTER(C.c_double)
+_u8p = C.POINTER(C.c_uint8)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liborc.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = C.CDLL(path)
+        L.orc_eos_init_pwp.argtypes = [C.POINTER(Eos), C.c_int, C.c_double, _dp, _dp, C.c_double]
+        L.orc_eps_cold.argtypes = [C.POINTER(Eos), C.c_double]
+        L.orc_eps_cold.restype = C.c_double
+        L.orc_press.argtypes = [C.POINTER(Eos), C.c_double, C.c_double]
+        L.orc_press.restype = C.c_double
+        L.orc_cs2.argtypes = [C.POINTER(Eos), C.c_double, C.c_double]
+        L.orc_cs2.restype = C.c_double
+        for name in ("orc_d1", "orc_d2", "orc_ko"):
+            getattr(L, name).restype = C.c_double
+        L.orc_d1.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double]
+        L.orc_d2.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double]
+        L.orc_d11.argtypes = [_dp, C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double]
+        L.orc_d11.restype = C.c_double
+        L.orc_dup.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double, C.c_double]
+        L.orc_dup.restype = C.c_double
+        L.orc_ko.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double, C.c_double]
+        L.orc_mp5.argtypes = [_dp, C.c_double]
+        L.orc_mp5.restype = C.c_double
+        L.orc_prim2con.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp, C.c_int]
+        L.orc_con2prim.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _u8p, _dp]
+        L.orc_con2prim.restype = C.c_int64
+        L.orc_c2p_point.argtypes = [C.POINTER(Eos), _dp, _dp, _dp, _dp, C.c_double, _dp, _dp,
+                                    C.POINTER(C.c_int)]
+        L.orc_c2p_point.restype = C.c_uint
+        L.orc_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp, _dp]
+        L.orc_rk4_stage.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, _dp, _dp, _dp]
+        L.orc_rk4_stage_interior.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, C.c_double,
+                                             _dp, _dp, _dp, _dp]
+        L.orc_fill_periodic.argtypes = [C.POINTER(Grid), _dp, C.c_int]
+        _LIB = L
+    return _LIB
+
+
+def ptr(a):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    if a.dtype == np.uint8:
+        return a.ctypes.data_as(_u8p)
+    assert a.dtype == np.float64, a.dtype
+    return a.ctypes.data_as(_dp)
+
+
+# ---------------------------------------------------------------- structs
+
+def make_grid(n, dx, ng=3):
+    g = Grid()
+    for i in range(3):
+        g.n[i] = int(n[i])
+        g.dx[i] = float(dx[i])
+    g.ng = ng
+    return g
+
+
+def make_eos(cfg):
+    """cfg: dict with K0, Gamma (list), rho_b (list), Gamma_th and thresholds."""
+    e = Eos()
+    G = (C.c_double * 4)(*(list(cfg["Gamma"]) + [0.0] * (4 - len(cfg["Gamma"]))))
+    rb = (C.c_double * 3)(*(list(cfg.get("rho_b", [])) + [0.0] * (3 - len(cfg.get("rho_b", [])))))
+    lib().orc_eos_init_pwp(C.byref(e), len(cfg["Gamma"]), cfg["K0"], G, rb, cfg["Gamma_th"])
+    for k in ("rho_atm", "rho_min", "rho_max", "eps_max", "W_max", "rho_low", "alpha_bh", "h0",
+              "ye_min", "ye_max", "ye_atm"):
+        setattr(e, k, float(cfg[k]))
+    return e
+
+
+def make_par(cfg):
+    p = Par()
+    for k in ("kappa_z", "kappa_c", "kappa_2", "eta", "sigma_ko", "c_b", "kappa_b", "alpha_mp5",
+              "f_beta"):
+        setattr(p, k, float(cfg[k]))
+    for i in range(3):
+        p.beta0[i] = float(cfg["beta0"][i])
+    p.f_alpha_kind = int(cfg["f_alpha_kind"])
+    p.evolve_st = int(cfg["evolve_st"])
+    p.evolve_mhd = int(cfg["evolve_mhd"])
+    p.couple_matter = int(cfg["couple_matter"])
+    return p
+
+
+# ---------------------------------------------------------------- calls
+
+def prim2con(g, e, U, P, EM, eps_mode=0):
+    lib().orc_prim2con(C.byref(g), C.byref(e), ptr(U), ptr(P), ptr(EM), eps_mode)
+
+
+def con2prim(g, e, U, P, flags=None, mu=None):
+    return lib().orc_con2prim(C.byref(g), C.byref(e), ptr(U), ptr(P), ptr(flags), ptr(mu))
+
+
+def rhs(g, par, e, U, P, out):
+    ms = C.c_double(0.0)
+    lib().orc_rhs(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(P), ptr(out), C.byref(ms))
+    return ms.value
+
+
+def rk4_stage_interior(g, nfields, stage, dt, Un, k, acc, Unext):
+    lib().orc_rk4_stage_interior(C.byref(g), nfields, stage, dt, ptr(Un), ptr(k), ptr(acc),
+                                 ptr(Unext))
+
+
+def rk4_stage(stage, dt, Un, k, acc, Unext):
+    lib().orc_rk4_stage(stage, dt, Un.size, ptr(Un), ptr(k), ptr(acc), ptr(Unext))
+
+
+def fill_periodic(g, U, nfields):
+    lib().orc_fill_periodic(C.byref(g), ptr(U), nfields)
+
+
+def c2p_point(e, cons, B, gdn, gup, alpha):
+    cons = np.ascontiguousarray(cons, dtype=np.float64)
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    gdn = np.ascontiguousarray(gdn, dtype=np.float64)
+    gup = np.ascontiguousarray(gup, dtype=np.float64)
+    prim = np.zeros(8)
+    mu = np.zeros(2)
+    it = C.c_int(0)
+    f = lib().orc_c2p_point(C.byref(e), ptr(cons), ptr(B), ptr(gdn), ptr(gup), float(alpha),
+                            ptr(prim), ptr(mu), C.byref(it))
+    return f, prim, mu, it.value
+
+
+def mp5(f5, alpha=4.0):
+    f5 = np.ascontiguousarray(f5, dtype=np.float64)
+    return lib().orc_mp5(ptr(f5), alpha)
+
+
+def eps_cold(e, rho):
+    return lib().orc_eps_cold(C.byref(e), rho)
+
+
+def press(e, rho, eps):
+    return lib().orc_press(C.byref(e), rho, eps)
+
+
+def cs2(e, rho, eps):
+    return lib().orc_cs2(C.byref(e), rho, eps)

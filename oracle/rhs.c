@@ -1,0 +1,118 @@
+/*
+ * Oracle (test infrastructure only): full method-of-lines right-hand side
+ * L(U) on one patch (Sec. 3, eq. d_t U = L(U)), Runge-Kutta stage update
+ * (Table I, explicit RK4) and periodic ghost filling.
+ */
+#include <math.h>
+#include <string.h>
+#include "orc.h"
+
+void orc_ccz4_point(const orc_par* par, const double* U, const double* P, int64_t N,
+                    int64_t p, const int64_t st[3], const double h[3], double out[22]);
+void orc_grmhd_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U,
+                   const double* P, double* rhs, double* max_speed);
+
+static int64_t npts(const orc_grid* g) {
+  return (int64_t)(g->n[0] + 2 * g->ng) * (g->n[1] + 2 * g->ng) * (g->n[2] + 2 * g->ng);
+}
+
+/* rhs is written at interior points only (fields 0..31); ghost entries untouched */
+void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U,
+             const double* P, double* rhs, double* max_speed) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  const int64_t st[3] = {1, Nx, Nx * Ny};
+  const double h[3] = {g->dx[0], g->dx[1], g->dx[2]};
+  int64_t k;
+#pragma omp parallel for schedule(static)
+  for (k = ng; k < Nz - ng; ++k)
+    for (int64_t j = ng; j < Ny - ng; ++j)
+      for (int64_t i = ng; i < Nx - ng; ++i) {
+        int64_t p = i + Nx * (j + Ny * k);
+        double out[22];
+        int f;
+        if (par->evolve_st) {
+          orc_ccz4_point(par, U, P, N, p, st, h, out);
+        } else {
+          for (f = 0; f < 22; ++f) out[f] = 0.0;
+        }
+        for (f = 0; f < 22; ++f) rhs[f * N + p] = out[f];
+      }
+  if (par->evolve_mhd) {
+    orc_grmhd_rhs(g, par, e, U, P, rhs, max_speed);
+  } else {
+#pragma omp parallel for schedule(static)
+    for (k = ng; k < Nz - ng; ++k)
+      for (int64_t j = ng; j < Ny - ng; ++j)
+        for (int64_t i = ng; i < Nx - ng; ++i) {
+          int64_t p = i + Nx * (j + Ny * k);
+          int f;
+          for (f = 22; f < 32; ++f) rhs[f * N + p] = 0.0;
+        }
+    if (max_speed) *max_speed = 0.0;
+  }
+}
+
+/* Explicit RK4 of Table I (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6),
+ * written with an accumulator:
+ *   stage s: acc  = (s == 0 ? 0 : acc) + b_s k_s
+ *            s < 3: Unext = Un + dt a_{s+1,s} k_s
+ *            s = 3: Unext = Un + dt acc                               */
+static const double RK4_A[3] = {0.5, 0.5, 1.0};
+static const double RK4_B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+
+static void stage_point(int stage, double dt, int64_t p, const double* Un, const double* k,
+                        double* acc, double* Unext) {
+  double a = (stage == 0 ? 0.0 : acc[p]) + RK4_B[stage] * k[p];
+  if (stage < 3) {
+    acc[p] = a;
+    Unext[p] = Un[p] + dt * RK4_A[stage] * k[p];
+  } else {
+    Unext[p] = Un[p] + dt * a;
+  }
+}
+
+void orc_rk4_stage(int stage, double dt, int64_t n, const double* Un, const double* k,
+                   double* acc, double* Unext) {
+  int64_t p;
+  for (p = 0; p < n; ++p) stage_point(stage, dt, p, Un, k, acc, Unext);
+}
+
+void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt,
+                            const double* Un, const double* k, double* acc, double* Unext) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  int f;
+  for (f = 0; f < nfields; ++f) {
+    int64_t kk;
+#pragma omp parallel for schedule(static)
+    for (kk = ng; kk < Nz - ng; ++kk)
+      for (int64_t j = ng; j < Ny - ng; ++j)
+        for (int64_t i = ng; i < Nx - ng; ++i)
+          stage_point(stage, dt, f * N + i + Nx * (j + Ny * kk), Un, k, acc, Unext);
+  }
+}
+
+/* periodic ghost fill: each ghost point takes the value of the interior point
+ * an integer number of periods away (edges and corners included) */
+void orc_fill_periodic(const orc_grid* g, double* U, int nfields) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  int f;
+  for (f = 0; f < nfields; ++f) {
+    double* u = U + f * N;
+    int64_t k;
+#pragma omp parallel for schedule(static)
+    for (k = 0; k < Nz; ++k)
+      for (int64_t j = 0; j < Ny; ++j)
+        for (int64_t i = 0; i < Nx; ++i) {
+          int64_t ii = ((i - ng) % g->n[0] + g->n[0]) % g->n[0] + ng;
+          int64_t jj = ((j - ng) % g->n[1] + g->n[1]) % g->n[1] + ng;
+          int64_t kk = ((k - ng) % g->n[2] + g->n[2]) % g->n[2] + ng;
+          if (ii != i || jj != j || kk != k) u[i + Nx * (j + Ny * k)] = u[ii + Nx * (jj + Ny * kk)];
+        }
+  }
+}
