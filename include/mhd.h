@@ -1,0 +1,179 @@
+/*
+ * mhd.h -- C ABI of the MI355X (gfx950) implementation of the MHDuet
+ * method-of-lines right-hand side on one mesh patch (arXiv:2510.13965).
+ *
+ * The library evaluates d_t U = L(U) (Sec. 3, method of lines) for
+ *   - the CCZ4 spacetime system with 1+log / Gamma-freezing gauge (Sec. 2.1),
+ *     4th-order centred derivatives, one-sided advection derivatives and
+ *     Kreiss-Oliger dissipation (Sec. 3.2);
+ *   - the GRMHD balance laws with hyperbolic divergence cleaning (Sec. 2.2),
+ *     in conservative form with Lax-Friedrichs flux splitting and MP5
+ *     reconstruction (Sec. 3.3), characteristic speeds from App. B;
+ *   - the per-point conserved-to-primitive recovery (App. D);
+ *   - the explicit RK4 stage update of Table I.
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ * Memory: every array argument is a DEVICE pointer owned by the caller; the
+ *   library never frees or retains it past the call (work is enqueued on
+ *   `stream`, a hipStream_t; NULL means the default stream).  Struct
+ *   arguments (mhd_patch_t, mhd_params_t, mhd_eos_t) are HOST pointers read
+ *   during the call only.
+ * Layout: structure of arrays, field-major.  Element (f, i, j, k) of a patch
+ *   array lives at base[f*sf + k*sz + j*sy + i] with padded indices
+ *   0 <= i < nx+2ng etc.  Interior points are ng <= i < ng+nx.
+ * Evolved fields U (MHD_NU = 32): gt_xx gt_xy gt_xz gt_yy gt_yz gt_zz (0-5),
+ *   At_xx..At_zz (6-11), chi (12), Khat (13), Theta (14), Ghat^x,y,z (15-17),
+ *   alpha (18), beta^x,y,z (19-21), Dbar (22), DYebar (23), taubar (24),
+ *   Sbar_x,y,z (25-27), Bbar^x,y,z (28-30), phibar (31); the MHD fields are
+ *   densitized by sqrt(gamma) (Sec. 2.2).
+ * Primitive fields P (MHD_NP = 8): rho, eps, p, v^x, v^y, v^z, W, Ye.
+ * Errors: 0 on success; a negative MHD_E* code otherwise, with a message
+ *   available from mhd_last_error() (per host thread).  Argument errors are
+ *   detected before any work is enqueued.
+ */
+#ifndef MHD_H
+#define MHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MHD_ABI_VERSION 1
+
+#define MHD_NST 22
+#define MHD_NMHD 10
+#define MHD_NU 32
+#define MHD_NP 8
+#define MHD_NEM 4
+
+/* return codes */
+#define MHD_OK 0
+#define MHD_EINVAL (-1)     /* invalid argument (shape, stride, pointer, parameter) */
+#define MHD_EHIP (-2)       /* a HIP runtime call failed */
+#define MHD_EWORKSPACE (-3) /* workspace missing or too small */
+
+/* con2prim per-point flag bits (App. D error policy) */
+#define MHD_FLAG_ATMO 1u        /* rho < rho_min: reset to atmosphere */
+#define MHD_FLAG_EPS_LO 2u      /* eps < eps_cold(rho): raised to it */
+#define MHD_FLAG_EPS_HI 4u      /* eps > eps_max in a low-density / BH region: lowered */
+#define MHD_FLAG_VEL_LIMIT 8u   /* W > W_max in a low-density / BH region: rescaled */
+#define MHD_FLAG_YE_RESET 16u   /* Ye out of range in a low-density / BH region */
+#define MHD_FLAG_FALLBACK 32u   /* learned guess rejected, bracketed solver used */
+#define MHD_FLAG_NOT_CONVERGED 64u /* bracketed solver hit its iteration cap */
+#define MHD_FLAG_FATAL 128u     /* error the paper treats as fatal (rho > rho_max, ...) */
+
+/* con2prim statistics slots (int64 counters, accumulated atomically) */
+#define MHD_STAT_FATAL 0
+#define MHD_STAT_CORRECTED 1
+#define MHD_STAT_FALLBACK 2
+#define MHD_STAT_ITERATIONS 3
+#define MHD_NSTAT 8
+
+/* flags of mhd_params_t.flags */
+#define MHD_EVOLVE_SPACETIME 1u
+#define MHD_EVOLVE_MHD 2u
+#define MHD_COUPLE_MATTER 4u
+
+/* f_alpha_kind: the slicing function f_alpha(alpha) of the lapse equation */
+#define MHD_FALPHA_ONE 0      /* 1+log slicing, f_alpha = 1 (the paper's standard) */
+#define MHD_FALPHA_HARMONIC 1 /* f_alpha = alpha/2 (harmonic slicing) */
+
+/* One vertex-centred patch (Sec. 4): nx*ny*nz interior points surrounded by
+ * ng ghost layers.  The RHS needs ng = 3 (MP5 window, KO and upwind stencils);
+ * con2prim and prim2con accept any ng >= 0 and process every padded point.
+ * Strides are in elements: x is contiguous, sy >= nx+2ng, sz >= sy*(ny+2ng),
+ * sf >= sz*(nz+2ng). */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t ng;
+  double dx, dy, dz;
+  double x0, y0, z0; /* coordinate of the first interior point (informational) */
+  int64_t sy, sz, sf;
+} mhd_patch_t;
+
+/* Hybrid EoS of Sec. 2.2: p = K_i rho^Gamma_i + (Gamma_th - 1) rho (eps - eps_cold),
+ * eps_cold = a_i + K_i/(Gamma_i - 1) rho^(Gamma_i - 1) on rho_{i-1} <= rho < rho_i.
+ * The ideal gas p = (Gamma-1) rho eps is npieces = 1, K[0] = 0, Gamma_th = Gamma.
+ * Fill K[0], Gamma[], rho_b[], Gamma_th and call mhd_eos_init_pwp() to derive
+ * K_i, a_i (i > 0) by continuity.  Thresholds follow App. D. */
+typedef struct {
+  int32_t npieces;   /* 1..4 */
+  int32_t reserved;
+  double K[4];
+  double Gamma[4];
+  double rho_b[3];
+  double a[4];
+  double Gamma_th;
+  double rho_atm, rho_min, rho_max, eps_max, W_max, rho_low, alpha_bh, h0;
+  double ye_min, ye_max, ye_atm;
+} mhd_eos_t;
+
+/* Physics parameters (Sec. 2.1 gauge and damping, Sec. 2.2 cleaning,
+ * Sec. 3.2 KO strength, Sec. 3.3 MP5 alpha). */
+typedef struct {
+  double kappa_z, kappa_c, kappa_2, eta;
+  double beta0[3];
+  double sigma_ko, c_b, kappa_b, alpha_mp5, f_beta;
+  int32_t f_alpha_kind;
+  uint32_t flags; /* MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER */
+} mhd_params_t;
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* mhd_last_error(void);
+int mhd_abi_version(void);
+
+/* Derive K_i (i>0) and a_i from K[0], Gamma[], rho_b[] by continuity of
+ * p_cold and eps_cold at the piece boundaries (Sec. 2.2, a_0 = 0).  Host only. */
+int mhd_eos_init_pwp(mhd_eos_t* eos);
+
+/* prim -> cons (definitions of Sec. 2.2, App. D) at every padded point.
+ * In: U[0..21] (spacetime, read), P slots rho, eps, v^i, Ye, and EM (4 fields:
+ *   undensitized B^x, B^y, B^z, phi; field stride patch->sf).
+ * Out: U[22..31] (densitized conserved fields), P slots p and W.
+ * eps_mode 0: P[eps] is the specific internal energy; 1: it is the thermal part
+ *   and eps_cold(rho) is added (the total is written back to P[eps]). */
+int mhd_prim2con(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, double* P,
+                 const double* EM, int eps_mode, void* stream);
+
+/* cons -> prim (App. D) at every padded point: mu_+ root of f_a on (0, 1/h0],
+ * mu root of f on (0, mu_+], both by Brent's method to a few ulp, primitives
+ * from mu, then the error policy.  Corrected points get their conserved fields
+ * (U[22..27]) rewritten from the corrected primitives.
+ * In/out: U.  Out: P (8 fields), flags (uint8 per padded point, may be NULL),
+ *   mu (2 fields mu_+, mu with stride patch->sf, may be NULL),
+ *   stats (MHD_NSTAT int64 device counters, accumulated, may be NULL). */
+int mhd_con2prim(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, double* P,
+                 uint8_t* flags, double* mu, int64_t* stats, void* stream);
+
+/* Workspace bytes mhd_rhs needs for this patch (point fluxes and speeds). */
+size_t mhd_rhs_workspace_size(const mhd_patch_t* patch);
+
+/* L(U) at the interior points (Sec. 2.1, 2.2, 3.2, 3.3, App. B).
+ * In: U (32 fields incl. ghosts), P (8 fields incl. ghosts; from con2prim).
+ * Out: rhs (32 fields, interior points only; ghost entries untouched).
+ * max_speed: device double, max over interior points and axes of the point
+ *   speed (fast magnetosonic bound and cleaning mode); updated with an atomic
+ *   max, the caller initialises it (to 0).  May be NULL.
+ * workspace: device buffer of mhd_rhs_workspace_size() bytes. */
+int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos,
+            const double* U, const double* P, double* rhs, double* max_speed,
+            void* workspace, size_t workspace_bytes, void* stream);
+
+/* Explicit RK4 stage of Table I at the interior points of `nfields` fields:
+ *   stage s (0..3): acc = (s ? acc : 0) + b_s k;  s < 3: Unext = Un + dt a_{s+1,s} k;
+ *   s = 3: Unext = Un + dt acc.
+ * Unext may alias Un only for s = 3.  Ghost entries of Unext are untouched. */
+int mhd_rk_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, const double* Un,
+                 const double* k, double* acc, double* Unext, void* stream);
+
+/* Periodic ghost fill of `nfields` fields (edges and corners included). */
+int mhd_fill_ghosts_periodic(const mhd_patch_t* patch, double* U, int nfields, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MHD_H */

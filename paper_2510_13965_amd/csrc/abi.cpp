@@ -1,0 +1,212 @@
+// C ABI of the library (include/mhd.h): argument validation, geometry set-up
+// and kernel launches.  No allocation happens here; every buffer is the
+// caller's.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "../../include/mhd.h"
+#include "dev_common.hpp"
+
+namespace mhd {
+int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
+                hipStream_t s);
+int ccz4_workspace_fields();
+int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,
+               double* ws, double* rhs, double* max_speed, hipStream_t s);
+int launch_con2prim(const Geom& g, const mhd_eos_t& eos, double* U, double* P, uint8_t* flags, double* mu,
+                    int64_t* stats, hipStream_t s);
+int launch_prim2con(const Geom& g, const mhd_eos_t& eos, double* U, double* P, const double* EM, int eps_mode,
+                    hipStream_t s);
+int launch_rk4_stage(const Geom& g, int nfields, int stage, double dt, const double* Un, const double* k, double* acc,
+                     double* Unext, hipStream_t s);
+int launch_ghosts_periodic(const Geom& g, double* U, int nfields, hipStream_t s);
+int launch_zero_interior(const Geom& g, int f0, int nfields, double* A, hipStream_t s);
+}  // namespace mhd
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int hip_check(int rc, const char* what) {
+  if (rc != (int)hipSuccess) return fail(MHD_EHIP, "%s: %s", what, hipGetErrorString((hipError_t)rc));
+  g_err[0] = 0;
+  return MHD_OK;
+}
+
+constexpr int64_t kMaxGridYZ = 65535;
+
+int check_patch(const mhd_patch_t* pt, int need_ng, int nfields_z, const char* fn) {
+  if (!pt) return fail(MHD_EINVAL, "%s: patch is NULL", fn);
+  if (pt->nx < 1 || pt->ny < 1 || pt->nz < 1)
+    return fail(MHD_EINVAL, "%s: interior extents must be >= 1 (got %d %d %d)", fn, pt->nx, pt->ny, pt->nz);
+  if (pt->ng < 0 || pt->ng > 16) return fail(MHD_EINVAL, "%s: ghost width %d out of range", fn, pt->ng);
+  if (need_ng >= 0 && pt->ng != need_ng) return fail(MHD_EINVAL, "%s: ghost width must be %d (got %d)", fn, need_ng, pt->ng);
+  const int64_t Nx = pt->nx + 2 * pt->ng, Ny = pt->ny + 2 * pt->ng, Nz = pt->nz + 2 * pt->ng;
+  if (pt->sy < Nx || pt->sz < pt->sy * Ny || pt->sf < pt->sz * Nz)
+    return fail(MHD_EINVAL, "%s: strides (sy=%lld sz=%lld sf=%lld) too small for padded extents %lld x %lld x %lld", fn,
+                (long long)pt->sy, (long long)pt->sz, (long long)pt->sf, (long long)Nx, (long long)Ny, (long long)Nz);
+  if (!(pt->dx > 0.0 && pt->dy > 0.0 && pt->dz > 0.0)) return fail(MHD_EINVAL, "%s: spacings must be > 0", fn);
+  if ((Ny + 3) / 4 > kMaxGridYZ || Nz * (int64_t)nfields_z > kMaxGridYZ)
+    return fail(MHD_EINVAL, "%s: patch too large for one launch (Ny=%lld, Nz*fields=%lld)", fn, (long long)Ny,
+                (long long)(Nz * nfields_z));
+  return MHD_OK;
+}
+
+int check_eos(const mhd_eos_t* e, const char* fn) {
+  if (!e) return fail(MHD_EINVAL, "%s: eos is NULL", fn);
+  if (e->npieces < 1 || e->npieces > 4) return fail(MHD_EINVAL, "%s: eos npieces must be 1..4", fn);
+  if (!(e->Gamma_th > 1.0)) return fail(MHD_EINVAL, "%s: Gamma_th must be > 1", fn);
+  for (int i = 0; i < e->npieces; ++i)
+    if (!(e->Gamma[i] > 1.0) || e->K[i] < 0.0) return fail(MHD_EINVAL, "%s: piece %d needs Gamma > 1, K >= 0", fn, i);
+  for (int i = 0; i + 1 < e->npieces; ++i)
+    if (!(e->rho_b[i] > 0.0) || (i > 0 && !(e->rho_b[i] > e->rho_b[i - 1])))
+      return fail(MHD_EINVAL, "%s: piece boundaries must be positive and increasing", fn);
+  if (!(e->rho_atm > 0.0 && e->rho_min >= e->rho_atm && e->rho_max > e->rho_min))
+    return fail(MHD_EINVAL, "%s: need 0 < rho_atm <= rho_min < rho_max", fn);
+  if (!(e->h0 > 0.0) || !(e->W_max > 1.0) || !(e->eps_max > 0.0))
+    return fail(MHD_EINVAL, "%s: need h0 > 0, W_max > 1, eps_max > 0", fn);
+  return MHD_OK;
+}
+
+mhd::Geom geom_of(const mhd_patch_t* pt) {
+  mhd::Geom g;
+  g.nx = pt->nx;
+  g.ny = pt->ny;
+  g.nz = pt->nz;
+  g.ng = pt->ng;
+  g.sy = pt->sy;
+  g.sz = pt->sz;
+  g.sf = pt->sf;
+  g.idx[0] = 1.0 / pt->dx;
+  g.idx[1] = 1.0 / pt->dy;
+  g.idx[2] = 1.0 / pt->dz;
+  const double h[3] = {pt->dx, pt->dy, pt->dz};
+  for (int a = 0; a < 3; ++a) {
+    g.h[a] = h[a];
+    g.i12[a] = 1.0 / (12.0 * h[a]);
+    g.i12s[a] = 1.0 / (12.0 * h[a] * h[a]);
+  }
+  return g;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mhd_last_error(void) { return g_err; }
+
+int mhd_abi_version(void) { return MHD_ABI_VERSION; }
+
+int mhd_eos_init_pwp(mhd_eos_t* e) {
+  if (!e) return fail(MHD_EINVAL, "mhd_eos_init_pwp: eos is NULL");
+  if (e->npieces < 1 || e->npieces > 4) return fail(MHD_EINVAL, "mhd_eos_init_pwp: npieces must be 1..4");
+  e->a[0] = 0.0;
+  for (int i = 1; i < e->npieces; ++i) {
+    const double rb = e->rho_b[i - 1];
+    const double Gm = e->Gamma[i - 1], G = e->Gamma[i];
+    // p_cold continuous: K_i rb^G_i = K_{i-1} rb^G_{i-1}
+    e->K[i] = e->K[i - 1] * std::pow(rb, Gm - G);
+    // eps_cold continuous
+    e->a[i] = e->a[i - 1] + e->K[i - 1] / (Gm - 1.0) * std::pow(rb, Gm - 1.0) - e->K[i] / (G - 1.0) * std::pow(rb, G - 1.0);
+  }
+  g_err[0] = 0;
+  return MHD_OK;
+}
+
+int mhd_prim2con(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, double* P, const double* EM, int eps_mode,
+                 void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, 1, "mhd_prim2con")) || (rc = check_eos(eos, "mhd_prim2con"))) return rc;
+  if (!U || !P || !EM) return fail(MHD_EINVAL, "mhd_prim2con: U, P and EM must be non-NULL");
+  if (eps_mode != 0 && eps_mode != 1) return fail(MHD_EINVAL, "mhd_prim2con: eps_mode must be 0 or 1");
+  return hip_check(mhd::launch_prim2con(geom_of(patch), *eos, U, P, EM, eps_mode, (hipStream_t)stream),
+                   "mhd_prim2con");
+}
+
+int mhd_con2prim(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, double* P, uint8_t* flags, double* mu,
+                 int64_t* stats, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, 1, "mhd_con2prim")) || (rc = check_eos(eos, "mhd_con2prim"))) return rc;
+  if (!U || !P) return fail(MHD_EINVAL, "mhd_con2prim: U and P must be non-NULL");
+  return hip_check(mhd::launch_con2prim(geom_of(patch), *eos, U, P, flags, mu, stats, (hipStream_t)stream),
+                   "mhd_con2prim");
+}
+
+size_t mhd_rhs_workspace_size(const mhd_patch_t* patch) {
+  if (!patch) return 0;
+  // 33 fields of point fluxes and speeds (GRMHD), then the CCZ4 second derivatives
+  return (size_t)(33 + mhd::ccz4_workspace_fields()) * (size_t)patch->sf * sizeof(double);
+}
+
+int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
+            const double* P, double* rhs, double* max_speed, void* workspace, size_t workspace_bytes, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, 3, MHD_NST, "mhd_rhs")) || (rc = check_eos(eos, "mhd_rhs"))) return rc;
+  if (!params) return fail(MHD_EINVAL, "mhd_rhs: params is NULL");
+  if (!U || !rhs) return fail(MHD_EINVAL, "mhd_rhs: U and rhs must be non-NULL");
+  const uint32_t fl = params->flags;
+  if ((fl & (MHD_EVOLVE_MHD | MHD_COUPLE_MATTER)) && !P)
+    return fail(MHD_EINVAL, "mhd_rhs: P is required when the fluid is evolved or coupled");
+  if ((fl & MHD_EVOLVE_MHD) && !(params->c_b > 0.0)) return fail(MHD_EINVAL, "mhd_rhs: c_b must be > 0");
+  if (params->f_alpha_kind != MHD_FALPHA_ONE && params->f_alpha_kind != MHD_FALPHA_HARMONIC)
+    return fail(MHD_EINVAL, "mhd_rhs: unknown f_alpha_kind %d", params->f_alpha_kind);
+  if (!workspace || workspace_bytes < mhd_rhs_workspace_size(patch))
+    return fail(MHD_EWORKSPACE, "mhd_rhs: workspace of %zu bytes needed (got %zu)", mhd_rhs_workspace_size(patch),
+                workspace_bytes);
+  if (patch->sf > (int64_t)(INT32_MAX / 8))
+    return fail(MHD_EINVAL, "mhd_rhs: a padded field of %lld points exceeds the 2^28-point limit of one launch",
+                (long long)patch->sf);
+  const mhd::Geom g = geom_of(patch);
+  hipStream_t s = (hipStream_t)stream;
+  if (fl & MHD_EVOLVE_SPACETIME) {
+    if ((rc = hip_check(mhd::launch_ccz4(g, *params, U, P, rhs, (double*)workspace + 33 * patch->sf, s),
+                        "mhd_rhs/ccz4")))
+      return rc;
+  } else {
+    // frozen spacetime: the CCZ4 block of the RHS is zero at interior points
+    if ((rc = hip_check(mhd::launch_zero_interior(g, 0, MHD_NST, rhs, s), "mhd_rhs/zero"))) return rc;
+  }
+  if (fl & MHD_EVOLVE_MHD) {
+    if ((rc = hip_check(mhd::launch_mhd(g, *params, *eos, U, P, (double*)workspace, rhs, max_speed, s), "mhd_rhs/grmhd")))
+      return rc;
+  } else {
+    if ((rc = hip_check(mhd::launch_zero_interior(g, MHD_NST, MHD_NMHD, rhs, s), "mhd_rhs/zero"))) return rc;
+  }
+  return MHD_OK;
+}
+
+int mhd_rk_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, const double* Un, const double* k,
+                 double* acc, double* Unext, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, nfields > 0 ? nfields : 1, "mhd_rk_stage"))) return rc;
+  if (nfields < 1) return fail(MHD_EINVAL, "mhd_rk_stage: nfields must be >= 1");
+  if (stage < 0 || stage > 3) return fail(MHD_EINVAL, "mhd_rk_stage: stage must be 0..3");
+  if (!Un || !k || !acc || !Unext) return fail(MHD_EINVAL, "mhd_rk_stage: NULL array");
+  if (Unext == Un && stage != 3) return fail(MHD_EINVAL, "mhd_rk_stage: Unext may alias Un only at stage 3");
+  if (!std::isfinite(dt)) return fail(MHD_EINVAL, "mhd_rk_stage: dt must be finite");
+  return hip_check(mhd::launch_rk4_stage(geom_of(patch), nfields, stage, dt, Un, k, acc, Unext, (hipStream_t)stream),
+                   "mhd_rk_stage");
+}
+
+int mhd_fill_ghosts_periodic(const mhd_patch_t* patch, double* U, int nfields, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, nfields > 0 ? nfields : 1, "mhd_fill_ghosts_periodic"))) return rc;
+  if (nfields < 1 || !U) return fail(MHD_EINVAL, "mhd_fill_ghosts_periodic: need nfields >= 1 and U");
+  if (patch->ng == 0) return MHD_OK;
+  return hip_check(mhd::launch_ghosts_periodic(geom_of(patch), U, nfields, (hipStream_t)stream),
+                   "mhd_fill_ghosts_periodic");
+}
+
+}  // extern "C"

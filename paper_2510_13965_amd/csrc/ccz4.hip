@@ -1,0 +1,530 @@
+// CCZ4 right-hand side (Sec. 2.1) at the interior points of one patch.
+//
+// The point algebra needs well over 256 live FP64 values when evaluated in one
+// piece, so it is split into kernels that each stay within the register file:
+//   k_ccz4_stencil  advection terms beta^k d_k u with the one-sided stencils and
+//                   Kreiss-Oliger dissipation for all 22 fields (Sec. 3.2);
+//                   writes the 22 RHS fields;
+//   k_ccz4_d2       the second derivatives, contracted where possible:
+//                   -1/2 gt^{mn} d_m d_n gt_ij, d_i d_j chi, d_i d_j alpha,
+//                   gt^{jk} d_j d_k beta^i and d_i d_k beta^k, into 24 workspace
+//                   fields (one field at a time, so few loads are in flight);
+//   k_ccz4_curv     d_t At_ij, d_t Khat, d_t Theta: the Ricci split
+//                   R_ij + 2 D_(i Z_j) = Rhat_ij + Rhat^chi_ij, D_i D_j alpha and
+//                   the Laplacian of the lapse, matter S_ij, tau (= E), S;
+//                   adds into the RHS;
+//   k_ccz4_gauge    d_t gt_ij, d_t chi, d_t Ghat^i and the gauge (1+log or
+//                   harmonic slicing, Gamma-freezing shift); adds into the RHS.
+// One thread per interior point; 64x4 blocks put a wavefront on 64 consecutive
+// x so every stencil row load is a coalesced 512-byte access and y/z
+// neighbours come from L1/L2.
+#include "dev_common.hpp"
+
+namespace mhd {
+
+struct Ccz4Args {
+  Geom g;
+  mhd_params_t par;
+  const double* __restrict__ U;
+  const double* __restrict__ P;
+  double* __restrict__ rhs;
+};
+
+constexpr double kPi = 3.141592653589793;
+
+__device__ __forceinline__ double wsym(int c) { return (c == 1 || c == 2 || c == 4) ? 2.0 : 1.0; }
+
+struct PointIdx {
+  int64_t p, sf;
+  int64_t st[3];
+  uint32_t voff;  // byte offset of the point within a field
+  bool live;
+};
+
+__device__ __forceinline__ PointIdx point_index(const Geom& g) {
+  PointIdx q;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  q.live = i < g.nx && j < g.ny;
+  q.p = g.at(i + g.ng, j + g.ng, k + g.ng);
+  q.voff = (uint32_t)(q.p * 8);
+  q.sf = g.sf;
+  q.st[0] = 1;
+  q.st[1] = g.sy;
+  q.st[2] = g.sz;
+  return q;
+}
+
+// conformal metric, its inverse and first derivatives, Christoffels of the
+// first kind c1[k][ij] = (d_i gt_kj + d_j gt_ki - d_k gt_ij)/2 and the
+// contracted Christoffel computed as printed, Gt^i = gt^{ij} gt^{kl} d_l gt_jk
+struct Conf {
+  double gt[6], gtu[6], det, c1[3][6], Gt[3];
+};
+
+__device__ __forceinline__ void conf_point(const double* __restrict__ U, const PointIdx& q, const Geom& g, Conf& c) {
+  const int64_t sf = q.sf, p = q.p;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) c.gt[a] = ldf(U + (a) * sf, q.voff);
+  c.det = sym_inv(c.gt, c.gtu);
+  double dg[3][6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) dg[d][a] = fd1(U + a * sf, q.st[d], q.voff, g.i12[d]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) c.c1[k][sym(i, j)] = 0.5 * (dg[i][sym(k, j)] + dg[j][sym(k, i)] - dg[k][sym(i, j)]);
+  double w[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) s += c.gtu[sym(k, l)] * dg[l][sym(j, k)];
+    w[j] = s;
+  }
+  sym_mv(c.gtu, w, c.Gt);
+}
+
+// matter projections of the magnetised fluid (Sec. 2.2): E = tau + D, S_i, S_ij
+struct Matter {
+  double E, S[3], Sij[6], Str;
+};
+
+__device__ __forceinline__ void matter_point(const double* __restrict__ U, const double* __restrict__ P,
+                                             const PointIdx& q, const Conf& c, double chi, bool want_sij, Matter& m) {
+  const int64_t sf = q.sf, p = q.p;
+  const double ichi = 1.0 / chi;
+  const double isg = 1.0 / sqrt(c.det * ichi * ichi * ichi);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) m.S[a] = ldf(U + ((25 + a)) * sf, q.voff) * isg;
+  m.E = (ldf(U + (24) * sf, q.voff) + ldf(U + (22) * sf, q.voff)) * isg;
+  if (!want_sij) return;
+  double gd[6];
+#pragma unroll
+  for (int a = 0; a < 6; ++a) gd[a] = c.gt[a] * ichi;
+  const double v[3] = {ldf(P + (3) * sf, q.voff), ldf(P + (4) * sf, q.voff), ldf(P + (5) * sf, q.voff)};
+  const double B[3] = {ldf(U + (28) * sf, q.voff) * isg, ldf(U + (29) * sf, q.voff) * isg, ldf(U + (30) * sf, q.voff) * isg};
+  double vd[3], Bd[3];
+  sym_mv(gd, v, vd);
+  sym_mv(gd, B, Bd);
+  const double B2 = B[0] * Bd[0] + B[1] * Bd[1] + B[2] * Bd[2];
+  const double Bv = B[0] * vd[0] + B[1] * vd[1] + B[2] * vd[2];
+  const double W = ldf(P + (6) * sf, q.voff), pr = ldf(P + (2) * sf, q.voff);
+  const double iW2 = 1.0 / (W * W);
+  const double iso = pr + 0.5 * iW2 * B2 + 0.5 * Bv * Bv;
+  m.Str = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const int a = sym(i, j);
+      m.Sij[a] = 0.5 * (vd[i] * m.S[j] + vd[j] * m.S[i]) + gd[a] * iso - iW2 * Bd[i] * Bd[j] -
+                 0.5 * Bv * (Bd[i] * vd[j] + Bd[j] * vd[i]);
+      m.Str += wsym(a) * c.gtu[a] * m.Sij[a];
+    }
+  m.Str *= chi;
+}
+
+// ------------------------------------------------------------------ advection + KO
+
+__global__ void __launch_bounds__(256) k_ccz4_stencil(Ccz4Args a) {
+  const Geom& g = a.g;
+  const PointIdx q = point_index(g);
+  if (!q.live) return;
+  const double* __restrict__ U = a.U;
+  const double beta[3] = {ldf(U + (19) * q.sf, q.voff), ldf(U + (20) * q.sf, q.voff), ldf(U + (21) * q.sf, q.voff)};
+  const double sko[3] = {a.par.sigma_ko * (1.0 / 64.0) * g.idx[0], a.par.sigma_ko * (1.0 / 64.0) * g.idx[1],
+                         a.par.sigma_ko * (1.0 / 64.0) * g.idx[2]};
+#pragma unroll 2
+  for (int f = 0; f < 22; ++f) {
+    const double* u = U + (int64_t)f * q.sf;
+    double s = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s += fdadv(u, q.st[d], q.voff, g.i12[d], beta[d]) + fdko(u, q.st[d], q.voff, sko[d]);
+    a.rhs[(int64_t)f * q.sf + q.p] = s;
+  }
+}
+
+
+// ------------------------------------------------------------------ second derivatives
+
+// workspace layout (field offsets, stride sf): 0-5 -1/2 gt^{mn} d_m d_n gt_ij,
+// 6-11 d_i d_j chi, 12-17 d_i d_j alpha, 18-20 gt^{jk} d_j d_k beta^i,
+// 21-23 d_i d_k beta^k
+constexpr int kD2Fields = 24;
+
+__global__ void __launch_bounds__(256) k_ccz4_d2(Ccz4Args a, double* __restrict__ W) {
+  const Geom& g = a.g;
+  const PointIdx q = point_index(g);
+  if (!q.live) return;
+  const double* __restrict__ U = a.U;
+  const int64_t sf = q.sf;
+  double gt[6], gtu[6];
+#pragma unroll
+  for (int b = 0; b < 6; ++b) gt[b] = ldf(U + b * sf, q.voff);
+  sym_inv(gt, gtu);
+  double* __restrict__ Wp = W + q.p;
+#pragma unroll 1
+  for (int b = 0; b < 6; ++b) {
+    const double* u = U + (int64_t)b * sf;
+    double r = -0.5 * (gtu[0] * fd2(u, q.st[0], q.voff, g.i12s[0]) + gtu[3] * fd2(u, q.st[1], q.voff, g.i12s[1]) +
+                       gtu[5] * fd2(u, q.st[2], q.voff, g.i12s[2]));
+    r -= gtu[1] * fd11(u, q.st[0], q.st[1], q.voff, g.i12[0], g.i12[1]);
+    r -= gtu[2] * fd11(u, q.st[0], q.st[2], q.voff, g.i12[0], g.i12[2]);
+    r -= gtu[4] * fd11(u, q.st[1], q.st[2], q.voff, g.i12[1], g.i12[2]);
+    Wp[(int64_t)b * sf] = r;
+  }
+#pragma unroll 1
+  for (int fi = 0; fi < 2; ++fi) {
+    const double* u = U + (int64_t)(fi == 0 ? 12 : 18) * sf;
+    double* o = Wp + (int64_t)(6 + 6 * fi) * sf;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int e = d; e < 3; ++e)
+        o[(int64_t)sym(d, e) * sf] = (d == e) ? fd2(u, q.st[d], q.voff, g.i12s[d])
+                                              : fd11(u, q.st[d], q.st[e], q.voff, g.i12[d], g.i12[e]);
+  }
+  double ddivb[3] = {0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int ci = 0; ci < 3; ++ci) {
+    const double* u = U + (int64_t)(19 + ci) * sf;
+    double v[6];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int e = d; e < 3; ++e)
+        v[sym(d, e)] = (d == e) ? fd2(u, q.st[d], q.voff, g.i12s[d])
+                                : fd11(u, q.st[d], q.st[e], q.voff, g.i12[d], g.i12[e]);
+    double lap = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) lap += wsym(b) * gtu[b] * v[b];
+    Wp[(int64_t)(18 + ci) * sf] = lap;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) ddivb[j] += (ci == 0) ? v[sym(j, 0)] : ((ci == 1) ? v[sym(j, 1)] : v[sym(j, 2)]);
+  }
+#pragma unroll
+  for (int j = 0; j < 3; ++j) Wp[(int64_t)(21 + j) * sf] = ddivb[j];
+}
+
+// ------------------------------------------------------------------ At_ij, Khat, Theta
+
+__global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __restrict__ W) {
+  const Geom& g = a.g;
+  const PointIdx q = point_index(g);
+  if (!q.live) return;
+  const double* __restrict__ U = a.U;
+  const int64_t sf = q.sf, p = q.p;
+
+  Conf c;
+  conf_point(U, q, g, c);
+  const double chi = ldf(U + (12) * sf, q.voff), Kh = ldf(U + (13) * sf, q.voff), Th = ldf(U + (14) * sf, q.voff);
+  const double Gh[3] = {ldf(U + (15) * sf, q.voff), ldf(U + (16) * sf, q.voff), ldf(U + (17) * sf, q.voff)};
+  const double alp = ldf(U + (18) * sf, q.voff);
+  const double ichi = 1.0 / chi;
+  double Z[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) Z[i] = 0.5 * chi * (Gh[i] - c.Gt[i]);
+
+  double dchi[3], dalp[3], ddchi[6], ddalp[6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    dchi[d] = fd1(U + 12 * sf, q.st[d], q.voff, g.i12[d]);
+    dalp[d] = fd1(U + 18 * sf, q.st[d], q.voff, g.i12[d]);
+  }
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    ddchi[b] = ldf(W + (6 + b) * sf, q.voff);
+    ddalp[b] = ldf(W + (12 + b) * sf, q.voff);
+  }
+  // raised gradients: Gt^k_ij d_k f = c1[l][ij] (gt^{lk} d_k f)
+  double uchi[3], ualp[3];
+  sym_mv(c.gtu, dchi, uchi);
+  sym_mv(c.gtu, dalp, ualp);
+
+  // Rs_ij = Rhat_ij + Rhat^chi_ij
+  double Rs[6];
+  {
+    // Q[k][n][i] = gt^{mn} Gamma^k_{mi},  Gamma^k_{mi} = gt^{kl} c1[l][mi]
+    double Q[3][3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double c2k[6];
+#pragma unroll
+      for (int b = 0; b < 6; ++b)
+        c2k[b] = c.gtu[sym(k, 0)] * c.c1[0][b] + c.gtu[sym(k, 1)] * c.c1[1][b] + c.gtu[sym(k, 2)] * c.c1[2][b];
+#pragma unroll
+      for (int n = 0; n < 3; ++n)
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+          Q[k][n][i] = c.gtu[sym(0, n)] * c2k[sym(0, i)] + c.gtu[sym(1, n)] * c2k[sym(1, i)] +
+                       c.gtu[sym(2, n)] * c2k[sym(2, i)];
+    }
+    double trchi = 0.0;  // gt^{km}(d_k d_m chi - 3/(2chi) d_k chi d_m chi) - Ghat^k d_k chi
+#pragma unroll
+    for (int b = 0; b < 6; ++b) trchi += wsym(b) * c.gtu[b] * ddchi[b];
+    trchi -= 1.5 * ichi * (dchi[0] * uchi[0] + dchi[1] * uchi[1] + dchi[2] * uchi[2]);
+    trchi -= Gh[0] * dchi[0] + Gh[1] * dchi[1] + Gh[2] * dchi[2];
+
+    double dGh[3][3];  // d_d Ghat^k
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) dGh[d][k] = fd1(U + (15 + k) * sf, q.st[d], q.voff, g.i12[d]);
+
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        const int b = sym(i, j);
+        // -1/2 gt^{mn} d_m d_n gt_ij
+        double r = ldf(W + b * sf, q.voff);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          r += 0.5 * (c.gt[sym(k, i)] * dGh[j][k] + c.gt[sym(k, j)] * dGh[i][k]);  // gt_k(i d_j) Ghat^k
+          r += 0.5 * Gh[k] * (c.c1[i][sym(j, k)] + c.c1[j][sym(i, k)]);          // Ghat^k Gt_(ij)k
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+          for (int n = 0; n < 3; ++n)
+            r += Q[k][n][i] * (c.c1[j][sym(k, n)] + c.c1[k][sym(n, j)]) + Q[k][n][j] * c.c1[i][sym(k, n)];
+        // chi Rhat^chi_ij
+        double rc = 0.5 * ddchi[b] - 0.25 * ichi * dchi[i] * dchi[j] + 0.5 * c.gt[b] * trchi;
+        rc -= 0.5 * (c.c1[0][b] * uchi[0] + c.c1[1][b] * uchi[1] + c.c1[2][b] * uchi[2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rc += ichi * Z[k] * (c.gt[sym(k, i)] * dchi[j] + c.gt[sym(k, j)] * dchi[i]);
+        Rs[b] = r + rc * ichi;
+      }
+  }
+  double Rtr = 0.0;  // R + 2 D_i Z^i = chi gt^{ij} Rs_ij
+#pragma unroll
+  for (int b = 0; b < 6; ++b) Rtr += wsym(b) * c.gtu[b] * Rs[b];
+  Rtr *= chi;
+
+  // D_i D_j alpha with the physical Christoffels
+  double DDa[6];
+  {
+    const double dad = dalp[0] * uchi[0] + dalp[1] * uchi[1] + dalp[2] * uchi[2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        const int b = sym(i, j);
+        DDa[b] = ddalp[b] - (c.c1[0][b] * ualp[0] + c.c1[1][b] * ualp[1] + c.c1[2][b] * ualp[2]) +
+                 0.5 * ichi * (dalp[i] * dchi[j] + dalp[j] * dchi[i] - c.gt[b] * dad);
+      }
+  }
+  // Laplacian as printed: chi gt^{ij} d_i d_j alpha - chi Gt^k d_k alpha - 1/2 gt^{ij} d_i alpha d_j chi
+  double lapA = 0.0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) lapA += wsym(b) * c.gtu[b] * ddalp[b];
+  lapA = chi * lapA - chi * (c.Gt[0] * dalp[0] + c.Gt[1] * dalp[1] + c.Gt[2] * dalp[2]) -
+         0.5 * (dalp[0] * uchi[0] + dalp[1] * uchi[1] + dalp[2] * uchi[2]);
+
+  Matter m;
+  const bool couple = (a.par.flags & MHD_COUPLE_MATTER) != 0;
+  if (couple) {
+    matter_point(U, a.P, q, c, chi, true, m);
+  } else {
+    m.E = m.Str = 0.0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) m.Sij[b] = 0.0;
+  }
+
+  double At[6], Amix[3][3];
+#pragma unroll
+  for (int b = 0; b < 6; ++b) At[b] = ldf(U + ((6 + b)) * sf, q.voff);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      Amix[i][j] = c.gtu[sym(i, 0)] * At[sym(0, j)] + c.gtu[sym(i, 1)] * At[sym(1, j)] + c.gtu[sym(i, 2)] * At[sym(2, j)];
+  const double trA = Amix[0][0] + Amix[1][1] + Amix[2][2];
+  double AA = 0.0;  // At_ij At^ij = At^i_j At^j_i
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) AA += Amix[i][j] * Amix[j][i];
+
+  double db[3][3];  // d_d beta^k
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) db[d][k] = fd1(U + (19 + k) * sf, q.st[d], q.voff, g.i12[d]);
+  const double divb = db[0][0] + db[1][1] + db[2][2];
+
+  double X[6], trX = 0.0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) {
+    X[b] = alp * (Rs[b] - 8.0 * kPi * m.Sij[b]) - DDa[b];
+    trX += wsym(b) * c.gtu[b] * X[b];
+  }
+  double* __restrict__ R = a.rhs + p;
+  const double kc = a.par.kappa_c;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const int b = sym(i, j);
+      double la = -2.0 / 3.0 * At[b] * divb - alp / 3.0 * kc * c.gt[b] * trA + chi * (X[b] - 1.0 / 3.0 * c.gt[b] * trX) +
+                  alp * Kh * At[b];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        la += At[sym(i, k)] * db[j][k] + At[sym(k, j)] * db[i][k];
+        la -= 2.0 * alp * At[sym(i, k)] * Amix[k][j];
+      }
+      R[(6 + b) * sf] += la;
+    }
+  const double Kf = Kh + 2.0 * Th;
+  const double Zda = Z[0] * dalp[0] + Z[1] * dalp[1] + Z[2] * dalp[2];
+  R[13 * sf] += -lapA + alp * (1.0 / 3.0 * Kf * Kf + AA + 4.0 * kPi * (m.E + m.Str) +
+                               a.par.kappa_z * (1.0 - a.par.kappa_2) * Th) + 2.0 * Zda;
+  R[14 * sf] += 0.5 * alp * (Rtr + 2.0 / 3.0 * Kh * Kh + 2.0 / 3.0 * Th * (Kh - 2.0 * Th) - AA) - Zda -
+                alp * (8.0 * kPi * m.E + a.par.kappa_z * (2.0 + a.par.kappa_2) * Th);
+}
+
+// ------------------------------------------------------------------ gt_ij, chi, Ghat^i, gauge
+
+__global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __restrict__ W) {
+  const Geom& g = a.g;
+  const PointIdx q = point_index(g);
+  if (!q.live) return;
+  const double* __restrict__ U = a.U;
+  const int64_t sf = q.sf, p = q.p;
+
+  Conf c;
+  conf_point(U, q, g, c);
+  const double chi = ldf(U + (12) * sf, q.voff), Kh = ldf(U + (13) * sf, q.voff), Th = ldf(U + (14) * sf, q.voff);
+  const double Gh[3] = {ldf(U + (15) * sf, q.voff), ldf(U + (16) * sf, q.voff), ldf(U + (17) * sf, q.voff)};
+  const double alp = ldf(U + (18) * sf, q.voff);
+  const double beta[3] = {ldf(U + (19) * sf, q.voff), ldf(U + (20) * sf, q.voff), ldf(U + (21) * sf, q.voff)};
+  const double ichi = 1.0 / chi;
+  const double Kf = Kh + 2.0 * Th;
+
+  double At[6], Au[6];
+#pragma unroll
+  for (int b = 0; b < 6; ++b) At[b] = ldf(U + ((6 + b)) * sf, q.voff);
+  double trA = 0.0;
+  {
+    double Amix[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        Amix[i][j] = c.gtu[sym(i, 0)] * At[sym(0, j)] + c.gtu[sym(i, 1)] * At[sym(1, j)] + c.gtu[sym(i, 2)] * At[sym(2, j)];
+    trA = Amix[0][0] + Amix[1][1] + Amix[2][2];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j)
+        Au[sym(i, j)] = Amix[i][0] * c.gtu[sym(0, j)] + Amix[i][1] * c.gtu[sym(1, j)] + Amix[i][2] * c.gtu[sym(2, j)];
+  }
+
+  double db[3][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) db[d][k] = fd1(U + (19 + k) * sf, q.st[d], q.voff, g.i12[d]);
+  const double divb = db[0][0] + db[1][1] + db[2][2];
+  double* __restrict__ R = a.rhs + p;
+
+  // d_t gt_ij
+  {
+    const double lndet = log(c.det);
+    const double kc = a.par.kappa_c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+      for (int j = i; j < 3; ++j) {
+        const int b = sym(i, j);
+        double lg = -2.0 / 3.0 * c.gt[b] * divb - 2.0 * alp * (At[b] - 1.0 / 3.0 * c.gt[b] * trA) -
+                    alp / 3.0 * kc * c.gt[b] * lndet;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lg += c.gt[sym(i, k)] * db[j][k] + c.gt[sym(k, j)] * db[i][k];
+        R[b * sf] += lg;
+      }
+  }
+  // d_t chi
+  R[12 * sf] += 2.0 / 3.0 * chi * (alp * Kf - divb);
+
+  // d_t Ghat^i
+  {
+    double dchi[3], dalp[3], dKh[3], dTh[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      dchi[d] = fd1(U + 12 * sf, q.st[d], q.voff, g.i12[d]);
+      dKh[d] = fd1(U + 13 * sf, q.st[d], q.voff, g.i12[d]);
+      dTh[d] = fd1(U + 14 * sf, q.st[d], q.voff, g.i12[d]);
+      dalp[d] = fd1(U + 18 * sf, q.st[d], q.voff, g.i12[d]);
+    }
+    double Sm[3] = {0.0, 0.0, 0.0};
+    if (a.par.flags & MHD_COUPLE_MATTER) {
+      Matter m;
+      matter_point(U, a.P, q, c, chi, false, m);
+      Sm[0] = m.S[0];
+      Sm[1] = m.S[1];
+      Sm[2] = m.S[2];
+    }
+    double Auda[3], Audchi[3], vK[3], vT[3], va[3], vS[3];
+    sym_mv(Au, dalp, Auda);
+    sym_mv(Au, dchi, Audchi);
+    sym_mv(c.gtu, dKh, vK);
+    sym_mv(c.gtu, dTh, vT);
+    sym_mv(c.gtu, dalp, va);
+    sym_mv(c.gtu, Sm, vS);
+    double lapb[3], ddivb[3];  // gt^{jk} d_j d_k beta^i, d_i d_k beta^k
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      lapb[i] = ldf(W + (18 + i) * sf, q.voff);
+      ddivb[i] = ldf(W + (21 + i) * sf, q.voff);
+    }
+    double gddivb[3];
+    sym_mv(c.gtu, ddivb, gddivb);
+    const double zfac = a.par.kappa_z + 2.0 / 3.0 * Kf;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      // Gt^i_jk At^jk with Gt^i_jk = gt^{il} c1[l][jk]
+      double t0 = 0.0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b)
+        t0 += wsym(b) * (c.gtu[sym(i, 0)] * c.c1[0][b] + c.gtu[sym(i, 1)] * c.c1[1][b] + c.gtu[sym(i, 2)] * c.c1[2][b]) *
+              Au[b];
+      const double Zi = 0.5 * chi * (Gh[i] - c.Gt[i]);
+      const double r = -(Gh[0] * db[0][i] + Gh[1] * db[1][i] + Gh[2] * db[2][i]) + 2.0 / 3.0 * Gh[i] * divb + lapb[i] +
+                       1.0 / 3.0 * gddivb[i] - 2.0 * Auda[i];
+      const double t1 = t0 - 1.5 * ichi * Audchi[i] - 2.0 / 3.0 * vK[i] - 8.0 * kPi * vS[i];
+      const double t2 = -(1.0 / 3.0 * vT[i] + Th / alp * va[i]) - ichi * Zi * zfac;
+      R[(15 + i) * sf] += r + 2.0 * alp * (t1 + t2);
+    }
+  }
+  // gauge
+  const double falpha = (a.par.f_alpha_kind == MHD_FALPHA_HARMONIC) ? 0.5 * alp : 1.0;
+  R[18 * sf] += -2.0 * alp * falpha * Kh;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    R[(19 + i) * sf] += 0.75 * a.par.f_beta * Gh[i] - a.par.eta * (beta[i] - a.par.beta0[i]);
+}
+
+int ccz4_workspace_fields() { return kD2Fields; }
+
+int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
+                hipStream_t s) {
+  Ccz4Args a{g, par, U, P, rhs};
+  dim3 blk(64, 4, 1);
+  dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  hipLaunchKernelGGL(k_ccz4_stencil, grd, blk, 0, s, a);
+  hipLaunchKernelGGL(k_ccz4_d2, grd, blk, 0, s, a, ws);
+  hipLaunchKernelGGL(k_ccz4_curv, grd, blk, 0, s, a, (const double*)ws);
+  hipLaunchKernelGGL(k_ccz4_gauge, grd, blk, 0, s, a, (const double*)ws);
+  return (int)hipGetLastError();
+}
+
+}  // namespace mhd

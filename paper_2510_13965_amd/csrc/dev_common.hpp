@@ -1,0 +1,213 @@
+// Device-side building blocks shared by the HIP kernels of the library:
+// patch geometry, the hybrid EoS of Sec. 2.2, 3x3 symmetric algebra and the
+// finite-difference operators of Sec. 3.2.  gfx950 only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mhd.h"
+
+namespace mhd {
+
+// symmetric 3x3 storage order: xx xy xz yy yz zz
+__host__ __device__ constexpr int sym(int i, int j) {
+  return (i <= j) ? (i == 0 ? j : (i == 1 ? 2 + j : 5)) : (j == 0 ? i : (j == 1 ? 2 + i : 5));
+}
+
+struct Geom {
+  int nx, ny, nz, ng;
+  int64_t sy, sz, sf;
+  double h[3];     // dx per axis
+  double idx[3];   // 1/dx per axis
+  double i12[3];   // 1/(12 dx)
+  double i12s[3];  // 1/(12 dx^2)
+  __device__ __forceinline__ int64_t at(int i, int j, int k) const {
+    return (int64_t)i + (int64_t)j * sy + (int64_t)k * sz;
+  }
+  __device__ __forceinline__ int64_t stride(int a) const { return a == 0 ? 1 : (a == 1 ? sy : sz); }
+};
+
+// ------------------------------------------------------------------ EoS
+
+struct Cold {
+  double p, e;  // p_cold, eps_cold
+  double K, G;  // piece constants
+};
+
+__device__ __forceinline__ Cold eos_cold(const mhd_eos_t& e, double rho) {
+#pragma clang fp contract(off)
+  int i = 0;
+#pragma unroll
+  for (int b = 0; b < 3; ++b)
+    if (b < e.npieces - 1 && rho >= e.rho_b[b]) i = b + 1;
+  Cold c;
+  c.K = e.K[i];
+  c.G = e.Gamma[i];
+  if (c.K == 0.0) {
+    c.p = 0.0;
+    c.e = e.a[i];
+  } else {
+    c.p = c.K * pow(rho, c.G);
+    c.e = e.a[i] + c.K / (c.G - 1.0) * pow(rho, c.G - 1.0);
+  }
+  return c;
+}
+
+__device__ __forceinline__ double eos_press(const mhd_eos_t& e, double rho, double eps) {
+#pragma clang fp contract(off)
+  const Cold c = eos_cold(e, rho);
+  return c.p + (e.Gamma_th - 1.0) * rho * (eps - c.e);
+}
+
+// c_s^2 = (dp/drho|_eps + p/rho^2 dp/deps|_rho) / (1 + eps + p/rho)
+__device__ __forceinline__ double eos_cs2(const mhd_eos_t& e, double rho, double eps, double p) {
+  const Cold c = eos_cold(e, rho);
+  const double gt1 = e.Gamma_th - 1.0;
+  const double dpdrho = (c.G - gt1) * c.p / rho + gt1 * (eps - c.e);
+  const double dpdeps = gt1 * rho;
+  return (dpdrho + p / (rho * rho) * dpdeps) / (1.0 + eps + p / rho);
+}
+
+// ------------------------------------------------------------------ 3x3 symmetric
+
+// inverse of a symmetric 3x3 matrix; returns the determinant
+__device__ __forceinline__ double sym_inv(const double g[6], double gi[6]) {
+#pragma clang fp contract(off)
+  const double c00 = g[3] * g[5] - g[4] * g[4];
+  const double c01 = g[2] * g[4] - g[1] * g[5];
+  const double c02 = g[1] * g[4] - g[2] * g[3];
+  const double det = g[0] * c00 + g[1] * c01 + g[2] * c02;
+  const double id = 1.0 / det;
+  gi[0] = c00 * id;
+  gi[1] = c01 * id;
+  gi[2] = c02 * id;
+  gi[3] = (g[0] * g[5] - g[2] * g[2]) * id;
+  gi[4] = (g[1] * g[2] - g[0] * g[4]) * id;
+  gi[5] = (g[0] * g[3] - g[1] * g[1]) * id;
+  return det;
+}
+
+__device__ __forceinline__ void sym_mv(const double g[6], const double v[3], double o[3]) {
+#pragma clang fp contract(off)
+  o[0] = g[0] * v[0] + g[1] * v[1] + g[2] * v[2];
+  o[1] = g[1] * v[0] + g[3] * v[1] + g[4] * v[2];
+  o[2] = g[2] * v[0] + g[4] * v[1] + g[5] * v[2];
+}
+
+// Physical metric in a fixed order of plain IEEE operations (used wherever a
+// result must be reproducible bit for bit): inverse by cofactors divided by
+// the determinant, gamma_ij = gt_ij/chi, gamma^ij = chi gt^ij,
+// sqrt(gamma) = sqrt(det/chi^3).
+struct MetricR {
+  double gtu[6], gd[6], gu[6], sqrtg;
+};
+
+__device__ __forceinline__ void metric_repro(const double g[6], double chi, MetricR& m) {
+#pragma clang fp contract(off)
+  const double c00 = g[3] * g[5] - g[4] * g[4];
+  const double c01 = g[2] * g[4] - g[1] * g[5];
+  const double c02 = g[1] * g[4] - g[2] * g[3];
+  const double det = g[0] * c00 + g[1] * c01 + g[2] * c02;
+  m.gtu[0] = c00 / det;
+  m.gtu[1] = c01 / det;
+  m.gtu[2] = c02 / det;
+  m.gtu[3] = (g[0] * g[5] - g[2] * g[2]) / det;
+  m.gtu[4] = (g[1] * g[2] - g[0] * g[4]) / det;
+  m.gtu[5] = (g[0] * g[3] - g[1] * g[1]) / det;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    m.gd[a] = g[a] / chi;
+    m.gu[a] = chi * m.gtu[a];
+  }
+  m.sqrtg = sqrt(det / (chi * chi * chi));
+}
+
+// physical metric from the conformal one: gamma_ij = gt_ij/chi, gamma^ij = chi gt^ij,
+// sqrt(gamma) = sqrt(det gt / chi^3)
+struct Metric {
+  double gd[6], gu[6], sqrtg;
+};
+
+__device__ __forceinline__ void metric_from(const double gt[6], double chi, Metric& m) {
+  double gtu[6];
+  const double det = sym_inv(gt, gtu);
+  const double ic = 1.0 / chi;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    m.gd[a] = gt[a] * ic;
+    m.gu[a] = gtu[a] * chi;
+  }
+  m.sqrtg = sqrt(det * ic * ic * ic);
+}
+
+// ------------------------------------------------------------------ stencils (Sec. 3.2)
+// u points at the centre value; s is the element stride along the axis; ih = 1/h.
+//
+// Conditioning: the fields carry O(1) values with small variations, so the
+// weighted sums of the second-derivative, upwind and dissipation stencils
+// cancel to a result many orders of magnitude below the summands.  Their
+// numerators are therefore summed in a fixed paired order with FMA contraction
+// disabled: every rounding is then a plain IEEE add or multiply, reproducible
+// on any FP64 implementation, and only the final scaling by 1/h carries a
+// (relative, harmless) rounding difference.
+
+// Loads of stencil points go through a buffer resource built from a
+// wavefront-uniform base (field start plus the stencil offset, kept in SGPRs)
+// and one 32-bit per-lane byte offset shared by every load of the point, so
+// the hundreds of stencil loads of a point need no per-load address VGPRs.
+__device__ __forceinline__ double ldf(const double* fb, uint32_t voff) {
+  const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)fb, 0, 0x7fffffff, 0x00020000);
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, 0));
+}
+
+// fb: field base (uniform); s: element stride along the axis (uniform);
+// voff: byte offset of the centre point; ih12 = 1/(12h), ih2_12 = 1/(12h^2)
+__device__ __forceinline__ double fd1(const double* fb, int64_t s, uint32_t voff, double ih12) {
+#pragma clang fp contract(off)
+  return (8.0 * (ldf(fb + s, voff) - ldf(fb - s, voff)) - (ldf(fb + 2 * s, voff) - ldf(fb - 2 * s, voff))) * ih12;
+}
+
+__device__ __forceinline__ double fd2(const double* fb, int64_t s, uint32_t voff, double ih2_12) {
+#pragma clang fp contract(off)
+  return (16.0 * (ldf(fb + s, voff) + ldf(fb - s, voff)) - (ldf(fb + 2 * s, voff) + ldf(fb - 2 * s, voff)) -
+          30.0 * ldf(fb, voff)) *
+         ih2_12;
+}
+
+// D_b(D_a u): the centred operator along a applied at the four b-neighbours,
+// then along b
+__device__ __forceinline__ double fd11(const double* fb, int64_t sa, int64_t sb, uint32_t voff, double iha12,
+                                       double ihb12) {
+#pragma clang fp contract(off)
+  const double a1 = fd1(fb + sb, sa, voff, iha12);
+  const double b1 = fd1(fb - sb, sa, voff, iha12);
+  const double a2 = fd1(fb + 2 * sb, sa, voff, iha12);
+  const double b2 = fd1(fb - 2 * sb, sa, voff, iha12);
+  return (8.0 * (a1 - b1) - (a2 - b2)) * ihb12;
+}
+
+// beta * D^upwind u with the one-sided 4th-order stencils of Sec. 3.2:
+//   beta >= 0: ( u_{+3} - 6u_{+2} + 18u_{+1} - 10u_0 - 3u_{-1})/(12h)
+//   beta <  0: (-u_{-3} + 6u_{-2} - 18u_{-1} + 10u_0 + 3u_{+1})/(12h)
+__device__ __forceinline__ double fdadv(const double* fb, int64_t s, uint32_t voff, double ih12, double beta) {
+#pragma clang fp contract(off)
+  double d;
+  if (beta >= 0.0)
+    d = ldf(fb + 3 * s, voff) - 6.0 * ldf(fb + 2 * s, voff) + 18.0 * ldf(fb + s, voff) - 10.0 * ldf(fb, voff) -
+        3.0 * ldf(fb - s, voff);
+  else
+    d = -ldf(fb - 3 * s, voff) + 6.0 * ldf(fb - 2 * s, voff) - 18.0 * ldf(fb - s, voff) + 10.0 * ldf(fb, voff) +
+        3.0 * ldf(fb + s, voff);
+  return beta * (d * ih12);
+}
+
+// Kreiss-Oliger dissipation along one axis, sigma/(64h) * 6th difference
+__device__ __forceinline__ double fdko(const double* fb, int64_t s, uint32_t voff, double sig_ih64) {
+#pragma clang fp contract(off)
+  const double q = (ldf(fb + 3 * s, voff) + ldf(fb - 3 * s, voff)) - 6.0 * (ldf(fb + 2 * s, voff) + ldf(fb - 2 * s, voff)) +
+                   15.0 * (ldf(fb + s, voff) + ldf(fb - s, voff)) - 20.0 * ldf(fb, voff);
+  return sig_ih64 * q;
+}
+
+}  // namespace mhd

@@ -1,0 +1,109 @@
+// Explicit RK4 stage update (Table I, explicit part) and periodic ghost fill.
+//
+// The stage kernel is a pure streaming kernel (HBM bound): each thread owns one
+// interior element of one field; a wavefront covers 64 consecutive x of a row,
+// so every access is a coalesced 512-byte transaction.  Per element it moves
+// 3 reads + 2 writes (stages 0-2) or 3 reads + 1 write (stage 3) of 8 bytes.
+#include "dev_common.hpp"
+
+namespace mhd {
+
+// plain IEEE adds and multiplies (no contraction): the stage update is then
+// reproducible bit for bit by any FP64 implementation of the same formula
+#pragma clang fp contract(off)
+
+__constant__ double kRk4A[3] = {0.5, 0.5, 1.0};
+__constant__ double kRk4B[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+
+struct RkArgs {
+  Geom g;
+  int stage;
+  double dt;
+  const double* Un;
+  const double* __restrict__ k;
+  double* acc;
+  double* Unext;
+};
+
+// block 64x4: x = 64 consecutive points of a row, y = 4 rows; grid z = k * nfields + f
+__global__ void __launch_bounds__(256) k_rk4_stage(RkArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int kz = blockIdx.z % g.nz;
+  const int f = blockIdx.z / g.nz;
+  if (i >= g.nx || j >= g.ny) return;
+  const int64_t p = (int64_t)f * g.sf + g.at(i + g.ng, j + g.ng, kz + g.ng);
+  const double kv = a.k[p];
+  const int s = a.stage;
+  const double b = kRk4B[s] * kv;
+  if (s < 3) {
+    a.acc[p] = (s == 0) ? b : a.acc[p] + b;
+    a.Unext[p] = a.Un[p] + a.dt * kRk4A[s] * kv;
+  } else {
+    a.Unext[p] = a.Un[p] + a.dt * (a.acc[p] + b);
+  }
+}
+
+struct GhostArgs {
+  Geom g;
+  double* U;
+};
+
+// periodic: every ghost point copies the interior point a whole number of
+// periods away (faces, edges and corners in one pass; interior threads exit)
+__global__ void __launch_bounds__(256) k_ghosts_periodic(GhostArgs a) {
+  const Geom& g = a.g;
+  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int kz = blockIdx.z % Nz;
+  const int f = blockIdx.z / Nz;
+  if (i >= Nx || j >= Ny) return;
+  auto wrap = [](int q, int n, int ng) { return ((q - ng) % n + n) % n + ng; };
+  const int si = wrap(i, g.nx, g.ng), sj = wrap(j, g.ny, g.ng), sk = wrap(kz, g.nz, g.ng);
+  if (si == i && sj == j && sk == kz) return;
+  double* u = a.U + (int64_t)f * g.sf;
+  u[g.at(i, j, kz)] = u[g.at(si, sj, sk)];
+}
+
+struct ZeroArgs {
+  Geom g;
+  int f0;
+  double* A;
+};
+
+__global__ void __launch_bounds__(256) k_zero_interior(ZeroArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int kz = blockIdx.z % g.nz;
+  const int f = a.f0 + blockIdx.z / g.nz;
+  if (i >= g.nx || j >= g.ny) return;
+  a.A[(int64_t)f * g.sf + g.at(i + g.ng, j + g.ng, kz + g.ng)] = 0.0;
+}
+
+int launch_zero_interior(const Geom& g, int f0, int nfields, double* A, hipStream_t s) {
+  ZeroArgs a{g, f0, A};
+  dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * nfields);
+  hipLaunchKernelGGL(k_zero_interior, grd, dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+int launch_rk4_stage(const Geom& g, int nfields, int stage, double dt, const double* Un, const double* k, double* acc,
+                     double* Unext, hipStream_t s) {
+  RkArgs a{g, stage, dt, Un, k, acc, Unext};
+  dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * nfields);
+  hipLaunchKernelGGL(k_rk4_stage, grd, dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+int launch_ghosts_periodic(const Geom& g, double* U, int nfields, hipStream_t s) {
+  GhostArgs a{g, U};
+  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
+  dim3 grd((Nx + 63) / 64, (Ny + 3) / 4, Nz * nfields);
+  hipLaunchKernelGGL(k_ghosts_periodic, grd, dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace mhd

@@ -1,0 +1,192 @@
+"""Thin ctypes binding of libmhd.so (include/mhd.h).
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Arrays are torch tensors on the HIP device (float64, laid out as
+(field, z, y, x) over the padded patch, or any strided layout described by the
+patch strides); the stream is torch's current stream unless one is given.
+There is no CPU fallback: a missing library or device raises.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmhd.so")
+
+MHD_NST, MHD_NMHD, MHD_NU, MHD_NP, MHD_NEM = 22, 10, 32, 8, 4
+MHD_NSTAT = 8
+EVOLVE_SPACETIME, EVOLVE_MHD, COUPLE_MATTER = 1, 2, 4
+FLAG = dict(ATMO=1, EPS_LO=2, EPS_HI=4, VEL_LIMIT=8, YE_RESET=16, FALLBACK=32, NOT_CONVERGED=64, FATAL=128)
+STAT_FATAL, STAT_CORRECTED, STAT_FALLBACK, STAT_ITERATIONS = 0, 1, 2, 3
+
+
+class Patch(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("ng", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
+                ("sy", C.c_int64), ("sz", C.c_int64), ("sf", C.c_int64)]
+
+
+class Eos(C.Structure):
+    _fields_ = [("npieces", C.c_int32), ("reserved", C.c_int32), ("K", C.c_double * 4),
+                ("Gamma", C.c_double * 4), ("rho_b", C.c_double * 3), ("a", C.c_double * 4),
+                ("Gamma_th", C.c_double), ("rho_atm", C.c_double), ("rho_min", C.c_double),
+                ("rho_max", C.c_double), ("eps_max", C.c_double), ("W_max", C.c_double),
+                ("rho_low", C.c_double), ("alpha_bh", C.c_double), ("h0", C.c_double),
+                ("ye_min", C.c_double), ("ye_max", C.c_double), ("ye_atm", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("kappa_z", C.c_double), ("kappa_c", C.c_double), ("kappa_2", C.c_double),
+                ("eta", C.c_double), ("beta0", C.c_double * 3), ("sigma_ko", C.c_double),
+                ("c_b", C.c_double), ("kappa_b", C.c_double), ("alpha_mp5", C.c_double),
+                ("f_beta", C.c_double), ("f_alpha_kind", C.c_int32), ("flags", C.c_uint32)]
+
+
+_vp = C.c_void_p
+_LIB = None
+
+# name -> (restype, argtypes); the exported C symbols of include/mhd.h
+SIGNATURES = {
+    "mhd_last_error": (C.c_char_p, []),
+    "mhd_abi_version": (C.c_int, []),
+    "mhd_eos_init_pwp": (C.c_int, [C.POINTER(Eos)]),
+    "mhd_prim2con": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, C.c_int, _vp]),
+    "mhd_con2prim": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp]),
+    "mhd_rhs_workspace_size": (C.c_size_t, [C.POINTER(Patch)]),
+    "mhd_rhs": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp,
+                          C.c_size_t, _vp]),
+    "mhd_rk_stage": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_double, _vp, _vp, _vp, _vp, _vp]),
+    "mhd_fill_ghosts_periodic": (C.c_int, [C.POINTER(Patch), _vp, C.c_int, _vp]),
+}
+
+
+class MhdError(RuntimeError):
+    pass
+
+
+def lib():
+    """Load libmhd.so (built in-tree by build.py); raises if it is missing."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise MhdError("libmhd.so not built: run paper_2510_13965_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIBPATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def _check(rc):
+    if rc != 0:
+        raise MhdError("libmhd error %d: %s" % (rc, lib().mhd_last_error().decode()))
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise MhdError("libmhd takes device tensors only (got a %s tensor)" % t.device)
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ structs
+
+def make_patch(n, dx, x0=(0.0, 0.0, 0.0), ng=3, strides=None):
+    p = Patch()
+    p.nx, p.ny, p.nz = (int(v) for v in n)
+    p.ng = int(ng)
+    p.dx, p.dy, p.dz = (float(v) for v in dx)
+    p.x0, p.y0, p.z0 = (float(v) for v in x0)
+    Nx, Ny, Nz = (int(n[a]) + 2 * ng for a in range(3))
+    if strides is None:
+        strides = (Nx, Nx * Ny, Nx * Ny * Nz)
+    p.sy, p.sz, p.sf = (int(v) for v in strides)
+    return p
+
+
+def patch_of(ip, strides=None):
+    """libmhd patch of an inputs.Patch."""
+    return make_patch(ip.n, ip.dx, ip.x0, ip.ng, strides)
+
+
+def make_eos(cfg):
+    e = Eos()
+    G = list(cfg["Gamma"])
+    e.npieces = len(G)
+    for i, g in enumerate(G):
+        e.Gamma[i] = g
+    for i, r in enumerate(cfg.get("rho_b", [])):
+        e.rho_b[i] = r
+    e.K[0] = cfg["K0"]
+    e.Gamma_th = cfg["Gamma_th"]
+    for k in ("rho_atm", "rho_min", "rho_max", "eps_max", "W_max", "rho_low", "alpha_bh", "h0",
+              "ye_min", "ye_max", "ye_atm"):
+        setattr(e, k, float(cfg[k]))
+    _check(lib().mhd_eos_init_pwp(C.byref(e)))
+    return e
+
+
+def make_params(cfg):
+    p = Params()
+    for k in ("kappa_z", "kappa_c", "kappa_2", "eta", "sigma_ko", "c_b", "kappa_b", "alpha_mp5", "f_beta"):
+        setattr(p, k, float(cfg[k]))
+    for i in range(3):
+        p.beta0[i] = float(cfg["beta0"][i])
+    p.f_alpha_kind = int(cfg["f_alpha_kind"])
+    fl = 0
+    if cfg.get("evolve_st", 1):
+        fl |= EVOLVE_SPACETIME
+    if cfg.get("evolve_mhd", 1):
+        fl |= EVOLVE_MHD
+    if cfg.get("couple_matter", 1):
+        fl |= COUPLE_MATTER
+    p.flags = fl
+    return p
+
+
+# ------------------------------------------------------------------ calls
+
+def prim2con(patch, eos, U, P, EM, eps_mode=0, stream=None):
+    _check(lib().mhd_prim2con(C.byref(patch), C.byref(eos), _ptr(U), _ptr(P), _ptr(EM), eps_mode,
+                              _stream(stream)))
+
+
+def con2prim(patch, eos, U, P, flags=None, mu=None, stats=None, stream=None):
+    _check(lib().mhd_con2prim(C.byref(patch), C.byref(eos), _ptr(U), _ptr(P), _ptr(flags), _ptr(mu),
+                              _ptr(stats), _stream(stream)))
+
+
+def rhs_workspace_size(patch):
+    return int(lib().mhd_rhs_workspace_size(C.byref(patch)))
+
+
+def rhs(patch, params, eos, U, P, out, max_speed=None, workspace=None, stream=None):
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(lib().mhd_rhs(C.byref(patch), C.byref(params), C.byref(eos), _ptr(U), _ptr(P), _ptr(out),
+                         _ptr(max_speed), _ptr(workspace), nbytes, _stream(stream)))
+
+
+def rk_stage(patch, nfields, stage, dt, Un, k, acc, Unext, stream=None):
+    _check(lib().mhd_rk_stage(C.byref(patch), nfields, stage, float(dt), _ptr(Un), _ptr(k), _ptr(acc),
+                              _ptr(Unext), _stream(stream)))
+
+
+def fill_ghosts_periodic(patch, U, nfields, stream=None):
+    _check(lib().mhd_fill_ghosts_periodic(C.byref(patch), _ptr(U), nfields, _stream(stream)))
+
+
+def workspace_for(patch, device="cuda"):
+    import torch
+
+    n = (rhs_workspace_size(patch) + 7) // 8
+    return torch.empty(n, dtype=torch.float64, device=device)
