@@ -35,7 +35,24 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="interior points per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-evals", type=int, default=4, help="oracle RHS evaluations in the CPU sample")
+    ap.add_argument("--strip", type=int, default=0, help="tile-order strip height (0: library default)")
+    ap.add_argument("--sweep-strip", action="store_true", help="time one RK4 step per strip height and report")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (3 times): the reference for scaling "
+                         "the FETCH_SIZE / WRITE_SIZE counters to bytes")
     return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+
+    n = (1 << 30) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print('{"copy_calibration_bytes_read": %d, "copy_calibration_bytes_written": %d, "launches": 3}' % (n * 8, n * 8))
 
 
 class CallTimer:
@@ -66,6 +83,9 @@ class CallTimer:
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(sharding is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
@@ -88,6 +108,8 @@ def main():
     mhd.prim2con(run.patch, run.eos, run.Un, Pd, EMd, 0)
     run.Us.copy_(run.Un)
     dt = 0.25 * ip.dx[0]
+    if args.strip:
+        mhd.set_tuning(args.strip)
 
     timer = CallTimer(torch, False)
 
@@ -101,6 +123,23 @@ def main():
             nxt = run.Us if s < 3 else run.Un
             timer.wrap("rk_stage", mhd.rk_stage, run.patch, I.NU, s, dt, run.Un, run.k, run.acc, nxt)
 
+    sweep = None
+    if args.sweep_strip:
+        sweep = {}
+        for sh in (1, 2, 4, 8, 16, 32):
+            mhd.set_tuning(sh)
+            step()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(3):
+                step()
+            e1.record()
+            torch.cuda.synchronize()
+            sweep[sh] = e0.elapsed_time(e1) / 3
+        best = min(sweep, key=sweep.get)
+        mhd.set_tuning(best)
+        sweep = {"ms_per_step": {k: round(v, 3) for k, v in sweep.items()}, "chosen": best}
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -148,7 +187,7 @@ def main():
                                   "RHS + plain con2prim + RK4 stage" % (args.n, ip.dx[0]),
                       "interior_points": nint, "padded_points": npad, "rhs_evals_per_step": 4, "path": "plain"},
            "breakdown_ms_per_call": {k: round(v, 4) for k, v in per.items()},
-           "wall_s": round(wall, 3), "finite": fin,
+           "wall_s": round(wall, 3), "finite": fin, "tuning": mhd.get_tuning(), "strip_sweep": sweep,
            "roofline": roof}
 
     if not args.no_cpu_baseline:

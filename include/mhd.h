@@ -122,6 +122,19 @@ typedef struct {
   uint32_t flags; /* MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER */
 } mhd_params_t;
 
+/* Launch tuning of the stencil kernels (process-wide; set it before enqueuing
+ * work, not concurrently with launches from other host threads).
+ * strip: height, in 64x4-point tiles, of the strips in which each XCD walks
+ * its contiguous range of tiles (z fastest inside a strip); 1..1024.
+ * The results do not depend on the tuning (bitwise). */
+typedef struct {
+  int32_t strip;
+  int32_t reserved[7];
+} mhd_tuning_t;
+
+int mhd_set_tuning(const mhd_tuning_t* t);
+int mhd_get_tuning(mhd_tuning_t* t);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char* mhd_last_error(void);
 int mhd_abi_version(void);

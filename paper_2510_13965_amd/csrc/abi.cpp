@@ -13,10 +13,10 @@
 
 namespace mhd {
 int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
-                hipStream_t s);
+                int strip, hipStream_t s);
 int ccz4_workspace_fields();
 int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,
-               double* ws, double* rhs, double* max_speed, hipStream_t s);
+               double* ws, double* rhs, double* max_speed, int strip, hipStream_t s);
 int launch_con2prim(const Geom& g, const mhd_eos_t& eos, double* U, double* P, uint8_t* flags, double* mu,
                     int64_t* stats, hipStream_t s);
 int launch_prim2con(const Geom& g, const mhd_eos_t& eos, double* U, double* P, const double* EM, int eps_mode,
@@ -30,6 +30,8 @@ int launch_zero_interior(const Geom& g, int f0, int nfields, double* A, hipStrea
 namespace {
 
 thread_local char g_err[512] = "";
+// strip height (in 64x4 tiles) of the XCD-aware tile order of the stencil kernels
+int g_strip = 4;
 
 int fail(int code, const char* fmt, ...) {
   va_list ap;
@@ -109,6 +111,21 @@ const char* mhd_last_error(void) { return g_err; }
 
 int mhd_abi_version(void) { return MHD_ABI_VERSION; }
 
+int mhd_set_tuning(const mhd_tuning_t* t) {
+  if (!t) return fail(MHD_EINVAL, "mhd_set_tuning: NULL");
+  if (t->strip < 1 || t->strip > 1024) return fail(MHD_EINVAL, "mhd_set_tuning: strip must be 1..1024");
+  g_strip = t->strip;
+  g_err[0] = 0;
+  return MHD_OK;
+}
+
+int mhd_get_tuning(mhd_tuning_t* t) {
+  if (!t) return fail(MHD_EINVAL, "mhd_get_tuning: NULL");
+  *t = mhd_tuning_t{};
+  t->strip = g_strip;
+  return MHD_OK;
+}
+
 int mhd_eos_init_pwp(mhd_eos_t* e) {
   if (!e) return fail(MHD_EINVAL, "mhd_eos_init_pwp: eos is NULL");
   if (e->npieces < 1 || e->npieces > 4) return fail(MHD_EINVAL, "mhd_eos_init_pwp: npieces must be 1..4");
@@ -171,7 +188,7 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
   const mhd::Geom g = geom_of(patch);
   hipStream_t s = (hipStream_t)stream;
   if (fl & MHD_EVOLVE_SPACETIME) {
-    if ((rc = hip_check(mhd::launch_ccz4(g, *params, U, P, rhs, (double*)workspace + 33 * patch->sf, s),
+    if ((rc = hip_check(mhd::launch_ccz4(g, *params, U, P, rhs, (double*)workspace + 33 * patch->sf, g_strip, s),
                         "mhd_rhs/ccz4")))
       return rc;
   } else {
@@ -179,7 +196,7 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
     if ((rc = hip_check(mhd::launch_zero_interior(g, 0, MHD_NST, rhs, s), "mhd_rhs/zero"))) return rc;
   }
   if (fl & MHD_EVOLVE_MHD) {
-    if ((rc = hip_check(mhd::launch_mhd(g, *params, *eos, U, P, (double*)workspace, rhs, max_speed, s), "mhd_rhs/grmhd")))
+    if ((rc = hip_check(mhd::launch_mhd(g, *params, *eos, U, P, (double*)workspace, rhs, max_speed, g_strip, s), "mhd_rhs/grmhd")))
       return rc;
   } else {
     if ((rc = hip_check(mhd::launch_zero_interior(g, MHD_NST, MHD_NMHD, rhs, s), "mhd_rhs/zero"))) return rc;

@@ -28,6 +28,7 @@ struct Ccz4Args {
   const double* __restrict__ U;
   const double* __restrict__ P;
   double* __restrict__ rhs;
+  int nbx, nby, nbz, strip;  // tile grid (64x4 tiles) and the strip height of the tile order
 };
 
 constexpr double kPi = 3.141592653589793;
@@ -41,12 +42,15 @@ struct PointIdx {
   bool live;
 };
 
-__device__ __forceinline__ PointIdx point_index(const Geom& g) {
+__device__ __forceinline__ PointIdx point_index(const Ccz4Args& a) {
+  const Geom& g = a.g;
   PointIdx q;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  q.live = i < g.nx && j < g.ny;
+  const TileXYZ t = tile_of_block(a.nbx, a.nby, a.nbz, a.strip);
+  int i = t.bx * 64 + threadIdx.x;
+  int j = t.by * 4 + threadIdx.y;
+  int k = t.bz;
+  q.live = t.bx >= 0 && i < g.nx && j < g.ny;
+  if (!q.live) i = j = k = 0;
   q.p = g.at(i + g.ng, j + g.ng, k + g.ng);
   q.voff = (uint32_t)(q.p * 8);
   q.sf = g.sf;
@@ -136,7 +140,7 @@ __device__ __forceinline__ void matter_point(const double* __restrict__ U, const
 
 __global__ void __launch_bounds__(256) k_ccz4_stencil(Ccz4Args a) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(g);
+  const PointIdx q = point_index(a);
   if (!q.live) return;
   const double* __restrict__ U = a.U;
   const double beta[3] = {ldf(U + (19) * q.sf, q.voff), ldf(U + (20) * q.sf, q.voff), ldf(U + (21) * q.sf, q.voff)};
@@ -162,7 +166,7 @@ constexpr int kD2Fields = 24;
 
 __global__ void __launch_bounds__(256) k_ccz4_d2(Ccz4Args a, double* __restrict__ W) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(g);
+  const PointIdx q = point_index(a);
   if (!q.live) return;
   const double* __restrict__ U = a.U;
   const int64_t sf = q.sf;
@@ -218,7 +222,7 @@ __global__ void __launch_bounds__(256) k_ccz4_d2(Ccz4Args a, double* __restrict_
 
 __global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __restrict__ W) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(g);
+  const PointIdx q = point_index(a);
   if (!q.live) return;
   const double* __restrict__ U = a.U;
   const int64_t sf = q.sf, p = q.p;
@@ -395,7 +399,7 @@ __global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __r
 
 __global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __restrict__ W) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(g);
+  const PointIdx q = point_index(a);
   if (!q.live) return;
   const double* __restrict__ U = a.U;
   const int64_t sf = q.sf, p = q.p;
@@ -516,10 +520,12 @@ __global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __
 int ccz4_workspace_fields() { return kD2Fields; }
 
 int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
-                hipStream_t s) {
-  Ccz4Args a{g, par, U, P, rhs};
+                int strip, hipStream_t s) {
+  const int nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4, nbz = g.nz;
+  Ccz4Args a{g, par, U, P, rhs, nbx, nby, nbz, strip};
   dim3 blk(64, 4, 1);
-  dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  const int nblk = nbx * nby * nbz;
+  dim3 grd(8 * ((nblk + 7) / 8), 1, 1);
   hipLaunchKernelGGL(k_ccz4_stencil, grd, blk, 0, s, a);
   hipLaunchKernelGGL(k_ccz4_d2, grd, blk, 0, s, a, ws);
   hipLaunchKernelGGL(k_ccz4_curv, grd, blk, 0, s, a, (const double*)ws);

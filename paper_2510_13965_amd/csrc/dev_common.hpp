@@ -28,6 +28,43 @@ struct Geom {
   __device__ __forceinline__ int64_t stride(int a) const { return a == 0 ? 1 : (a == 1 ? sy : sz); }
 };
 
+// ------------------------------------------------------------------ tile order
+//
+// Stencil kernels run on a 1D grid of 64x4 (x,y) tiles.  The hardware hands
+// consecutive workgroups to the 8 XCDs round-robin, and each XCD has its own
+// L2, so with the natural order y-neighbour tiles (which share halo rows) land
+// on different L2s.  The mapping below gives every XCD a contiguous range of
+// tiles, and walks that range in strips of `strip` tile rows, z fastest, so
+// the tiles an XCD has in flight are stacked in z and share their +-3-plane
+// halos in its L2.
+struct TileXYZ {
+  int bx, by, bz;
+};
+
+__device__ __forceinline__ TileXYZ tile_of_block(int nbx, int nby, int nbz, int strip) {
+  const int nblk = nbx * nby * nbz;
+  const int b = blockIdx.x;
+  const int per_xcd = (nblk + 7) / 8;
+  const int xcd = b & 7, slot = b >> 3;
+  int id = xcd * per_xcd + slot;  // contiguous range per XCD
+  if (id >= nblk) {
+    TileXYZ t{-1, -1, -1};
+    return t;
+  }
+  const int sh = strip < nby ? strip : nby;
+  const int per_strip = sh * nbx * nbz;
+  const int st = id / per_strip;
+  int r = id - st * per_strip;
+  const int rows = (st * sh + sh <= nby) ? sh : (nby - st * sh);  // last strip may be short
+  const int per_plane = rows * nbx;
+  TileXYZ t;
+  t.bz = r / per_plane;
+  r -= t.bz * per_plane;
+  t.by = st * sh + r / nbx;
+  t.bx = r - (r / nbx) * nbx;
+  return t;
+}
+
 // ------------------------------------------------------------------ EoS
 
 struct Cold {

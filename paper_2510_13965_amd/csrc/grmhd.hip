@@ -194,6 +194,7 @@ __global__ void __launch_bounds__(256) k_mhd_point(MhdPointArgs a) {
 
 struct MhdUpdArgs {
   Geom g;
+  int nbx, nby, nbz, strip;  // tile grid (64x4 tiles) and strip height of the tile order
   mhd_params_t par;
   const double* __restrict__ U;
   const double* __restrict__ P;
@@ -204,10 +205,11 @@ struct MhdUpdArgs {
 
 __global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
   const Geom& g = a.g;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  const bool live = (i < g.nx && j < g.ny);
+  const TileXYZ t = tile_of_block(a.nbx, a.nby, a.nbz, a.strip);
+  const int i = t.bx * 64 + threadIdx.x;
+  const int j = t.by * 4 + threadIdx.y;
+  const int k = t.bz < 0 ? 0 : t.bz;
+  const bool live = (t.bx >= 0 && i < g.nx && j < g.ny);
   const int64_t sf = g.sf;
   const int64_t p = live ? g.at(i + g.ng, j + g.ng, k + g.ng) : g.at(g.ng, g.ng, k + g.ng);
   const double* __restrict__ U = a.U;
@@ -383,13 +385,15 @@ __global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
 }
 
 int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,
-               double* ws, double* rhs, double* max_speed, hipStream_t s) {
+               double* ws, double* rhs, double* max_speed, int strip, hipStream_t s) {
   MhdPointArgs pa{g, par, eos, U, P, ws};
   dim3 blk(64, 4, 1);
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
   hipLaunchKernelGGL(k_mhd_point, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), blk, 0, s, pa);
-  MhdUpdArgs ua{g, par, U, P, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed)};
-  hipLaunchKernelGGL(k_mhd_update, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), blk, 0, s, ua);
+  const int nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4, nbz = g.nz;
+  MhdUpdArgs ua{g, nbx, nby, nbz, strip, par, U, P, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed)};
+  const int nblk = nbx * nby * nbz;
+  hipLaunchKernelGGL(k_mhd_update, dim3(8 * ((nblk + 7) / 8), 1, 1), blk, 0, s, ua);
   return (int)hipGetLastError();
 }
 

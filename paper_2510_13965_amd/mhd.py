@@ -42,6 +42,10 @@ class Params(C.Structure):
                 ("f_beta", C.c_double), ("f_alpha_kind", C.c_int32), ("flags", C.c_uint32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("strip", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
 _vp = C.c_void_p
 _LIB = None
 
@@ -57,6 +61,8 @@ SIGNATURES = {
                           C.c_size_t, _vp]),
     "mhd_rk_stage": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_double, _vp, _vp, _vp, _vp, _vp]),
     "mhd_fill_ghosts_periodic": (C.c_int, [C.POINTER(Patch), _vp, C.c_int, _vp]),
+    "mhd_set_tuning": (C.c_int, [C.POINTER(Tuning)]),
+    "mhd_get_tuning": (C.c_int, [C.POINTER(Tuning)]),
 }
 
 
@@ -183,6 +189,18 @@ def rk_stage(patch, nfields, stage, dt, Un, k, acc, Unext, stream=None):
 
 def fill_ghosts_periodic(patch, U, nfields, stream=None):
     _check(lib().mhd_fill_ghosts_periodic(C.byref(patch), _ptr(U), nfields, _stream(stream)))
+
+
+def set_tuning(strip):
+    t = Tuning()
+    t.strip = int(strip)
+    _check(lib().mhd_set_tuning(C.byref(t)))
+
+
+def get_tuning():
+    t = Tuning()
+    _check(lib().mhd_get_tuning(C.byref(t)))
+    return {"strip": t.strip}
 
 
 def workspace_for(patch, device="cuda"):
