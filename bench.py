@@ -55,32 +55,6 @@ def copy_calibration():
     print('{"copy_calibration_bytes_read": %d, "copy_calibration_bytes_written": %d, "launches": 3}' % (n * 8, n * 8))
 
 
-class CallTimer:
-    """HIP events around each library call, on the stream the call is issued on."""
-
-    def __init__(self, torch, enabled):
-        self.torch = torch
-        self.enabled = enabled
-        self.ev = {}
-
-    def wrap(self, name, fn, *a, **kw):
-        if not self.enabled:
-            return fn(*a, **kw)
-        s = self.torch.cuda.Event(enable_timing=True)
-        e = self.torch.cuda.Event(enable_timing=True)
-        s.record()
-        r = fn(*a, **kw)
-        e.record()
-        self.ev.setdefault(name, []).append((s, e))
-        return r
-
-    def avg_ms(self):
-        return {k: sum(s.elapsed_time(e) for s, e in v) / len(v) for k, v in self.ev.items()}
-
-    def count(self):
-        return {k: len(v) for k, v in self.ev.items()}
-
-
 def main():
     args = parse()
     if args.copy_calibration:
@@ -111,17 +85,12 @@ def main():
     if args.strip:
         mhd.set_tuning(args.strip)
 
-    timer = CallTimer(torch, False)
-
-    def rhs_eval(Ux):
-        timer.wrap("con2prim", mhd.con2prim, run.patch, run.eos, Ux, run.P, run.flags, None, run.stats)
-        timer.wrap("rhs", mhd.rhs, run.patch, run.par, run.eos, Ux, run.P, run.k, run.vmax, run.ws)
-
     def step():
         for s in range(4):
-            rhs_eval(run.Un if s == 0 else run.Us)
-            nxt = run.Us if s < 3 else run.Un
-            timer.wrap("rk_stage", mhd.rk_stage, run.patch, I.NU, s, dt, run.Un, run.k, run.acc, nxt)
+            Ux = run.Un if s == 0 else run.Us
+            mhd.con2prim(run.patch, run.eos, Ux, run.P, run.flags, None, run.stats)
+            mhd.rhs(run.patch, run.par, run.eos, Ux, run.P, run.k, run.vmax, run.ws)
+            mhd.rk_stage(run.patch, I.NU, s, dt, run.Un, run.k, run.acc, run.Us if s < 3 else run.Un)
 
     sweep = None
     if args.sweep_strip:
@@ -148,6 +117,7 @@ def main():
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     w0 = time.perf_counter()
+    mhd.profile_start()
     t0.record()
     for _ in range(args.steps):
         step()
@@ -160,39 +130,98 @@ def main():
     zu_s = nint * 4 / (ms_step * 1e-3)
     fin = bool(torch.isfinite(run.Un).all().item())
 
-    # per-call durations in a second timed pass with events around each call
-    timer.enabled = True
-    for _ in range(max(2, args.steps // 4)):
-        step()
-    torch.cuda.synchronize()
-    per = timer.avg_ms()
-
-    # algorithmic bytes per call (minimum HBM traffic, FP64, perfect halo reuse)
-    npad = ip.npts
-    bytes_call = {
-        "con2prim": npad * ((17 + 8) * 8 + 1),           # 17 inputs, 8 prims, 1 flag byte
-        "rhs": nint * ((32 + 7 + 32) * 8),                 # U and prims in, 32 RHS out
-        "rk_stage": nint * (32 * 8 * 5 * 3 + 32 * 8 * 4) / 4,   # stages 0-2: 5 arrays, stage 3: 4
-    }
-    dom = max(per, key=lambda k: per[k] * timer.count()[k])
-    achieved = bytes_call[dom] / (per[dom] * 1e-3) / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "note": "provisional: algorithmic bytes of the dominant library call / its event-timed duration"}
-
+    prof = mhd.profile_stop()
+    kern = kernel_table(prof, ip, args.steps)
+    roof = roofline(prof, ip, args.n)
     out = {"metric": METRIC, "value": round(zu_s, 1), "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "C2: TOV star K=100 Gamma=2 rho_c=1.28e-3, %d^3 interior, dx=%.4g, full CCZ4+GRMHD "
+           "config": {"workload": "TOV star K=100 Gamma=2 rho_c=1.28e-3, %d^3 interior, dx=%.4g, full CCZ4+GRMHD "
                                   "RHS + plain con2prim + RK4 stage" % (args.n, ip.dx[0]),
-                      "interior_points": nint, "padded_points": npad, "rhs_evals_per_step": 4, "path": "plain"},
-           "breakdown_ms_per_call": {k: round(v, 4) for k, v in per.items()},
+                      "interior_points": nint, "padded_points": ip.npts, "rhs_evals_per_step": 4, "path": "plain"},
+           "kernels": kern,
            "wall_s": round(wall, 3), "finite": fin, "tuning": mhd.get_tuning(), "strip_sweep": sweep,
            "roofline": roof}
 
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ip, U, P, EM, args.cpu_evals)
     print(json.dumps(out), flush=True)
+
+
+# Algorithmic work per unit, counted on this workload by oracle/opcount.py
+# (the oracle's own evaluation with an op-counting scalar type; add/sub, mul,
+# div, sqrt and pow/exp/log count one flop each).  Units: interior points for
+# the RHS kernels, padded points for con2prim and the point fluxes, interior
+# point-fields for the RK stage.  The MHD update counts every interface once.
+FLOP_PER_UNIT = {
+    "k_con2prim": 188.85,
+    "k_mhd_point": 1608.0,
+    "k_mhd_update": 5136.11,
+    "ccz4 (4 kernels)": 10396.0,
+    "k_rk4_stage": 4.75,
+}
+# HBM bytes per launch of the dominant kernel from rocprofv3 --pmc (FETCH_SIZE x 2
+# + WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read and write 1 GiB),
+# valid only for the kernel sources they were taken on (sha256 of these files).
+TRAFFIC = {}
+TRAFFIC_SOURCES = {"k_mhd_update": ["paper_2510_13965_amd/csrc/grmhd.hip", "paper_2510_13965_amd/csrc/dev_common.hpp"]}
+
+
+def sources_sha(files):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_table(prof, ip, steps):
+    """Per-kernel launches and event-timed durations, with the achieved FP64
+    rate of the algorithmic flops where the count exists."""
+    units = {"k_con2prim": ip.npts, "k_mhd_point": ip.npts, "k_mhd_update": ip.ninterior,
+             "k_rk4_stage": ip.ninterior * 32}
+    tab = {}
+    for k, (n, t) in prof.items():
+        e = {"launches": n, "ms_per_launch": round(t / n, 4), "ms_per_step": round(t / steps, 4)}
+        if k in units:
+            e["fp64_tflops"] = round(FLOP_PER_UNIT[k] * units[k] / (t / n * 1e-3) / 1e12, 3)
+        tab[k] = e
+    cz = [k for k in prof if k.startswith("k_ccz4_")]
+    if cz:
+        t = sum(prof[k][1] for k in cz) / prof[cz[0]][0]
+        tab["ccz4 (4 kernels)"] = {"ms_per_launch": round(t, 4),
+                                   "fp64_tflops": round(FLOP_PER_UNIT["ccz4 (4 kernels)"] * ip.ninterior
+                                                        / (t * 1e-3) / 1e12, 3)}
+    return tab
+
+
+def roofline(prof, ip, n):
+    """Roofline entry of the kernel with the largest share of the step.
+
+    The RHS kernels are FP64-vector bound (arithmetic intensity above the ridge
+    of 78.6 TFLOP/s / 8 TB/s); their achieved rate is the algorithmic flops of
+    one launch over its average event-timed duration."""
+    nint, npad = ip.ninterior, ip.npts
+    units = {"k_con2prim": npad, "k_mhd_point": npad, "k_mhd_update": nint, "k_rk4_stage": nint * 32}
+    dom = max(prof, key=lambda k: prof[k][1])
+    launches, tot = prof[dom]
+    ms = tot / launches
+    out = {"kernel": dom, "ms_per_launch": round(ms, 4)}
+    if dom in units and dom != "k_rk4_stage":
+        flop = FLOP_PER_UNIT[dom] * units[dom]
+        ach = flop / (ms * 1e-3) / 1e12
+        out.update({"bound": "alu", "achieved": round(ach, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(ach / FP64_PEAK_TFLOPS, 4), "flop_per_launch": flop})
+    else:
+        nbytes = nint * 32 * 8 * 4.75  # stages 0-2 move 5 arrays, stage 3 moves 4
+        ach = nbytes / (ms * 1e-3) / 1e9
+        out.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes})
+    t = TRAFFIC.get(dom)
+    out["traffic"] = t[0] if t and t[1] == sources_sha(TRAFFIC_SOURCES[dom]) else None
+    return out
 
 
 def cpu_baseline(ip, U, P, EM, nevals):

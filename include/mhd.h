@@ -70,7 +70,7 @@ extern "C" {
 #define MHD_STAT_FATAL 0
 #define MHD_STAT_CORRECTED 1
 #define MHD_STAT_FALLBACK 2
-#define MHD_STAT_ITERATIONS 3
+#define MHD_STAT_ITERATIONS 3 /* root-function evaluations (Newton or bracketed, bracket ends included) */
 #define MHD_NSTAT 8
 
 /* flags of mhd_params_t.flags */
@@ -135,6 +135,23 @@ typedef struct {
 int mhd_set_tuning(const mhd_tuning_t* t);
 int mhd_get_tuning(mhd_tuning_t* t);
 
+/* Per-kernel timing, for benchmarks.  Between mhd_profile_start() and
+ * mhd_profile_stop() every kernel the library launches (outside stream
+ * capture) is bracketed by two HIP events recorded on the stream it is launched
+ * on; stop waits for the recorded events and returns, per kernel name, the
+ * number of launches and the summed event-to-event time.  Up to 65536 launches
+ * are recorded per session (more: stop returns MHD_EINVAL after filling `out`).
+ * out: host array of max_entries records (may be NULL); *n_entries receives
+ * the number of kernels seen.  Process-wide; not for concurrent sessions. */
+typedef struct {
+  char name[40];
+  int64_t launches;
+  double total_ms;
+} mhd_kernel_time_t;
+
+int mhd_profile_start(void);
+int mhd_profile_stop(mhd_kernel_time_t* out, int max_entries, int* n_entries);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char* mhd_last_error(void);
 int mhd_abi_version(void);
@@ -161,6 +178,60 @@ int mhd_prim2con(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, doub
  *   stats (MHD_NSTAT int64 device counters, accumulated, may be NULL). */
 int mhd_con2prim(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, double* P,
                  uint8_t* flags, double* mu, int64_t* stats, void* stream);
+
+/* ---- learned starting guess for con2prim ------------------------------------
+ * A small MLP (8 -> 64 -> 64 -> 2, ReLU; hidden layers on bf16 matrix cores with
+ * FP32 accumulation) predicts the two roots of App. D from 8 metric-invariant
+ * scalars of the state: log10 D, log10 q, log10 r^2, log10 calB^2,
+ * (r.calB)^2 / (r^2 calB^2), log10(1+q), log10 r^2/(1+q)^2, log10 calB^2/(1+q)
+ * (q = tau/D, r_i = S_i/D, calB^i = B^i/sqrt(D); tiny floors keep the logs
+ * finite).  Outputs: logit(mu_+ h0) and logit(mu / mu_+).
+ * Parameter block (float32, device, MHD_MLP_NBLOCK floats): W1[64][8] at 0,
+ * b1[64] at 512, W2[64][64] at 576, b2[64] at 4672, W3[2][64] at 4736, b3[2] at
+ * 4864 (the MHD_MLP_NPARAM trainable values), feature mean[8] at 4866 and
+ * inverse standard deviation[8] at 4874. */
+#define MHD_MLP_NPARAM 4866
+#define MHD_MLP_NBLOCK 4882
+
+/* con2prim (App. D) with the learned guess: per padded point, the network
+ * guesses mu_+ and mu; each is polished by at most 3 Newton iterations in FP64
+ * and accepted when the residual is <= 1e-12 (|f_a|, and |f| relative to mu)
+ * with 0 < mu <= mu_+.  Rejected points are queued and finished by the same
+ * bracketed solver as mhd_con2prim (their flag gets MHD_FLAG_FALLBACK).  The
+ * error policy, outputs and U rewrite are those of mhd_con2prim; stats also
+ * counts MHD_STAT_FALLBACK points and, in MHD_STAT_ITERATIONS, Newton
+ * evaluations plus bracketed iterations.
+ * workspace: device buffer of mhd_con2prim_learned_workspace_size() bytes
+ * (the fallback queue); the padded patch must have < 2^32 points. */
+size_t mhd_con2prim_learned_workspace_size(const mhd_patch_t* patch);
+int mhd_con2prim_learned(const mhd_patch_t* patch, const mhd_eos_t* eos, const float* mlp, double* U, double* P,
+                         uint8_t* flags, double* mu, int64_t* stats, void* workspace, size_t workspace_bytes,
+                         void* stream);
+
+/* Training set-up and steps (device arrays, row-major):
+ * mhd_mlp_features: X[N][8] raw features (float32) of every padded point in
+ *   linear padded order (i fastest); points with D < rho_min get NaN rows.
+ *   If mu (2 fields mu_+, mu, as written by mhd_con2prim) and T are non-NULL,
+ *   T[N][2] gets the targets logit(mu_+ h0), logit(mu/mu_+), arguments clamped
+ *   to [1e-6, 1 - 1e-6].
+ * mhd_mlp_normalize: mean and inverse std of each feature over the non-NaN rows
+ *   of X[n][8], written into the parameter block.
+ * mhd_mlp_forward: Y[n][2] network outputs for raw features X[n][8].
+ * mhd_mlp_grad: grad[MHD_MLP_NPARAM] = dL/dtheta and *loss = L (device float,
+ *   may be NULL) for L = 1/(2n) sum over non-NaN rows of |y - t|^2; the same
+ *   bf16 rounding as the forward pass; deterministic (fixed reduction order).
+ *   workspace: mhd_mlp_grad_workspace_size(n) bytes.
+ * mhd_mlp_adam: one Adam step (step counts from 1) on the trainable
+ *   parameters, with moment buffers m, v[MHD_MLP_NPARAM] (zeroed before step 1). */
+int mhd_mlp_features(const mhd_patch_t* patch, const mhd_eos_t* eos, const double* U, const double* mu, float* X,
+                     float* T, void* stream);
+int mhd_mlp_normalize(float* mlp, const float* X, int64_t n, void* stream);
+int mhd_mlp_forward(const float* mlp, const float* X, int64_t n, float* Y, void* stream);
+size_t mhd_mlp_grad_workspace_size(int64_t n);
+int mhd_mlp_grad(const float* mlp, const float* X, const float* T, int64_t n, float* grad, float* loss,
+                 void* workspace, size_t workspace_bytes, void* stream);
+int mhd_mlp_adam(float* mlp, const float* grad, float* m, float* v, int step, float lr, float beta1, float beta2,
+                 float eps, void* stream);
 
 /* Workspace bytes mhd_rhs needs for this patch (point fluxes and speeds). */
 size_t mhd_rhs_workspace_size(const mhd_patch_t* patch);

@@ -306,6 +306,7 @@ static int64_t npts(const orc_grid* g) {
 void orc_prim2con(const orc_grid* g, const orc_eos* e, double* U, double* P,
                   const double* EM, int eps_mode) {
   int64_t N = npts(g), p;
+  ORC_PHASE(ORC_PH_P2C);
 #pragma omp parallel for schedule(static)
   for (p = 0; p < N; ++p) {
     double gdn[6], gup[6], sg, prim[8], B[3], cons[6], v[3], vd[3], v2;
@@ -327,11 +328,13 @@ void orc_prim2con(const orc_grid* g, const orc_eos* e, double* U, double* P,
     P[2 * N + p] = prim[2];
     P[6 * N + p] = prim[6];
   }
+  ORC_PHASE(ORC_PH_OTHER);
 }
 
 int64_t orc_con2prim(const orc_grid* g, const orc_eos* e, double* U, double* P,
                      uint8_t* flags, double* mu) {
   int64_t N = npts(g), p, nfatal = 0;
+  ORC_PHASE(ORC_PH_C2P);
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : nfatal)
   for (p = 0; p < N; ++p) {
     double gdn[6], gup[6], sg, cons[6], B[3], prim[8], m[2];
@@ -350,5 +353,33 @@ int64_t orc_con2prim(const orc_grid* g, const orc_eos* e, double* U, double* P,
     if (mu) { mu[p] = m[0]; mu[N + p] = m[1]; }
     if (f & ORC_F_FATAL) nfatal += 1;
   }
+  ORC_PHASE(ORC_PH_OTHER);
   return nfatal;
+}
+
+void orc_c2p_features(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,
+                      float* X, float* T) {
+  int64_t N = npts(g), p;
+#pragma omp parallel for schedule(static)
+  for (p = 0; p < N; ++p) {
+    double gdn[6], gup[6], sg, cons[6], B[3], x[8], m[2], t[2];
+    int i;
+    metric_at(U, p, N, gdn, gup, &sg);
+    for (i = 0; i < 6; ++i) cons[i] = U[(22 + i) * N + p] / sg;
+    for (i = 0; i < 3; ++i) B[i] = U[(28 + i) * N + p] / sg;
+    if (!(cons[0] >= e->rho_min)) {
+      for (i = 0; i < 8; ++i) X[p * 8 + i] = (float)NAN;
+      if (T) T[p * 2] = T[p * 2 + 1] = (float)NAN;
+      continue;
+    }
+    orc_mlp_features(cons, B, gdn, gup, x);
+    for (i = 0; i < 8; ++i) X[p * 8 + i] = (float)x[i];
+    if (T && mu) {
+      m[0] = mu[p];
+      m[1] = mu[N + p];
+      orc_mlp_targets(e->h0, m, t);
+      T[p * 2] = (float)t[0];
+      T[p * 2 + 1] = (float)t[1];
+    }
+  }
 }

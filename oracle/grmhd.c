@@ -136,8 +136,9 @@ static int64_t npts(const orc_grid* g) {
 /* numerical flux at interface between p and p+s (i.e. i+1/2 with i = p) */
 static double iface_flux(const double* Ff, const double* Uf, const double* lam, int64_t p,
                          int64_t s, double alpha_mp5) {
-  double l = 0.0, fp[5], fm[5];
+  double l = 0.0, fp[5], fm[5], r;
   int m;
+  ORC_PHASE(ORC_PH_MHD_RECON);
   for (m = -2; m <= 3; ++m) l = fmax(l, lam[p + m * s]);
   for (m = 0; m < 5; ++m) {
     int64_t q = p + (m - 2) * s;        /* i-2 .. i+2 */
@@ -145,7 +146,9 @@ static double iface_flux(const double* Ff, const double* Uf, const double* lam, 
     fp[m] = 0.5 * (Ff[q] + l * Uf[q]);
     fm[m] = 0.5 * (Ff[r] - l * Uf[r]);
   }
-  return orc_mp5(fp, alpha_mp5) + orc_mp5(fm, alpha_mp5);
+  r = orc_mp5(fp, alpha_mp5) + orc_mp5(fm, alpha_mp5);
+  ORC_PHASE(ORC_PH_MHD_UPD);
+  return r;
 }
 
 /* GRMHD contribution for all interior points: rhs[22..31] (overwritten). */
@@ -161,6 +164,7 @@ void orc_grmhd_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, cons
   int64_t p;
   int d;
 
+  ORC_PHASE(ORC_PH_MHD_POINT);
 #pragma omp parallel for schedule(static)
   for (p = 0; p < N; ++p) {
     int dd, f;
@@ -172,6 +176,7 @@ void orc_grmhd_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, cons
     }
   }
 
+  ORC_PHASE(ORC_PH_MHD_UPD);
 #pragma omp parallel for collapse(2) schedule(static) reduction(max : vmax)
   for (int64_t k = ng; k < Nz - ng; ++k)
     for (int64_t j = ng; j < Ny - ng; ++j)
@@ -268,6 +273,7 @@ void orc_grmhd_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, cons
         }
         for (f = 0; f < 10; ++f) rhs[(22 + f) * N + q] = out[f];
       }
+  ORC_PHASE(ORC_PH_OTHER);
   free(F);
   free(lam);
   if (max_speed) *max_speed = vmax;

@@ -31,6 +31,26 @@
 
 #include <stdint.h>
 
+#ifdef __cplusplus
+extern "C" { /* the op-counting build compiles these sources as C++ */
+#endif
+
+/* Op-count hooks.  Empty in the oracle build; the op-counting build
+ * (opcount.py, opcount.hpp) defines ORC_PHASE to attribute every counted
+ * floating-point operation to the step of the path it belongs to. */
+#ifndef ORC_PHASE
+#define ORC_PHASE(id) ((void)0)
+#endif
+#define ORC_PH_OTHER 0
+#define ORC_PH_CCZ4 1      /* CCZ4 point RHS incl. matter terms and KO */
+#define ORC_PH_MHD_POINT 2 /* point fluxes and speeds */
+#define ORC_PH_MHD_RECON 3 /* LF split + MP5 at one interface */
+#define ORC_PH_MHD_UPD 4   /* conservative difference + geometric sources */
+#define ORC_PH_C2P 5       /* con2prim incl. rewriting corrected points */
+#define ORC_PH_RK 6        /* RK stage */
+#define ORC_PH_P2C 7       /* prim -> cons */
+#define ORC_NPHASE 8
+
 #define ORC_NST 22
 #define ORC_NMHD 10
 #define ORC_NU 32
@@ -100,6 +120,23 @@ unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3]
                        const double gdn[6], const double gup[6], double alpha,
                        double prim[8], double mu[2], int* iters);
 
+/* ---- learned con2prim starting guess (MLP 8 -> 64 -> 64 -> 2) ---- */
+#define ORC_MLP_NPARAM 4866
+#define ORC_MLP_NBLOCK 4882
+float orc_bf16(float x);
+void orc_mlp_features(const double cons[6], const double B[3], const double gdn[6],
+                      const double gup[6], double x[8]);
+void orc_mlp_targets(double h0, const double mu[2], double t[2]);
+/* features (and, if mu != NULL, targets) at every padded point; X is [N][8],
+ * T is [N][2], binary32; points with D < rho_min get NaN rows */
+void orc_c2p_features(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,
+                      float* X, float* T);
+void orc_mlp_forward(const double* prm, const float* X, int64_t n, int emulate, double* Y);
+double orc_mlp_grad(const double* prm, const float* X, const float* T, int64_t n, int emulate,
+                    double* grad);
+void orc_mlp_adam(double* prm, const double* grad, double* m, double* v, int step, double lr,
+                  double beta1, double beta2, double eps);
+
 /* ---- right-hand side ---- */
 void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e,
              const double* U, const double* P, double* rhs, double* max_speed);
@@ -114,4 +151,7 @@ void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt
 /* ---- ghost fill ---- */
 void orc_fill_periodic(const orc_grid* g, double* U, int nfields);
 
+#ifdef __cplusplus
+}
+#endif
 #endif

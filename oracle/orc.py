@@ -35,6 +35,7 @@ class Par(C.Structure):
 
 
 _dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
 _u8p = C.POINTER(C.c_uint8)
 
 
@@ -45,38 +46,61 @@ def lib():
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
-        L = C.CDLL(path)
-        L.orc_eos_init_pwp.argtypes = [C.POINTER(Eos), C.c_int, C.c_double, _dp, _dp, C.c_double]
-        L.orc_eps_cold.argtypes = [C.POINTER(Eos), C.c_double]
-        L.orc_eps_cold.restype = C.c_double
-        L.orc_press.argtypes = [C.POINTER(Eos), C.c_double, C.c_double]
-        L.orc_press.restype = C.c_double
-        L.orc_cs2.argtypes = [C.POINTER(Eos), C.c_double, C.c_double]
-        L.orc_cs2.restype = C.c_double
-        for name in ("orc_d1", "orc_d2", "orc_ko"):
-            getattr(L, name).restype = C.c_double
-        L.orc_d1.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double]
-        L.orc_d2.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double]
-        L.orc_d11.argtypes = [_dp, C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double]
-        L.orc_d11.restype = C.c_double
-        L.orc_dup.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double, C.c_double]
-        L.orc_dup.restype = C.c_double
-        L.orc_ko.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double, C.c_double]
-        L.orc_mp5.argtypes = [_dp, C.c_double]
-        L.orc_mp5.restype = C.c_double
-        L.orc_prim2con.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp, C.c_int]
-        L.orc_con2prim.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _u8p, _dp]
-        L.orc_con2prim.restype = C.c_int64
-        L.orc_c2p_point.argtypes = [C.POINTER(Eos), _dp, _dp, _dp, _dp, C.c_double, _dp, _dp,
-                                    C.POINTER(C.c_int)]
-        L.orc_c2p_point.restype = C.c_uint
-        L.orc_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp, _dp]
-        L.orc_rk4_stage.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, _dp, _dp, _dp]
-        L.orc_rk4_stage_interior.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, C.c_double,
-                                             _dp, _dp, _dp, _dp]
-        L.orc_fill_periodic.argtypes = [C.POINTER(Grid), _dp, C.c_int]
-        _LIB = L
+        _LIB = _bind(C.CDLL(path))
     return _LIB
+
+
+def use_library(path):
+    """Bind this module to another build of the same sources (the op-counting
+    build of opcount.py); returns the previous library."""
+    global _LIB
+    old = _LIB
+    _LIB = _bind(C.CDLL(path))
+    return old
+
+
+def _bind(L):
+    L.orc_eos_init_pwp.argtypes = [C.POINTER(Eos), C.c_int, C.c_double, _dp, _dp, C.c_double]
+    L.orc_eps_cold.argtypes = [C.POINTER(Eos), C.c_double]
+    L.orc_eps_cold.restype = C.c_double
+    L.orc_press.argtypes = [C.POINTER(Eos), C.c_double, C.c_double]
+    L.orc_press.restype = C.c_double
+    L.orc_cs2.argtypes = [C.POINTER(Eos), C.c_double, C.c_double]
+    L.orc_cs2.restype = C.c_double
+    for name in ("orc_d1", "orc_d2", "orc_ko"):
+        getattr(L, name).restype = C.c_double
+    L.orc_d1.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double]
+    L.orc_d2.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double]
+    L.orc_d11.argtypes = [_dp, C.c_int64, C.c_int64, C.c_int64, C.c_double, C.c_double]
+    L.orc_d11.restype = C.c_double
+    L.orc_dup.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double, C.c_double]
+    L.orc_dup.restype = C.c_double
+    L.orc_ko.argtypes = [_dp, C.c_int64, C.c_int64, C.c_double, C.c_double]
+    L.orc_mp5.argtypes = [_dp, C.c_double]
+    L.orc_mp5.restype = C.c_double
+    L.orc_prim2con.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp, C.c_int]
+    L.orc_con2prim.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _u8p, _dp]
+    L.orc_con2prim.restype = C.c_int64
+    L.orc_c2p_point.argtypes = [C.POINTER(Eos), _dp, _dp, _dp, _dp, C.c_double, _dp, _dp,
+                                C.POINTER(C.c_int)]
+    L.orc_c2p_point.restype = C.c_uint
+    L.orc_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp, _dp]
+    L.orc_rk4_stage.argtypes = [C.c_int, C.c_double, C.c_int64, _dp, _dp, _dp, _dp]
+    L.orc_rk4_stage_interior.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, C.c_double,
+                                         _dp, _dp, _dp, _dp]
+    L.orc_fill_periodic.argtypes = [C.POINTER(Grid), _dp, C.c_int]
+    if hasattr(L, "orc_mlp_forward"):
+        L.orc_bf16.argtypes = [C.c_float]
+        L.orc_bf16.restype = C.c_float
+        L.orc_mlp_features.argtypes = [_dp, _dp, _dp, _dp, _dp]
+        L.orc_mlp_targets.argtypes = [C.c_double, _dp, _dp]
+        L.orc_c2p_features.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _fp, _fp]
+        L.orc_mlp_forward.argtypes = [_dp, _fp, C.c_int64, C.c_int, _dp]
+        L.orc_mlp_grad.argtypes = [_dp, _fp, _fp, C.c_int64, C.c_int, _dp]
+        L.orc_mlp_grad.restype = C.c_double
+        L.orc_mlp_adam.argtypes = [_dp, _dp, _dp, _dp, C.c_int, C.c_double, C.c_double, C.c_double,
+                                   C.c_double]
+    return L
 
 
 def ptr(a):
@@ -85,6 +109,8 @@ def ptr(a):
     assert a.flags["C_CONTIGUOUS"]
     if a.dtype == np.uint8:
         return a.ctypes.data_as(_u8p)
+    if a.dtype == np.float32:
+        return a.ctypes.data_as(_fp)
     assert a.dtype == np.float64, a.dtype
     return a.ctypes.data_as(_dp)
 
@@ -183,3 +209,68 @@ def press(e, rho, eps):
 
 def cs2(e, rho, eps):
     return lib().orc_cs2(C.byref(e), rho, eps)
+
+
+# ---------------------------------------------------------------- learned guess (MLP)
+
+MLP_NPARAM = 4866
+MLP_NBLOCK = 4882
+MLP_OFF = dict(W1=0, b1=512, W2=576, b2=4672, W3=4736, b3=4864, mean=4866, istd=4874)
+
+
+def bf16(x):
+    """bfloat16 rounding (nearest-even) of binary32 values, elementwise."""
+    a = np.asarray(x, dtype=np.float32)
+    return np.array([lib().orc_bf16(float(v)) for v in a.ravel()], dtype=np.float32).reshape(a.shape)
+
+
+def mlp_features(cons, B, gdn, gup):
+    x = np.zeros(8)
+    lib().orc_mlp_features(ptr(np.ascontiguousarray(cons, dtype=np.float64)),
+                           ptr(np.ascontiguousarray(B, dtype=np.float64)),
+                           ptr(np.ascontiguousarray(gdn, dtype=np.float64)),
+                           ptr(np.ascontiguousarray(gup, dtype=np.float64)), ptr(x))
+    return x
+
+
+def mlp_targets(h0, mu):
+    t = np.zeros(2)
+    lib().orc_mlp_targets(float(h0), ptr(np.ascontiguousarray(mu, dtype=np.float64)), ptr(t))
+    return t
+
+
+def c2p_features(g, e, U, mu=None):
+    """Features X [N][8] and (if mu is given) targets T [N][2], binary32."""
+    N = U[0].size
+    X = np.zeros((N, 8), dtype=np.float32)
+    T = np.zeros((N, 2), dtype=np.float32) if mu is not None else None
+    lib().orc_c2p_features(C.byref(g), C.byref(e), ptr(U), ptr(mu), ptr(X), ptr(T))
+    return X, T
+
+
+def _prm(prm):
+    return np.ascontiguousarray(prm, dtype=np.float64)
+
+
+def mlp_forward(prm, X, emulate=1):
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    Y = np.zeros((X.shape[0], 2))
+    lib().orc_mlp_forward(ptr(_prm(prm)), ptr(X), X.shape[0], int(emulate), ptr(Y))
+    return Y
+
+
+def mlp_grad(prm, X, T, emulate=1):
+    """(loss, gradient of the 4866 trainable parameters) over the batch."""
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    g = np.zeros(MLP_NPARAM)
+    loss = lib().orc_mlp_grad(ptr(_prm(prm)), ptr(X), ptr(T), X.shape[0], int(emulate), ptr(g))
+    return loss, g
+
+
+def mlp_adam(prm, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step in place on float64 arrays prm (>= 4866), m, v."""
+    for a in (prm, m, v):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    lib().orc_mlp_adam(ptr(prm), ptr(np.ascontiguousarray(grad, dtype=np.float64)), ptr(m), ptr(v), int(step),
+                       float(lr), float(beta1), float(beta2), float(eps))

@@ -25,6 +25,7 @@ void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const doub
   const int64_t st[3] = {1, Nx, Nx * Ny};
   const double h[3] = {g->dx[0], g->dx[1], g->dx[2]};
   int64_t k;
+  ORC_PHASE(ORC_PH_CCZ4);
 #pragma omp parallel for schedule(static)
   for (k = ng; k < Nz - ng; ++k)
     for (int64_t j = ng; j < Ny - ng; ++j)
@@ -39,6 +40,7 @@ void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const doub
         }
         for (f = 0; f < 22; ++f) rhs[f * N + p] = out[f];
       }
+  ORC_PHASE(ORC_PH_OTHER);
   if (par->evolve_mhd) {
     orc_grmhd_rhs(g, par, e, U, P, rhs, max_speed);
   } else {
@@ -76,7 +78,9 @@ static void stage_point(int stage, double dt, int64_t p, const double* Un, const
 void orc_rk4_stage(int stage, double dt, int64_t n, const double* Un, const double* k,
                    double* acc, double* Unext) {
   int64_t p;
+  ORC_PHASE(ORC_PH_RK);
   for (p = 0; p < n; ++p) stage_point(stage, dt, p, Un, k, acc, Unext);
+  ORC_PHASE(ORC_PH_OTHER);
 }
 
 void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt,
@@ -85,6 +89,7 @@ void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
   int f;
+  ORC_PHASE(ORC_PH_RK);
   for (f = 0; f < nfields; ++f) {
     int64_t kk;
 #pragma omp parallel for schedule(static)
@@ -93,6 +98,7 @@ void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt
         for (int64_t i = ng; i < Nx - ng; ++i)
           stage_point(stage, dt, f * N + i + Nx * (j + Ny * kk), Un, k, acc, Unext);
   }
+  ORC_PHASE(ORC_PH_OTHER);
 }
 
 /* periodic ghost fill: each ghost point takes the value of the interior point

@@ -25,6 +25,17 @@ int launch_rk4_stage(const Geom& g, int nfields, int stage, double dt, const dou
                      double* Unext, hipStream_t s);
 int launch_ghosts_periodic(const Geom& g, double* U, int nfields, hipStream_t s);
 int launch_zero_interior(const Geom& g, int f0, int nfields, double* A, hipStream_t s);
+int launch_mlp_features(const Geom& g, const mhd_eos_t& eos, const double* U, const double* mu, float* X, float* T,
+                        hipStream_t s);
+int launch_mlp_normalize(float* prm, const float* X, int64_t n, hipStream_t s);
+int launch_mlp_forward(const float* prm, const float* X, int64_t n, float* Y, hipStream_t s);
+int mlp_grad_blocks(int64_t n);
+int launch_mlp_grad(const float* prm, const float* X, const float* T, int64_t n, float* grad, float* loss, void* ws,
+                    hipStream_t s);
+int launch_mlp_adam(float* prm, const float* grad, float* m, float* v, int step, float lr, float b1, float b2,
+                    float eps, hipStream_t s);
+int launch_con2prim_learned(const Geom& g, const mhd_eos_t& eos, const float* prm, double* U, double* P,
+                            uint8_t* flags, double* mu, int64_t* stats, void* ws, hipStream_t s);
 }  // namespace mhd
 
 namespace {
@@ -159,6 +170,75 @@ int mhd_con2prim(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, doub
   if (!U || !P) return fail(MHD_EINVAL, "mhd_con2prim: U and P must be non-NULL");
   return hip_check(mhd::launch_con2prim(geom_of(patch), *eos, U, P, flags, mu, stats, (hipStream_t)stream),
                    "mhd_con2prim");
+}
+
+static int64_t padded_points(const mhd_patch_t* p) {
+  return (int64_t)(p->nx + 2 * p->ng) * (p->ny + 2 * p->ng) * (p->nz + 2 * p->ng);
+}
+
+size_t mhd_con2prim_learned_workspace_size(const mhd_patch_t* patch) {
+  if (!patch) return 0;
+  return 256 + 4 * (size_t)padded_points(patch);
+}
+
+int mhd_con2prim_learned(const mhd_patch_t* patch, const mhd_eos_t* eos, const float* mlp, double* U, double* P,
+                         uint8_t* flags, double* mu, int64_t* stats, void* workspace, size_t workspace_bytes,
+                         void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, 1, "mhd_con2prim_learned")) || (rc = check_eos(eos, "mhd_con2prim_learned")))
+    return rc;
+  if (!U || !P || !mlp) return fail(MHD_EINVAL, "mhd_con2prim_learned: U, P and mlp must be non-NULL");
+  if (padded_points(patch) >= ((int64_t)1 << 32))
+    return fail(MHD_EINVAL, "mhd_con2prim_learned: the padded patch must have fewer than 2^32 points");
+  if (!workspace || workspace_bytes < mhd_con2prim_learned_workspace_size(patch))
+    return fail(MHD_EWORKSPACE, "mhd_con2prim_learned: workspace of %zu bytes needed (got %zu)",
+                mhd_con2prim_learned_workspace_size(patch), workspace_bytes);
+  return hip_check(mhd::launch_con2prim_learned(geom_of(patch), *eos, mlp, U, P, flags, mu, stats, workspace,
+                                                (hipStream_t)stream),
+                   "mhd_con2prim_learned");
+}
+
+int mhd_mlp_features(const mhd_patch_t* patch, const mhd_eos_t* eos, const double* U, const double* mu, float* X,
+                     float* T, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, 1, "mhd_mlp_features")) || (rc = check_eos(eos, "mhd_mlp_features"))) return rc;
+  if (!U || !X) return fail(MHD_EINVAL, "mhd_mlp_features: U and X must be non-NULL");
+  return hip_check(mhd::launch_mlp_features(geom_of(patch), *eos, U, mu, X, T, (hipStream_t)stream),
+                   "mhd_mlp_features");
+}
+
+int mhd_mlp_normalize(float* mlp, const float* X, int64_t n, void* stream) {
+  if (!mlp || !X || n < 1) return fail(MHD_EINVAL, "mhd_mlp_normalize: need mlp, X and n >= 1");
+  return hip_check(mhd::launch_mlp_normalize(mlp, X, n, (hipStream_t)stream), "mhd_mlp_normalize");
+}
+
+int mhd_mlp_forward(const float* mlp, const float* X, int64_t n, float* Y, void* stream) {
+  if (!mlp || !X || !Y || n < 1) return fail(MHD_EINVAL, "mhd_mlp_forward: need mlp, X, Y and n >= 1");
+  if (n > ((int64_t)1 << 31) - 256) return fail(MHD_EINVAL, "mhd_mlp_forward: n too large for one launch");
+  return hip_check(mhd::launch_mlp_forward(mlp, X, n, Y, (hipStream_t)stream), "mhd_mlp_forward");
+}
+
+size_t mhd_mlp_grad_workspace_size(int64_t n) {
+  if (n < 1) return 0;
+  return 1024 * sizeof(double) + (size_t)mhd::mlp_grad_blocks(n) * MHD_MLP_NPARAM * sizeof(float);
+}
+
+int mhd_mlp_grad(const float* mlp, const float* X, const float* T, int64_t n, float* grad, float* loss,
+                 void* workspace, size_t workspace_bytes, void* stream) {
+  if (!mlp || !X || !T || !grad || n < 1) return fail(MHD_EINVAL, "mhd_mlp_grad: need mlp, X, T, grad and n >= 1");
+  if (!workspace || workspace_bytes < mhd_mlp_grad_workspace_size(n))
+    return fail(MHD_EWORKSPACE, "mhd_mlp_grad: workspace of %zu bytes needed (got %zu)", mhd_mlp_grad_workspace_size(n),
+                workspace_bytes);
+  return hip_check(mhd::launch_mlp_grad(mlp, X, T, n, grad, loss, workspace, (hipStream_t)stream), "mhd_mlp_grad");
+}
+
+int mhd_mlp_adam(float* mlp, const float* grad, float* m, float* v, int step, float lr, float beta1, float beta2,
+                 float eps, void* stream) {
+  if (!mlp || !grad || !m || !v) return fail(MHD_EINVAL, "mhd_mlp_adam: NULL array");
+  if (step < 1 || !(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+    return fail(MHD_EINVAL, "mhd_mlp_adam: need step >= 1, lr > 0, 0 <= beta < 1, eps > 0");
+  return hip_check(mhd::launch_mlp_adam(mlp, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream),
+                   "mhd_mlp_adam");
 }
 
 size_t mhd_rhs_workspace_size(const mhd_patch_t* patch) {

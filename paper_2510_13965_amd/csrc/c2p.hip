@@ -13,6 +13,7 @@
 // the kernel is divergence bound; the learned-guess path in learned.hip
 // replaces most of the Brent iterations with three Newton steps.
 #include "c2p_dev.hpp"
+#include "prof.hpp"
 
 namespace mhd {
 
@@ -93,7 +94,7 @@ int launch_con2prim(const Geom& g, const mhd_eos_t& eos, double* U, double* P, u
                     int64_t* stats, hipStream_t s) {
   C2pArgs a{g, eos, U, P, flags, mu, stats};
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
-  hipLaunchKernelGGL(k_con2prim, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
+  MHD_LAUNCH(KID_CON2PRIM, k_con2prim, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 
@@ -101,7 +102,7 @@ int launch_prim2con(const Geom& g, const mhd_eos_t& eos, double* U, double* P, c
                     hipStream_t s) {
   P2cArgs a{g, eos, U, P, EM, eps_mode};
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
-  hipLaunchKernelGGL(k_prim2con, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
+  MHD_LAUNCH(KID_PRIM2CON, k_prim2con, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 

@@ -373,7 +373,7 @@ __device__ __forceinline__ void c2p_plain(const mhd_eos_t& e, const C2pPoint& pt
   const double mu = (f1 <= 0.0) ? mup : brent_root(f, 0.0, mup, f0, f1, it2, ok2);
   o.mup = mup;
   o.mu = mu;
-  o.iters = it1 + it2;
+  o.iters = it1 + it2 + 3;  // root-function evaluations, the three bracket ends included
   if (!(ok1 && ok2)) o.flags |= MHD_FLAG_NOT_CONVERGED;
   c2p_finish(e, pt, c, mu, o);
 }

@@ -19,6 +19,7 @@
 // x so every stencil row load is a coalesced 512-byte access and y/z
 // neighbours come from L1/L2.
 #include "dev_common.hpp"
+#include "prof.hpp"
 
 namespace mhd {
 
@@ -526,10 +527,10 @@ int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const d
   dim3 blk(64, 4, 1);
   const int nblk = nbx * nby * nbz;
   dim3 grd(8 * ((nblk + 7) / 8), 1, 1);
-  hipLaunchKernelGGL(k_ccz4_stencil, grd, blk, 0, s, a);
-  hipLaunchKernelGGL(k_ccz4_d2, grd, blk, 0, s, a, ws);
-  hipLaunchKernelGGL(k_ccz4_curv, grd, blk, 0, s, a, (const double*)ws);
-  hipLaunchKernelGGL(k_ccz4_gauge, grd, blk, 0, s, a, (const double*)ws);
+  MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil, grd, blk, 0, s, a);
+  MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2, grd, blk, 0, s, a, ws);
+  MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv, grd, blk, 0, s, a, (const double*)ws);
+  MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge, grd, blk, 0, s, a, (const double*)ws);
   return (int)hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 //                 plus the geometric sources with centred metric derivatives,
 //                 plus the wavefront max of the point speeds (CFL reduction).
 #include "dev_common.hpp"
+#include "prof.hpp"
 
 namespace mhd {
 
@@ -389,11 +390,11 @@ int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, con
   MhdPointArgs pa{g, par, eos, U, P, ws};
   dim3 blk(64, 4, 1);
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
-  hipLaunchKernelGGL(k_mhd_point, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), blk, 0, s, pa);
+  MHD_LAUNCH(KID_MHD_POINT, k_mhd_point, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), blk, 0, s, pa);
   const int nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4, nbz = g.nz;
   MhdUpdArgs ua{g, nbx, nby, nbz, strip, par, U, P, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed)};
   const int nblk = nbx * nby * nbz;
-  hipLaunchKernelGGL(k_mhd_update, dim3(8 * ((nblk + 7) / 8), 1, 1), blk, 0, s, ua);
+  MHD_LAUNCH(KID_MHD_UPDATE, k_mhd_update, dim3(8 * ((nblk + 7) / 8), 1, 1), blk, 0, s, ua);
   return (int)hipGetLastError();
 }
 

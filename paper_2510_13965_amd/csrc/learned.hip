@@ -1,0 +1,732 @@
+// Learned starting guess for the con2prim root solves, and its training.
+//
+// The recovery of App. D solves f_a(mu_+) = 0 on (0, 1/h0] and then
+// f(mu) = 0 on (0, mu_+] by bracketed iterations.  Here a small MLP
+// (8 -> 64 -> 64 -> 2, ReLU) maps 8 metric-invariant scalars of the state
+// (log D, log q, log r^2, log calB^2, (r.calB)^2/(r^2 calB^2), log(1+q),
+// log r^2/(1+q)^2, log calB^2/(1+q)) to logit(mu_+ h0) and logit(mu/mu_+);
+// Newton's method in FP64 polishes each guess for at most three iterations,
+// and a point is accepted only if the residual falls below 1e-12 (f_a
+// absolute, f relative to mu) with 0 < mu <= mu_+.  Every other point goes to
+// a queue that the bracketed solver then finishes, so the plain solver stays
+// the judge and the answer is the root either way.
+//
+// Network arithmetic: the two hidden layers run on the bf16 matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with inputs, weights and
+// hidden activations rounded to bf16 (nearest-even); biases, ReLU and the
+// 64 -> 2 output layer are FP32 on the vector ALU.
+//
+// Data layout on the matrix cores (one wavefront = 64 points, lane l owns
+// point l).  Each layer is computed transposed, H^T = W X^T, so that the
+// accumulator of a 32x32 tile holds, in lane l, the column m = l%32 (a point)
+// and rows 8(i/4) + 4(l/32) + i%4, i = 0..15 (hidden units).  The next layer's
+// B operand needs, in lane l, column m and 8 consecutive k; instead of moving
+// data between lanes, the hidden units are relabelled: B-operand index
+// kappa = 16 ks + 8 g + j (g = l/32) stands for hidden unit pi(kappa), the
+// unit the lane already holds in accumulator slot idx = 8 ks + j, and the
+// weight matrix is loaded with its columns permuted by pi.
+#include "c2p_dev.hpp"
+#include "prof.hpp"
+
+namespace mhd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// parameter block (float32): same offsets as the oracle's
+constexpr int kOW1 = 0, kOB1 = 512, kOW2 = 576, kOB2 = 4672, kOW3 = 4736, kOB3 = 4864;
+constexpr int kOMean = 4866, kOIstd = 4874, kNTrain = 4866;
+constexpr int kLd = 72;  // padded LDS row stride (bf16 elements) of 64-wide matrices
+
+// binary32 -> bfloat16, round to nearest even (finite inputs)
+__device__ __forceinline__ __bf16 to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
+}
+__device__ __forceinline__ float from_bf16(__bf16 b) {
+  return __uint_as_float(((uint32_t)__builtin_bit_cast(unsigned short, b)) << 16);
+}
+
+// hidden unit held in B-operand index kappa (see the header comment)
+__host__ __device__ constexpr int mlp_pi(int kappa) {
+  const int idx = 8 * (kappa >> 4) + (kappa & 7);  // accumulator slot 16 nt + i
+  const int g = (kappa >> 3) & 1;                   // lane half
+  return 32 * (idx >> 4) + 8 * ((idx & 15) >> 2) + 4 * g + (idx & 3);
+}
+// row (hidden unit) of accumulator slot i in a lane of half g, tile nt
+__device__ __forceinline__ constexpr int acc_row(int nt, int i, int g) { return 32 * nt + 8 * (i >> 2) + 4 * g + (i & 3); }
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// bf16 matrices are read 16 bytes at a time (ds_read_b128): 16-byte aligned rows
+struct MlpLds {
+  alignas(16) __bf16 w1[64 * 16];   // [n][k], k = 8..15 zero
+  alignas(16) __bf16 w2p[64 * kLd]; // [n2][kappa] = W2[n2][pi(kappa)]
+  float b1[64], b2[64], w3[128], b3[2], mean[8], istd[8];
+};
+
+__device__ void mlp_stage(const float* __restrict__ prm, MlpLds& s) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < 64 * 16; e += nt) {
+    const int n = e >> 4, k = e & 15;
+    s.w1[e] = to_bf16(k < 8 ? prm[kOW1 + n * 8 + k] : 0.0f);
+  }
+  for (int e = t; e < 64 * 64; e += nt) {
+    const int n = e >> 6, kap = e & 63;
+    s.w2p[n * kLd + kap] = to_bf16(prm[kOW2 + n * 64 + mlp_pi(kap)]);
+  }
+  for (int e = t; e < 64; e += nt) {
+    s.b1[e] = prm[kOB1 + e];
+    s.b2[e] = prm[kOB2 + e];
+  }
+  for (int e = t; e < 128; e += nt) s.w3[e] = prm[kOW3 + e];
+  for (int e = t; e < 8; e += nt) {
+    s.mean[e] = prm[kOMean + e];
+    s.istd[e] = prm[kOIstd + e];
+  }
+  if (t < 2) s.b3[t] = prm[kOB3 + t];
+}
+
+__device__ __forceinline__ bf16x8 lds8(const __bf16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+struct MlpFwd {
+  bf16x8 xb[2];      // layer-1 B operands, per point tile mt
+  f32x16 a1[2][2];   // layer-1 pre-activations (with bias) [nt][mt]
+  bf16x8 hb[2][4];   // layer-2 B operands [mt][ks]
+  f32x16 a2[2][2];   // layer-2 pre-activations (with bias) [nt][mt]
+};
+
+// standardized features of this lane's point -> network outputs of this lane's point
+__device__ __forceinline__ void mlp_forward(const MlpLds& s, const float z[8], MlpFwd& f, float y[2]) {
+#pragma clang fp contract(off)
+  const int l = lane_id(), g = l >> 5, c = l & 31;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const float other = __shfl(z[j], c + 32, 64);
+    f.xb[0][j] = to_bf16(g ? 0.0f : z[j]);
+    f.xb[1][j] = to_bf16(g ? 0.0f : other);
+  }
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    const bf16x8 aw = lds8(&s.w1[(32 * nt + c) * 16 + 8 * g]);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      const f32x16 zero = {};
+      f.a1[nt][mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, f.xb[mt], zero, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) f.a1[nt][mt][i] += s.b1[acc_row(nt, i, g)];
+    }
+  }
+#pragma unroll
+  for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float v = f.a1[(8 * ks + j) >> 4][mt][(8 * ks + j) & 15];
+        f.hb[mt][ks][j] = to_bf16(v > 0.0f ? v : 0.0f);
+      }
+#pragma unroll
+  for (int nt = 0; nt < 2; ++nt) {
+    f32x16 acc[2] = {{}, {}};
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const bf16x8 aw = lds8(&s.w2p[(32 * nt + c) * kLd + 16 * ks + 8 * g]);
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, f.hb[mt][ks], acc[mt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) f.a2[nt][mt][i] = acc[mt][i] + s.b2[acc_row(nt, i, g)];
+  }
+  float part[2][2];
+#pragma unroll
+  for (int o = 0; o < 2; ++o)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+      float sacc = 0.0f;
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const float h = f.a2[nt][mt][i];
+          sacc += s.w3[o * 64 + acc_row(nt, i, g)] * (h > 0.0f ? h : 0.0f);
+        }
+      part[o][mt] = sacc;
+    }
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    const float mine = g ? part[o][1] : part[o][0];
+    const float send = g ? part[o][0] : part[o][1];
+    y[o] = mine + __shfl_xor(send, 32, 64) + s.b3[o];
+  }
+}
+
+// --------------------------------------------------------------- features
+
+__device__ __forceinline__ void c2p_features(const C2pInv& c, double x[8]) {
+#pragma clang fp contract(off)
+  const double onep = 1.0 + c.q;
+  x[0] = log10(c.D);
+  x[1] = log10(fmax(c.q, 1e-30));
+  x[2] = log10(c.r2 + 1e-30);
+  x[3] = log10(c.B2 + 1e-30);
+  x[4] = c.rB * c.rB / (c.r2 * c.B2 + 1e-300);
+  x[5] = log10(onep);
+  x[6] = log10(c.r2 / (onep * onep) + 1e-30);
+  x[7] = log10(c.B2 / onep + 1e-30);
+}
+
+__device__ __forceinline__ void standardize(const MlpLds& s, const float x[8], float z[8]) {
+#pragma clang fp contract(off)
+#pragma unroll
+  for (int k = 0; k < 8; ++k) z[k] = (x[k] - s.mean[k]) * s.istd[k];
+}
+
+__device__ __forceinline__ double logit_clamped(double y) {
+  y = fmin(fmax(y, 1e-6), 1.0 - 1e-6);
+  return log(y / (1.0 - y));
+}
+
+struct FeatArgs {
+  Geom g;
+  mhd_eos_t eos;
+  const double* __restrict__ U;
+  const double* __restrict__ mu;
+  float* __restrict__ X;
+  float* __restrict__ T;
+  int Nx, Ny;
+  int64_t npts;
+};
+
+// features (and targets) at every padded point, rows in linear padded order;
+// points below the density threshold get NaN rows
+__global__ void __launch_bounds__(256) k_mlp_features(FeatArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.npts) return;
+  const int i = (int)(t % a.Nx), j = (int)((t / a.Nx) % a.Ny), k = (int)(t / ((int64_t)a.Nx * a.Ny));
+  const int64_t p = a.g.at(i, j, k);
+  C2pPoint pt;
+  load_point(a.U, a.g.sf, p, pt);
+  C2pInv c;
+  if (!c2p_setup(a.eos, pt, c)) {
+    const float nan = __builtin_nanf("");
+#pragma unroll
+    for (int q = 0; q < 8; ++q) a.X[t * 8 + q] = nan;
+    if (a.T) a.T[t * 2] = a.T[t * 2 + 1] = nan;
+    return;
+  }
+  double x[8];
+  c2p_features(c, x);
+#pragma unroll
+  for (int q = 0; q < 8; ++q) a.X[t * 8 + q] = (float)x[q];
+  if (a.T && a.mu) {
+    const double mup = a.mu[p], mu = a.mu[a.g.sf + p];
+    a.T[t * 2] = (float)logit_clamped(mup * a.eos.h0);
+    a.T[t * 2 + 1] = (float)logit_clamped(mu / mup);
+  }
+}
+
+// mean and inverse standard deviation of each feature over the non-NaN rows (one block)
+__global__ void __launch_bounds__(256) k_mlp_normalize(float* __restrict__ prm, const float* __restrict__ X, int64_t n) {
+  __shared__ double red[3][8][256];
+  const int t = threadIdx.x;
+  double s1[8] = {0}, s2[8] = {0}, cnt = 0.0;
+  for (int64_t r = t; r < n; r += 256) {
+    if (isnan(X[r * 8])) continue;
+    cnt += 1.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double v = X[r * 8 + q];
+      s1[q] += v;
+      s2[q] += v * v;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    red[0][q][t] = s1[q];
+    red[1][q][t] = s2[q];
+    red[2][q][t] = cnt;
+  }
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w)
+      for (int q = 0; q < 8; ++q) {
+        red[0][q][t] += red[0][q][t + w];
+        red[1][q][t] += red[1][q][t + w];
+        red[2][q][t] += red[2][q][t + w];
+      }
+    __syncthreads();
+  }
+  if (t < 8) {
+    const double N = red[2][t][0] > 0.0 ? red[2][t][0] : 1.0;
+    const double m = red[0][t][0] / N;
+    const double var = fmax(red[1][t][0] / N - m * m, 0.0);
+    prm[kOMean + t] = (float)m;
+    prm[kOIstd + t] = var > 1e-12 ? (float)(1.0 / sqrt(var)) : 1.0f;
+  }
+}
+
+// network outputs for n raw feature rows (NaN rows give NaN)
+__global__ void __launch_bounds__(256) k_mlp_forward(const float* __restrict__ prm, const float* __restrict__ X, int64_t n,
+                                                     float* __restrict__ Y) {
+  __shared__ MlpLds s;
+  mlp_stage(prm, s);
+  __syncthreads();
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // whole waves run the MFMA
+  const bool live = r < n && !isnan(X[(r < n ? r : 0) * 8]);
+  float x[8], z[8], y[2];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) x[q] = live ? X[r * 8 + q] : 0.0f;
+  standardize(s, x, z);
+  MlpFwd f;
+  mlp_forward(s, z, f, y);
+  if (r < n) {
+    Y[r * 2] = live ? y[0] : __builtin_nanf("");
+    Y[r * 2 + 1] = live ? y[1] : __builtin_nanf("");
+  }
+}
+
+// --------------------------------------------------------------- training
+
+struct MlpLdsTrain {
+  MlpLds s;
+  alignas(16) __bf16 w2tp[64 * kLd];  // [k][kappa] = W2[pi(kappa)][k]  (A operand of W2^T g2)
+  alignas(16) __bf16 G[64 * kLd];     // [hidden][sample] staging of bf16 back-propagated signals
+  alignas(16) __bf16 H[64 * kLd];     // [hidden][sample] staging of bf16 layer-1 activations
+  alignas(16) __bf16 XT[32 * kLd];    // [feature][sample] staging of bf16 inputs (rows 8..31 zero)
+  float acc[kNTrain];     // this block's gradient
+  double loss;
+};
+
+// half-wave (32-lane) butterfly sum
+__device__ __forceinline__ float half_sum(float v) {
+#pragma unroll
+  for (int off = 16; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Per-block gradient of L = 1/(2n) sum (y - t)^2 over the rows [0, n) the
+// block owns (chunks of 64 rows, grid-strided); written to part[block][.] so
+// that the reduction over blocks has a fixed order.  One wavefront per block.
+__global__ void __launch_bounds__(64) k_mlp_grad(const float* __restrict__ prm, const float* __restrict__ X,
+                                                 const float* __restrict__ T, int64_t n, float* __restrict__ part,
+                                                 double* __restrict__ loss_part) {
+#pragma clang fp contract(off)
+  __shared__ MlpLdsTrain L;
+  MlpLds& s = L.s;
+  mlp_stage(prm, s);
+  const int l = lane_id(), g = l >> 5, c = l & 31;
+  for (int e = l; e < 64 * 64; e += 64) {
+    const int k = e >> 6, kap = e & 63;
+    L.w2tp[k * kLd + kap] = to_bf16(prm[kOW2 + mlp_pi(kap) * 64 + k]);
+  }
+  for (int e = l; e < kNTrain; e += 64) L.acc[e] = 0.0f;
+  for (int e = l; e < 32 * kLd; e += 64) L.XT[e] = to_bf16(0.0f);
+  double lsum = 0.0;
+  __syncthreads();
+  const float inv_n = 1.0f / (float)n;
+  for (int64_t chunk = blockIdx.x; chunk * 64 < n; chunk += gridDim.x) {
+    const int64_t r = chunk * 64 + l;
+    const bool live = r < n && !isnan(X[(r < n ? r : 0) * 8]);
+    float x[8], z[8], y[2];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = live ? X[r * 8 + q] : 0.0f;
+    standardize(s, x, z);
+    MlpFwd f;
+    mlp_forward(s, z, f, y);
+    float dy[2];
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+      const float res = live ? y[o] - T[r * 2 + o] : 0.0f;
+      lsum += 0.5 * (double)res * (double)res;
+      dy[o] = res * inv_n;
+    }
+    // dy of the two points of this lane's column (tiles mt = 0, 1)
+    float dym[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) dym[mt][o] = __shfl(dy[o], 32 * mt + c, 64);
+    // output layer: dW3, db3, and g2 = (W3^T dy) relu'(a2)
+    f32x16 g2[2][2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int n2 = acc_row(nt, i, g);
+        float w0 = 0.0f, w1 = 0.0f, gb = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          const float a = f.a2[nt][mt][i];
+          const float h = a > 0.0f ? a : 0.0f;
+          w0 += dym[mt][0] * h;
+          w1 += dym[mt][1] * h;
+          const float gg = dym[mt][0] * s.w3[n2] + dym[mt][1] * s.w3[64 + n2];
+          g2[nt][mt][i] = a > 0.0f ? gg : 0.0f;
+          gb += g2[nt][mt][i];
+        }
+        w0 = half_sum(w0);
+        w1 = half_sum(w1);
+        gb = half_sum(gb);
+        if (c == 0) {
+          L.acc[kOW3 + n2] += w0;
+          L.acc[kOW3 + 64 + n2] += w1;
+          L.acc[kOB2 + n2] += gb;
+        }
+      }
+    {
+      float d0 = dy[0], d1 = dy[1];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        d0 += __shfl_xor(d0, off, 64);
+        d1 += __shfl_xor(d1, off, 64);
+      }
+      if (l == 0) {
+        L.acc[kOB3] += d0;
+        L.acc[kOB3 + 1] += d1;
+      }
+    }
+    // stage bf16 g2 and layer-1 activations as [hidden][sample]
+    bf16x8 g2b[2][4];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+      for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) L.G[acc_row(nt, i, g) * kLd + 32 * mt + c] = to_bf16(g2[nt][mt][i]);
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int idx = 8 * ks + j;
+          g2b[mt][ks][j] = to_bf16(g2[idx >> 4][mt][idx & 15]);
+          L.H[mlp_pi(16 * ks + 8 * g + j) * kLd + 32 * mt + c] = f.hb[mt][ks][j];
+        }
+    }
+    if (g == 0)
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) L.XT[q * kLd + 32 * mt + c] = f.xb[mt][q];
+    __syncthreads();
+    // dW2[n2][k] = sum_m g2b[n2][m] h1b[k][m]
+#pragma unroll
+    for (int na = 0; na < 2; ++na)
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) {
+        f32x16 acc = {};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+          const bf16x8 a = lds8(&L.G[(32 * na + c) * kLd + 16 * ks + 8 * g]);
+          const bf16x8 b = lds8(&L.H[(32 * nb + c) * kLd + 16 * ks + 8 * g]);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) L.acc[kOW2 + acc_row(na, i, g) * 64 + 32 * nb + c] += acc[i];
+      }
+    // g1[k][m] = (sum_n2 W2[n2][k] g2b[n2][m]) relu'(a1)
+    f32x16 g1[2][2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      f32x16 acc[2] = {{}, {}};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x8 a = lds8(&L.w2tp[(32 * nt + c) * kLd + 16 * ks + 8 * g]);
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, g2b[mt][ks], acc[mt], 0, 0, 0);
+      }
+#pragma unroll
+      for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) g1[nt][mt][i] = f.a1[nt][mt][i] > 0.0f ? acc[mt][i] : 0.0f;
+    }
+    __syncthreads();  // every lane is done reading L.G
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        float gb = 0.0f;
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+          gb += g1[nt][mt][i];
+          L.G[acc_row(nt, i, g) * kLd + 32 * mt + c] = to_bf16(g1[nt][mt][i]);
+        }
+        gb = half_sum(gb);
+        if (c == 0) L.acc[kOB1 + acc_row(nt, i, g)] += gb;
+      }
+    __syncthreads();
+    // dW1[k][q] = sum_m g1b[k][m] xb[q][m]
+#pragma unroll
+    for (int na = 0; na < 2; ++na) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x8 a = lds8(&L.G[(32 * na + c) * kLd + 16 * ks + 8 * g]);
+        const bf16x8 b = lds8(&L.XT[c * kLd + 16 * ks + 8 * g]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      }
+      if (c < 8)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) L.acc[kOW1 + acc_row(na, i, g) * 8 + c] += acc[i];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+  for (int e = l; e < kNTrain; e += 64) part[(int64_t)blockIdx.x * kNTrain + e] = L.acc[e];
+  if (l == 0) loss_part[blockIdx.x] = lsum / (double)n;
+}
+
+// grad[i] = sum over blocks (fixed order); loss likewise
+__global__ void __launch_bounds__(256) k_mlp_grad_reduce(const float* __restrict__ part, const double* __restrict__ loss_part,
+                                                         int nblk, float* __restrict__ grad, float* __restrict__ loss) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < kNTrain) {
+    float s = 0.0f;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * kNTrain + e];
+    grad[e] = s;
+  }
+  if (e == 0 && loss) {
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += loss_part[b];
+    *loss = (float)s;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_mlp_adam(float* __restrict__ prm, const float* __restrict__ grad,
+                                                  float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                                  float b2, float eps, float c1, float c2) {
+#pragma clang fp contract(off)
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= kNTrain) return;
+  const float gr = grad[e];
+  const float mn = b1 * m[e] + (1.0f - b1) * gr;
+  const float vn = b2 * v[e] + (1.0f - b2) * gr * gr;
+  m[e] = mn;
+  v[e] = vn;
+  prm[e] -= lr * (mn / c1) / (sqrtf(vn / c2) + eps);
+}
+
+// --------------------------------------------------------------- con2prim with the learned guess
+
+struct LearnedArgs {
+  Geom g;
+  mhd_eos_t eos;
+  const float* __restrict__ prm;
+  double* __restrict__ U;
+  double* __restrict__ P;
+  uint8_t* __restrict__ flags;
+  double* __restrict__ mu;
+  int64_t* __restrict__ stats;
+  uint32_t* __restrict__ qcount;
+  uint32_t* __restrict__ queue;
+  int Nx, Ny;
+  int64_t npts;
+};
+
+constexpr int kNewtonIt = 3;
+
+// Newton on F from x0 with at most kNewtonIt updates; accepted when
+// |F(x)| <= tol(x) (then one more correction is applied) and lo < x <= hi.
+template <class Fn>
+__device__ __forceinline__ bool newton_polish(const Fn& F, double x, double hi, bool rel, double& out, int& nev) {
+#pragma clang fp contract(off)
+  for (int it = 0; it <= kNewtonIt; ++it) {
+    const Dual r = F(Dual{x, 1.0});
+    ++nev;
+    const double tol = rel ? 1e-12 * x : 1e-12;
+    if (fabs(r.v) <= tol) {
+      if (r.d != 0.0) x = x - r.v / r.d;
+      out = fmin(x, hi);
+      return out > 0.0;
+    }
+    if (it == kNewtonIt || !(r.d != 0.0)) return false;
+    x = x - r.v / r.d;
+    if (!(x > 0.0 && x <= hi)) return false;
+  }
+  return false;
+}
+
+struct FaDual {
+  const C2pInv& c;
+  __device__ Dual operator()(Dual mu) const { return fa_t<Dual>(c, mu); }
+};
+struct FDual {
+  const mhd_eos_t& e;
+  const C2pInv& c;
+  __device__ Dual operator()(Dual mu) const { return f_t<Dual>(e, c, mu); }
+};
+
+__device__ __forceinline__ double sigmoid(double y) { return 1.0 / (1.0 + exp(-y)); }
+
+__global__ void __launch_bounds__(256) k_c2p_learned(LearnedArgs a) {
+  __shared__ MlpLds s;
+  mlp_stage(a.prm, s);
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool inside = t < a.npts;
+  int64_t p = 0;
+  C2pPoint pt;
+  C2pInv c;
+  bool solve = false;
+  if (inside) {
+    const int i = (int)(t % a.Nx), j = (int)((t / a.Nx) % a.Ny), k = (int)(t / ((int64_t)a.Nx * a.Ny));
+    p = a.g.at(i, j, k);
+    load_point(a.U, a.g.sf, p, pt);
+    solve = c2p_setup(a.eos, pt, c);
+  }
+  // network guess (whole wave, dead lanes with zero inputs)
+  float z[8] = {0, 0, 0, 0, 0, 0, 0, 0}, y[2];
+  if (solve) {
+    double x[8];
+    c2p_features(c, x);
+    float xf[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) xf[q] = (float)x[q];
+    standardize(s, xf, z);
+  }
+  {
+    MlpFwd f;
+    mlp_forward(s, z, f, y);
+  }
+  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
+  bool fallback = false;
+  if (inside) {
+    C2pOut o;
+    o.flags = 0;
+    o.iters = 0;
+    o.mup = o.mu = 0.0;
+    if (!solve) {
+      atmosphere_prims(a.eos, o.prim);
+      o.flags = MHD_FLAG_ATMO;
+      double Wn;
+      const double zv[3] = {0.0, 0.0, 0.0};
+      prim_to_cons(pt.gd, o.prim[0], o.prim[1], o.prim[2], zv, o.prim[7], pt.B, o.cons, Wn);
+    } else {
+      int nev = 0;
+      const double hi = 1.0 / c.h0;
+      const double fhi = fa_t<double>(c, hi);
+      double mup = hi;
+      bool ok = true;
+      if (fhi > 0.0) ok = newton_polish(FaDual{c}, sigmoid((double)y[0]) * hi, hi, false, mup, nev);
+      double mu = mup;
+      if (ok) {
+        const FFn fp{a.eos, c};
+        const double f1 = fp(mup);
+        ++nev;
+        if (f1 > 0.0) ok = newton_polish(FDual{a.eos, c}, sigmoid((double)y[1]) * mup, mup, true, mu, nev);
+      }
+      nit = nev + 1;  // root-function evaluations, f_a(1/h0) included
+      if (ok) {
+        o.mup = mup;
+        o.mu = mu;
+        c2p_finish(a.eos, pt, c, mu, o);
+      } else {
+        fallback = true;
+      }
+    }
+    if (!fallback) {
+      store_point(a.U, a.P, a.flags, a.mu, a.g.sf, p, pt, o);
+      nfatal = (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
+      ncorr = (o.flags & C2P_CORRECTED) ? 1 : 0;
+    }
+  }
+  // wave-aggregated append of the rejected points to the fallback queue
+  const uint64_t mask = __ballot(fallback);
+  if (mask) {
+    const int l = lane_id();
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    uint32_t base = 0;
+    if (l == leader) base = atomicAdd(a.qcount, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    if (fallback) a.queue[base + __popcll(mask & ((1ull << l) - 1ull))] = (uint32_t)t;
+  }
+  nfb = fallback ? 1 : 0;
+  if (a.stats) wave_add_stats(a.stats, nfatal, ncorr, nfb, nit);
+}
+
+// the bracketed solver on the queued points (grid-strided over the queue)
+__global__ void __launch_bounds__(256) k_c2p_fallback(LearnedArgs a) {
+  const uint32_t nq = *a.qcount;
+  int64_t nfatal = 0, ncorr = 0, nit = 0;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    const int64_t t = a.queue[q];
+    const int i = (int)(t % a.Nx), j = (int)((t / a.Nx) % a.Ny), k = (int)(t / ((int64_t)a.Nx * a.Ny));
+    const int64_t p = a.g.at(i, j, k);
+    C2pPoint pt;
+    load_point(a.U, a.g.sf, p, pt);
+    C2pOut o;
+    c2p_plain(a.eos, pt, o);
+    o.flags |= MHD_FLAG_FALLBACK;
+    store_point(a.U, a.P, a.flags, a.mu, a.g.sf, p, pt, o);
+    nfatal += (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
+    ncorr += (o.flags & C2P_CORRECTED) ? 1 : 0;
+    nit += o.iters;
+  }
+  if (a.stats) wave_add_stats(a.stats, nfatal, ncorr, 0, nit);
+}
+
+__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+
+// ------------------------------------------------------------------ launchers
+
+int launch_mlp_features(const Geom& g, const mhd_eos_t& eos, const double* U, const double* mu, float* X, float* T,
+                        hipStream_t s) {
+  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
+  FeatArgs a{g, eos, U, mu, X, T, Nx, Ny, (int64_t)Nx * Ny * Nz};
+  MHD_LAUNCH(KID_MLP_FEATURES, k_mlp_features, dim3((unsigned)((a.npts + 255) / 256)), dim3(256), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+int launch_mlp_normalize(float* prm, const float* X, int64_t n, hipStream_t s) {
+  MHD_LAUNCH(KID_MLP_NORMALIZE, k_mlp_normalize, dim3(1), dim3(256), 0, s, prm, X, n);
+  return (int)hipGetLastError();
+}
+
+int launch_mlp_forward(const float* prm, const float* X, int64_t n, float* Y, hipStream_t s) {
+  MHD_LAUNCH(KID_MLP_FORWARD, k_mlp_forward, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, prm, X, n, Y);
+  return (int)hipGetLastError();
+}
+
+int mlp_grad_blocks(int64_t n) {
+  const int64_t chunks = (n + 63) / 64;
+  return (int)(chunks < 1024 ? chunks : 1024);
+}
+
+int launch_mlp_grad(const float* prm, const float* X, const float* T, int64_t n, float* grad, float* loss, void* ws,
+                    hipStream_t s) {
+  const int nblk = mlp_grad_blocks(n);
+  double* lpart = reinterpret_cast<double*>(ws);
+  float* part = reinterpret_cast<float*>(lpart + 1024);
+  MHD_LAUNCH(KID_MLP_GRAD, k_mlp_grad, dim3(nblk), dim3(64), 0, s, prm, X, T, n, part, lpart);
+  MHD_LAUNCH(KID_MLP_GRAD_REDUCE, k_mlp_grad_reduce, dim3((kNTrain + 255) / 256), dim3(256), 0, s, part, lpart, nblk, grad,
+             loss);
+  return (int)hipGetLastError();
+}
+
+int launch_mlp_adam(float* prm, const float* grad, float* m, float* v, int step, float lr, float b1, float b2,
+                    float eps, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  MHD_LAUNCH(KID_MLP_ADAM, k_mlp_adam, dim3((kNTrain + 255) / 256), dim3(256), 0, s, prm, grad, m, v, lr, b1, b2, eps,
+             c1, c2);
+  return (int)hipGetLastError();
+}
+
+int launch_con2prim_learned(const Geom& g, const mhd_eos_t& eos, const float* prm, double* U, double* P,
+                            uint8_t* flags, double* mu, int64_t* stats, void* ws, hipStream_t s) {
+  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
+  uint32_t* qcount = reinterpret_cast<uint32_t*>(ws);
+  uint32_t* queue = qcount + 64;  // 256-byte offset
+  LearnedArgs a{g, eos, prm, U, P, flags, mu, stats, qcount, queue, Nx, Ny, (int64_t)Nx * Ny * Nz};
+  MHD_LAUNCH(KID_ZERO, k_zero_u32, dim3(1), dim3(1), 0, s, qcount);
+  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_learned, dim3((unsigned)((a.npts + 255) / 256)), dim3(256), 0, s, a);
+  const int64_t fb_blocks = (a.npts + 255) / 256;
+  MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback, dim3((unsigned)(fb_blocks < 2048 ? fb_blocks : 2048)), dim3(256), 0, s,
+             a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace mhd

@@ -5,6 +5,7 @@
 // so every access is a coalesced 512-byte transaction.  Per element it moves
 // 3 reads + 2 writes (stages 0-2) or 3 reads + 1 write (stage 3) of 8 bytes.
 #include "dev_common.hpp"
+#include "prof.hpp"
 
 namespace mhd {
 
@@ -86,7 +87,7 @@ __global__ void __launch_bounds__(256) k_zero_interior(ZeroArgs a) {
 int launch_zero_interior(const Geom& g, int f0, int nfields, double* A, hipStream_t s) {
   ZeroArgs a{g, f0, A};
   dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * nfields);
-  hipLaunchKernelGGL(k_zero_interior, grd, dim3(64, 4, 1), 0, s, a);
+  MHD_LAUNCH(KID_ZERO, k_zero_interior, grd, dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 
@@ -94,7 +95,7 @@ int launch_rk4_stage(const Geom& g, int nfields, int stage, double dt, const dou
                      double* Unext, hipStream_t s) {
   RkArgs a{g, stage, dt, Un, k, acc, Unext};
   dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * nfields);
-  hipLaunchKernelGGL(k_rk4_stage, grd, dim3(64, 4, 1), 0, s, a);
+  MHD_LAUNCH(KID_RK4_STAGE, k_rk4_stage, grd, dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 
@@ -102,7 +103,7 @@ int launch_ghosts_periodic(const Geom& g, double* U, int nfields, hipStream_t s)
   GhostArgs a{g, U};
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
   dim3 grd((Nx + 63) / 64, (Ny + 3) / 4, Nz * nfields);
-  hipLaunchKernelGGL(k_ghosts_periodic, grd, dim3(64, 4, 1), 0, s, a);
+  MHD_LAUNCH(KID_GHOSTS, k_ghosts_periodic, grd, dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 

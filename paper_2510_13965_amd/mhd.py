@@ -46,6 +46,10 @@ class Tuning(C.Structure):
     _fields_ = [("strip", C.c_int32), ("reserved", C.c_int32 * 7)]
 
 
+class KernelTime(C.Structure):
+    _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double)]
+
+
 _vp = C.c_void_p
 _LIB = None
 
@@ -63,6 +67,17 @@ SIGNATURES = {
     "mhd_fill_ghosts_periodic": (C.c_int, [C.POINTER(Patch), _vp, C.c_int, _vp]),
     "mhd_set_tuning": (C.c_int, [C.POINTER(Tuning)]),
     "mhd_get_tuning": (C.c_int, [C.POINTER(Tuning)]),
+    "mhd_con2prim_learned_workspace_size": (C.c_size_t, [C.POINTER(Patch)]),
+    "mhd_con2prim_learned": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
+                                       C.c_size_t, _vp]),
+    "mhd_mlp_features": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp]),
+    "mhd_mlp_normalize": (C.c_int, [_vp, _vp, C.c_int64, _vp]),
+    "mhd_mlp_forward": (C.c_int, [_vp, _vp, C.c_int64, _vp, _vp]),
+    "mhd_mlp_grad_workspace_size": (C.c_size_t, [C.c_int64]),
+    "mhd_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]),
+    "mhd_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "mhd_profile_start": (C.c_int, []),
+    "mhd_profile_stop": (C.c_int, [C.POINTER(KernelTime), C.c_int, C.POINTER(C.c_int)]),
 }
 
 
@@ -191,6 +206,49 @@ def fill_ghosts_periodic(patch, U, nfields, stream=None):
     _check(lib().mhd_fill_ghosts_periodic(C.byref(patch), _ptr(U), nfields, _stream(stream)))
 
 
+MLP_NPARAM, MLP_NBLOCK = 4866, 4882
+
+
+def con2prim_learned_workspace_size(patch):
+    return int(lib().mhd_con2prim_learned_workspace_size(C.byref(patch)))
+
+
+def con2prim_learned(patch, eos, mlp, U, P, workspace, flags=None, mu=None, stats=None, stream=None):
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().mhd_con2prim_learned(C.byref(patch), C.byref(eos), _ptr(mlp), _ptr(U), _ptr(P), _ptr(flags), _ptr(mu),
+                                      _ptr(stats), _ptr(workspace), nbytes, _stream(stream)))
+
+
+def mlp_features(patch, eos, U, X, mu=None, T=None, stream=None):
+    _check(lib().mhd_mlp_features(C.byref(patch), C.byref(eos), _ptr(U), _ptr(mu), _ptr(X), _ptr(T), _stream(stream)))
+
+
+def mlp_normalize(mlp, X, n=None, stream=None):
+    n = X.shape[0] if n is None else n
+    _check(lib().mhd_mlp_normalize(_ptr(mlp), _ptr(X), int(n), _stream(stream)))
+
+
+def mlp_forward(mlp, X, Y, n=None, stream=None):
+    n = X.shape[0] if n is None else n
+    _check(lib().mhd_mlp_forward(_ptr(mlp), _ptr(X), int(n), _ptr(Y), _stream(stream)))
+
+
+def mlp_grad_workspace_size(n):
+    return int(lib().mhd_mlp_grad_workspace_size(int(n)))
+
+
+def mlp_grad(mlp, X, T, grad, workspace, loss=None, n=None, stream=None):
+    n = X.shape[0] if n is None else n
+    nbytes = workspace.numel() * workspace.element_size()
+    _check(lib().mhd_mlp_grad(_ptr(mlp), _ptr(X), _ptr(T), int(n), _ptr(grad), _ptr(loss), _ptr(workspace), nbytes,
+                              _stream(stream)))
+
+
+def mlp_adam(mlp, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().mhd_mlp_adam(_ptr(mlp), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1), float(beta2),
+                              float(eps), _stream(stream)))
+
+
 def set_tuning(strip):
     t = Tuning()
     t.strip = int(strip)
@@ -201,6 +259,18 @@ def get_tuning():
     t = Tuning()
     _check(lib().mhd_get_tuning(C.byref(t)))
     return {"strip": t.strip}
+
+
+def profile_start():
+    _check(lib().mhd_profile_start())
+
+
+def profile_stop():
+    """{kernel name: (launches, total ms)} since profile_start()."""
+    out = (KernelTime * 32)()
+    n = C.c_int(0)
+    _check(lib().mhd_profile_stop(out, 32, C.byref(n)))
+    return {out[i].name.decode(): (int(out[i].launches), float(out[i].total_ms)) for i in range(min(n.value, 32))}
 
 
 def workspace_for(patch, device="cuda"):

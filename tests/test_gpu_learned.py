@@ -1,0 +1,253 @@
+"""GPU parity of the learned con2prim starting guess and its training kernels.
+
+The network is checked against the oracle's FP64 network with the same bf16
+roundings; agreement is to the arithmetic the two sides do differently (FP32
+accumulation on the matrix cores vs exact sums), which can flip a bf16
+rounding of a hidden activation now and then.  The con2prim answer with the
+learned guess is checked against the plain bracketed solver, which stays the
+judge: mu and mu_+ to 1e-12 relative, flags equal apart from the fallback bit
+(and the eps-floor decision of the plain test), primitives to 1e-12 on
+well-conditioned cells, and a backward error of 1e-12 on every cell.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2510_13965_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2510_13965_amd import mhd
+
+    mhd.lib()
+    return torch.device("cuda")
+
+
+def rand_params(seed, scale=0.3):
+    from oracle import orc
+
+    r = np.random.default_rng(seed)
+    p = np.zeros(orc.MLP_NBLOCK, dtype=np.float32)
+    p[:orc.MLP_NPARAM] = r.normal(0.0, scale, orc.MLP_NPARAM)
+    p[4866:4874] = r.normal(0.0, 1.0, 8)
+    p[4874:4882] = r.uniform(0.5, 2.0, 8)
+    return p
+
+
+def rand_rows(seed, n, nan_every=17):
+    r = np.random.default_rng(seed)
+    X = r.normal(0.0, 2.0, (n, 8)).astype(np.float32)
+    X[::nan_every] = np.nan
+    T = r.normal(0.0, 1.0, (n, 2)).astype(np.float32)
+    return X, T
+
+
+def test_mlp_forward_parity(orc, dev):
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    say("case mlp forward n=4133")
+    p = rand_params(1)
+    X, _ = rand_rows(2, 4133)
+    Y = torch.empty((X.shape[0], 2), dtype=torch.float32, device=dev)
+    mhd.mlp_forward(torch.as_tensor(p).to(dev), torch.as_tensor(X).to(dev), Y)
+    Yg = Y.cpu().numpy().astype(np.float64)
+    Yo = orc.mlp_forward(p.astype(np.float64), X, emulate=1)
+    nan = np.isnan(X[:, 0])
+    assert np.all(np.isnan(Yg[nan]))
+    d = np.abs(Yg[~nan] - Yo[~nan]) / (1.0 + np.abs(Yo[~nan]))
+    say("forward |dy|/(1+|y|): median %.2e  99%% %.2e  max %.2e" % (np.median(d), np.quantile(d, 0.99), d.max()))
+    assert np.median(d) <= 1e-5
+    assert d.max() <= 2e-2
+
+
+def test_mlp_grad_parity_and_determinism(orc, dev):
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    say("case mlp grad n=1000")
+    p = rand_params(3)
+    X, T = rand_rows(4, 1000)
+    pd, Xd, Td = (torch.as_tensor(a).to(dev) for a in (p, X, T))
+    g1 = torch.empty(mhd.MLP_NPARAM, dtype=torch.float32, device=dev)
+    g2 = torch.empty_like(g1)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    ws = torch.empty((mhd.mlp_grad_workspace_size(1000) + 3) // 4, dtype=torch.float32, device=dev)
+    mhd.mlp_grad(pd, Xd, Td, g1, ws, loss)
+    mhd.mlp_grad(pd, Xd, Td, g2, ws)
+    torch.cuda.synchronize()
+    assert torch.equal(g1, g2)
+    gg = g1.cpu().numpy().astype(np.float64)
+    lo, go = orc.mlp_grad(p.astype(np.float64), X, T, emulate=1)
+    assert float(loss.item()) == pytest.approx(lo, rel=1e-5)
+    for name, a, b in (("W1", 0, 512), ("b1", 512, 576), ("W2", 576, 4672), ("b2", 4672, 4736),
+                       ("W3", 4736, 4864), ("b3", 4864, 4866)):
+        rel = np.linalg.norm(gg[a:b] - go[a:b]) / np.linalg.norm(go[a:b])
+        say("grad %s rel %.2e" % (name, rel))
+        assert rel <= 2e-3, name
+
+
+def test_mlp_adam_and_normalize(orc, dev):
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    say("case mlp adam/normalize")
+    r = np.random.default_rng(5)
+    p0 = rand_params(6)
+    gr = r.normal(size=mhd.MLP_NPARAM).astype(np.float32)
+    pd = torch.as_tensor(p0).to(dev)
+    m = torch.zeros(mhd.MLP_NPARAM, dtype=torch.float32, device=dev)
+    v = torch.zeros_like(m)
+    gd = torch.as_tensor(gr).to(dev)
+    po = p0.astype(np.float64)
+    mo = np.zeros(mhd.MLP_NPARAM)
+    vo = np.zeros(mhd.MLP_NPARAM)
+    for step in (1, 2, 3):
+        mhd.mlp_adam(pd, gd, m, v, step, 1e-3)
+        orc.mlp_adam(po, gr.astype(np.float64), mo, vo, step, 1e-3)
+    pg = pd.cpu().numpy().astype(np.float64)
+    assert np.abs(pg[:4866] - po[:4866]).max() <= 1e-6 * max(1.0, np.abs(po[:4866]).max())
+    assert np.array_equal(pg[4866:], po[4866:])
+    X, _ = rand_rows(7, 5000)
+    mhd.mlp_normalize(pd, torch.as_tensor(X).to(dev))
+    pg = pd.cpu().numpy().astype(np.float64)
+    ok = ~np.isnan(X[:, 0])
+    Xv = X[ok].astype(np.float64)
+    assert np.allclose(pg[4866:4874], Xv.mean(0), rtol=1e-6, atol=1e-6)
+    assert np.allclose(pg[4874:4882], 1.0 / Xv.std(0), rtol=1e-5)
+
+
+def test_mlp_features_parity(orc, dev):
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    say("case mlp features 2^12")
+    ip, U, P, EM = I.c4_cells(ncell=1 << 12, seed=77)
+    g = orc.make_grid(ip.n, ip.dx, ng=0)
+    e = orc.make_eos(I.EOS_PWP3)
+    orc.prim2con(g, e, U, P, EM, 1)
+    Uo = U.copy()
+    Po = np.zeros_like(P)
+    mu = np.zeros((2,) + ip.shape)
+    orc.con2prim(g, e, Uo, Po, None, mu)
+    Xo, To = orc.c2p_features(g, e, U, mu)
+    X = torch.empty((ip.npts, 8), dtype=torch.float32, device=dev)
+    T = torch.empty((ip.npts, 2), dtype=torch.float32, device=dev)
+    mhd.mlp_features(mhd.patch_of(ip), mhd.make_eos(I.EOS_PWP3), torch.as_tensor(U).to(dev), X,
+                     torch.as_tensor(mu).to(dev), T)
+    Xg, Tg = X.cpu().numpy(), T.cpu().numpy()
+    atm = np.isnan(Xo[:, 0])   # atmosphere rows are NaN on both sides
+    assert np.array_equal(np.isnan(Xg), np.isnan(Xo)) and np.array_equal(np.isnan(Tg), np.isnan(To))
+    ok = ~atm
+    assert ok.sum() > 3000
+    assert np.allclose(Xg[ok], Xo[ok], rtol=4e-7, atol=4e-7)
+    assert np.allclose(Tg[ok], To[ok], rtol=4e-7, atol=4e-6)
+
+
+# ---------------------------------------------------------------- con2prim with the learned guess
+
+def c2p_both(ip, U, prm, eos_cfg):
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    pt = mhd.patch_of(ip)
+    eos = mhd.make_eos(eos_cfg)
+    out = {}
+    for mode in ("plain", "learned"):
+        Ud = torch.as_tensor(U).cuda()
+        P = torch.zeros((I.NP,) + ip.shape, dtype=torch.float64, device="cuda")
+        fl = torch.zeros(ip.shape, dtype=torch.uint8, device="cuda")
+        mu = torch.zeros((2,) + ip.shape, dtype=torch.float64, device="cuda")
+        st = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device="cuda")
+        if mode == "plain":
+            mhd.con2prim(pt, eos, Ud, P, fl, mu, st)
+        else:
+            ws = torch.empty((mhd.con2prim_learned_workspace_size(pt) + 7) // 8, dtype=torch.float64, device="cuda")
+            mhd.con2prim_learned(pt, eos, prm, Ud, P, ws, fl, mu, st)
+        torch.cuda.synchronize()
+        out[mode] = tuple(a.cpu().numpy() for a in (Ud, P, fl, mu, st))
+    return out
+
+
+def check_learned_against_plain(orc, ip, U, P, EM, out, eos_cfg):
+    Up, Pp, flp, mup, stp = out["plain"]
+    Ul, Pl, fll, mul, stl = out["learned"]
+    FB = np.uint8(32)
+    fb = (fll & FB) != 0
+    # fallback points were solved by the plain solver: bitwise identical
+    assert np.array_equal(Pl[:, fb], Pp[:, fb])
+    assert np.array_equal(mul[:, fb], mup[:, fb])
+    flg = fll & ~FB
+    same = flg == flp
+    diff = ~same
+    assert diff.mean() < 1e-3
+    assert np.all(((flg ^ flp)[diff] & ~np.uint8(2)) == 0)
+    solved = same & (mup[1] > 0)
+    for c in range(2):
+        rel = np.abs(mul[c][solved] - mup[c][solved]) / mup[c][solved]
+        assert rel.max() <= 1e-12, (c, rel.max())
+    wc = same & (flp == 0) & (P[I.WLOR] < 2.0) & ((EM[0:3] ** 2).sum(0) < 0.1 * P[I.RHO])
+    for c in range(I.NP):
+        rel = np.abs(Pl[c][wc] - Pp[c][wc]) / np.maximum(np.abs(Pp[c][wc]), 1e-300)
+        assert rel.max() <= 1e-12, (c, rel.max())
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    e = orc.make_eos(eos_cfg)
+    ok = flg == 0
+    U2 = U.copy()
+    P2 = Pl.copy()
+    orc.prim2con(g, e, U2, P2, EM, 0)
+    C0, C2 = U[22:28][:, ok], U2[22:28][:, ok]
+    scale = np.abs(C0[0]) + np.abs(C0[2]) + np.sqrt((C0[3:6] ** 2).sum(0))
+    assert (np.abs(C2 - C0).max(0) / scale).max() <= 1e-12
+    assert stl[2] == fb.sum()
+    return fb.mean(), stp[3], stl[3]
+
+
+def test_learned_c2p_untrained_is_plain(orc, dev):
+    """With random weights most guesses are rejected; the answer is still the
+    plain solver's (bitwise on the fallback points)."""
+    import torch
+
+    say("case learned c2p, random weights, 2^14")
+    ip, U, P, EM = I.c4_cells(ncell=1 << 14, seed=91)
+    g = orc.make_grid(ip.n, ip.dx, ng=0)
+    orc.prim2con(g, orc.make_eos(I.EOS_PWP3), U, P, EM, 1)
+    prm = torch.as_tensor(rand_params(8, scale=0.05)).cuda()
+    out = c2p_both(ip, U, prm, I.EOS_PWP3)
+    rate, itp, itl = check_learned_against_plain(orc, ip, U, P, EM, out, I.EOS_PWP3)
+    say("fallback rate with random weights %.3f" % rate)
+
+
+def test_learned_c2p_trained_parity_and_gain(orc, dev):
+    """Train on 2^16 states (own seed), test on 2^16 fresh states: the answer
+    matches the plain solver, most points are accepted after Newton, and the
+    root-function evaluations per point drop below the plain solver's."""
+    from paper_2510_13965_amd import learned
+
+    say("case learned c2p, trained 2^16 -> 2^16")
+    X, T = learned.training_set(1 << 16, seed=I.SEED0 + 40)
+    prm, hist = learned.train(X, T, seed=3, epochs=40, batch=1024)
+    say("training loss per epoch: first %.3e last %.3e" % (hist[0], hist[-1]))
+    assert hist[-1] < 0.2 * hist[0]
+    ip, U, P, EM = I.c4_cells(ncell=1 << 16, seed=I.SEED0 + 41)
+    g = orc.make_grid(ip.n, ip.dx, ng=0)
+    orc.prim2con(g, orc.make_eos(I.EOS_PWP3), U, P, EM, 1)
+    out = c2p_both(ip, U, prm, I.EOS_PWP3)
+    rate, itp, itl = check_learned_against_plain(orc, ip, U, P, EM, out, I.EOS_PWP3)
+    n = ip.npts
+    say("fallback rate %.4f; root-function evaluations per point: plain %.2f learned %.2f"
+        % (rate, itp / n, itl / n))
+    assert rate < 0.25
+    assert itl < itp
