@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--cpu-evals", type=int, default=4, help="oracle RHS evaluations in the CPU sample")
     ap.add_argument("--strip", type=int, default=0, help="tile-order strip height (0: library default)")
     ap.add_argument("--sweep-strip", action="store_true", help="time one RK4 step per strip height and report")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-con2prim path")
+    ap.add_argument("--no-level", action="store_true", help="skip the batched AMR-level paths")
+    ap.add_argument("--level-boxes", type=int, default=192)
+    ap.add_argument("--level-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times): the reference for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -53,6 +57,113 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print('{"copy_calibration_bytes_read": %d, "copy_calibration_bytes_written": %d, "launches": 3}' % (n * 8, n * 8))
+
+
+def say(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def time_steps(torch, step, steps, warmup):
+    """Mean event-timed milliseconds per step on the current stream."""
+    for _ in range(warmup):
+        step()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def learned_path(torch, mhd, I, run, step, args, nint):
+    """Same patch and steps with the learned con2prim guess.  The network is
+    trained here (own kernels) on 2^18 random states of the star workloads'
+    distribution; training time is reported, not part of the step."""
+    from paper_2510_13965_amd import learned
+
+    t0 = time.perf_counter()
+    X, T = learned.training_set(1 << 18, seed=I.SEED0 + 50, eos_cfg=I.EOS_IDEAL2, **learned.STAR_SAMPLING)
+    prm, hist = learned.train(X, T, seed=7, epochs=24, batch=4096)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    say("learned path: trained in %.1f s, loss %.3e -> %.3e" % (t_train, hist[0], hist[-1]))
+    run.use_learned(prm)
+    step()
+    run.stats.zero_()
+    ms = time_steps(torch, step, args.steps, 0)
+    st = run.stats.cpu().numpy()
+    run.use_learned(None)
+    nev = 4 * args.steps * run.ip.npts
+    say("learned path: %.3f ms/step, fallback %.4f" % (ms, st[2] / nev))
+    return {"zone_updates_per_s": round(nint * 4 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+            "fallback_rate": round(float(st[2]) / nev, 6), "root_evals_per_point": round(float(st[3]) / nev, 3),
+            "train_s": round(t_train, 2), "train_loss_first_last": [hist[0], hist[-1]], "train_states": 1 << 18,
+            "_mlp": prm}
+
+
+def level_paths(torch, mhd, I, args, mlp):
+    """The AMR-level workload: uneven boxes (edges 16..64) on three 2:1 levels of
+    the star; per-box launches vs one batched level (autotuned), eager, as a
+    replayed hipGraph, and with the learned con2prim."""
+    from paper_2510_13965_amd.step import LevelRun
+
+    t0 = time.perf_counter()
+    boxes = I.c3_boxes(nboxes=args.level_boxes)
+    Ab = I.star_field_amplitude()
+    eos = mhd.make_eos(I.EOS_IDEAL2)
+    ips, states = [], []
+    for b in boxes:
+        ip, U, P, EM = I.c3_box_state(b, Ab)
+        Ud = torch.as_tensor(U).cuda()
+        mhd.prim2con(mhd.patch_of(ip), eos, Ud, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
+        ips.append(ip)
+        states.append(Ud)
+    lr = LevelRun(ips, states, I.EOS_IDEAL2, I.PARAMS)
+    del states
+    torch.cuda.synchronize()
+    say("level: %d boxes, %d interior points, built in %.1f s" % (len(ips), lr.ninterior, time.perf_counter() - t0))
+    dt = 0.25 * min(ip.dx[0] for ip in ips)
+    nzu = lr.ninterior * 4
+    res = {"workload": "%d boxes, edges from {16,24,32,48,64}, 3 levels dx=1,1/2,1/4 of the TOV star; dt=%.4g"
+                       % (len(ips), dt),
+           "interior_points": lr.ninterior, "padded_points": lr.npts}
+
+    def per_box_step():
+        for s in range(4):
+            for b in lr.boxes:
+                Ux = b["U"] if s == 0 else b["Us"]
+                mhd.con2prim(b["patch"], lr.eos, Ux, b["P"], b.get("flags"), None, None)
+                mhd.rhs(b["patch"], lr.par, lr.eos, Ux, b["P"], b["k"], None, b["ws"])
+                mhd.rk_stage(b["patch"], I.NU, s, dt, b["U"], b["k"], b["acc"], b["Us"] if s < 3 else b["U"])
+
+    ms = time_steps(torch, per_box_step, 2, 1)
+    res["per_box"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+    say("level per-box: %.2f ms/step" % ms)
+    tun = lr.level.autotune(dt)
+    res["autotuned"] = tun
+    ms = time_steps(torch, lambda: lr.level.rk4_step(dt), args.level_steps, 1)
+    res["batched_eager"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+    say("level batched eager (%s): %.2f ms/step" % (tun, ms))
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        ms = time_steps(torch, lambda: lr.level.rk4_step(dt, use_graph=True, stream=stream), args.level_steps, 1)
+    res["batched_graph"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+    say("level batched graph: %.2f ms/step" % ms)
+    if mlp is not None:
+        lr.level.set_learned(mlp)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            ms = time_steps(torch, lambda: lr.level.rk4_step(dt, use_graph=True, stream=stream), args.level_steps, 1)
+        res["batched_graph_learned"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+        say("level batched graph + learned: %.2f ms/step" % ms)
+    fin = all(bool(torch.isfinite(b["U"]).all().item()) for b in lr.boxes)
+    res["finite"] = fin
+    lr.level.close()
+    return res
 
 
 def main():
@@ -75,6 +186,7 @@ def main():
     mhd.lib()
     ip, U, P, EM = I.c2_state(n=args.n)
     dev = "cuda"
+    say("building the %d^3 star patch" % args.n)
     run = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS, periodic=False, device=dev)
     # prim -> cons on the device
     Pd = torch.as_tensor(P).to(dev).contiguous()
@@ -86,59 +198,50 @@ def main():
         mhd.set_tuning(args.strip)
 
     def step():
-        for s in range(4):
-            Ux = run.Un if s == 0 else run.Us
-            mhd.con2prim(run.patch, run.eos, Ux, run.P, run.flags, None, run.stats)
-            mhd.rhs(run.patch, run.par, run.eos, Ux, run.P, run.k, run.vmax, run.ws)
-            mhd.rk_stage(run.patch, I.NU, s, dt, run.Un, run.k, run.acc, run.Us if s < 3 else run.Un)
+        run.step(dt)
 
     sweep = None
     if args.sweep_strip:
         sweep = {}
         for sh in (1, 2, 4, 8, 16, 32):
             mhd.set_tuning(sh)
-            step()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(3):
-                step()
-            e1.record()
-            torch.cuda.synchronize()
-            sweep[sh] = e0.elapsed_time(e1) / 3
+            sweep[sh] = time_steps(torch, step, 3, 1)
         best = min(sweep, key=sweep.get)
         mhd.set_tuning(best)
         sweep = {"ms_per_step": {k: round(v, 3) for k, v in sweep.items()}, "chosen": best}
+    say("plain path: warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed region: whole steps only
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    # timed region: whole steps only, per-kernel events recorded by the library
     w0 = time.perf_counter()
     mhd.profile_start()
-    t0.record()
-    for _ in range(args.steps):
-        step()
-    t1.record()
-    torch.cuda.synchronize()
+    ms_step = time_steps(torch, step, args.steps, 0)
+    prof = mhd.profile_stop()
     wall = time.perf_counter() - w0
-    ms_total = t0.elapsed_time(t1)
-    ms_step = ms_total / args.steps
     nint = ip.ninterior
     zu_s = nint * 4 / (ms_step * 1e-3)
     fin = bool(torch.isfinite(run.Un).all().item())
-
-    prof = mhd.profile_stop()
     kern = kernel_table(prof, ip, args.steps)
     roof = roofline(prof, ip, args.n)
+    say("plain path: %.3f ms/step" % ms_step)
+
+    paths = {"plain": {"zone_updates_per_s": round(zu_s, 1), "ms_per_step": round(ms_step, 4)}}
+    level = None
+    if not args.no_learned:
+        paths["learned"] = learned_path(torch, mhd, I, run, step, args, nint)
+    if not args.no_level:
+        level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
+    if "learned" in paths:
+        paths["learned"].pop("_mlp", None)
+
     out = {"metric": METRIC, "value": round(zu_s, 1), "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "TOV star K=100 Gamma=2 rho_c=1.28e-3, %d^3 interior, dx=%.4g, full CCZ4+GRMHD "
                                   "RHS + plain con2prim + RK4 stage" % (args.n, ip.dx[0]),
                       "interior_points": nint, "padded_points": ip.npts, "rhs_evals_per_step": 4, "path": "plain"},
+           "paths": paths, "level": level,
            "kernels": kern,
            "wall_s": round(wall, 3), "finite": fin, "tuning": mhd.get_tuning(), "strip_sweep": sweep,
            "roofline": roof}

@@ -122,14 +122,22 @@ typedef struct {
   uint32_t flags; /* MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER */
 } mhd_params_t;
 
-/* Launch tuning of the stencil kernels (process-wide; set it before enqueuing
- * work, not concurrently with launches from other host threads).
- * strip: height, in 64x4-point tiles, of the strips in which each XCD walks
- * its contiguous range of tiles (z fastest inside a strip); 1..1024.
- * The results do not depend on the tuning (bitwise). */
+/* Launch tuning.  The results never depend on it (bitwise).
+ * strip: height, in tiles, of the strips in which each XCD walks its
+ *   contiguous range of tiles (z fastest inside a strip); 1..1024.  Used by
+ *   the single-patch stencil kernels (process-wide, set with mhd_set_tuning
+ *   before enqueuing work, not concurrently with launches from other host
+ *   threads) and per level (mhd_level_set_tuning).
+ * block_threads: level kernels only: threads per workgroup = points per tile
+ *   (a tile is that many consecutive points of one z plane); 64, 128 or 256.
+ * grid_per_cu: level kernels only: persistent grid of grid_per_cu workgroups
+ *   per compute unit, each looping over tiles; 0 launches one workgroup per
+ *   tile. */
 typedef struct {
   int32_t strip;
-  int32_t reserved[7];
+  int32_t block_threads;
+  int32_t grid_per_cu;
+  int32_t reserved[5];
 } mhd_tuning_t;
 
 int mhd_set_tuning(const mhd_tuning_t* t);
@@ -232,6 +240,60 @@ int mhd_mlp_grad(const float* mlp, const float* X, const float* T, int64_t n, fl
                  void* workspace, size_t workspace_bytes, void* stream);
 int mhd_mlp_adam(float* mlp, const float* grad, float* m, float* v, int step, float lr, float beta1, float beta2,
                  float eps, void* stream);
+
+/* ---- batched levels ---------------------------------------------------------
+ * All boxes of one refinement level (patches of any shape, ng = 3, each with its
+ * own arrays) go through one persistent kernel per phase of the right-hand
+ * side; an RK4 step is 33 launches whatever the number of boxes, and can be
+ * replayed as one hipGraph.  Per point the arithmetic is that of the
+ * single-patch entry points, so results are bitwise equal to per-box calls of
+ * mhd_con2prim, mhd_rhs and mhd_rk_stage.  Ghost values are taken as given
+ * (frozen; the level does not exchange or fill them).  The level evolves the
+ * full coupled system (params->flags must hold all three MHD_* flags).
+ * mhd_level_create copies the descriptors to the device (the only allocation,
+ * with a capture stream); the arrays stay the caller's and must outlive it. */
+typedef struct {
+  mhd_patch_t patch;
+  double* U;        /* state at t^n (32 fields); the RK4 step updates it in place */
+  double* Us;       /* stage state (32 fields) */
+  double* P;        /* primitives (8 fields) */
+  double* k;        /* right-hand side (32 fields) */
+  double* acc;      /* RK4 accumulator (32 fields) */
+  void* workspace;  /* mhd_rhs_workspace_size(&patch) bytes or more */
+  size_t workspace_bytes;
+  uint8_t* flags;   /* con2prim flags, may be NULL */
+} mhd_box_t;
+
+typedef struct mhd_level mhd_level_t;
+
+int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* params, const mhd_eos_t* eos,
+                     mhd_level_t** level);
+int mhd_level_destroy(mhd_level_t* level);
+/* Tuning of the level's launches (see mhd_tuning_t); waits for the device. */
+int mhd_level_set_tuning(mhd_level_t* level, const mhd_tuning_t* tuning);
+int mhd_level_get_tuning(const mhd_level_t* level, mhd_tuning_t* tuning);
+/* con2prim + L(U) of every box, evaluated at U (src 0) or Us (src 1), into k;
+ * max_speed (device double, may be NULL) gets an atomic max as in mhd_rhs;
+ * stats (may be NULL) accumulates the con2prim counters. */
+int mhd_level_rhs(mhd_level_t* level, int src, double* max_speed, int64_t* stats, void* stream);
+/* One RK4 step of size dt (Table I) of every box: four evaluations and stage
+ * updates; U is advanced in place.  max_speed (may be NULL) is zeroed and then
+ * receives the maximum over the four evaluations.  use_graph != 0: the step is
+ * captured once into a hipGraph (again whenever dt or max_speed change) and
+ * replayed on `stream`. */
+int mhd_level_rk4_step(mhd_level_t* level, double dt, double* max_speed, int use_graph, void* stream);
+/* Times the candidate tunings (block_threads 64/128/256 x strip 1/4/16 x
+ * grid_per_cu 0/4/16) on one evaluation at Us plus a stage-1 update, and keeps
+ * the fastest.  It overwrites Us, P, k, acc, flags and the workspaces; U is only
+ * read.  chosen may be NULL. */
+int mhd_level_autotune(mhd_level_t* level, double dt, void* stream, mhd_tuning_t* chosen);
+
+/* Use the learned con2prim guess (as mhd_con2prim_learned, over all boxes, with
+ * one fallback queue) in the level's con2prim phase; mlp = NULL returns to the
+ * bracketed solver.  workspace: mhd_level_learned_workspace_size() bytes.  Both
+ * must outlive their use by the level; waits for the device. */
+size_t mhd_level_learned_workspace_size(const mhd_level_t* level);
+int mhd_level_set_learned(mhd_level_t* level, const float* mlp, void* workspace, size_t workspace_bytes);
 
 /* Workspace bytes mhd_rhs needs for this patch (point fluxes and speeds). */
 size_t mhd_rhs_workspace_size(const mhd_patch_t* patch);

@@ -116,6 +116,13 @@ mhd::Geom geom_of(const mhd_patch_t* pt) {
 
 }  // namespace
 
+namespace mhd {
+int abi_fail(int code, const char* msg) { return fail(code, "%s", msg); }
+int abi_hip(int rc, const char* what) { return hip_check(rc, what); }
+Geom abi_geom(const mhd_patch_t* p) { return geom_of(p); }
+int abi_check_patch(const mhd_patch_t* p, int need_ng, const char* fn) { return check_patch(p, need_ng, 1, fn); }
+}  // namespace mhd
+
 extern "C" {
 
 const char* mhd_last_error(void) { return g_err; }
@@ -134,6 +141,7 @@ int mhd_get_tuning(mhd_tuning_t* t) {
   if (!t) return fail(MHD_EINVAL, "mhd_get_tuning: NULL");
   *t = mhd_tuning_t{};
   t->strip = g_strip;
+  t->block_threads = 256;
   return MHD_OK;
 }
 

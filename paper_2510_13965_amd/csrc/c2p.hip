@@ -27,26 +27,50 @@ struct C2pArgs {
   int64_t* __restrict__ stats;
 };
 
-__global__ void __launch_bounds__(256) k_con2prim(C2pArgs a) {
+// padded indices; every lane of the wavefront calls this (statistics are a
+// wavefront reduction)
+__device__ __forceinline__ void con2prim_at(const C2pArgs& a, const mhd_eos_t& eos, int i, int j, int k, bool live) {
   const Geom& g = a.g;
-  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  const bool live = i < Nx && j < Ny;
   int64_t nfatal = 0, ncorr = 0, nit = 0;
   if (live) {
     const int64_t p = g.at(i, j, k);
     C2pPoint pt;
     load_point(a.U, g.sf, p, pt);
     C2pOut o;
-    c2p_plain(a.eos, pt, o);
+    c2p_plain(eos, pt, o);
     store_point(a.U, a.P, a.flags, a.mu, g.sf, p, pt, o);
     nfatal = (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
     ncorr = (o.flags & C2P_CORRECTED) ? 1 : 0;
     nit = o.iters;
   }
   if (a.stats) wave_add_stats(a.stats, nfatal, ncorr, 0, nit);
+}
+
+__global__ void __launch_bounds__(256) k_con2prim(C2pArgs a) {
+  const Geom& g = a.g;
+  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  con2prim_at(a, a.eos, i, j, k, i < Nx && j < Ny);
+}
+
+__global__ void __launch_bounds__(256) k_con2prim_lv(LevelArgs L) {
+  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    C2pArgs a;  // eos stays in the kernel arguments (read with dynamic indices)
+    a.g = B.g;
+    a.U = L.src ? B.Us : B.U;
+    a.P = B.P;
+    a.flags = B.flags;
+    a.mu = nullptr;
+    a.stats = L.stats;
+    con2prim_at(a, L.eos, i, j, k, live);
+  });
+}
+
+int launch_con2prim_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_CON2PRIM, k_con2prim_lv, dim3(grid), dim3(block), 0, s, L);
+  return (int)hipGetLastError();
 }
 
 struct P2cArgs {

@@ -43,21 +43,29 @@ struct PointIdx {
   bool live;
 };
 
-__device__ __forceinline__ PointIdx point_index(const Ccz4Args& a) {
-  const Geom& g = a.g;
+// interior indices (i, j, k) -> addressing of the point
+__device__ __forceinline__ PointIdx point_at(const Geom& g, int i, int j, int k) {
   PointIdx q;
-  const TileXYZ t = tile_of_block(a.nbx, a.nby, a.nbz, a.strip);
-  int i = t.bx * 64 + threadIdx.x;
-  int j = t.by * 4 + threadIdx.y;
-  int k = t.bz;
-  q.live = t.bx >= 0 && i < g.nx && j < g.ny;
-  if (!q.live) i = j = k = 0;
+  q.live = true;
   q.p = g.at(i + g.ng, j + g.ng, k + g.ng);
   q.voff = (uint32_t)(q.p * 8);
   q.sf = g.sf;
   q.st[0] = 1;
   q.st[1] = g.sy;
   q.st[2] = g.sz;
+  return q;
+}
+
+__device__ __forceinline__ PointIdx point_index(const Ccz4Args& a) {
+  const Geom& g = a.g;
+  const TileXYZ t = tile_of_block(a.nbx, a.nby, a.nbz, a.strip);
+  int i = t.bx * 64 + threadIdx.x;
+  int j = t.by * 4 + threadIdx.y;
+  int k = t.bz;
+  const bool live = t.bx >= 0 && i < g.nx && j < g.ny;
+  if (!live) i = j = k = 0;
+  PointIdx q = point_at(g, i, j, k);
+  q.live = live;
   return q;
 }
 
@@ -139,10 +147,8 @@ __device__ __forceinline__ void matter_point(const double* __restrict__ U, const
 
 // ------------------------------------------------------------------ advection + KO
 
-__global__ void __launch_bounds__(256) k_ccz4_stencil(Ccz4Args a) {
+__device__ __forceinline__ void ccz4_stencil_at(const Ccz4Args& a, const PointIdx& q) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(a);
-  if (!q.live) return;
   const double* __restrict__ U = a.U;
   const double beta[3] = {ldf(U + (19) * q.sf, q.voff), ldf(U + (20) * q.sf, q.voff), ldf(U + (21) * q.sf, q.voff)};
   const double sko[3] = {a.par.sigma_ko * (1.0 / 64.0) * g.idx[0], a.par.sigma_ko * (1.0 / 64.0) * g.idx[1],
@@ -165,10 +171,8 @@ __global__ void __launch_bounds__(256) k_ccz4_stencil(Ccz4Args a) {
 // 21-23 d_i d_k beta^k
 constexpr int kD2Fields = 24;
 
-__global__ void __launch_bounds__(256) k_ccz4_d2(Ccz4Args a, double* __restrict__ W) {
+__device__ __forceinline__ void ccz4_d2_at(const Ccz4Args& a, double* __restrict__ W, const PointIdx& q) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(a);
-  if (!q.live) return;
   const double* __restrict__ U = a.U;
   const int64_t sf = q.sf;
   double gt[6], gtu[6];
@@ -221,10 +225,8 @@ __global__ void __launch_bounds__(256) k_ccz4_d2(Ccz4Args a, double* __restrict_
 
 // ------------------------------------------------------------------ At_ij, Khat, Theta
 
-__global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __restrict__ W) {
+__device__ __forceinline__ void ccz4_curv_at(const Ccz4Args& a, const double* __restrict__ W, const PointIdx& q) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(a);
-  if (!q.live) return;
   const double* __restrict__ U = a.U;
   const int64_t sf = q.sf, p = q.p;
 
@@ -398,10 +400,8 @@ __global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __r
 
 // ------------------------------------------------------------------ gt_ij, chi, Ghat^i, gauge
 
-__global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __restrict__ W) {
+__device__ __forceinline__ void ccz4_gauge_at(const Ccz4Args& a, const double* __restrict__ W, const PointIdx& q) {
   const Geom& g = a.g;
-  const PointIdx q = point_index(a);
-  if (!q.live) return;
   const double* __restrict__ U = a.U;
   const int64_t sf = q.sf, p = q.p;
 
@@ -518,6 +518,64 @@ __global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __
     R[(19 + i) * sf] += 0.75 * a.par.f_beta * Gh[i] - a.par.eta * (beta[i] - a.par.beta0[i]);
 }
 
+// ------------------------------------------------------------------ kernels
+
+__global__ void __launch_bounds__(256) k_ccz4_stencil(Ccz4Args a) {
+  const PointIdx q = point_index(a);
+  if (!q.live) return;
+  ccz4_stencil_at(a, q);
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_stencil_lv(LevelArgs L) {
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0};
+    ccz4_stencil_at(a, point_at(B.g, i, j, k));
+  });
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_d2(Ccz4Args a, double* __restrict__ W) {
+  const PointIdx q = point_index(a);
+  if (!q.live) return;
+  ccz4_d2_at(a, W, q);
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_d2_lv(LevelArgs L) {
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0};
+    ccz4_d2_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
+  });
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __restrict__ W) {
+  const PointIdx q = point_index(a);
+  if (!q.live) return;
+  ccz4_curv_at(a, W, q);
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_curv_lv(LevelArgs L) {
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0};
+    ccz4_curv_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
+  });
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __restrict__ W) {
+  const PointIdx q = point_index(a);
+  if (!q.live) return;
+  ccz4_gauge_at(a, W, q);
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_gauge_lv(LevelArgs L) {
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0};
+    ccz4_gauge_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
+  });
+}
+
 int ccz4_workspace_fields() { return kD2Fields; }
 
 int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
@@ -531,6 +589,14 @@ int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const d
   MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2, grd, blk, 0, s, a, ws);
   MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv, grd, blk, 0, s, a, (const double*)ws);
   MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge, grd, blk, 0, s, a, (const double*)ws);
+  return (int)hipGetLastError();
+}
+
+int launch_ccz4_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lv, dim3(grid), dim3(block), 0, s, L);
+  MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2_lv, dim3(grid), dim3(block), 0, s, L);
+  MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv_lv, dim3(grid), dim3(block), 0, s, L);
+  MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge_lv, dim3(grid), dim3(block), 0, s, L);
   return (int)hipGetLastError();
 }
 

@@ -41,16 +41,8 @@ struct TileXYZ {
   int bx, by, bz;
 };
 
-__device__ __forceinline__ TileXYZ tile_of_block(int nbx, int nby, int nbz, int strip) {
-  const int nblk = nbx * nby * nbz;
-  const int b = blockIdx.x;
-  const int per_xcd = (nblk + 7) / 8;
-  const int xcd = b & 7, slot = b >> 3;
-  int id = xcd * per_xcd + slot;  // contiguous range per XCD
-  if (id >= nblk) {
-    TileXYZ t{-1, -1, -1};
-    return t;
-  }
+// tile of linear id `id` (0 <= id < nbx*nby*nbz) in the strip order
+__device__ __forceinline__ TileXYZ tile_of_index(int id, int nbx, int nby, int nbz, int strip) {
   const int sh = strip < nby ? strip : nby;
   const int per_strip = sh * nbx * nbz;
   const int st = id / per_strip;
@@ -63,6 +55,98 @@ __device__ __forceinline__ TileXYZ tile_of_block(int nbx, int nby, int nbz, int 
   t.by = st * sh + r / nbx;
   t.bx = r - (r / nbx) * nbx;
   return t;
+}
+
+__device__ __forceinline__ TileXYZ tile_of_block(int nbx, int nby, int nbz, int strip) {
+  const int nblk = nbx * nby * nbz;
+  const int b = blockIdx.x;
+  const int per_xcd = (nblk + 7) / 8;
+  const int xcd = b & 7, slot = b >> 3;
+  const int id = xcd * per_xcd + slot;  // contiguous range per XCD
+  if (id >= nblk) {
+    TileXYZ t{-1, -1, -1};
+    return t;
+  }
+  return tile_of_index(id, nbx, nby, nbz, strip);
+}
+
+// ------------------------------------------------------------------ batched levels
+//
+// A level is a list of boxes (patches of any shape) processed by persistent
+// kernels, one per phase of the right-hand side.  Each phase walks a global
+// tile space: box-major, and inside a box the chunks of `blockDim.x`
+// consecutive points of a z plane (row-major, so narrow boxes still fill the
+// wavefront), in the strip order (z fastest inside strips of `strip` chunks).
+// Every XCD takes a contiguous range of the global space.  The per-point work
+// is the same device code as the single-patch kernels, so results are bitwise
+// those of per-box launches.
+struct BoxDev {
+  Geom g;
+  double* U;    // state at t^n
+  double* Us;   // stage state
+  double* P;    // primitives
+  double* k;    // right-hand side
+  double* acc;  // RK accumulator
+  double* ws;   // RHS workspace
+  uint8_t* flags;
+  int cpp_int, cpp_pad;    // chunks per interior / padded z plane
+  int64_t t0_int, t0_pad;  // first global tile id of the box in each space
+};
+
+struct LevelArgs {
+  const BoxDev* __restrict__ boxes;
+  int nboxes;
+  int strip;
+  int src;  // 0: evaluate at U, 1: at Us
+  int stage;
+  int64_t ntile_int, ntile_pad;
+  double dt;
+  mhd_params_t par;
+  mhd_eos_t eos;
+  unsigned long long* max_speed;
+  int64_t* stats;
+  // con2prim with the learned guess (mlp == nullptr: the bracketed solver)
+  const float* mlp;
+  uint32_t* qcount;
+  uint64_t* queue;
+};
+
+__device__ __forceinline__ int find_box(const LevelArgs& L, int64_t id, bool padded) {
+  int lo = 0, hi = L.nboxes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    const int64_t t0 = padded ? L.boxes[mid].t0_pad : L.boxes[mid].t0_int;
+    if (t0 <= id) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Calls body(box, i, j, k, live) for every point of the tile space, once per
+// thread and tile (i, j, k interior indices, or padded indices if `padded`).
+template <class F>
+__device__ __forceinline__ void for_each_level_point(const LevelArgs& L, bool padded, F&& body) {
+  const int64_t total = padded ? L.ntile_pad : L.ntile_int;
+  const int per_g = gridDim.x >> 3;  // gridDim.x is a multiple of 8
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int64_t per = (total + 7) / 8;
+  const int64_t lo = xcd * per;
+  const int64_t hi = lo + per < total ? lo + per : total;
+  for (int64_t id = lo + slot; id < hi; id += per_g) {
+    const int b = find_box(L, id, padded);
+    const BoxDev& B = L.boxes[b];
+    const int nx = padded ? B.g.nx + 2 * B.g.ng : B.g.nx;
+    const int ny = padded ? B.g.ny + 2 * B.g.ng : B.g.ny;
+    const int nz = padded ? B.g.nz + 2 * B.g.ng : B.g.nz;
+    const int cpp = padded ? B.cpp_pad : B.cpp_int;
+    const int local = (int)(id - (padded ? B.t0_pad : B.t0_int));
+    const TileXYZ t = tile_of_index(local, 1, cpp, nz, L.strip);
+    const int q = t.by * (int)blockDim.x + (int)threadIdx.x;
+    const bool live = q < nx * ny;
+    const int j = live ? q / nx : 0;
+    const int i = live ? q - j * nx : 0;
+    body(B, i, j, t.bz, live);
+  }
 }
 
 // ------------------------------------------------------------------ EoS

@@ -115,12 +115,10 @@ __device__ __forceinline__ double cs2_repro(const mhd_eos_t& e, double rho, doub
   return (dpdrho + p / (rho * rho) * dpdeps) / (1.0 + eps + p / rho);
 }
 
-__global__ void __launch_bounds__(256) k_mhd_point(MhdPointArgs a) {
+// padded indices (i, j, k) of a point inside the padded patch
+__device__ __forceinline__ void mhd_point_at(const MhdPointArgs& a, const mhd_params_t& par, const mhd_eos_t& eos, int i,
+                                             int j, int k) {
   const Geom& g = a.g;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx + 2 * g.ng || j >= g.ny + 2 * g.ng) return;
   const int64_t sf = g.sf;
   const int64_t p = g.at(i, j, k);
   const double* __restrict__ U = a.U;
@@ -156,10 +154,10 @@ __global__ void __launch_bounds__(256) k_mhd_point(MhdPointArgs a) {
   // characteristic speed ingredients (App. B)
   const double h = rho * (1.0 + eps) + pr;
   const double b2 = B2 / (W * W) + Bv * Bv;
-  const double cs2 = cs2_repro(a.eos, rho, eps);
+  const double cs2 = cs2_repro(eos, rho, eps);
   const double ca2 = b2 / (h + b2);
   const double a2 = cs2 + ca2 - cs2 * ca2;
-  const double cb = a.par.c_b;
+  const double cb = par.c_b;
 
   double* __restrict__ Wk = a.W + p;
 #pragma unroll
@@ -204,13 +202,11 @@ struct MhdUpdArgs {
   unsigned long long* max_speed;  // bit pattern of a non-negative double
 };
 
-__global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
+// interior indices (i, j, k); every lane of the wavefront calls this (the
+// speed maximum is a wavefront reduction), lanes without a point with live =
+// false and a valid k
+__device__ __forceinline__ void mhd_update_at(const MhdUpdArgs& a, int i, int j, int k, bool live) {
   const Geom& g = a.g;
-  const TileXYZ t = tile_of_block(a.nbx, a.nby, a.nbz, a.strip);
-  const int i = t.bx * 64 + threadIdx.x;
-  const int j = t.by * 4 + threadIdx.y;
-  const int k = t.bz < 0 ? 0 : t.bz;
-  const bool live = (t.bx >= 0 && i < g.nx && j < g.ny);
   const int64_t sf = g.sf;
   const int64_t p = live ? g.at(i + g.ng, j + g.ng, k + g.ng) : g.at(g.ng, g.ng, k + g.ng);
   const double* __restrict__ U = a.U;
@@ -383,6 +379,50 @@ __global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
     if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0)
       atomicMax(a.max_speed, (unsigned long long)__double_as_longlong(v));
   }
+}
+
+__global__ void __launch_bounds__(256) k_mhd_point(MhdPointArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx + 2 * g.ng || j >= g.ny + 2 * g.ng) return;
+  mhd_point_at(a, a.par, a.eos, i, j, k);
+}
+
+__global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
+  const Geom& g = a.g;
+  const TileXYZ t = tile_of_block(a.nbx, a.nby, a.nbz, a.strip);
+  const int i = t.bx * 64 + threadIdx.x;
+  const int j = t.by * 4 + threadIdx.y;
+  const int k = t.bz < 0 ? 0 : t.bz;
+  const bool live = (t.bx >= 0 && i < g.nx && j < g.ny);
+  mhd_update_at(a, i, j, k, live);
+}
+
+__global__ void __launch_bounds__(256) k_mhd_point_lv(LevelArgs L) {
+  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    MhdPointArgs a;  // par and eos stay in the kernel arguments
+    a.g = B.g;
+    a.U = L.src ? B.Us : B.U;
+    a.P = B.P;
+    a.W = B.ws;
+    mhd_point_at(a, L.par, L.eos, i, j, k);
+  });
+}
+
+__global__ void __launch_bounds__(256) k_mhd_update_lv(LevelArgs L) {
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    const MhdUpdArgs a{B.g, 0, 0, 0, 0, L.par, L.src ? B.Us : B.U, B.P, B.ws, B.k, L.max_speed};
+    mhd_update_at(a, i, j, k, live);
+  });
+}
+
+int launch_mhd_level(const LevelArgs& L, int grid_pad, int grid_int, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_MHD_POINT, k_mhd_point_lv, dim3(grid_pad), dim3(block), 0, s, L);
+  MHD_LAUNCH(KID_MHD_UPDATE, k_mhd_update_lv, dim3(grid_int), dim3(block), 0, s, L);
+  return (int)hipGetLastError();
 }
 
 int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,

@@ -562,21 +562,27 @@ struct FDual {
 
 __device__ __forceinline__ double sigmoid(double y) { return 1.0 / (1.0 + exp(-y)); }
 
-__global__ void __launch_bounds__(256) k_c2p_learned(LearnedArgs a) {
-  __shared__ MlpLds s;
-  mlp_stage(a.prm, s);
-  __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool inside = t < a.npts;
+struct LearnedOut {
+  bool fallback;
+  int64_t nfatal, ncorr, nit;
+};
+
+// con2prim of padded point (i, j, k) with the learned guess; every lane of the
+// wavefront calls this (the network runs on the whole wavefront), lanes
+// without a point with inside = false.  Returns whether the point needs the
+// bracketed solver (then nothing is stored for it).
+__device__ __forceinline__ LearnedOut learned_point(const MlpLds& s, const mhd_eos_t& eos, const Geom& g, double* U,
+                                                    double* P, uint8_t* flags, double* mu, int i, int j, int k,
+                                                    bool inside) {
+  LearnedOut r{false, 0, 0, 0};
   int64_t p = 0;
   C2pPoint pt;
   C2pInv c;
   bool solve = false;
   if (inside) {
-    const int i = (int)(t % a.Nx), j = (int)((t / a.Nx) % a.Ny), k = (int)(t / ((int64_t)a.Nx * a.Ny));
-    p = a.g.at(i, j, k);
-    load_point(a.U, a.g.sf, p, pt);
-    solve = c2p_setup(a.eos, pt, c);
+    p = g.at(i, j, k);
+    load_point(U, g.sf, p, pt);
+    solve = c2p_setup(eos, pt, c);
   }
   // network guess (whole wave, dead lanes with zero inputs)
   float z[8] = {0, 0, 0, 0, 0, 0, 0, 0}, y[2];
@@ -592,60 +598,109 @@ __global__ void __launch_bounds__(256) k_c2p_learned(LearnedArgs a) {
     MlpFwd f;
     mlp_forward(s, z, f, y);
   }
-  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
-  bool fallback = false;
-  if (inside) {
+  if (!inside) return r;
+  C2pOut o;
+  o.flags = 0;
+  o.iters = 0;
+  o.mup = o.mu = 0.0;
+  if (!solve) {
+    atmosphere_prims(eos, o.prim);
+    o.flags = MHD_FLAG_ATMO;
+    double Wn;
+    const double zv[3] = {0.0, 0.0, 0.0};
+    prim_to_cons(pt.gd, o.prim[0], o.prim[1], o.prim[2], zv, o.prim[7], pt.B, o.cons, Wn);
+  } else {
+    int nev = 0;
+    const double hi = 1.0 / c.h0;
+    const double fhi = fa_t<double>(c, hi);
+    double mup = hi;
+    bool ok = true;
+    if (fhi > 0.0) ok = newton_polish(FaDual{c}, sigmoid((double)y[0]) * hi, hi, false, mup, nev);
+    double m = mup;
+    if (ok) {
+      const FFn fp{eos, c};
+      const double f1 = fp(mup);
+      ++nev;
+      if (f1 > 0.0) ok = newton_polish(FDual{eos, c}, sigmoid((double)y[1]) * mup, mup, true, m, nev);
+    }
+    r.nit = nev + 1;  // root-function evaluations, f_a(1/h0) included
+    if (!ok) {
+      r.fallback = true;
+      return r;
+    }
+    o.mup = mup;
+    o.mu = m;
+    c2p_finish(eos, pt, c, m, o);
+  }
+  store_point(U, P, flags, mu, g.sf, p, pt, o);
+  r.nfatal = (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
+  r.ncorr = (o.flags & C2P_CORRECTED) ? 1 : 0;
+  return r;
+}
+
+// wave-aggregated append of `entry` for the lanes with `take` set
+template <class T>
+__device__ __forceinline__ void queue_append(bool take, T entry, uint32_t* count, T* queue) {
+  const uint64_t mask = __ballot(take);
+  if (!mask) return;
+  const int l = lane_id();
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (l == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader, 64);
+  if (take) queue[base + __popcll(mask & ((1ull << l) - 1ull))] = entry;
+}
+
+__global__ void __launch_bounds__(256) k_c2p_learned(LearnedArgs a) {
+  __shared__ MlpLds s;
+  mlp_stage(a.prm, s);
+  __syncthreads();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool inside = t < a.npts;
+  const int i = inside ? (int)(t % a.Nx) : 0, j = inside ? (int)((t / a.Nx) % a.Ny) : 0;
+  const int k = inside ? (int)(t / ((int64_t)a.Nx * a.Ny)) : 0;
+  const LearnedOut r = learned_point(s, a.eos, a.g, a.U, a.P, a.flags, a.mu, i, j, k, inside);
+  queue_append<uint32_t>(r.fallback, (uint32_t)t, a.qcount, a.queue);
+  if (a.stats) wave_add_stats(a.stats, r.nfatal, r.ncorr, r.fallback ? 1 : 0, r.nit);
+}
+
+// level version: queue entries are (box << 32) | linear padded point of the box
+__global__ void __launch_bounds__(256) k_c2p_learned_lv(LevelArgs L) {
+  __shared__ MlpLds s;
+  mlp_stage(L.mlp, s);
+  __syncthreads();
+  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    const LearnedOut r = learned_point(s, L.eos, B.g, L.src ? B.Us : B.U, B.P, B.flags, nullptr, i, j, k, live);
+    const int Nx = B.g.nx + 2 * B.g.ng, Ny = B.g.ny + 2 * B.g.ng;
+    const uint64_t box = (uint64_t)(&B - L.boxes);
+    const uint64_t entry = (box << 32) | (uint64_t)((int64_t)i + (int64_t)Nx * ((int64_t)j + (int64_t)Ny * k));
+    queue_append<uint64_t>(r.fallback, entry, L.qcount, L.queue);
+    if (L.stats) wave_add_stats(L.stats, r.nfatal, r.ncorr, r.fallback ? 1 : 0, r.nit);
+  });
+}
+
+__global__ void __launch_bounds__(256) k_c2p_fallback_lv(LevelArgs L) {
+  const uint32_t nq = *L.qcount;
+  int64_t nfatal = 0, ncorr = 0, nit = 0;
+  for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
+    const uint64_t e = L.queue[q];
+    const BoxDev& B = L.boxes[(int)(e >> 32)];
+    const int64_t t = (int64_t)(e & 0xffffffffull);
+    const int Nx = B.g.nx + 2 * B.g.ng, Ny = B.g.ny + 2 * B.g.ng;
+    const int i = (int)(t % Nx), j = (int)((t / Nx) % Ny), k = (int)(t / ((int64_t)Nx * Ny));
+    const int64_t p = B.g.at(i, j, k);
+    double* U = L.src ? B.Us : B.U;
+    C2pPoint pt;
+    load_point(U, B.g.sf, p, pt);
     C2pOut o;
-    o.flags = 0;
-    o.iters = 0;
-    o.mup = o.mu = 0.0;
-    if (!solve) {
-      atmosphere_prims(a.eos, o.prim);
-      o.flags = MHD_FLAG_ATMO;
-      double Wn;
-      const double zv[3] = {0.0, 0.0, 0.0};
-      prim_to_cons(pt.gd, o.prim[0], o.prim[1], o.prim[2], zv, o.prim[7], pt.B, o.cons, Wn);
-    } else {
-      int nev = 0;
-      const double hi = 1.0 / c.h0;
-      const double fhi = fa_t<double>(c, hi);
-      double mup = hi;
-      bool ok = true;
-      if (fhi > 0.0) ok = newton_polish(FaDual{c}, sigmoid((double)y[0]) * hi, hi, false, mup, nev);
-      double mu = mup;
-      if (ok) {
-        const FFn fp{a.eos, c};
-        const double f1 = fp(mup);
-        ++nev;
-        if (f1 > 0.0) ok = newton_polish(FDual{a.eos, c}, sigmoid((double)y[1]) * mup, mup, true, mu, nev);
-      }
-      nit = nev + 1;  // root-function evaluations, f_a(1/h0) included
-      if (ok) {
-        o.mup = mup;
-        o.mu = mu;
-        c2p_finish(a.eos, pt, c, mu, o);
-      } else {
-        fallback = true;
-      }
-    }
-    if (!fallback) {
-      store_point(a.U, a.P, a.flags, a.mu, a.g.sf, p, pt, o);
-      nfatal = (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
-      ncorr = (o.flags & C2P_CORRECTED) ? 1 : 0;
-    }
+    c2p_plain(L.eos, pt, o);
+    o.flags |= MHD_FLAG_FALLBACK;
+    store_point(U, B.P, B.flags, nullptr, B.g.sf, p, pt, o);
+    nfatal += (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
+    ncorr += (o.flags & C2P_CORRECTED) ? 1 : 0;
+    nit += o.iters;
   }
-  // wave-aggregated append of the rejected points to the fallback queue
-  const uint64_t mask = __ballot(fallback);
-  if (mask) {
-    const int l = lane_id();
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (l == leader) base = atomicAdd(a.qcount, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    if (fallback) a.queue[base + __popcll(mask & ((1ull << l) - 1ull))] = (uint32_t)t;
-  }
-  nfb = fallback ? 1 : 0;
-  if (a.stats) wave_add_stats(a.stats, nfatal, ncorr, nfb, nit);
+  if (L.stats) wave_add_stats(L.stats, nfatal, ncorr, 0, nit);
 }
 
 // the bracketed solver on the queued points (grid-strided over the queue)
@@ -726,6 +781,13 @@ int launch_con2prim_learned(const Geom& g, const mhd_eos_t& eos, const float* pr
   const int64_t fb_blocks = (a.npts + 255) / 256;
   MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback, dim3((unsigned)(fb_blocks < 2048 ? fb_blocks : 2048)), dim3(256), 0, s,
              a);
+  return (int)hipGetLastError();
+}
+
+int launch_con2prim_learned_level(const LevelArgs& L, int grid, int block, int grid_fb, hipStream_t s) {
+  MHD_LAUNCH(KID_ZERO, k_zero_u32, dim3(1), dim3(1), 0, s, L.qcount);
+  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_learned_lv, dim3(grid), dim3(block), 0, s, L);
+  MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback_lv, dim3(grid_fb), dim3(256), 0, s, L);
   return (int)hipGetLastError();
 }
 

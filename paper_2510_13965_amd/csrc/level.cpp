@@ -1,0 +1,347 @@
+// Batched levels: all boxes of a refinement level through one persistent
+// kernel per phase, an optional hipGraph of the whole RK4 step, and an
+// autotuner for the launch shape (chunk size, strip height, persistent grid).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/mhd.h"
+#include "dev_common.hpp"
+
+namespace mhd {
+int launch_con2prim_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int launch_ccz4_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int launch_mhd_level(const LevelArgs& L, int grid_pad, int grid_int, int block, hipStream_t s);
+int launch_rk4_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int launch_zero_u64(unsigned long long* p, hipStream_t s);
+int launch_con2prim_learned_level(const LevelArgs& L, int grid, int block, int grid_fb, hipStream_t s);
+int abi_fail(int code, const char* msg);
+int abi_hip(int rc, const char* what);
+Geom abi_geom(const mhd_patch_t* p);
+int abi_check_patch(const mhd_patch_t* p, int need_ng, const char* fn);
+}  // namespace mhd
+
+struct mhd_level {
+  std::vector<mhd_box_t> boxes;
+  std::vector<mhd::BoxDev> host;
+  mhd::BoxDev* dev = nullptr;
+  mhd_params_t par;
+  mhd_eos_t eos;
+  mhd_tuning_t tun;
+  int64_t ntile_int = 0, ntile_pad = 0;
+  int ncu = 256;
+  // graph of one RK4 step, valid for (dt, max_speed)
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double g_dt = 0.0;
+  double* g_ms = nullptr;
+  // learned con2prim guess (nullptr: bracketed solver) and its fallback queue
+  const float* mlp = nullptr;
+  void* lws = nullptr;
+  int64_t npad = 0;
+};
+
+namespace {
+
+using mhd::abi_fail;
+using mhd::abi_hip;
+
+int block_threads(const mhd_tuning_t& t) { return t.block_threads ? t.block_threads : 256; }
+
+// tile prefix sums for the current chunk size, uploaded to the device array
+int layout(mhd_level_t* lv) {
+  // kernels of earlier calls may still read the descriptor array
+  int rc0 = abi_hip((int)hipDeviceSynchronize(), "mhd_level: synchronize");
+  if (rc0) return rc0;
+  const int T = block_threads(lv->tun);
+  int64_t ti = 0, tp = 0;
+  for (size_t b = 0; b < lv->boxes.size(); ++b) {
+    mhd::BoxDev& B = lv->host[b];
+    const mhd::Geom& g = B.g;
+    const int64_t plane_i = (int64_t)g.nx * g.ny;
+    const int64_t plane_p = (int64_t)(g.nx + 2 * g.ng) * (g.ny + 2 * g.ng);
+    B.cpp_int = (int)((plane_i + T - 1) / T);
+    B.cpp_pad = (int)((plane_p + T - 1) / T);
+    B.t0_int = ti;
+    B.t0_pad = tp;
+    ti += (int64_t)B.cpp_int * g.nz;
+    tp += (int64_t)B.cpp_pad * (g.nz + 2 * g.ng);
+  }
+  if (ti >= ((int64_t)1 << 31) || tp >= ((int64_t)1 << 31))
+    return abi_fail(MHD_EINVAL, "mhd_level: too many tiles for one launch");
+  lv->ntile_int = ti;
+  lv->ntile_pad = tp;
+  if (lv->exec) {
+    (void)hipGraphExecDestroy(lv->exec);
+    lv->exec = nullptr;
+  }
+  return abi_hip((int)hipMemcpy(lv->dev, lv->host.data(), sizeof(mhd::BoxDev) * lv->host.size(), hipMemcpyHostToDevice),
+                 "mhd_level: upload");
+}
+
+int grid_for(const mhd_level_t* lv, int64_t ntile) {
+  int64_t g = (ntile + 7) / 8 * 8;
+  if (lv->tun.grid_per_cu > 0) {
+    const int64_t cap = ((int64_t)lv->ncu * lv->tun.grid_per_cu + 7) / 8 * 8;
+    if (cap < g) g = cap;
+  }
+  return (int)(g > 0 ? g : 8);
+}
+
+mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, double* max_speed, int64_t* stats) {
+  mhd::LevelArgs L;
+  L.boxes = lv->dev;
+  L.nboxes = (int)lv->boxes.size();
+  L.strip = lv->tun.strip;
+  L.src = src;
+  L.stage = stage;
+  L.ntile_int = lv->ntile_int;
+  L.ntile_pad = lv->ntile_pad;
+  L.dt = dt;
+  L.par = lv->par;
+  L.eos = lv->eos;
+  L.max_speed = reinterpret_cast<unsigned long long*>(max_speed);
+  L.stats = stats;
+  L.mlp = lv->mlp;
+  L.qcount = static_cast<uint32_t*>(lv->lws);
+  L.queue = lv->lws ? reinterpret_cast<uint64_t*>(static_cast<char*>(lv->lws) + 256) : nullptr;
+  return L;
+}
+
+// con2prim + RHS of every box at U (src 0) or Us (src 1)
+int enqueue_rhs(const mhd_level_t* lv, int src, double* max_speed, int64_t* stats, hipStream_t s) {
+  const mhd::LevelArgs L = args_of(lv, src, 0, 0.0, max_speed, stats);
+  const int T = block_threads(lv->tun);
+  const int gi = grid_for(lv, lv->ntile_int), gp = grid_for(lv, lv->ntile_pad);
+  int rc;
+  if (lv->mlp) {
+    const int64_t fb = (lv->npad + 255) / 256;
+    if ((rc = mhd::launch_con2prim_learned_level(L, gp, T, (int)(fb < 2048 ? fb : 2048), s))) return rc;
+  } else if ((rc = mhd::launch_con2prim_level(L, gp, T, s))) {
+    return rc;
+  }
+  if ((rc = mhd::launch_ccz4_level(L, gi, T, s))) return rc;
+  return mhd::launch_mhd_level(L, gp, gi, T, s);
+}
+
+int enqueue_stage(const mhd_level_t* lv, int stage, double dt, hipStream_t s) {
+  const mhd::LevelArgs L = args_of(lv, 0, stage, dt, nullptr, nullptr);
+  return mhd::launch_rk4_level(L, grid_for(lv, lv->ntile_int), block_threads(lv->tun), s);
+}
+
+int enqueue_step(const mhd_level_t* lv, double dt, double* max_speed, hipStream_t s) {
+  int rc;
+  if (max_speed && (rc = mhd::launch_zero_u64(reinterpret_cast<unsigned long long*>(max_speed), s))) return rc;
+  for (int st = 0; st < 4; ++st) {
+    if ((rc = enqueue_rhs(lv, st > 0, max_speed, nullptr, s))) return rc;
+    if ((rc = enqueue_stage(lv, st, dt, s))) return rc;
+  }
+  return 0;
+}
+
+int check_tuning(const mhd_tuning_t* t) {
+  if (t->strip < 1 || t->strip > 1024) return abi_fail(MHD_EINVAL, "mhd_level: strip must be 1..1024");
+  if (t->block_threads != 0 && t->block_threads != 64 && t->block_threads != 128 && t->block_threads != 256)
+    return abi_fail(MHD_EINVAL, "mhd_level: block_threads must be 64, 128 or 256 (0: 256)");
+  if (t->grid_per_cu < 0 || t->grid_per_cu > 64) return abi_fail(MHD_EINVAL, "mhd_level: grid_per_cu must be 0..64");
+  return MHD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par, const mhd_eos_t* eos,
+                     mhd_level_t** out) {
+  if (!out) return abi_fail(MHD_EINVAL, "mhd_level_create: out is NULL");
+  *out = nullptr;
+  if (!boxes || nboxes < 1) return abi_fail(MHD_EINVAL, "mhd_level_create: need at least one box");
+  if (!par || !eos) return abi_fail(MHD_EINVAL, "mhd_level_create: params and eos are required");
+  const uint32_t need = MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER;
+  if ((par->flags & need) != need)
+    return abi_fail(MHD_EINVAL, "mhd_level_create: a level evolves the full coupled system (all flags set)");
+  if (par->f_alpha_kind != MHD_FALPHA_ONE && par->f_alpha_kind != MHD_FALPHA_HARMONIC)
+    return abi_fail(MHD_EINVAL, "mhd_level_create: unknown f_alpha_kind");
+  if (!(par->c_b > 0.0)) return abi_fail(MHD_EINVAL, "mhd_level_create: c_b must be > 0");
+  if (eos->npieces < 1 || eos->npieces > 4) return abi_fail(MHD_EINVAL, "mhd_level_create: bad eos");
+  for (int b = 0; b < nboxes; ++b) {
+    const mhd_box_t& B = boxes[b];
+    int rc;
+    if ((rc = mhd::abi_check_patch(&B.patch, 3, "mhd_level_create"))) return rc;
+    if (!B.U || !B.Us || !B.P || !B.k || !B.acc || !B.workspace)
+      return abi_fail(MHD_EINVAL, "mhd_level_create: box arrays must be non-NULL (flags may be NULL)");
+    if (B.workspace_bytes < mhd_rhs_workspace_size(&B.patch))
+      return abi_fail(MHD_EWORKSPACE, "mhd_level_create: box workspace too small");
+    if (B.patch.sf > (int64_t)(INT32_MAX / 8))
+      return abi_fail(MHD_EINVAL, "mhd_level_create: a padded field exceeds the 2^28-point limit");
+  }
+  mhd_level_t* lv = new (std::nothrow) mhd_level;
+  if (!lv) return abi_fail(MHD_EINVAL, "mhd_level_create: out of host memory");
+  lv->boxes.assign(boxes, boxes + nboxes);
+  lv->host.resize(nboxes);
+  for (int b = 0; b < nboxes; ++b) {
+    mhd::BoxDev& D = lv->host[b];
+    const mhd_box_t& B = boxes[b];
+    D.g = mhd::abi_geom(&B.patch);
+    D.U = B.U;
+    D.Us = B.Us;
+    D.P = B.P;
+    D.k = B.k;
+    D.acc = B.acc;
+    D.ws = static_cast<double*>(B.workspace);
+    D.flags = B.flags;
+    lv->npad += (int64_t)(B.patch.nx + 6) * (B.patch.ny + 6) * (B.patch.nz + 6);
+  }
+  lv->par = *par;
+  lv->eos = *eos;
+  lv->tun = mhd_tuning_t{};
+  lv->tun.strip = 4;
+  lv->tun.block_threads = 256;
+  lv->tun.grid_per_cu = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&lv->ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  int rc;
+  if ((rc = abi_hip((int)hipMalloc(&lv->dev, sizeof(mhd::BoxDev) * nboxes), "mhd_level_create: hipMalloc")) ||
+      (rc = layout(lv)) ||
+      (rc = abi_hip((int)hipStreamCreateWithFlags(&lv->cap, hipStreamNonBlocking), "mhd_level_create: stream"))) {
+    mhd_level_destroy(lv);
+    return rc;
+  }
+  *out = lv;
+  return MHD_OK;
+}
+
+int mhd_level_destroy(mhd_level_t* lv) {
+  if (!lv) return MHD_OK;
+  if (lv->exec) (void)hipGraphExecDestroy(lv->exec);
+  if (lv->cap) (void)hipStreamDestroy(lv->cap);
+  if (lv->dev) (void)hipFree(lv->dev);
+  delete lv;
+  return MHD_OK;
+}
+
+int mhd_level_set_tuning(mhd_level_t* lv, const mhd_tuning_t* t) {
+  if (!lv || !t) return abi_fail(MHD_EINVAL, "mhd_level_set_tuning: NULL");
+  int rc;
+  if ((rc = check_tuning(t))) return rc;
+  lv->tun = *t;
+  if (!lv->tun.block_threads) lv->tun.block_threads = 256;
+  return layout(lv);
+}
+
+int mhd_level_get_tuning(const mhd_level_t* lv, mhd_tuning_t* t) {
+  if (!lv || !t) return abi_fail(MHD_EINVAL, "mhd_level_get_tuning: NULL");
+  *t = lv->tun;
+  return MHD_OK;
+}
+
+size_t mhd_level_learned_workspace_size(const mhd_level_t* lv) {
+  if (!lv) return 0;
+  return 256 + 8 * (size_t)lv->npad;
+}
+
+int mhd_level_set_learned(mhd_level_t* lv, const float* mlp, void* workspace, size_t workspace_bytes) {
+  if (!lv) return abi_fail(MHD_EINVAL, "mhd_level_set_learned: NULL level");
+  if (mlp && (!workspace || workspace_bytes < mhd_level_learned_workspace_size(lv)))
+    return abi_fail(MHD_EWORKSPACE, "mhd_level_set_learned: workspace too small for the fallback queue");
+  if (mlp && lv->npad >= ((int64_t)1 << 32))
+    return abi_fail(MHD_EINVAL, "mhd_level_set_learned: more than 2^32 padded points in the level");
+  int rc = abi_hip((int)hipDeviceSynchronize(), "mhd_level_set_learned: synchronize");
+  if (rc) return rc;
+  lv->mlp = mlp;
+  lv->lws = mlp ? workspace : nullptr;
+  if (lv->exec) {
+    (void)hipGraphExecDestroy(lv->exec);
+    lv->exec = nullptr;
+  }
+  return MHD_OK;
+}
+
+int mhd_level_rhs(mhd_level_t* lv, int src, double* max_speed, int64_t* stats, void* stream) {
+  if (!lv) return abi_fail(MHD_EINVAL, "mhd_level_rhs: NULL level");
+  if (src != 0 && src != 1) return abi_fail(MHD_EINVAL, "mhd_level_rhs: src must be 0 (U) or 1 (Us)");
+  return abi_hip(enqueue_rhs(lv, src, max_speed, stats, (hipStream_t)stream), "mhd_level_rhs");
+}
+
+int mhd_level_rk4_step(mhd_level_t* lv, double dt, double* max_speed, int use_graph, void* stream) {
+  if (!lv) return abi_fail(MHD_EINVAL, "mhd_level_rk4_step: NULL level");
+  if (!(dt == dt) || dt > 1e300 || dt < -1e300) return abi_fail(MHD_EINVAL, "mhd_level_rk4_step: dt must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  if (!use_graph) return abi_hip(enqueue_step(lv, dt, max_speed, s), "mhd_level_rk4_step");
+  if (!lv->exec || lv->g_dt != dt || lv->g_ms != max_speed) {
+    if (lv->exec) {
+      (void)hipGraphExecDestroy(lv->exec);
+      lv->exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    int rc = abi_hip((int)hipStreamBeginCapture(lv->cap, hipStreamCaptureModeThreadLocal), "mhd_level: capture");
+    if (rc) return rc;
+    const int erc = enqueue_step(lv, dt, max_speed, lv->cap);
+    const hipError_t e2 = hipStreamEndCapture(lv->cap, &graph);
+    if (erc || e2 != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return abi_hip(erc ? erc : (int)e2, "mhd_level: capture of the RK4 step");
+    }
+    const hipError_t e3 = hipGraphInstantiate(&lv->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      lv->exec = nullptr;
+      return abi_hip((int)e3, "mhd_level: graph instantiate");
+    }
+    lv->g_dt = dt;
+    lv->g_ms = max_speed;
+  }
+  return abi_hip((int)hipGraphLaunch(lv->exec, s), "mhd_level: graph launch");
+}
+
+int mhd_level_autotune(mhd_level_t* lv, double dt, void* stream, mhd_tuning_t* chosen) {
+  if (!lv) return abi_fail(MHD_EINVAL, "mhd_level_autotune: NULL level");
+  hipStream_t s = (hipStream_t)stream;
+  static const int kBlock[3] = {64, 128, 256};
+  static const int kStrip[3] = {1, 4, 16};
+  static const int kGrid[3] = {0, 4, 16};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return abi_fail(MHD_EHIP, "mhd_level_autotune: event");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return abi_fail(MHD_EHIP, "mhd_level_autotune: event");
+  }
+  mhd_tuning_t best = lv->tun;
+  float best_ms = 1e30f;
+  int rc = MHD_OK;
+  for (int bi = 0; bi < 3 && !rc; ++bi)
+    for (int si = 0; si < 3 && !rc; ++si)
+      for (int gi = 0; gi < 3 && !rc; ++gi) {
+        mhd_tuning_t t = mhd_tuning_t{};
+        t.strip = kStrip[si];
+        t.block_threads = kBlock[bi];
+        t.grid_per_cu = kGrid[gi];
+        if ((rc = mhd_level_set_tuning(lv, &t))) break;
+        // timed unit: one evaluation at Us plus the stage-1 update (U is only read)
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3 && !rc; ++rep) {
+          if (rep == 1) rc = abi_hip((int)hipEventRecord(e0, s), "mhd_level_autotune: event");
+          if (!rc) rc = abi_hip(enqueue_rhs(lv, 1, nullptr, nullptr, s), "mhd_level_autotune");
+          if (!rc) rc = abi_hip(enqueue_stage(lv, 1, dt, s), "mhd_level_autotune");
+        }
+        if (!rc) rc = abi_hip((int)hipEventRecord(e1, s), "mhd_level_autotune: event");
+        if (!rc) rc = abi_hip((int)hipEventSynchronize(e1), "mhd_level_autotune: sync");
+        if (!rc) rc = abi_hip((int)hipEventElapsedTime(&ms, e0, e1), "mhd_level_autotune: time");
+        if (!rc && ms < best_ms) {
+          best_ms = ms;
+          best = t;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if ((rc = mhd_level_set_tuning(lv, &best))) return rc;
+  if (chosen) *chosen = best;
+  return MHD_OK;
+}
+
+}  // extern "C"

@@ -26,15 +26,8 @@ struct RkArgs {
   double* Unext;
 };
 
-// block 64x4: x = 64 consecutive points of a row, y = 4 rows; grid z = k * nfields + f
-__global__ void __launch_bounds__(256) k_rk4_stage(RkArgs a) {
-  const Geom& g = a.g;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int kz = blockIdx.z % g.nz;
-  const int f = blockIdx.z / g.nz;
-  if (i >= g.nx || j >= g.ny) return;
-  const int64_t p = (int64_t)f * g.sf + g.at(i + g.ng, j + g.ng, kz + g.ng);
+// one element: acc and Unext of Table I's stage `a.stage`
+__device__ __forceinline__ void rk4_element(const RkArgs& a, int64_t p) {
   const double kv = a.k[p];
   const int s = a.stage;
   const double b = kRk4B[s] * kv;
@@ -44,6 +37,40 @@ __global__ void __launch_bounds__(256) k_rk4_stage(RkArgs a) {
   } else {
     a.Unext[p] = a.Un[p] + a.dt * (a.acc[p] + b);
   }
+}
+
+// block 64x4: x = 64 consecutive points of a row, y = 4 rows; grid z = k * nfields + f
+__global__ void __launch_bounds__(256) k_rk4_stage(RkArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int kz = blockIdx.z % g.nz;
+  const int f = blockIdx.z / g.nz;
+  if (i >= g.nx || j >= g.ny) return;
+  rk4_element(a, (int64_t)f * g.sf + g.at(i + g.ng, j + g.ng, kz + g.ng));
+}
+
+// all 32 fields of every interior point of a level's boxes
+__global__ void __launch_bounds__(256) k_rk4_stage_lv(LevelArgs L) {
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    const RkArgs a{B.g, L.stage, L.dt, B.U, B.k, B.acc, L.stage < 3 ? B.Us : B.U};
+    const int64_t p = B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng);
+#pragma unroll 4
+    for (int f = 0; f < MHD_NU; ++f) rk4_element(a, (int64_t)f * B.g.sf + p);
+  });
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+int launch_rk4_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_RK4_STAGE, k_rk4_stage_lv, dim3(grid), dim3(block), 0, s, L);
+  return (int)hipGetLastError();
+}
+
+int launch_zero_u64(unsigned long long* p, hipStream_t s) {
+  MHD_LAUNCH(KID_ZERO, k_zero_u64, dim3(1), dim3(1), 0, s, p);
+  return (int)hipGetLastError();
 }
 
 struct GhostArgs {

@@ -352,7 +352,8 @@ def star_field_amplitude():
 
 # ----------------------------------------------------------------------- C4
 
-def c4_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None):
+def c4_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None, log_rho=(-12.0, -3.0), log_eps=(-6.0, 0.0),
+             log_sigma=(-4.0, 1.0), log_wm1=None, static_frac=0.0):
     """Random con2prim states laid out as a ghost-free patch.
 
     rho log-uniform [1e-12, 1e-3]; thermal specific energy log-uniform
@@ -360,7 +361,9 @@ def c4_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None):
     inside the EoS validity region); W uniform [1, 10]; magnetisation
     sigma = b^2/rho log-uniform [1e-4, 10]; random unit directions of v and B
     in the physical metric; gamma_ij = psi^4 (delta_ij + h_ij), psi^4 in [1,2],
-    |h_ij| <= 0.1; alpha in [0.5, 1], |beta| <= 0.3 (unused by con2prim)."""
+    |h_ij| <= 0.1; alpha in [0.5, 1], |beta| <= 0.3 (unused by con2prim).
+    The ranges (log10 bounds) can be changed; log_wm1 = (lo, hi) draws W - 1
+    log-uniform instead, and a fraction static_frac of the states gets v = 0."""
     if shape is None:
         shape = (ncell, 1, 1)
     nx, ny, nz = shape
@@ -394,10 +397,15 @@ def c4_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None):
         nrm = np.sqrt(np.einsum("i...,ij...,j...->...", d, g, d))
         return d / nrm
 
-    rho = 10.0 ** r.uniform(-12.0, -3.0, sh)
-    epsth = 10.0 ** r.uniform(-6.0, 0.0, sh)
-    W = r.uniform(1.0, 10.0, sh)
-    sig = 10.0 ** r.uniform(-4.0, 1.0, sh)
+    rho = 10.0 ** r.uniform(log_rho[0], log_rho[1], sh)
+    epsth = 10.0 ** r.uniform(log_eps[0], log_eps[1], sh)
+    if log_wm1 is None:
+        W = r.uniform(1.0, 10.0, sh)
+    else:
+        W = 1.0 + 10.0 ** r.uniform(log_wm1[0], log_wm1[1], sh)
+    if static_frac > 0.0:
+        W = np.where(r.uniform(0.0, 1.0, sh) < static_frac, 1.0, W)
+    sig = 10.0 ** r.uniform(log_sigma[0], log_sigma[1], sh)
     vdir = unit_dir()
     vmag = np.sqrt(1.0 - 1.0 / (W * W))
     v = vmag * vdir

@@ -29,13 +29,20 @@ def init_params(seed):
     return p
 
 
-def training_set(ncell, seed, eos_cfg=I.EOS_PWP3, device="cuda"):
+# sampling of the star workloads (ideal gas, static to mildly relativistic flow,
+# weak fields, the star's density range and its atmosphere)
+STAR_SAMPLING = dict(log_rho=(-12.0, -2.5), log_eps=(-11.0, 0.0), log_sigma=(-7.0, -1.0), log_wm1=(-14.0, -1.0),
+                     static_frac=0.1)
+
+
+def training_set(ncell, seed, eos_cfg=I.EOS_PWP3, device="cuda", **sampling):
     """(X, T) device tensors for `ncell` random con2prim states: raw features of
     the conserved state and the logit targets of the plain solver's roots.
-    Rows of atmosphere states are NaN (skipped by the kernels)."""
+    Rows of atmosphere states are NaN (skipped by the kernels).  `sampling`
+    overrides the state distribution (inputs.c4_cells)."""
     import torch
 
-    ip, U, P, EM = I.c4_cells(seed=seed, ncell=ncell)
+    ip, U, P, EM = I.c4_cells(seed=seed, ncell=ncell, **sampling)
     pt = mhd.patch_of(ip)
     eos = mhd.make_eos(eos_cfg)
     Ud = torch.as_tensor(U).to(device)

@@ -43,7 +43,14 @@ class Params(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("strip", C.c_int32), ("reserved", C.c_int32 * 7)]
+    _fields_ = [("strip", C.c_int32), ("block_threads", C.c_int32), ("grid_per_cu", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
+
+
+class Box(C.Structure):
+    _fields_ = [("patch", Patch), ("U", C.c_void_p), ("Us", C.c_void_p), ("P", C.c_void_p), ("k", C.c_void_p),
+                ("acc", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("flags", C.c_void_p)]
 
 
 class KernelTime(C.Structure):
@@ -76,6 +83,16 @@ SIGNATURES = {
     "mhd_mlp_grad_workspace_size": (C.c_size_t, [C.c_int64]),
     "mhd_mlp_grad": (C.c_int, [_vp, _vp, _vp, C.c_int64, _vp, _vp, _vp, C.c_size_t, _vp]),
     "mhd_mlp_adam": (C.c_int, [_vp, _vp, _vp, _vp, C.c_int, C.c_float, C.c_float, C.c_float, C.c_float, _vp]),
+    "mhd_level_create": (C.c_int, [C.POINTER(Box), C.c_int, C.POINTER(Params), C.POINTER(Eos),
+                                   C.POINTER(C.c_void_p)]),
+    "mhd_level_destroy": (C.c_int, [_vp]),
+    "mhd_level_set_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
+    "mhd_level_get_tuning": (C.c_int, [_vp, C.POINTER(Tuning)]),
+    "mhd_level_rhs": (C.c_int, [_vp, C.c_int, _vp, _vp, _vp]),
+    "mhd_level_rk4_step": (C.c_int, [_vp, C.c_double, _vp, C.c_int, _vp]),
+    "mhd_level_autotune": (C.c_int, [_vp, C.c_double, _vp, C.POINTER(Tuning)]),
+    "mhd_level_learned_workspace_size": (C.c_size_t, [_vp]),
+    "mhd_level_set_learned": (C.c_int, [_vp, _vp, _vp, C.c_size_t]),
     "mhd_profile_start": (C.c_int, []),
     "mhd_profile_stop": (C.c_int, [C.POINTER(KernelTime), C.c_int, C.POINTER(C.c_int)]),
 }
@@ -249,16 +266,89 @@ def mlp_adam(mlp, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream
                               float(eps), _stream(stream)))
 
 
-def set_tuning(strip):
+def _tuning(strip=4, block_threads=256, grid_per_cu=0):
     t = Tuning()
-    t.strip = int(strip)
-    _check(lib().mhd_set_tuning(C.byref(t)))
+    t.strip, t.block_threads, t.grid_per_cu = int(strip), int(block_threads), int(grid_per_cu)
+    return t
+
+
+def _tuning_dict(t):
+    return {"strip": t.strip, "block_threads": t.block_threads, "grid_per_cu": t.grid_per_cu}
+
+
+def set_tuning(strip):
+    _check(lib().mhd_set_tuning(C.byref(_tuning(strip))))
 
 
 def get_tuning():
     t = Tuning()
     _check(lib().mhd_get_tuning(C.byref(t)))
     return {"strip": t.strip}
+
+
+class Level:
+    """A batched level (mhd_level_*).  `boxes` is a list of dicts with the
+    patch (mhd_patch_t) and device tensors U, Us, P, k, acc, ws and
+    optionally flags; the tensors are kept alive with the level."""
+
+    def __init__(self, boxes, params, eos):
+        self._keep = boxes
+        arr = (Box * len(boxes))()
+        for b, d in enumerate(boxes):
+            arr[b].patch = d["patch"]
+            for name in ("U", "Us", "P", "k", "acc"):
+                setattr(arr[b], name, _ptr(d[name]))
+            arr[b].workspace = _ptr(d["ws"])
+            arr[b].workspace_bytes = d["ws"].numel() * d["ws"].element_size()
+            arr[b].flags = _ptr(d.get("flags"))
+        self._params, self._eos = params, eos
+        h = C.c_void_p()
+        _check(lib().mhd_level_create(arr, len(boxes), C.byref(params), C.byref(eos), C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            lib().mhd_level_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_tuning(self, strip=4, block_threads=256, grid_per_cu=0):
+        _check(lib().mhd_level_set_tuning(self.h, C.byref(_tuning(strip, block_threads, grid_per_cu))))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().mhd_level_get_tuning(self.h, C.byref(t)))
+        return _tuning_dict(t)
+
+    def rhs(self, src=0, max_speed=None, stats=None, stream=None):
+        _check(lib().mhd_level_rhs(self.h, int(src), _ptr(max_speed), _ptr(stats), _stream(stream)))
+
+    def rk4_step(self, dt, max_speed=None, use_graph=False, stream=None):
+        _check(lib().mhd_level_rk4_step(self.h, float(dt), _ptr(max_speed), int(bool(use_graph)), _stream(stream)))
+
+    def set_learned(self, mlp, device="cuda"):
+        """Use the learned con2prim guess (mlp: device float32 parameter block), or
+        the bracketed solver (mlp = None)."""
+        import torch
+
+        if mlp is None:
+            _check(lib().mhd_level_set_learned(self.h, None, None, 0))
+            self._lws = self._mlp = None
+            return
+        n = int(lib().mhd_level_learned_workspace_size(self.h))
+        self._lws = torch.empty((n + 7) // 8, dtype=torch.float64, device=device)
+        self._mlp = mlp
+        _check(lib().mhd_level_set_learned(self.h, _ptr(mlp), _ptr(self._lws), self._lws.numel() * 8))
+
+    def autotune(self, dt, stream=None):
+        t = Tuning()
+        _check(lib().mhd_level_autotune(self.h, float(dt), _stream(stream), C.byref(t)))
+        return _tuning_dict(t)
 
 
 def profile_start():

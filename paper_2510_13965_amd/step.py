@@ -29,12 +29,26 @@ class PatchRun:
         self.ws = mhd.workspace_for(self.patch, device)
         self.vmax = torch.zeros(1, dtype=torch.float64, device=device)
         self.stats = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device=device)
+        self.mlp = None
+        self.lws = None
+
+    def use_learned(self, mlp):
+        """con2prim with the learned guess (mlp: device parameter block), or the
+        bracketed solver (None)."""
+        self.mlp = mlp
+        if mlp is not None and self.lws is None:
+            n = mhd.con2prim_learned_workspace_size(self.patch)
+            self.lws = torch.empty((n + 7) // 8, dtype=torch.float64, device=self.dev)
 
     def rhs_eval(self, U):
         """con2prim on the padded patch, then L(U) into self.k."""
         if self.periodic:
             mhd.fill_ghosts_periodic(self.patch, U, I.NU, self.stream)
-        mhd.con2prim(self.patch, self.eos, U, self.P, self.flags, None, self.stats, self.stream)
+        if self.mlp is not None:
+            mhd.con2prim_learned(self.patch, self.eos, self.mlp, U, self.P, self.lws, self.flags, None, self.stats,
+                                 self.stream)
+        else:
+            mhd.con2prim(self.patch, self.eos, U, self.P, self.flags, None, self.stats, self.stream)
         mhd.rhs(self.patch, self.par, self.eos, U, self.P, self.k, self.vmax, self.ws, self.stream)
 
     def step(self, dt):
@@ -47,3 +61,31 @@ class PatchRun:
             mhd.rk_stage(self.patch, I.NU, s, dt, self.Un, self.k, self.acc, nxt, self.stream)
         if self.periodic:
             mhd.fill_ghosts_periodic(self.patch, self.Un, I.NU, self.stream)
+
+
+class LevelRun:
+    """Device buffers of a list of boxes and their batched level (mhd_level_*).
+    Us starts as a copy of U so the stage states carry the (frozen) ghosts."""
+
+    def __init__(self, ipatches, states, eos_cfg, par_cfg, device="cuda", flags=True):
+        self.eos = mhd.make_eos(eos_cfg)
+        self.par = mhd.make_params(par_cfg)
+        self.boxes = []
+        for ip, U0 in zip(ipatches, states):
+            pt = mhd.patch_of(ip)
+            U = torch.as_tensor(U0, dtype=torch.float64).to(device).contiguous()
+            d = dict(patch=pt, ip=ip, U=U, Us=U.clone(), k=torch.zeros_like(U), acc=torch.zeros_like(U),
+                     P=torch.zeros((I.NP,) + tuple(ip.shape), dtype=torch.float64, device=device),
+                     ws=mhd.workspace_for(pt, device))
+            if flags:
+                d["flags"] = torch.zeros(tuple(ip.shape), dtype=torch.uint8, device=device)
+            self.boxes.append(d)
+        self.level = mhd.Level(self.boxes, self.par, self.eos)
+
+    @property
+    def ninterior(self):
+        return sum(b["ip"].ninterior for b in self.boxes)
+
+    @property
+    def npts(self):
+        return sum(b["ip"].npts for b in self.boxes)

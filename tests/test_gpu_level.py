@@ -1,0 +1,215 @@
+"""Batched levels (mhd_level_*): uneven boxes through one persistent kernel per
+phase, eager or as a replayed hipGraph, under every tuning.
+
+The per-point arithmetic is the single-patch kernels' own, so the bar is
+bitwise equality with per-box calls of mhd_con2prim / mhd_rhs / mhd_rk_stage
+(themselves parity-tested against the oracle); one box is also compared with
+the oracle directly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2510_13965_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2510_13965_amd import mhd
+
+    mhd.lib()
+    return torch.device("cuda")
+
+
+@pytest.fixture(scope="module")
+def level_states(dev):
+    """Eight uneven boxes on three levels of the star, cons built on the device."""
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    boxes = I.c3_boxes(seed=I.SEED0 + 30, nboxes=8, edges=(16, 24, 32))
+    Ab = I.star_field_amplitude()
+    eos = mhd.make_eos(I.EOS_IDEAL2)
+    out = []
+    for b in boxes:
+        ip, U, P, EM = I.c3_box_state(b, Ab)
+        Ud = torch.as_tensor(U).cuda()
+        mhd.prim2con(mhd.patch_of(ip), eos, Ud, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
+        out.append((ip, Ud.cpu().numpy()))
+    say("level boxes", [ip.n for ip, _ in out])
+    return out
+
+
+def per_box_rhs(states):
+    import torch
+    from paper_2510_13965_amd.step import PatchRun
+
+    res = []
+    vmax = 0.0
+    for ip, U in states:
+        r = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS)
+        r.rhs_eval(r.Un)
+        torch.cuda.synchronize()
+        vmax = max(vmax, float(r.vmax.item()))
+        res.append(dict(k=r.k.cpu().numpy(), P=r.P.cpu().numpy(), flags=r.flags.cpu().numpy(), U=r.Un.cpu().numpy()))
+    return res, vmax
+
+
+def level_rhs(run, src=0):
+    import torch
+
+    ms = torch.zeros(1, dtype=torch.float64, device="cuda")
+    run.level.rhs(src, ms)
+    torch.cuda.synchronize()
+    return [dict(k=b["k"].cpu().numpy(), P=b["P"].cpu().numpy(), flags=b["flags"].cpu().numpy(),
+                 U=b["U"].cpu().numpy()) for b in run.boxes], float(ms.item())
+
+
+def assert_same(ref, got, tag):
+    for b, (r, g) in enumerate(zip(ref, got)):
+        for key in r:
+            assert np.array_equal(r[key], g[key]), (tag, b, key)
+
+
+def test_level_rhs_bitwise_equals_per_box(level_states):
+    from paper_2510_13965_amd.step import LevelRun
+
+    say("case level rhs vs per-box, 8 boxes")
+    ref, vref = per_box_rhs(level_states)
+    run = LevelRun([ip for ip, _ in level_states], [U for _, U in level_states], I.EOS_IDEAL2, I.PARAMS)
+    got, v = level_rhs(run)
+    assert_same(ref, got, "default tuning")
+    assert v == vref
+
+
+@pytest.mark.parametrize("tun", [dict(strip=1, block_threads=64, grid_per_cu=0),
+                                 dict(strip=16, block_threads=128, grid_per_cu=4),
+                                 dict(strip=4, block_threads=256, grid_per_cu=1)])
+def test_level_rhs_tuning_invariant(level_states, tun):
+    from paper_2510_13965_amd.step import LevelRun
+
+    say("case level rhs tuning", tun)
+    ref, vref = per_box_rhs(level_states)
+    run = LevelRun([ip for ip, _ in level_states], [U for _, U in level_states], I.EOS_IDEAL2, I.PARAMS)
+    run.level.set_tuning(**tun)
+    assert run.level.get_tuning() == tun
+    got, v = level_rhs(run)
+    assert_same(ref, got, str(tun))
+    assert v == vref
+
+
+def test_level_rk4_eager_and_graph_replays(level_states):
+    """Two RK4 steps per-box, eager level and graph level; the graph is
+    replayed with eager work between replays and checked after every replay."""
+    import torch
+    from paper_2510_13965_amd.step import LevelRun, PatchRun
+
+    say("case level rk4 eager/graph, 8 boxes, 2 steps")
+    dt = 0.25 * 0.25
+    ips = [ip for ip, _ in level_states]
+    Us = [U for _, U in level_states]
+    boxes = [PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS) for ip, U in level_states]
+    eager = LevelRun(ips, Us, I.EOS_IDEAL2, I.PARAMS)
+    graph = LevelRun(ips, Us, I.EOS_IDEAL2, I.PARAMS)
+    ms_e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ms_g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    for step in range(3):
+        for r in boxes:
+            r.step(dt)
+        eager.level.rk4_step(dt, ms_e)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            graph.level.rk4_step(dt, ms_g, use_graph=True, stream=stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for b, r in enumerate(boxes):
+            ref = r.Un.cpu().numpy()
+            assert np.array_equal(ref, eager.boxes[b]["U"].cpu().numpy()), ("eager", step, b)
+            assert np.array_equal(ref, graph.boxes[b]["U"].cpu().numpy()), ("graph", step, b)
+        assert float(ms_e.item()) == float(ms_g.item()) > 0.0
+        say("step", step, "ok, max speed", float(ms_e.item()))
+
+
+def test_level_autotune_keeps_results(level_states):
+    import torch
+    from paper_2510_13965_amd.step import LevelRun
+
+    say("case level autotune")
+    ref, vref = per_box_rhs(level_states)
+    run = LevelRun([ip for ip, _ in level_states], [U for _, U in level_states], I.EOS_IDEAL2, I.PARAMS)
+    U0 = [b["U"].clone() for b in run.boxes]
+    t = run.level.autotune(0.0625)
+    torch.cuda.synchronize()
+    say("autotune chose", t)
+    assert t["block_threads"] in (64, 128, 256) and t["strip"] in (1, 4, 16) and t["grid_per_cu"] in (0, 4, 16)
+    for b, u in zip(run.boxes, U0):
+        assert torch.equal(b["U"], u)   # the tuner only reads U
+    got, v = level_rhs(run)
+    assert_same(ref, got, "after autotune")
+
+
+def test_level_box_against_oracle(orc, level_states):
+    """The level's RHS on its smallest box against the FP64 oracle (1e-10 per field)."""
+    from paper_2510_13965_amd.step import LevelRun
+
+    ip, U = min(level_states, key=lambda s: s[0].npts)
+    say("case level box vs oracle", ip.n)
+    run = LevelRun([ip], [U], I.EOS_IDEAL2, I.PARAMS)
+    got, _ = level_rhs(run)
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    e = orc.make_eos(I.EOS_IDEAL2)
+    Uo = U.copy()
+    Po = np.zeros((I.NP,) + ip.shape)
+    orc.con2prim(g, e, Uo, Po, None, None)
+    ko = np.zeros_like(U)
+    orc.rhs(g, orc.make_par(I.PARAMS), e, Uo, Po, ko)
+    sl = (slice(None),) + ip.interior()
+    kg, ko = got[0]["k"][sl], ko[sl]
+    for f in range(I.NU):
+        m = np.abs(ko[f]).max()
+        if m > 0:
+            assert np.abs(kg[f] - ko[f]).max() <= 1e-10 * m, f
+
+
+def test_level_learned_equals_per_box_learned(level_states):
+    """The level's con2prim with the learned guess (one fallback queue for all
+    boxes) against per-box mhd_con2prim_learned + mhd_rhs: bitwise."""
+    import torch
+    from paper_2510_13965_amd import mhd
+    from paper_2510_13965_amd.step import LevelRun, PatchRun
+
+    say("case level learned vs per-box learned")
+    r = np.random.default_rng(13)
+    p = np.zeros(mhd.MLP_NBLOCK, dtype=np.float32)
+    p[:mhd.MLP_NPARAM] = r.normal(0.0, 0.05, mhd.MLP_NPARAM)
+    p[4866:4874] = 0.0
+    p[4874:4882] = 0.2
+    p[4864] = 3.0   # bias the guesses towards mu ~ 1/h0, where most points sit
+    p[4865] = 3.0
+    prm = torch.as_tensor(p).cuda()
+    ref = []
+    for ip, U in level_states:
+        b = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS)
+        ws = torch.empty((mhd.con2prim_learned_workspace_size(b.patch) + 7) // 8, dtype=torch.float64, device="cuda")
+        mhd.con2prim_learned(b.patch, b.eos, prm, b.Un, b.P, ws, b.flags, None, b.stats)
+        mhd.rhs(b.patch, b.par, b.eos, b.Un, b.P, b.k, b.vmax, b.ws)
+        torch.cuda.synchronize()
+        ref.append(dict(k=b.k.cpu().numpy(), P=b.P.cpu().numpy(), flags=b.flags.cpu().numpy(), U=b.Un.cpu().numpy()))
+    run = LevelRun([ip for ip, _ in level_states], [U for _, U in level_states], I.EOS_IDEAL2, I.PARAMS)
+    run.level.set_learned(prm)
+    got, _ = level_rhs(run)
+    assert_same(ref, got, "learned")
+    fb = np.mean([((g["flags"] & 32) != 0).mean() for g in got])
+    say("fallback share with these weights %.3f" % fb)
