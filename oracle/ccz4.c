@@ -238,6 +238,7 @@ void orc_ccz4_point(const orc_par* par, const double* U, const double* P, int64_
   /* matter */
   if (par->couple_matter) {
     orc_matter_point(U, P, N, p, gdn, sqrtg, &E, Sm, Sij);
+    if (par->evolve_m1) orc_m1_matter(U, P, N, p, &E, Sm, Sij);
     for (i = 0; i < 3; ++i)
       for (j = 0; j < 3; ++j) Str += gup[i][j] * Sij[i][j];
   }

@@ -1,0 +1,405 @@
+/*
+ * Oracle (test infrastructure only): grey M1 neutrino moments.
+ *
+ * Per species the evolved fields are the densitized energy and flux
+ * (Ebar, Fbar_i) = sqrt(gamma) (E, F_i), at U indices 32 + 4 s (s = 0, 1, 2).
+ * Per point and species the auxiliary inputs are kappa_a, kappa_s and eta at
+ * aux[(3 s + c) N + p], c = 0, 1, 2.
+ *
+ *   closure    Minerbo (Sec. 2.3): P_ij = d_thin P^thin_ij + d_thick P^thick_ij,
+ *              d_thick = 3(1 - chi)/2, chi(xi) = 1/3 + xi^2 (6 - 2 xi + 6 xi^2)/15,
+ *              xi the root on [0, 1] of R(xi) = (xi^2 J^2 - H_a H^a)/E^2, with J and
+ *              H from the fluid-frame projections; Brent's method to full precision
+ *   fluxes     d_k-flux of Ebar: -beta^k Ebar + alpha Fbar^k; of Fbar_i:
+ *              -beta^k Fbar_i + alpha Pbar^k_i (Sec. 2.3)
+ *   speeds     Minerbo interpolation of the thin and thick speeds (App. B)
+ *   interfaces HO/LO flux splitting with the limiter Phi, the opacity switch
+ *              A = tanh(1/(kappa dx)) and the odd-even fix (Sec. 3.4)
+ *   sources    geometric terms of the Ebar, Fbar_i equations and the collision
+ *              terms alpha sqrt(gamma) (S_n, S_i); the fluid loses what the
+ *              radiation gains (tau and S_i get -alpha sqrt(gamma) sum S)
+ *   matter     E, S_i, S_ij of the radiation for the CCZ4 matter terms
+ *
+ * Readings (where the text is silent or garbled): the low-order flux is the
+ * Lax-Friedrichs flux 1/2 (F_i + F_i+1) - lambda/2 (u_i+1 - u_i); lambda at an
+ * interface is the larger of the two point speeds; Phi = 0 when u_i+1 = u_i;
+ * Phi and the odd-even test act per field; P^thin and the thin speed are dropped
+ * when F_k F^k = 0; xi = 1 when R(1) <= 0 and xi = 0 when R(0) >= 0; a negative
+ * argument of the thick-speed square root counts as 0; kappa = 0 gives A = 1.
+ */
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include "orc.h"
+
+static const int S6m[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+
+typedef struct {
+  double gdn[3][3], gup[3][3], sqrtg, chi;
+} m1_metric;
+
+static void m1_metric_at(const double* U, int64_t N, int64_t p, m1_metric* m) {
+  double g[3][3], gi[3][3], det;
+  int i, j;
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) g[i][j] = U[S6m[i][j] * N + p];
+  m->chi = U[12 * N + p];
+  det = g[0][0] * (g[1][1] * g[2][2] - g[1][2] * g[2][1]) - g[0][1] * (g[1][0] * g[2][2] - g[1][2] * g[2][0]) +
+        g[0][2] * (g[1][0] * g[2][1] - g[1][1] * g[2][0]);
+  gi[0][0] = (g[1][1] * g[2][2] - g[1][2] * g[2][1]) / det;
+  gi[0][1] = (g[0][2] * g[2][1] - g[0][1] * g[2][2]) / det;
+  gi[0][2] = (g[0][1] * g[1][2] - g[0][2] * g[1][1]) / det;
+  gi[1][1] = (g[0][0] * g[2][2] - g[0][2] * g[2][0]) / det;
+  gi[1][2] = (g[0][2] * g[1][0] - g[0][0] * g[1][2]) / det;
+  gi[2][2] = (g[0][0] * g[1][1] - g[0][1] * g[1][0]) / det;
+  gi[1][0] = gi[0][1];
+  gi[2][0] = gi[0][2];
+  gi[2][1] = gi[1][2];
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) {
+      m->gdn[i][j] = g[i][j] / m->chi;
+      m->gup[i][j] = m->chi * gi[i][j];
+    }
+  m->sqrtg = sqrt(det / (m->chi * m->chi * m->chi));
+}
+
+/* one species at one point, undensitized */
+typedef struct {
+  double E, F[3], Fu[3], F2, v[3], vd[3], W, vF;
+  double gdn[3][3], gup[3][3];
+} m1_state;
+
+double orc_m1_eddington(double xi) { return 1.0 / 3.0 + xi * xi * (6.0 - 2.0 * xi + 6.0 * xi * xi) / 15.0; }
+
+/* P_ij, J, H_i (lower), H.n and H_a H^a for the Eddington factor chi */
+static void closure_eval(const m1_state* s, double chi, double P[3][3], double* J, double H[3], double* Hn,
+                         double* HH) {
+  const double W = s->W, W2 = W * W;
+  const double dthick = 1.5 * (1.0 - chi), dthin = 1.0 - dthick;
+  double Jth, Hth[3], Pv[3], vPv = 0.0, hh = 0.0;
+  int i, j;
+  Jth = 3.0 / (2.0 * W2 + 1.0) * ((2.0 * W2 - 1.0) * s->E - 2.0 * W2 * s->vF);
+  for (i = 0; i < 3; ++i)
+    Hth[i] = s->F[i] / W + W * s->vd[i] / (2.0 * W2 + 1.0) * ((4.0 * W2 + 1.0) * s->vF - 4.0 * W2 * s->E);
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) {
+      double thin = s->F2 > 0.0 ? s->E * s->F[i] * s->F[j] / s->F2 : 0.0;
+      double thick = 4.0 / 3.0 * Jth * W2 * s->vd[i] * s->vd[j] + W * (Hth[i] * s->vd[j] + Hth[j] * s->vd[i]) +
+                     1.0 / 3.0 * Jth * s->gdn[i][j];
+      P[i][j] = dthin * thin + dthick * thick;
+    }
+  for (i = 0; i < 3; ++i) {
+    Pv[i] = 0.0;
+    for (j = 0; j < 3; ++j) Pv[i] += P[i][j] * s->v[j];
+    vPv += s->v[i] * Pv[i];
+  }
+  *J = W2 * (s->E - 2.0 * s->vF + vPv);
+  for (i = 0; i < 3; ++i) H[i] = W * (s->F[i] - Pv[i] - *J * s->vd[i]);
+  *Hn = W * (*J - s->E + s->vF);
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) hh += s->gup[i][j] * H[i] * H[j];
+  *HH = hh - *Hn * *Hn;
+}
+
+static double R_of(const m1_state* s, double xi) {
+  double P[3][3], J, H[3], Hn, HH;
+  closure_eval(s, orc_m1_eddington(xi), P, &J, H, &Hn, &HH);
+  return (xi * xi * J * J - HH) / (s->E * s->E);
+}
+
+/* Brent's method (Brent 1973, ch. 4) for R on [a, b] with R(a) < 0 < R(b) */
+static double brent_xi(const m1_state* s, double a, double b, double fa, double fb, int* iters) {
+  double c = a, fc = fa, d = b - a, e = d;
+  int it;
+  for (it = 0; it < 200; ++it) {
+    double tol, m, p, q, r, t;
+    if ((fb > 0.0 && fc > 0.0) || (fb < 0.0 && fc < 0.0)) {
+      c = a; fc = fa; d = b - a; e = d;
+    }
+    if (fabs(fc) < fabs(fb)) {
+      a = b; b = c; c = a;
+      fa = fb; fb = fc; fc = fa;
+    }
+    tol = 2.0 * DBL_EPSILON * fabs(b) + 0.5 * DBL_MIN;
+    m = 0.5 * (c - b);
+    if (fabs(m) <= tol || fb == 0.0) break;
+    if (fabs(e) < tol || fabs(fa) <= fabs(fb)) {
+      d = m; e = m;
+    } else {
+      t = fb / fa;
+      if (a == c) {
+        p = 2.0 * m * t;
+        q = 1.0 - t;
+      } else {
+        q = fa / fc;
+        r = fb / fc;
+        p = t * (2.0 * m * q * (q - r) - (b - a) * (r - 1.0));
+        q = (q - 1.0) * (r - 1.0) * (t - 1.0);
+      }
+      if (p > 0.0) q = -q; else p = -p;
+      t = e;
+      e = d;
+      if (2.0 * p < 3.0 * m * q - fabs(tol * q) && p < fabs(0.5 * t * q)) {
+        d = p / q;
+      } else {
+        d = m; e = m;
+      }
+    }
+    a = b;
+    fa = fb;
+    if (fabs(d) > tol) b += d;
+    else b += (m > 0.0 ? tol : -tol);
+    fb = R_of(s, b);
+  }
+  if (iters) *iters = it;
+  return b;
+}
+
+static void state_init(m1_state* s, double E, const double F[3], const double v[3], double W,
+                       const double gdn[3][3], const double gup[3][3]) {
+  int i, j;
+  s->E = E;
+  s->W = W;
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) {
+      s->gdn[i][j] = gdn[i][j];
+      s->gup[i][j] = gup[i][j];
+    }
+  s->F2 = 0.0;
+  s->vF = 0.0;
+  for (i = 0; i < 3; ++i) {
+    s->F[i] = F[i];
+    s->v[i] = v[i];
+  }
+  for (i = 0; i < 3; ++i) {
+    s->Fu[i] = 0.0;
+    s->vd[i] = 0.0;
+    for (j = 0; j < 3; ++j) {
+      s->Fu[i] += gup[i][j] * F[j];
+      s->vd[i] += gdn[i][j] * v[j];
+    }
+  }
+  for (i = 0; i < 3; ++i) {
+    s->F2 += s->Fu[i] * F[i];
+    s->vF += F[i] * v[i];
+  }
+}
+
+/* xi of the closure, and P_ij, J, H_i at it */
+static double closure(const m1_state* s, double P[3][3], double* J, double H[3], double* chi_out, int* iters) {
+  double xi, r0, r1, Hn, HH;
+  if (iters) *iters = 0;
+  r0 = R_of(s, 0.0);
+  r1 = R_of(s, 1.0);
+  if (r1 <= 0.0) xi = 1.0;
+  else if (r0 >= 0.0) xi = 0.0;
+  else xi = brent_xi(s, 0.0, 1.0, r0, r1, iters);
+  *chi_out = orc_m1_eddington(xi);
+  closure_eval(s, *chi_out, P, J, H, &Hn, &HH);
+  return xi;
+}
+
+double orc_m1_closure(double E, const double F[3], const double v[3], double W, const double gdn6[6],
+                      const double gup6[6], double P6[6], double* J, double H[3], double* chi, int* iters) {
+  double gdn[3][3], gup[3][3], P[3][3], xi;
+  m1_state s;
+  int i, j;
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) {
+      gdn[i][j] = gdn6[S6m[i][j]];
+      gup[i][j] = gup6[S6m[i][j]];
+    }
+  state_init(&s, E, F, v, W, gdn, gup);
+  xi = closure(&s, P, J, H, chi, iters);
+  for (i = 0; i < 3; ++i)
+    for (j = i; j < 3; ++j) P6[S6m[i][j]] = P[i][j];
+  return xi;
+}
+
+/* point speed along axis d (Minerbo interpolation of the thin and thick speeds) */
+static double speed(const m1_state* s, double chi, double alp, double beta_d, int d) {
+  const double dthick = 1.5 * (1.0 - chi), dthin = 1.0 - dthick, W2 = s->W * s->W;
+  double lthin = fabs(beta_d), lthick, a;
+  if (s->F2 > 0.0) lthin += alp * fmax(fabs(s->Fu[d]) / sqrt(s->F2), s->E * fabs(s->Fu[d]) / s->F2);
+  a = (2.0 * W2 + 1.0) * s->gup[d][d] - 2.0 * W2 * s->v[d] * s->v[d];
+  lthick = fabs(beta_d) +
+           alp * fmax((2.0 * W2 * fabs(s->v[d]) + sqrt(fmax(a, 0.0))) / (2.0 * W2 + 1.0), fabs(s->v[d]));
+  return dthin * lthin + dthick * lthick;
+}
+
+/* interface value between p and p + st of one field (HO/LO splitting) */
+static double holo(const double* u, const double* f, const double* lam, const double* ka, const double* ks,
+                   int64_t p, int64_t st, double h) {
+  const double um = u[p - st], u0 = u[p], u1 = u[p + st], u2 = u[p + 2 * st];
+  const double fho = 0.5 * (f[p] + f[p + st]);
+  const double lh = fmax(lam[p], lam[p + st]);
+  const double flo = fho - 0.5 * lh * (u1 - u0);
+  const double du = u1 - u0;
+  double phi = 0.0, A, kap;
+  if (du != 0.0) phi = fmax(0.0, fmin(1.0, fmin(2.0 * (u0 - um) / du, 2.0 * (u2 - u1) / du)));
+  kap = 0.5 * (ka[p] + ka[p + st] + ks[p] + ks[p + st]);
+  A = kap > 0.0 ? tanh(1.0 / (kap * h)) : 1.0;
+  if ((u0 - um) * du < 0.0 && du * (u2 - u1) < 0.0) A = 1.0;
+  return fho - A * (1.0 - phi) * (fho - flo);
+}
+
+static int64_t npts(const orc_grid* g) {
+  return (int64_t)(g->n[0] + 2 * g->ng) * (g->n[1] + 2 * g->ng) * (g->n[2] + 2 * g->ng);
+}
+
+static void point_state(const double* U, const double* P, int64_t N, int64_t p, int sp, const m1_metric* m,
+                        m1_state* s) {
+  double F[3], v[3];
+  int i;
+  for (i = 0; i < 3; ++i) {
+    F[i] = U[(33 + 4 * sp + i) * N + p] / m->sqrtg;
+    v[i] = P[(3 + i) * N + p];
+  }
+  state_init(s, U[(32 + 4 * sp) * N + p] / m->sqrtg, F, v, P[6 * N + p], m->gdn, m->gup);
+}
+
+/* radiation part of the CCZ4 matter terms at p: E, S_i, S_ij are incremented */
+void orc_m1_matter(const double* U, const double* P, int64_t N, int64_t p, double* E, double S[3],
+                   double Sij[3][3]) {
+  m1_metric m;
+  int sp, i, j;
+  m1_metric_at(U, N, p, &m);
+  for (sp = 0; sp < 3; ++sp) {
+    m1_state s;
+    double Pij[3][3], J, H[3], chi;
+    point_state(U, P, N, p, sp, &m, &s);
+    closure(&s, Pij, &J, H, &chi, NULL);
+    *E += s.E;
+    for (i = 0; i < 3; ++i) {
+      S[i] += s.F[i];
+      for (j = 0; j < 3; ++j) Sij[i][j] += Pij[i][j];
+    }
+  }
+}
+
+/* M1 part of L(U) at interior points: rhs[32..43] written; the collision
+ * exchange is subtracted from rhs[24] (taubar) and rhs[25..27] (Sbar_i), which
+ * must already hold the fluid part.  max_speed (may be NULL) gets the max of
+ * the M1 point speeds. */
+void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
+                double* rhs, double* max_speed) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  const int64_t st[3] = {1, Nx, Nx * Ny};
+  /* per species and axis: 4 point fluxes and the point speed */
+  double* FL = (double*)malloc(sizeof(double) * 3 * 3 * 4 * N);
+  double* LM = (double*)malloc(sizeof(double) * 3 * 3 * N);
+  double vmax = 0.0;
+  int64_t p;
+
+#pragma omp parallel for schedule(static)
+  for (p = 0; p < N; ++p) {
+    m1_metric m;
+    int sp, d, i, j;
+    const double alp = U[18 * N + p];
+    m1_metric_at(U, N, p, &m);
+    for (sp = 0; sp < 3; ++sp) {
+      m1_state s;
+      double Pij[3][3], J, H[3], chi;
+      const double Eb = U[(32 + 4 * sp) * N + p];
+      point_state(U, P, N, p, sp, &m, &s);
+      closure(&s, Pij, &J, H, &chi, NULL);
+      for (d = 0; d < 3; ++d) {
+        const double bd = U[(19 + d) * N + p];
+        double* f = FL + ((sp * 3 + d) * 4) * N;
+        f[p] = -bd * Eb + alp * m.sqrtg * s.Fu[d];
+        for (i = 0; i < 3; ++i) {
+          double Pdi = 0.0;
+          for (j = 0; j < 3; ++j) Pdi += m.gup[d][j] * Pij[j][i];
+          f[(1 + i) * N + p] = -bd * U[(33 + 4 * sp + i) * N + p] + alp * m.sqrtg * Pdi;
+        }
+        LM[(sp * 3 + d) * N + p] = speed(&s, chi, alp, bd, d);
+      }
+    }
+  }
+
+#pragma omp parallel for collapse(2) schedule(static) reduction(max : vmax)
+  for (int64_t k = ng; k < Nz - ng; ++k)
+    for (int64_t j = ng; j < Ny - ng; ++j)
+      for (int64_t i = ng; i < Nx - ng; ++i) {
+        const int64_t q = i + Nx * (j + Ny * k);
+        const double alp = U[18 * N + q], Kh = U[13 * N + q], Th = U[14 * N + q];
+        m1_metric m;
+        double dalp[3], dchi[3], dbeta[3][3], dgt[3][3][3];
+        int sp, d, c, a, b, e2;
+        m1_metric_at(U, N, q, &m);
+        for (d = 0; d < 3; ++d) {
+          dalp[d] = orc_d1(U + 18 * N, q, st[d], g->dx[d]);
+          dchi[d] = orc_d1(U + 12 * N, q, st[d], g->dx[d]);
+          for (a = 0; a < 3; ++a) dbeta[d][a] = orc_d1(U + (19 + a) * N, q, st[d], g->dx[d]);
+          for (a = 0; a < 3; ++a)
+            for (b = 0; b < 3; ++b) dgt[d][a][b] = orc_d1(U + S6m[a][b] * N, q, st[d], g->dx[d]);
+        }
+        for (sp = 0; sp < 3; ++sp) {
+          double out[4] = {0.0, 0.0, 0.0, 0.0};
+          m1_state s;
+          double Pij[3][3], J, H[3], chi, Pbu[3][3], trP = 0.0, Fbu[3], Sn, Si[3];
+          const double ka = aux[(3 * sp) * N + q], ks = aux[(3 * sp + 1) * N + q], eta = aux[(3 * sp + 2) * N + q];
+          const double Eb = U[(32 + 4 * sp) * N + q];
+          for (d = 0; d < 3; ++d) {
+            const double* lam = LM + (sp * 3 + d) * N;
+            vmax = fmax(vmax, lam[q]);
+            for (c = 0; c < 4; ++c) {
+              const double* u = U + (32 + 4 * sp + c) * N;
+              const double* f = FL + ((sp * 3 + d) * 4 + c) * N;
+              const double* kap = aux + (3 * sp) * N;
+              const double* kas = aux + (3 * sp + 1) * N;
+              const double fr = holo(u, f, lam, kap, kas, q, st[d], g->dx[d]);
+              const double fl = holo(u, f, lam, kap, kas, q - st[d], st[d], g->dx[d]);
+              out[c] -= (fr - fl) / g->dx[d];
+            }
+          }
+          /* geometric sources */
+          point_state(U, P, N, q, sp, &m, &s);
+          closure(&s, Pij, &J, H, &chi, NULL);
+          for (a = 0; a < 3; ++a)
+            for (b = 0; b < 3; ++b) {
+              double t = 0.0;
+              for (c = 0; c < 3; ++c)
+                for (e2 = 0; e2 < 3; ++e2) t += m.gup[a][c] * m.gup[b][e2] * Pij[c][e2];
+              Pbu[a][b] = m.sqrtg * t;
+            }
+          for (a = 0; a < 3; ++a)
+            for (b = 0; b < 3; ++b) trP += m.gdn[a][b] * Pbu[a][b];
+          for (a = 0; a < 3; ++a) {
+            Fbu[a] = 0.0;
+            for (b = 0; b < 3; ++b) Fbu[a] += m.gup[a][b] * U[(33 + 4 * sp + b) * N + q];
+          }
+          {
+            double r = 0.0;
+            for (a = 0; a < 3; ++a)
+              for (b = 0; b < 3; ++b) r += alp / m.chi * Pbu[a][b] * U[(6 + S6m[a][b]) * N + q];
+            r += alp / 3.0 * trP * (Kh + 2.0 * Th);
+            for (a = 0; a < 3; ++a) r -= Fbu[a] * dalp[a];
+            out[0] += r;
+          }
+          for (a = 0; a < 3; ++a) {
+            double r = 0.0;
+            for (b = 0; b < 3; ++b)
+              for (c = 0; c < 3; ++c) r += Pbu[b][c] * dgt[a][b][c];
+            r = alp / (2.0 * m.chi) * (r - trP * dchi[a]);
+            for (b = 0; b < 3; ++b) r += U[(33 + 4 * sp + b) * N + q] * dbeta[a][b];
+            r -= Eb * dalp[a];
+            out[1 + a] += r;
+          }
+          /* collisions, and the opposite exchange with the fluid */
+          Sn = s.W * ((eta + ks * J) - (ka + ks) * (s.E - s.vF));
+          for (a = 0; a < 3; ++a) Si[a] = s.W * (eta - ka * J) * s.vd[a] - (ka + ks) * H[a];
+          out[0] += alp * m.sqrtg * Sn;
+          for (a = 0; a < 3; ++a) out[1 + a] += alp * m.sqrtg * Si[a];
+          rhs[24 * N + q] -= alp * m.sqrtg * Sn;
+          for (a = 0; a < 3; ++a) rhs[(25 + a) * N + q] -= alp * m.sqrtg * Si[a];
+          for (c = 0; c < 4; ++c) rhs[(32 + 4 * sp + c) * N + q] = out[c];
+        }
+      }
+  free(FL);
+  free(LM);
+  if (max_speed) *max_speed = fmax(*max_speed, vmax);
+  (void)par;
+}

@@ -91,6 +91,7 @@ typedef struct {
   int evolve_st;        /* CCZ4 block on/off */
   int evolve_mhd;       /* GRMHD block on/off */
   int couple_matter;    /* matter terms in the CCZ4 block on/off */
+  int evolve_m1;        /* M1 radiation (fields 32..43, aux kappa_a, kappa_s, eta) on/off */
 } orc_par;
 
 /* ---- EoS (Sec. 2.2, hybrid piecewise polytrope + thermal ideal gas) ---- */
@@ -136,6 +137,18 @@ double orc_mlp_grad(const double* prm, const float* X, const float* T, int64_t n
                     double* grad);
 void orc_mlp_adam(double* prm, const double* grad, double* m, double* v, int step, double lr,
                   double beta1, double beta2, double eps);
+
+/* ---- grey M1 radiation, three species (Sec. 2.3, 3.4, App. B) ---- */
+double orc_m1_eddington(double xi);
+double orc_m1_closure(double E, const double F[3], const double v[3], double W, const double gdn6[6],
+                      const double gup6[6], double P6[6], double* J, double H[3], double* chi, int* iters);
+void orc_m1_matter(const double* U, const double* P, int64_t N, int64_t p, double* E, double S[3],
+                   double Sij[3][3]);
+void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
+                double* rhs, double* max_speed);
+/* orc_rhs plus, if par->evolve_m1, the M1 part (U has 44 fields) */
+void orc_rhs_full(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
+                  const double* aux, double* rhs, double* max_speed);
 
 /* ---- right-hand side ---- */
 void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e,

@@ -31,7 +31,7 @@ class Par(C.Structure):
                 ("eta", C.c_double), ("beta0", C.c_double * 3), ("sigma_ko", C.c_double),
                 ("c_b", C.c_double), ("kappa_b", C.c_double), ("alpha_mp5", C.c_double),
                 ("f_beta", C.c_double), ("f_alpha_kind", C.c_int), ("evolve_st", C.c_int),
-                ("evolve_mhd", C.c_int), ("couple_matter", C.c_int)]
+                ("evolve_mhd", C.c_int), ("couple_matter", C.c_int), ("evolve_m1", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -89,6 +89,14 @@ def _bind(L):
     L.orc_rk4_stage_interior.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, C.c_double,
                                          _dp, _dp, _dp, _dp]
     L.orc_fill_periodic.argtypes = [C.POINTER(Grid), _dp, C.c_int]
+    if hasattr(L, "orc_m1_rhs"):
+        L.orc_m1_eddington.argtypes = [C.c_double]
+        L.orc_m1_eddington.restype = C.c_double
+        L.orc_m1_closure.argtypes = [C.c_double, _dp, _dp, C.c_double, _dp, _dp, _dp, _dp, _dp, _dp,
+                                     C.POINTER(C.c_int)]
+        L.orc_m1_closure.restype = C.c_double
+        L.orc_m1_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), _dp, _dp, _dp, _dp, _dp]
+        L.orc_rhs_full.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp, _dp, _dp]
     if hasattr(L, "orc_mlp_forward"):
         L.orc_bf16.argtypes = [C.c_float]
         L.orc_bf16.restype = C.c_float
@@ -149,6 +157,7 @@ def make_par(cfg):
     p.evolve_st = int(cfg["evolve_st"])
     p.evolve_mhd = int(cfg["evolve_mhd"])
     p.couple_matter = int(cfg["couple_matter"])
+    p.evolve_m1 = int(cfg.get("evolve_m1", 0))
     return p
 
 
@@ -274,3 +283,29 @@ def mlp_adam(prm, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
     lib().orc_mlp_adam(ptr(prm), ptr(np.ascontiguousarray(grad, dtype=np.float64)), ptr(m), ptr(v), int(step),
                        float(lr), float(beta1), float(beta2), float(eps))
+
+
+# ---------------------------------------------------------------- M1 radiation
+
+def m1_eddington(xi):
+    return lib().orc_m1_eddington(float(xi))
+
+
+def m1_closure(E, F, v, W, gdn, gup):
+    """(xi, chi, P_ij (6, lower), J, H_i (lower), Brent iterations) of the Minerbo closure."""
+    P = np.zeros(6)
+    J = C.c_double()
+    H = np.zeros(3)
+    chi = C.c_double()
+    it = C.c_int()
+    f = lambda a: ptr(np.ascontiguousarray(a, dtype=np.float64))
+    xi = lib().orc_m1_closure(float(E), f(F), f(v), float(W), f(gdn), f(gup), ptr(P), C.byref(J), ptr(H),
+                              C.byref(chi), C.byref(it))
+    return xi, chi.value, P, J.value, H, it.value
+
+
+def rhs_full(g, par, e, U, P, aux, out):
+    """L(U) with the M1 part when par.evolve_m1 (U: 44 fields, aux: 9 fields)."""
+    ms = C.c_double(0.0)
+    lib().orc_rhs_full(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(P), ptr(aux), ptr(out), C.byref(ms))
+    return ms.value

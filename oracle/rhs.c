@@ -56,6 +56,12 @@ void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const doub
   }
 }
 
+void orc_rhs_full(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
+                  const double* aux, double* rhs, double* max_speed) {
+  orc_rhs(g, par, e, U, P, rhs, max_speed);
+  if (par->evolve_m1) orc_m1_rhs(g, par, U, P, aux, rhs, max_speed);
+}
+
 /* Explicit RK4 of Table I (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6),
  * written with an accumulator:
  *   stage s: acc  = (s == 0 ? 0 : acc) + b_s k_s
