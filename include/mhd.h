@@ -26,7 +26,10 @@
  *   At_xx..At_zz (6-11), chi (12), Khat (13), Theta (14), Ghat^x,y,z (15-17),
  *   alpha (18), beta^x,y,z (19-21), Dbar (22), DYebar (23), taubar (24),
  *   Sbar_x,y,z (25-27), Bbar^x,y,z (28-30), phibar (31); the MHD fields are
- *   densitized by sqrt(gamma) (Sec. 2.2).
+ *   densitized by sqrt(gamma) (Sec. 2.2).  With MHD_EVOLVE_M1, 12 more fields:
+ *   per species s = 0, 1, 2 the densitized neutrino energy and flux Ebar,
+ *   Fbar_x,y,z at 32 + 4 s (Sec. 2.3), and an aux array of MHD_NAUX fields
+ *   (kappa_a, kappa_s, eta of species s at 3 s, 3 s + 1, 3 s + 2).
  * Primitive fields P (MHD_NP = 8): rho, eps, p, v^x, v^y, v^z, W, Ye.
  * Errors: 0 on success; a negative MHD_E* code otherwise, with a message
  *   available from mhd_last_error() (per host thread).  Argument errors are
@@ -42,11 +45,13 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 1
+#define MHD_ABI_VERSION 2
 
 #define MHD_NST 22
 #define MHD_NMHD 10
 #define MHD_NU 32
+#define MHD_NU_M1 44 /* with three grey M1 species (MHD_EVOLVE_M1) */
+#define MHD_NAUX 9   /* per species kappa_a, kappa_s, eta */
 #define MHD_NP 8
 #define MHD_NEM 4
 
@@ -77,6 +82,7 @@ extern "C" {
 #define MHD_EVOLVE_SPACETIME 1u
 #define MHD_EVOLVE_MHD 2u
 #define MHD_COUPLE_MATTER 4u
+#define MHD_EVOLVE_M1 8u /* grey M1 radiation, three species (Sec. 2.3): U has MHD_NU_M1 fields */
 
 /* f_alpha_kind: the slicing function f_alpha(alpha) of the lapse equation */
 #define MHD_FALPHA_ONE 0      /* 1+log slicing, f_alpha = 1 (the paper's standard) */
@@ -298,15 +304,23 @@ int mhd_level_set_learned(mhd_level_t* level, const float* mlp, void* workspace,
 /* Workspace bytes mhd_rhs needs for this patch (point fluxes and speeds). */
 size_t mhd_rhs_workspace_size(const mhd_patch_t* patch);
 
-/* L(U) at the interior points (Sec. 2.1, 2.2, 3.2, 3.3, App. B).
- * In: U (32 fields incl. ghosts), P (8 fields incl. ghosts; from con2prim).
- * Out: rhs (32 fields, interior points only; ghost entries untouched).
+/* Workspace of mhd_rhs with MHD_EVOLVE_M1 (closure, point fluxes, speeds). */
+size_t mhd_rhs_workspace_size_m1(const mhd_patch_t* patch);
+
+/* L(U) at the interior points (Sec. 2.1, 2.2, 2.3, 3.2, 3.3, 3.4, App. B).
+ * In: U (32 fields incl. ghosts, 44 with MHD_EVOLVE_M1), P (8 fields incl.
+ *   ghosts; from con2prim), aux (MHD_NAUX fields, required with
+ *   MHD_EVOLVE_M1, else ignored and may be NULL).
+ * Out: rhs (32 or 44 fields, interior points only; ghost entries untouched).
+ *   With MHD_EVOLVE_M1 the radiation also enters the CCZ4 matter terms (if
+ *   MHD_COUPLE_MATTER) and exchanges energy and momentum with the fluid.
  * max_speed: device double, max over interior points and axes of the point
- *   speed (fast magnetosonic bound and cleaning mode); updated with an atomic
- *   max, the caller initialises it (to 0).  May be NULL.
- * workspace: device buffer of mhd_rhs_workspace_size() bytes. */
+ *   speed (fast magnetosonic bound and cleaning mode, and the M1 speed);
+ *   updated with an atomic max, the caller initialises it (to 0).  May be NULL.
+ * workspace: device buffer of mhd_rhs_workspace_size() bytes
+ *   (mhd_rhs_workspace_size_m1() with MHD_EVOLVE_M1). */
 int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos,
-            const double* U, const double* P, double* rhs, double* max_speed,
+            const double* U, const double* P, const double* aux, double* rhs, double* max_speed,
             void* workspace, size_t workspace_bytes, void* stream);
 
 /* Explicit RK4 stage of Table I at the interior points of `nfields` fields:

@@ -13,7 +13,11 @@
 
 namespace mhd {
 int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
-                int strip, hipStream_t s);
+                int strip, const double* m1P, hipStream_t s);
+int m1_workspace_fields();
+int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, hipStream_t s);
+int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
+                     double* max_speed, hipStream_t s);
 int ccz4_workspace_fields();
 int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,
                double* ws, double* rhs, double* max_speed, int strip, hipStream_t s);
@@ -255,28 +259,41 @@ size_t mhd_rhs_workspace_size(const mhd_patch_t* patch) {
   return (size_t)(33 + mhd::ccz4_workspace_fields()) * (size_t)patch->sf * sizeof(double);
 }
 
+size_t mhd_rhs_workspace_size_m1(const mhd_patch_t* patch) {
+  if (!patch) return 0;
+  return mhd_rhs_workspace_size(patch) + (size_t)mhd::m1_workspace_fields() * (size_t)patch->sf * sizeof(double);
+}
+
 int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
-            const double* P, double* rhs, double* max_speed, void* workspace, size_t workspace_bytes, void* stream) {
+            const double* P, const double* aux, double* rhs, double* max_speed, void* workspace,
+            size_t workspace_bytes, void* stream) {
   int rc;
   if ((rc = check_patch(patch, 3, MHD_NST, "mhd_rhs")) || (rc = check_eos(eos, "mhd_rhs"))) return rc;
   if (!params) return fail(MHD_EINVAL, "mhd_rhs: params is NULL");
   if (!U || !rhs) return fail(MHD_EINVAL, "mhd_rhs: U and rhs must be non-NULL");
   const uint32_t fl = params->flags;
+  const bool m1 = (fl & MHD_EVOLVE_M1) != 0;
   if ((fl & (MHD_EVOLVE_MHD | MHD_COUPLE_MATTER)) && !P)
     return fail(MHD_EINVAL, "mhd_rhs: P is required when the fluid is evolved or coupled");
+  if (m1 && (!P || !aux)) return fail(MHD_EINVAL, "mhd_rhs: P and aux are required with MHD_EVOLVE_M1");
   if ((fl & MHD_EVOLVE_MHD) && !(params->c_b > 0.0)) return fail(MHD_EINVAL, "mhd_rhs: c_b must be > 0");
   if (params->f_alpha_kind != MHD_FALPHA_ONE && params->f_alpha_kind != MHD_FALPHA_HARMONIC)
     return fail(MHD_EINVAL, "mhd_rhs: unknown f_alpha_kind %d", params->f_alpha_kind);
-  if (!workspace || workspace_bytes < mhd_rhs_workspace_size(patch))
-    return fail(MHD_EWORKSPACE, "mhd_rhs: workspace of %zu bytes needed (got %zu)", mhd_rhs_workspace_size(patch),
-                workspace_bytes);
+  const size_t need = m1 ? mhd_rhs_workspace_size_m1(patch) : mhd_rhs_workspace_size(patch);
+  if (!workspace || workspace_bytes < need)
+    return fail(MHD_EWORKSPACE, "mhd_rhs: workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
   if (patch->sf > (int64_t)(INT32_MAX / 8))
     return fail(MHD_EINVAL, "mhd_rhs: a padded field of %lld points exceeds the 2^28-point limit of one launch",
                 (long long)patch->sf);
   const mhd::Geom g = geom_of(patch);
   hipStream_t s = (hipStream_t)stream;
+  double* ws = (double*)workspace;
+  double* ws_m1 = ws + (int64_t)(33 + mhd::ccz4_workspace_fields()) * patch->sf;
+  if (m1 && (rc = hip_check(mhd::launch_m1_point(g, U, P, aux, ws_m1, s), "mhd_rhs/m1 point"))) return rc;
+  const bool radiation_matter = m1 && (fl & MHD_COUPLE_MATTER);
   if (fl & MHD_EVOLVE_SPACETIME) {
-    if ((rc = hip_check(mhd::launch_ccz4(g, *params, U, P, rhs, (double*)workspace + 33 * patch->sf, g_strip, s),
+    if ((rc = hip_check(mhd::launch_ccz4(g, *params, U, P, rhs, ws + 33 * patch->sf, g_strip,
+                                         radiation_matter ? ws_m1 : nullptr, s),
                         "mhd_rhs/ccz4")))
       return rc;
   } else {
@@ -284,11 +301,13 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
     if ((rc = hip_check(mhd::launch_zero_interior(g, 0, MHD_NST, rhs, s), "mhd_rhs/zero"))) return rc;
   }
   if (fl & MHD_EVOLVE_MHD) {
-    if ((rc = hip_check(mhd::launch_mhd(g, *params, *eos, U, P, (double*)workspace, rhs, max_speed, g_strip, s), "mhd_rhs/grmhd")))
+    if ((rc = hip_check(mhd::launch_mhd(g, *params, *eos, U, P, ws, rhs, max_speed, g_strip, s), "mhd_rhs/grmhd")))
       return rc;
   } else {
     if ((rc = hip_check(mhd::launch_zero_interior(g, MHD_NST, MHD_NMHD, rhs, s), "mhd_rhs/zero"))) return rc;
   }
+  if (m1 && (rc = hip_check(mhd::launch_m1_update(g, U, P, aux, ws_m1, rhs, max_speed, s), "mhd_rhs/m1 update")))
+    return rc;
   return MHD_OK;
 }
 

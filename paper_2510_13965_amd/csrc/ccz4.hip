@@ -30,6 +30,7 @@ struct Ccz4Args {
   const double* __restrict__ P;
   double* __restrict__ rhs;
   int nbx, nby, nbz, strip;  // tile grid (64x4 tiles) and the strip height of the tile order
+  const double* __restrict__ m1P;  // closure P_ij of the three M1 species (6 s + c fields), or null
 };
 
 constexpr double kPi = 3.141592653589793;
@@ -111,13 +112,24 @@ struct Matter {
 };
 
 __device__ __forceinline__ void matter_point(const double* __restrict__ U, const double* __restrict__ P,
-                                             const PointIdx& q, const Conf& c, double chi, bool want_sij, Matter& m) {
+                                             const double* __restrict__ m1P, const PointIdx& q, const Conf& c,
+                                             double chi, bool want_sij, Matter& m) {
   const int64_t sf = q.sf, p = q.p;
   const double ichi = 1.0 / chi;
   const double isg = 1.0 / sqrt(c.det * ichi * ichi * ichi);
+  double Sf[3];  // fluid momentum (the fluid stress needs it alone)
 #pragma unroll
-  for (int a = 0; a < 3; ++a) m.S[a] = ldf(U + ((25 + a)) * sf, q.voff) * isg;
+  for (int a = 0; a < 3; ++a) Sf[a] = m.S[a] = ldf(U + ((25 + a)) * sf, q.voff) * isg;
   m.E = (ldf(U + (24) * sf, q.voff) + ldf(U + (22) * sf, q.voff)) * isg;
+  if (m1P) {
+    // radiation: E += sum E_nu, S_i += sum F_i (the stress is added below)
+#pragma unroll 1
+    for (int sp = 0; sp < 3; ++sp) {
+      m.E += ldf(U + (32 + 4 * sp) * sf, q.voff) * isg;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) m.S[a] += ldf(U + (33 + 4 * sp + a) * sf, q.voff) * isg;
+    }
+  }
   if (!want_sij) return;
   double gd[6];
 #pragma unroll
@@ -138,8 +150,9 @@ __device__ __forceinline__ void matter_point(const double* __restrict__ U, const
 #pragma unroll
     for (int j = i; j < 3; ++j) {
       const int a = sym(i, j);
-      m.Sij[a] = 0.5 * (vd[i] * m.S[j] + vd[j] * m.S[i]) + gd[a] * iso - iW2 * Bd[i] * Bd[j] -
+      m.Sij[a] = 0.5 * (vd[i] * Sf[j] + vd[j] * Sf[i]) + gd[a] * iso - iW2 * Bd[i] * Bd[j] -
                  0.5 * Bv * (Bd[i] * vd[j] + Bd[j] * vd[i]);
+      if (m1P) m.Sij[a] += ldf(m1P + a * sf, q.voff) + ldf(m1P + (6 + a) * sf, q.voff) + ldf(m1P + (12 + a) * sf, q.voff);
       m.Str += wsym(a) * c.gtu[a] * m.Sij[a];
     }
   m.Str *= chi;
@@ -339,7 +352,7 @@ __device__ __forceinline__ void ccz4_curv_at(const Ccz4Args& a, const double* __
   Matter m;
   const bool couple = (a.par.flags & MHD_COUPLE_MATTER) != 0;
   if (couple) {
-    matter_point(U, a.P, q, c, chi, true, m);
+    matter_point(U, a.P, a.m1P, q, c, chi, true, m);
   } else {
     m.E = m.Str = 0.0;
 #pragma unroll
@@ -473,7 +486,7 @@ __device__ __forceinline__ void ccz4_gauge_at(const Ccz4Args& a, const double* _
     double Sm[3] = {0.0, 0.0, 0.0};
     if (a.par.flags & MHD_COUPLE_MATTER) {
       Matter m;
-      matter_point(U, a.P, q, c, chi, false, m);
+      matter_point(U, a.P, a.m1P, q, c, chi, false, m);
       Sm[0] = m.S[0];
       Sm[1] = m.S[1];
       Sm[2] = m.S[2];
@@ -579,9 +592,9 @@ __global__ void __launch_bounds__(256) k_ccz4_gauge_lv(LevelArgs L) {
 int ccz4_workspace_fields() { return kD2Fields; }
 
 int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
-                int strip, hipStream_t s) {
+                int strip, const double* m1P, hipStream_t s) {
   const int nbx = (g.nx + 63) / 64, nby = (g.ny + 3) / 4, nbz = g.nz;
-  Ccz4Args a{g, par, U, P, rhs, nbx, nby, nbz, strip};
+  Ccz4Args a{g, par, U, P, rhs, nbx, nby, nbz, strip, m1P};
   dim3 blk(64, 4, 1);
   const int nblk = nbx * nby * nbz;
   dim3 grd(8 * ((nblk + 7) / 8), 1, 1);

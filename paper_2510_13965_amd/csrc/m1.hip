@@ -1,0 +1,442 @@
+// Grey M1 neutrino moments, three species (Sec. 2.3, Sec. 3.4, App. B).
+//
+// Per species s the evolved fields are Ebar, Fbar_x,y,z (densitized by
+// sqrt(gamma)) at U fields 32 + 4 s; per point and species the inputs
+// kappa_a, kappa_s, eta sit in aux fields 3 s + (0, 1, 2).
+//
+//   k_m1_point   every padded point: the Minerbo closure (root xi in [0, 1] of
+//                R(xi) = (xi^2 J^2 - H_a H^a)/E^2 by Brent's method), the
+//                closure P_ij, the point fluxes of the four fields along each
+//                axis and the Minerbo-interpolated point speeds -> workspace
+//   k_m1_update  interior points: HO/LO interface fluxes (limiter Phi,
+//                opacity switch A = tanh(1/(kappa dx)), odd-even fix), the
+//                conservative difference, the geometric sources, the
+//                collision sources alpha sqrt(gamma) (S_n, S_i) and their
+//                opposite on the fluid's taubar, Sbar_i
+// The CCZ4 kernels read the closure P_ij from the same workspace for the
+// radiation part of the matter terms.
+//
+// Readings where the text is silent or garbled: the low-order flux is
+// 1/2 (F_i + F_i+1) - lambda/2 (u_i+1 - u_i); lambda at an interface is the
+// larger point speed; Phi = 0 when u_i+1 = u_i; Phi and the odd-even test act
+// per field; P^thin and the thin speed are dropped when F_k F^k = 0; xi = 1 when
+// R(1) <= 0 and xi = 0 when R(0) >= 0; a negative argument of the thick-speed
+// root counts as 0; kappa = 0 gives A = 1.  Everything runs in one fixed
+// evaluation order without FMA contraction.
+#include "dev_common.hpp"
+#include "prof.hpp"
+
+namespace mhd {
+
+#pragma clang fp contract(off)
+
+constexpr int kM1Closure = 0;  // workspace: P_ij of species s at 6 s + c
+constexpr int kM1Flux = 18;    // fluxes and speed of (species s, axis d): 18 + 5 (3 s + d) + c, c = 4 speed
+constexpr int kM1Fields = 63;
+
+struct M1State {
+  double E, F[3], Fu[3], F2, v[3], vd[3], W, vF;
+};
+
+__device__ __forceinline__ double m1_eddington(double xi) {
+  return 1.0 / 3.0 + xi * xi * (6.0 - 2.0 * xi + 6.0 * xi * xi) / 15.0;
+}
+
+__device__ __forceinline__ void m1_state_init(M1State& s, double E, const double F[3], const double v[3], double W,
+                                              const double gd[6], const double gu[6]) {
+  s.E = E;
+  s.W = W;
+  s.F2 = 0.0;
+  s.vF = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s.F[i] = F[i];
+    s.v[i] = v[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s.Fu[i] = 0.0;
+    s.vd[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      s.Fu[i] += gu[sym(i, j)] * F[j];
+      s.vd[i] += gd[sym(i, j)] * v[j];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    s.F2 += s.Fu[i] * F[i];
+    s.vF += F[i] * v[i];
+  }
+}
+
+// P_ij (symmetric storage), J, H_i and H_a H^a for Eddington factor chi
+__device__ __forceinline__ void m1_closure_eval(const M1State& s, const double gd[6], const double gu[6], double chi,
+                                                double P[6], double& J, double H[3], double& HH) {
+  const double W = s.W, W2 = W * W;
+  const double dthick = 1.5 * (1.0 - chi), dthin = 1.0 - dthick;
+  const double Jth = 3.0 / (2.0 * W2 + 1.0) * ((2.0 * W2 - 1.0) * s.E - 2.0 * W2 * s.vF);
+  double Hth[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    Hth[i] = s.F[i] / W + W * s.vd[i] / (2.0 * W2 + 1.0) * ((4.0 * W2 + 1.0) * s.vF - 4.0 * W2 * s.E);
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const double thin = s.F2 > 0.0 ? s.E * s.F[i] * s.F[j] / s.F2 : 0.0;
+      const double thick = 4.0 / 3.0 * Jth * W2 * s.vd[i] * s.vd[j] + W * (Hth[i] * s.vd[j] + Hth[j] * s.vd[i]) +
+                           1.0 / 3.0 * Jth * gd[sym(i, j)];
+      P[sym(i, j)] = dthin * thin + dthick * thick;
+    }
+  double Pv[3], vPv = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Pv[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) Pv[i] += P[sym(i, j)] * s.v[j];
+    vPv += s.v[i] * Pv[i];
+  }
+  J = W2 * (s.E - 2.0 * s.vF + vPv);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) H[i] = W * (s.F[i] - Pv[i] - J * s.vd[i]);
+  const double Hn = W * (J - s.E + s.vF);
+  double hh = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) hh += gu[sym(i, j)] * H[i] * H[j];
+  HH = hh - Hn * Hn;
+}
+
+__device__ __forceinline__ double m1_R(const M1State& s, const double gd[6], const double gu[6], double xi) {
+  double P[6], J, H[3], HH;
+  m1_closure_eval(s, gd, gu, m1_eddington(xi), P, J, H, HH);
+  return (xi * xi * J * J - HH) / (s.E * s.E);
+}
+
+// Brent's method on [a, b] with R(a) < 0 < R(b), to a bracket of a few ulp
+__device__ double m1_brent(const M1State& s, const double gd[6], const double gu[6], double a, double b, double fa,
+                           double fb) {
+  double c = a, fc = fa, d = b - a, e = d;
+  for (int it = 0; it < 200; ++it) {
+    if ((fb > 0.0 && fc > 0.0) || (fb < 0.0 && fc < 0.0)) {
+      c = a;
+      fc = fa;
+      d = b - a;
+      e = d;
+    }
+    if (fabs(fc) < fabs(fb)) {
+      a = b;
+      b = c;
+      c = a;
+      fa = fb;
+      fb = fc;
+      fc = fa;
+    }
+    const double tol = 2.0 * 2.220446049250313e-16 * fabs(b) + 0.5 * 2.2250738585072014e-308;
+    const double m = 0.5 * (c - b);
+    if (fabs(m) <= tol || fb == 0.0) break;
+    if (fabs(e) < tol || fabs(fa) <= fabs(fb)) {
+      d = m;
+      e = m;
+    } else {
+      double p, q, r, t = fb / fa;
+      if (a == c) {
+        p = 2.0 * m * t;
+        q = 1.0 - t;
+      } else {
+        q = fa / fc;
+        r = fb / fc;
+        p = t * (2.0 * m * q * (q - r) - (b - a) * (r - 1.0));
+        q = (q - 1.0) * (r - 1.0) * (t - 1.0);
+      }
+      if (p > 0.0) q = -q;
+      else p = -p;
+      t = e;
+      e = d;
+      if (2.0 * p < 3.0 * m * q - fabs(tol * q) && p < fabs(0.5 * t * q)) {
+        d = p / q;
+      } else {
+        d = m;
+        e = m;
+      }
+    }
+    a = b;
+    fa = fb;
+    if (fabs(d) > tol) b += d;
+    else b += (m > 0.0 ? tol : -tol);
+    fb = m1_R(s, gd, gu, b);
+  }
+  return b;
+}
+
+// Eddington factor of the closure at this state
+__device__ __forceinline__ double m1_closure_chi(const M1State& s, const double gd[6], const double gu[6]) {
+  const double r0 = m1_R(s, gd, gu, 0.0), r1 = m1_R(s, gd, gu, 1.0);
+  double xi;
+  if (r1 <= 0.0) xi = 1.0;
+  else if (r0 >= 0.0) xi = 0.0;
+  else xi = m1_brent(s, gd, gu, 0.0, 1.0, r0, r1);
+  return m1_eddington(xi);
+}
+
+__device__ __forceinline__ double m1_speed(const M1State& s, const double gu[6], double chi, double alp, double bd,
+                                           int d) {
+  const double dthick = 1.5 * (1.0 - chi), dthin = 1.0 - dthick, W2 = s.W * s.W;
+  double lthin = fabs(bd);
+  if (s.F2 > 0.0) lthin += alp * fmax(fabs(s.Fu[d]) / sqrt(s.F2), s.E * fabs(s.Fu[d]) / s.F2);
+  const double a = (2.0 * W2 + 1.0) * gu[sym(d, d)] - 2.0 * W2 * s.v[d] * s.v[d];
+  const double lthick =
+      fabs(bd) + alp * fmax((2.0 * W2 * fabs(s.v[d]) + sqrt(fmax(a, 0.0))) / (2.0 * W2 + 1.0), fabs(s.v[d]));
+  return dthin * lthin + dthick * lthick;
+}
+
+__device__ __forceinline__ void m1_load_state(const double* __restrict__ U, const double* __restrict__ P, int64_t sf,
+                                              int64_t p, int sp, const MetricR& m, M1State& s) {
+  double F[3], v[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    F[i] = U[(33 + 4 * sp + i) * sf + p] / m.sqrtg;
+    v[i] = P[(3 + i) * sf + p];
+  }
+  m1_state_init(s, U[(32 + 4 * sp) * sf + p] / m.sqrtg, F, v, P[6 * sf + p], m.gd, m.gu);
+}
+
+__device__ __forceinline__ void m1_metric(const double* __restrict__ U, int64_t sf, int64_t p, MetricR& m) {
+  double gt[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) gt[c] = U[c * sf + p];
+  metric_repro(gt, U[12 * sf + p], m);
+}
+
+struct M1Args {
+  Geom g;
+  const double* __restrict__ U;
+  const double* __restrict__ P;
+  const double* __restrict__ aux;
+  double* __restrict__ W;  // M1 workspace (kM1Fields fields)
+  double* __restrict__ rhs;
+  unsigned long long* max_speed;
+};
+
+// padded indices
+__device__ __forceinline__ void m1_point_at(const M1Args& a, int i, int j, int k) {
+  const Geom& g = a.g;
+  const int64_t sf = g.sf, p = g.at(i, j, k);
+  MetricR m;
+  m1_metric(a.U, sf, p, m);
+  const double alp = a.U[18 * sf + p];
+#pragma unroll 1
+  for (int sp = 0; sp < 3; ++sp) {
+    M1State s;
+    m1_load_state(a.U, a.P, sf, p, sp, m, s);
+    const double chi = m1_closure_chi(s, m.gd, m.gu);
+    double Pij[6], J, H[3], HH;
+    m1_closure_eval(s, m.gd, m.gu, chi, Pij, J, H, HH);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a.W[(kM1Closure + 6 * sp + c) * sf + p] = Pij[c];
+    const double Eb = a.U[(32 + 4 * sp) * sf + p];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double bd = a.U[(19 + d) * sf + p];
+      double* f = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d)) * sf + p;
+      f[0] = -bd * Eb + alp * m.sqrtg * s.Fu[d];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double Pdc = 0.0;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) Pdc += m.gu[sym(d, e)] * Pij[sym(e, c)];
+        f[(1 + c) * sf] = -bd * a.U[(33 + 4 * sp + c) * sf + p] + alp * m.sqrtg * Pdc;
+      }
+      f[4 * sf] = m1_speed(s, m.gu, chi, alp, bd, d);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_m1_point(M1Args a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx + 2 * g.ng || j >= g.ny + 2 * g.ng) return;
+  m1_point_at(a, i, j, k);
+}
+
+// interface value between p and p + st of one field
+__device__ __forceinline__ double m1_holo(const double* __restrict__ u, const double* __restrict__ f,
+                                          const double* __restrict__ lam, const double* __restrict__ ka,
+                                          const double* __restrict__ ks, int64_t p, int64_t st, double h) {
+  const double um = u[p - st], u0 = u[p], u1 = u[p + st], u2 = u[p + 2 * st];
+  const double fho = 0.5 * (f[p] + f[p + st]);
+  const double lh = fmax(lam[p], lam[p + st]);
+  const double flo = fho - 0.5 * lh * (u1 - u0);
+  const double du = u1 - u0;
+  double phi = 0.0;
+  if (du != 0.0) phi = fmax(0.0, fmin(1.0, fmin(2.0 * (u0 - um) / du, 2.0 * (u2 - u1) / du)));
+  const double kap = 0.5 * (ka[p] + ka[p + st] + ks[p] + ks[p + st]);
+  double A = kap > 0.0 ? tanh(1.0 / (kap * h)) : 1.0;
+  if ((u0 - um) * du < 0.0 && du * (u2 - u1) < 0.0) A = 1.0;
+  return fho - A * (1.0 - phi) * (fho - flo);
+}
+
+// interior indices; every lane of the wavefront calls this (speed reduction)
+__device__ __forceinline__ void m1_update_at(const M1Args& a, int i, int j, int k, bool live) {
+  const Geom& g = a.g;
+  const int64_t sf = g.sf;
+  const int64_t q = live ? g.at(i + g.ng, j + g.ng, k + g.ng) : g.at(g.ng, g.ng, k + g.ng);
+  const double* __restrict__ U = a.U;
+  double vmax = 0.0;
+  if (live) {
+    const uint32_t voff = (uint32_t)(q * 8);
+    MetricR m;
+    m1_metric(U, sf, q, m);
+    const double chi = U[12 * sf + q];
+    const double alp = U[18 * sf + q], Kh = U[13 * sf + q], Th = U[14 * sf + q];
+    double dalp[3], dchi[3], dbeta[3][3], dgt[3][6];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const int64_t st = g.stride(d);
+      dalp[d] = fd1(U + 18 * sf, st, voff, g.i12[d]);
+      dchi[d] = fd1(U + 12 * sf, st, voff, g.i12[d]);
+#pragma unroll
+      for (int b = 0; b < 3; ++b) dbeta[d][b] = fd1(U + (19 + b) * sf, st, voff, g.i12[d]);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) dgt[d][c] = fd1(U + c * sf, st, voff, g.i12[d]);
+    }
+#pragma unroll 1
+    for (int sp = 0; sp < 3; ++sp) {
+      double out[4] = {0.0, 0.0, 0.0, 0.0};
+      const double* ka = a.aux + (int64_t)(3 * sp) * sf;
+      const double* ks = a.aux + (int64_t)(3 * sp + 1) * sf;
+#pragma unroll 1
+      for (int d = 0; d < 3; ++d) {
+        const int64_t st = g.stride(d);
+        const double* lam = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + 4) * sf;
+        vmax = fmax(vmax, lam[q]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double* u = U + (int64_t)(32 + 4 * sp + c) * sf;
+          const double* f = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + c) * sf;
+          const double fr = m1_holo(u, f, lam, ka, ks, q, st, g.h[d]);
+          const double fl = m1_holo(u, f, lam, ka, ks, q - st, st, g.h[d]);
+          out[c] -= (fr - fl) / g.h[d];
+        }
+      }
+      // closure quantities at the point
+      M1State s;
+      m1_load_state(U, a.P, sf, q, sp, m, s);
+      double Pij[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Pij[c] = a.W[(kM1Closure + 6 * sp + c) * sf + q];
+      double Pv[3], vPv = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        Pv[r] = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Pv[r] += Pij[sym(r, c)] * s.v[c];
+        vPv += s.v[r] * Pv[r];
+      }
+      const double J = s.W * s.W * (s.E - 2.0 * s.vF + vPv);
+      double H[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) H[r] = s.W * (s.F[r] - Pv[r] - J * s.vd[r]);
+      // geometric sources
+      double Pbu[3][3], trP = 0.0, Fbu[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          double t = 0.0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int e = 0; e < 3; ++e) t += m.gu[sym(r, c)] * m.gu[sym(b, e)] * Pij[sym(c, e)];
+          Pbu[r][b] = m.sqrtg * t;
+        }
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) trP += m.gd[sym(r, b)] * Pbu[r][b];
+      const double Fb[3] = {U[(33 + 4 * sp) * sf + q], U[(34 + 4 * sp) * sf + q], U[(35 + 4 * sp) * sf + q]};
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        Fbu[r] = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b) Fbu[r] += m.gu[sym(r, b)] * Fb[b];
+      }
+      const double Eb = U[(32 + 4 * sp) * sf + q];
+      {
+        double r = 0.0;
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2)
+#pragma unroll
+          for (int b = 0; b < 3; ++b) r += alp / chi * Pbu[a2][b] * U[(6 + sym(a2, b)) * sf + q];
+        r += alp / 3.0 * trP * (Kh + 2.0 * Th);
+#pragma unroll
+        for (int a2 = 0; a2 < 3; ++a2) r -= Fbu[a2] * dalp[a2];
+        out[0] += r;
+      }
+#pragma unroll
+      for (int a2 = 0; a2 < 3; ++a2) {
+        double r = 0.0;
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+#pragma unroll
+          for (int c = 0; c < 3; ++c) r += Pbu[b][c] * dgt[a2][sym(b, c)];
+        r = alp / (2.0 * chi) * (r - trP * dchi[a2]);
+#pragma unroll
+        for (int b = 0; b < 3; ++b) r += Fb[b] * dbeta[a2][b];
+        r -= Eb * dalp[a2];
+        out[1 + a2] += r;
+      }
+      // collisions, and the opposite exchange with the fluid
+      const double kA = ka[q], kS = ks[q], eta = a.aux[(int64_t)(3 * sp + 2) * sf + q];
+      const double Sn = s.W * ((eta + kS * J) - (kA + kS) * (s.E - s.vF));
+      double Si[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) Si[r] = s.W * (eta - kA * J) * s.vd[r] - (kA + kS) * H[r];
+      out[0] += alp * m.sqrtg * Sn;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) out[1 + r] += alp * m.sqrtg * Si[r];
+      a.rhs[24 * sf + q] -= alp * m.sqrtg * Sn;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) a.rhs[(25 + r) * sf + q] -= alp * m.sqrtg * Si[r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) a.rhs[(int64_t)(32 + 4 * sp + c) * sf + q] = out[c];
+    }
+  }
+  if (a.max_speed) {
+    double v = vmax;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0)
+      atomicMax(a.max_speed, (unsigned long long)__double_as_longlong(v));
+  }
+}
+
+__global__ void __launch_bounds__(256) k_m1_update(M1Args a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  m1_update_at(a, i, j, k, i < g.nx && j < g.ny);
+}
+
+int m1_workspace_fields() { return kM1Fields; }
+
+int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, hipStream_t s) {
+  M1Args a{g, U, P, aux, ws, nullptr, nullptr};
+  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
+  MHD_LAUNCH(KID_M1_POINT, k_m1_point, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
+                     double* max_speed, hipStream_t s) {
+  M1Args a{g, U, P, aux, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed)};
+  MHD_LAUNCH(KID_M1_UPDATE, k_m1_update, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace mhd

@@ -30,6 +30,8 @@ enum KernelId : int {
   KID_MLP_ADAM,
   KID_C2P_LEARNED,
   KID_C2P_FALLBACK,
+  KID_M1_POINT,
+  KID_M1_UPDATE,
   KID_COUNT
 };
 

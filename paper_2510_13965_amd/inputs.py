@@ -419,3 +419,53 @@ def c4_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None, log_rho=(-12.0, -3.0), l
     P[YE] = 0.1
     EM[0:3] = Bm * bd
     return patch, U, P, EM
+
+
+# ----------------------------------------------------------------------- M1 radiation
+
+NU_M1 = 44       # evolved fields with three M1 species
+NAUX = 9         # kappa_a, kappa_s, eta per species
+
+
+def _smooth01(r, patch, X, Y, Z, count=4):
+    """Sum of `count` Gaussian bumps (width a quarter of the patch) scaled to [0, 1]."""
+    L = [patch.n[a] * patch.dx[a] for a in range(3)]
+    w = min(L) / 4.0
+    f = np.zeros_like(X)
+    for _ in range(count):
+        c = [patch.x0[a] + r.uniform(0, L[a]) for a in range(3)]
+        A = r.uniform(0.2, 1.0)
+        f += A * np.exp(-((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) / (2 * w * w))
+    lo, hi = f.min(), f.max()
+    return (f - lo) / (hi - lo) if hi > lo else np.zeros_like(f)
+
+
+def m1_fields(patch, U32, P, seed):
+    """Three grey species on `patch`: returns U with 44 fields (U32 extended by
+    Ebar, Fbar_i per species) and the 9 aux fields (kappa_a, kappa_s, eta).
+
+    Ebar = 10^(-10 + 6 s(x)) with s a smooth field in [0, 1] (so Ebar spans
+    [1e-10, 1e-4]); Fbar_i = f(x) Ebar d_i/|d| with f smooth in [0, 0.95] and d a
+    smooth direction field (|F|/E <= 0.95 wherever chi <= 1 and the conformal
+    metric is flat, as on the star and the perturbed flat patches); kappa_a,
+    kappa_s log-uniform in [1e-8, 1e-2] per point and species; eta = kappa_a
+    E_eq with E_eq = 1e-2 rho eps."""
+    r = rng(seed)
+    Z, Y, X = patch.coords()
+    U = np.zeros((NU_M1,) + patch.shape)
+    U[:NU] = U32[:NU]
+    aux = np.zeros((NAUX,) + patch.shape)
+    for s in range(3):
+        Eb = 10.0 ** (-10.0 + 6.0 * _smooth01(r, patch, X, Y, Z))
+        frac = 0.95 * _smooth01(r, patch, X, Y, Z)
+        d = np.array([2.0 * _smooth01(r, patch, X, Y, Z) - 1.0 for _ in range(3)]) + 1e-3
+        d /= np.sqrt((d * d).sum(0))
+        U[32 + 4 * s] = Eb
+        for a in range(3):
+            U[33 + 4 * s + a] = frac * Eb * d[a]
+        ka = 10.0 ** r.uniform(-8.0, -2.0, patch.shape)
+        ks = 10.0 ** r.uniform(-8.0, -2.0, patch.shape)
+        aux[3 * s] = ka
+        aux[3 * s + 1] = ks
+        aux[3 * s + 2] = ka * 1e-2 * P[RHO] * P[EPS]
+    return U, aux

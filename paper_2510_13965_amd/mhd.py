@@ -13,8 +13,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmhd.so")
 
 MHD_NST, MHD_NMHD, MHD_NU, MHD_NP, MHD_NEM = 22, 10, 32, 8, 4
+MHD_NU_M1, MHD_NAUX = 44, 9
 MHD_NSTAT = 8
-EVOLVE_SPACETIME, EVOLVE_MHD, COUPLE_MATTER = 1, 2, 4
+EVOLVE_SPACETIME, EVOLVE_MHD, COUPLE_MATTER, EVOLVE_M1 = 1, 2, 4, 8
 FLAG = dict(ATMO=1, EPS_LO=2, EPS_HI=4, VEL_LIMIT=8, YE_RESET=16, FALLBACK=32, NOT_CONVERGED=64, FATAL=128)
 STAT_FATAL, STAT_CORRECTED, STAT_FALLBACK, STAT_ITERATIONS = 0, 1, 2, 3
 
@@ -68,7 +69,8 @@ SIGNATURES = {
     "mhd_prim2con": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, C.c_int, _vp]),
     "mhd_con2prim": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp]),
     "mhd_rhs_workspace_size": (C.c_size_t, [C.POINTER(Patch)]),
-    "mhd_rhs": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp,
+    "mhd_rhs_workspace_size_m1": (C.c_size_t, [C.POINTER(Patch)]),
+    "mhd_rhs": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
                           C.c_size_t, _vp]),
     "mhd_rk_stage": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_double, _vp, _vp, _vp, _vp, _vp]),
     "mhd_fill_ghosts_periodic": (C.c_int, [C.POINTER(Patch), _vp, C.c_int, _vp]),
@@ -188,6 +190,8 @@ def make_params(cfg):
         fl |= EVOLVE_MHD
     if cfg.get("couple_matter", 1):
         fl |= COUPLE_MATTER
+    if cfg.get("evolve_m1", 0):
+        fl |= EVOLVE_M1
     p.flags = fl
     return p
 
@@ -208,9 +212,9 @@ def rhs_workspace_size(patch):
     return int(lib().mhd_rhs_workspace_size(C.byref(patch)))
 
 
-def rhs(patch, params, eos, U, P, out, max_speed=None, workspace=None, stream=None):
+def rhs(patch, params, eos, U, P, out, max_speed=None, workspace=None, stream=None, aux=None):
     nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
-    _check(lib().mhd_rhs(C.byref(patch), C.byref(params), C.byref(eos), _ptr(U), _ptr(P), _ptr(out),
+    _check(lib().mhd_rhs(C.byref(patch), C.byref(params), C.byref(eos), _ptr(U), _ptr(P), _ptr(aux), _ptr(out),
                          _ptr(max_speed), _ptr(workspace), nbytes, _stream(stream)))
 
 
@@ -363,8 +367,9 @@ def profile_stop():
     return {out[i].name.decode(): (int(out[i].launches), float(out[i].total_ms)) for i in range(min(n.value, 32))}
 
 
-def workspace_for(patch, device="cuda"):
+def workspace_for(patch, device="cuda", m1=False):
     import torch
 
-    n = (rhs_workspace_size(patch) + 7) // 8
+    size = int(lib().mhd_rhs_workspace_size_m1(C.byref(patch))) if m1 else rhs_workspace_size(patch)
+    n = (size + 7) // 8
     return torch.empty(n, dtype=torch.float64, device=device)

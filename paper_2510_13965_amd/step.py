@@ -11,7 +11,7 @@ from . import mhd
 
 
 class PatchRun:
-    def __init__(self, ipatch, U0, eos_cfg, par_cfg, periodic=False, device="cuda", stream=None):
+    def __init__(self, ipatch, U0, eos_cfg, par_cfg, periodic=False, device="cuda", stream=None, aux=None):
         self.ip = ipatch
         self.patch = mhd.patch_of(ipatch)
         self.eos = mhd.make_eos(eos_cfg)
@@ -26,7 +26,10 @@ class PatchRun:
         self.acc = torch.zeros_like(self.Un)
         self.P = torch.zeros((I.NP,) + tuple(ipatch.shape), dtype=torch.float64, device=device)
         self.flags = torch.zeros(tuple(ipatch.shape), dtype=torch.uint8, device=device)
-        self.ws = mhd.workspace_for(self.patch, device)
+        self.m1 = bool(par_cfg.get("evolve_m1", 0))
+        self.nfields = I.NU_M1 if self.m1 else I.NU
+        self.aux = None if aux is None else t(aux)
+        self.ws = mhd.workspace_for(self.patch, device, m1=self.m1)
         self.vmax = torch.zeros(1, dtype=torch.float64, device=device)
         self.stats = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device=device)
         self.mlp = None
@@ -43,13 +46,13 @@ class PatchRun:
     def rhs_eval(self, U):
         """con2prim on the padded patch, then L(U) into self.k."""
         if self.periodic:
-            mhd.fill_ghosts_periodic(self.patch, U, I.NU, self.stream)
+            mhd.fill_ghosts_periodic(self.patch, U, self.nfields, self.stream)
         if self.mlp is not None:
             mhd.con2prim_learned(self.patch, self.eos, self.mlp, U, self.P, self.lws, self.flags, None, self.stats,
                                  self.stream)
         else:
             mhd.con2prim(self.patch, self.eos, U, self.P, self.flags, None, self.stats, self.stream)
-        mhd.rhs(self.patch, self.par, self.eos, U, self.P, self.k, self.vmax, self.ws, self.stream)
+        mhd.rhs(self.patch, self.par, self.eos, U, self.P, self.k, self.vmax, self.ws, self.stream, aux=self.aux)
 
     def step(self, dt):
         """One RK4 step (Table I).  Stage 0 evaluates L at Un itself (so
@@ -58,9 +61,9 @@ class PatchRun:
         for s in range(4):
             self.rhs_eval(self.Un if s == 0 else self.Us)
             nxt = self.Us if s < 3 else self.Un
-            mhd.rk_stage(self.patch, I.NU, s, dt, self.Un, self.k, self.acc, nxt, self.stream)
+            mhd.rk_stage(self.patch, self.nfields, s, dt, self.Un, self.k, self.acc, nxt, self.stream)
         if self.periodic:
-            mhd.fill_ghosts_periodic(self.patch, self.Un, I.NU, self.stream)
+            mhd.fill_ghosts_periodic(self.patch, self.Un, self.nfields, self.stream)
 
 
 class LevelRun:

@@ -43,7 +43,7 @@ def test_binding_covers_header(lib):
 
 
 def test_abi_version(lib):
-    assert lib.mhd_abi_version() == 1
+    assert lib.mhd_abi_version() == 2
 
 
 def test_eos_init_matches_oracle(lib, orc):
@@ -73,6 +73,12 @@ def test_argument_errors_before_device_work(lib):
     assert rc == -1 and b"rho_atm" in lib.mhd_last_error()
     assert lib.mhd_rhs_workspace_size(C.byref(p)) >= 33 * p.sf * 8
     par = mhd.make_params(I.PARAMS)
-    rc = lib.mhd_rhs(C.byref(p), C.byref(par), C.byref(e), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8), None,
-                     None, 0, None)
+    rc = lib.mhd_rhs(C.byref(p), C.byref(par), C.byref(e), C.c_void_p(8), C.c_void_p(8), None, C.c_void_p(8),
+                     None, None, 0, None)
     assert rc == -3 and b"workspace" in lib.mhd_last_error()
+    # radiation needs its aux array and the larger workspace
+    par_m1 = mhd.make_params(dict(I.PARAMS, evolve_m1=1))
+    rc = lib.mhd_rhs(C.byref(p), C.byref(par_m1), C.byref(e), C.c_void_p(8), C.c_void_p(8), None, C.c_void_p(8),
+                     None, C.c_void_p(8), 1 << 40, None)
+    assert rc == -1 and b"aux" in lib.mhd_last_error()
+    assert lib.mhd_rhs_workspace_size_m1(C.byref(p)) > lib.mhd_rhs_workspace_size(C.byref(p))
