@@ -9,10 +9,12 @@
  *
  *   features   8 metric-invariant scalars of one state (con2prim depends on
  *              the metric only through q, r^2, calB^2, (r.calB), App. D step 1)
- *   targets    logit(mu_+ h0) and logit(mu / mu_+) of the plain solver's roots
+ *   targets    log(mu_+ h0) and log(mu / mu_+) of the plain solver's roots
  *   forward    y = W3 relu(W2 relu(W1 z + b1) + b2) + b3, z the standardized
  *              features
  *   gradient   of L = 1/(2n) sum_samples sum_o (y_o - t_o)^2 by backpropagation
+ *              (rows whose first feature is NaN, points without a state, are
+ *              skipped but still counted in n; the forward pass gives NaN there)
  *   Adam       one step (Kingma & Ba, 2015, Algorithm 1)
  *
  * With emulate = 1 the forward and backward passes round to bfloat16 and to
@@ -90,15 +92,11 @@ void orc_mlp_features(const double cons[6], const double B[3], const double gdn[
   x[7] = log10(B2 / onep + 1e-30);
 }
 
-/* logit of y clamped to [1e-6, 1 - 1e-6] */
-static double logit_c(double y) {
-  y = fmin(fmax(y, 1e-6), 1.0 - 1e-6);
-  return log(y / (1.0 - y));
-}
-
+/* the roots as fractions of their upper bounds, in log space:
+ * log(mu_+ h0) and log(mu / mu_+), both <= 0 */
 void orc_mlp_targets(double h0, const double mu[2], double t[2]) {
-  t[0] = logit_c(mu[0] * h0);
-  t[1] = logit_c(mu[1] / mu[0]);
+  t[0] = log(mu[0] * h0);
+  t[1] = log(mu[1] / mu[0]);
 }
 
 /* one sample through the network; keeps the intermediate values for backprop */
@@ -144,6 +142,10 @@ void orc_mlp_forward(const double* prm, const float* X, int64_t n, int emulate, 
 #pragma omp parallel for schedule(static)
   for (i = 0; i < n; ++i) {
     mlp_trace t;
+    if (isnan(X[i * NI])) {
+      Y[i * NO] = Y[i * NO + 1] = NAN;
+      continue;
+    }
     forward_one(prm, X + i * NI, emulate, &t);
     Y[i * NO] = t.y[0];
     Y[i * NO + 1] = t.y[1];
@@ -159,6 +161,7 @@ double orc_mlp_grad(const double* prm, const float* X, const float* T, int64_t n
     mlp_trace t;
     double dy[NO], g2[NH], g1[NH];
     int o, j, k;
+    if (isnan(X[i * NI])) continue;  /* rows without a state (atmosphere) carry no loss */
     forward_one(prm, X + i * NI, emulate, &t);
     for (o = 0; o < NO; ++o) {
       double r = t.y[o] - (double)T[i * NO + o];

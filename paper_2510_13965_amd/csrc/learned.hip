@@ -4,7 +4,7 @@
 // f(mu) = 0 on (0, mu_+] by bracketed iterations.  Here a small MLP
 // (8 -> 64 -> 64 -> 2, ReLU) maps 8 metric-invariant scalars of the state
 // (log D, log q, log r^2, log calB^2, (r.calB)^2/(r^2 calB^2), log(1+q),
-// log r^2/(1+q)^2, log calB^2/(1+q)) to logit(mu_+ h0) and logit(mu/mu_+);
+// log r^2/(1+q)^2, log calB^2/(1+q)) to log(mu_+ h0) and log(mu/mu_+);
 // Newton's method in FP64 polishes each guess for at most three iterations,
 // and a point is accepted only if the residual falls below 1e-12 (f_a
 // absolute, f relative to mu) with 0 < mu <= mu_+.  Every other point goes to
@@ -185,10 +185,6 @@ __device__ __forceinline__ void standardize(const MlpLds& s, const float x[8], f
   for (int k = 0; k < 8; ++k) z[k] = (x[k] - s.mean[k]) * s.istd[k];
 }
 
-__device__ __forceinline__ double logit_clamped(double y) {
-  y = fmin(fmax(y, 1e-6), 1.0 - 1e-6);
-  return log(y / (1.0 - y));
-}
 
 struct FeatArgs {
   Geom g;
@@ -224,8 +220,8 @@ __global__ void __launch_bounds__(256) k_mlp_features(FeatArgs a) {
   for (int q = 0; q < 8; ++q) a.X[t * 8 + q] = (float)x[q];
   if (a.T && a.mu) {
     const double mup = a.mu[p], mu = a.mu[a.g.sf + p];
-    a.T[t * 2] = (float)logit_clamped(mup * a.eos.h0);
-    a.T[t * 2 + 1] = (float)logit_clamped(mu / mup);
+    a.T[t * 2] = (float)log(mup * a.eos.h0);
+    a.T[t * 2 + 1] = (float)log(mu / mup);
   }
 }
 
@@ -529,10 +525,14 @@ struct LearnedArgs {
 
 constexpr int kNewtonIt = 3;
 
-// Newton on F from x0 with at most kNewtonIt updates; accepted when
-// |F(x)| <= tol(x) (then one more correction is applied) and lo < x <= hi.
-template <class Fn>
-__device__ __forceinline__ bool newton_polish(const Fn& F, double x, double hi, bool rel, double& out, int& nev) {
+// Newton on F from x0 with at most kNewtonIt updates; accepted when |F(x)| <=
+// tol(x) (then one more correction is applied), 0 < x <= hi, and F changes
+// sign across [x (1 - 5e-13), min(x (1 + 5e-13), hi)] (F increases through
+// its only root in the bracket), which puts x within 5e-13 relative of the
+// root.  nev counts the function evaluations.
+template <class FnD, class Fn>
+__device__ __forceinline__ bool newton_polish(const FnD& F, const Fn& Fv, double x, double hi, bool rel, double& out,
+                                              int& nev) {
 #pragma clang fp contract(off)
   for (int it = 0; it <= kNewtonIt; ++it) {
     const Dual r = F(Dual{x, 1.0});
@@ -540,8 +540,14 @@ __device__ __forceinline__ bool newton_polish(const Fn& F, double x, double hi, 
     const double tol = rel ? 1e-12 * x : 1e-12;
     if (fabs(r.v) <= tol) {
       if (r.d != 0.0) x = x - r.v / r.d;
-      out = fmin(x, hi);
-      return out > 0.0;
+      x = fmin(x, hi);
+      if (!(x > 0.0)) return false;
+      const double lo = x * (1.0 - 5e-13), up = fmin(x * (1.0 + 5e-13), hi);
+      const double flo = Fv(lo), fup = up < hi ? Fv(up) : 1.0;  // F(hi) > 0 is known
+      nev += up < hi ? 2 : 1;
+      if (!(flo <= 0.0 && fup >= 0.0)) return false;
+      out = x;
+      return true;
     }
     if (it == kNewtonIt || !(r.d != 0.0)) return false;
     x = x - r.v / r.d;
@@ -560,7 +566,8 @@ struct FDual {
   __device__ Dual operator()(Dual mu) const { return f_t<Dual>(e, c, mu); }
 };
 
-__device__ __forceinline__ double sigmoid(double y) { return 1.0 / (1.0 + exp(-y)); }
+// network output y (a log fraction) -> fraction of the bracket's upper end, in (0, 1]
+__device__ __forceinline__ double frac_of(double y) { return exp(fmin(y, 0.0)); }
 
 struct LearnedOut {
   bool fallback;
@@ -615,13 +622,13 @@ __device__ __forceinline__ LearnedOut learned_point(const MlpLds& s, const mhd_e
     const double fhi = fa_t<double>(c, hi);
     double mup = hi;
     bool ok = true;
-    if (fhi > 0.0) ok = newton_polish(FaDual{c}, sigmoid((double)y[0]) * hi, hi, false, mup, nev);
+    if (fhi > 0.0) ok = newton_polish(FaDual{c}, FaFn{c}, frac_of((double)y[0]) * hi, hi, false, mup, nev);
     double m = mup;
     if (ok) {
       const FFn fp{eos, c};
       const double f1 = fp(mup);
       ++nev;
-      if (f1 > 0.0) ok = newton_polish(FDual{eos, c}, sigmoid((double)y[1]) * mup, mup, true, m, nev);
+      if (f1 > 0.0) ok = newton_polish(FDual{eos, c}, fp, frac_of((double)y[1]) * mup, mup, true, m, nev);
     }
     r.nit = nev + 1;  // root-function evaluations, f_a(1/h0) included
     if (!ok) {

@@ -211,10 +211,9 @@ def test_features_frame_invariant():
 
 
 def test_targets_invert_to_roots():
-    for mu in ([0.7, 0.3], [0.999, 0.5], [1e-3, 1e-3 * 0.25]):
+    for mu in ([0.7, 0.3], [0.999, 0.5], [1e-3, 1e-3 * 0.25], [1.0, 1.0]):
         t = orc.mlp_targets(1.0, np.array(mu))
-        s = 1 / (1 + np.exp(-t))
-        assert s[0] == pytest.approx(mu[0], rel=1e-12)
-        assert s[1] * mu[0] == pytest.approx(mu[1], rel=1e-12)
-    t = orc.mlp_targets(1.0, np.array([1.0, 1.0]))   # roots at the bracket end: clamped
-    assert t[0] == pytest.approx(math.log((1 - 1e-6) / 1e-6))
+        assert np.exp(t[0]) == pytest.approx(mu[0], rel=1e-14)
+        assert np.exp(t[1]) * mu[0] == pytest.approx(mu[1], rel=1e-14)
+    t = orc.mlp_targets(2.0, np.array([0.25, 0.2]))
+    assert t[0] == pytest.approx(math.log(0.5)) and t[1] == pytest.approx(math.log(0.8))
