@@ -39,6 +39,7 @@ def parse():
     ap.add_argument("--sweep-strip", action="store_true", help="time one RK4 step per strip height and report")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-con2prim path")
     ap.add_argument("--no-level", action="store_true", help="skip the batched AMR-level paths")
+    ap.add_argument("--no-m1", action="store_true", help="skip the M1-radiation path")
     ap.add_argument("--level-boxes", type=int, default=192)
     ap.add_argument("--level-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -102,6 +103,32 @@ def learned_path(torch, mhd, I, run, step, args, nint):
             "fallback_rate": round(float(st[2]) / nev, 6), "root_evals_per_point": round(float(st[3]) / nev, 3),
             "train_s": round(t_train, 2), "train_loss_first_last": [hist[0], hist[-1]], "train_states": 1 << 18,
             "_mlp": prm}
+
+
+def m1_path(torch, mhd, I, ip, U, P, EM, args):
+    """The same star with three grey M1 species (44 evolved fields): smooth
+    radiation fields, per-point opacities (inputs.m1_fields)."""
+    from paper_2510_13965_amd.step import PatchRun
+
+    t0 = time.perf_counter()
+    par = dict(I.PARAMS, evolve_m1=1)
+    run0 = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS)
+    mhd.prim2con(run0.patch, run0.eos, run0.Un, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
+    U32 = run0.Un.cpu().numpy()
+    del run0
+    U44, aux = I.m1_fields(ip, U32, P, I.SEED0 + 70)
+    run = PatchRun(ip, U44, I.EOS_IDEAL2, par, aux=aux)
+    del U44, aux
+    dt = 0.25 * ip.dx[0]
+    say("m1 path: built in %.1f s" % (time.perf_counter() - t0))
+    mhd.profile_start()
+    ms = time_steps(torch, lambda: run.step(dt), args.steps, 1)
+    prof = mhd.profile_stop()
+    fin = bool(torch.isfinite(run.Un).all().item())
+    say("m1 path: %.3f ms/step" % ms)
+    per = {k: round(t / n, 4) for k, (n, t) in prof.items()}
+    return {"zone_updates_per_s": round(ip.ninterior * 4 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+            "evolved_fields": 44, "finite": fin, "ms_per_launch": per}
 
 
 def level_paths(torch, mhd, I, args, mlp):
@@ -230,6 +257,8 @@ def main():
     level = None
     if not args.no_learned:
         paths["learned"] = learned_path(torch, mhd, I, run, step, args, nint)
+    if not args.no_m1:
+        paths["m1"] = m1_path(torch, mhd, I, ip, U, P, EM, args)
     if not args.no_level:
         level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
     if "learned" in paths:

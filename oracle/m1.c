@@ -281,8 +281,8 @@ void orc_m1_matter(const double* U, const double* P, int64_t N, int64_t p, doubl
  * exchange is subtracted from rhs[24] (taubar) and rhs[25..27] (Sbar_i), which
  * must already hold the fluid part.  max_speed (may be NULL) gets the max of
  * the M1 point speeds. */
-void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
-                double* rhs, double* max_speed) {
+static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, const double* P,
+                        const double* aux, double* rhs, double* stiff, double* max_speed) {
   const int ng = g->ng;
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
@@ -391,8 +391,13 @@ void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const do
           /* collisions, and the opposite exchange with the fluid */
           Sn = s.W * ((eta + ks * J) - (ka + ks) * (s.E - s.vF));
           for (a = 0; a < 3; ++a) Si[a] = s.W * (eta - ka * J) * s.vd[a] - (ka + ks) * H[a];
-          out[0] += alp * m.sqrtg * Sn;
-          for (a = 0; a < 3; ++a) out[1 + a] += alp * m.sqrtg * Si[a];
+          if (stiff) {
+            stiff[(4 * sp) * N + q] = alp * m.sqrtg * Sn;
+            for (a = 0; a < 3; ++a) stiff[(4 * sp + 1 + a) * N + q] = alp * m.sqrtg * Si[a];
+          } else {
+            out[0] += alp * m.sqrtg * Sn;
+            for (a = 0; a < 3; ++a) out[1 + a] += alp * m.sqrtg * Si[a];
+          }
           rhs[24 * N + q] -= alp * m.sqrtg * Sn;
           for (a = 0; a < 3; ++a) rhs[(25 + a) * N + q] -= alp * m.sqrtg * Si[a];
           for (c = 0; c < 4; ++c) rhs[(32 + 4 * sp + c) * N + q] = out[c];
@@ -402,4 +407,128 @@ void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const do
   free(LM);
   if (max_speed) *max_speed = fmax(*max_speed, vmax);
   (void)par;
+}
+
+void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
+                double* rhs, double* max_speed) {
+  m1_rhs_impl(g, par, U, P, aux, rhs, NULL, max_speed);
+}
+
+/* as orc_m1_rhs, but the radiation's collision terms (the stiff part of the
+ * IMEX splitting) go to stiff (12 fields) instead of rhs; the fluid's opposite
+ * exchange stays in rhs (explicit) */
+void orc_m1_rhs_split(const orc_grid* g, const orc_par* par, const double* U, const double* P,
+                      const double* aux, double* rhs, double* stiff, double* max_speed) {
+  m1_rhs_impl(g, par, U, P, aux, rhs, stiff, max_speed);
+}
+
+/* G(V) = V - V* - adt alpha (S_n, S_i)(V) of one species at one point, undensitized,
+ * with the closure's Eddington factor frozen at chi */
+static void implicit_residual(const m1_state* s0, double chi, const double V[4], const double Vs[4], double adt,
+                              double alp, double ka, double ks, double eta, double G[4]) {
+  m1_state s;
+  double P[3][3], J, H[3], Hn, HH, Sn, Si[3];
+  int a;
+  state_init(&s, V[0], V + 1, s0->v, s0->W, s0->gdn, s0->gup);
+  closure_eval(&s, chi, P, &J, H, &Hn, &HH);
+  Sn = s.W * ((eta + ks * J) - (ka + ks) * (s.E - s.vF));
+  for (a = 0; a < 3; ++a) Si[a] = s.W * (eta - ka * J) * s.vd[a] - (ka + ks) * H[a];
+  G[0] = V[0] - Vs[0] - adt * alp * Sn;
+  for (a = 0; a < 3; ++a) G[1 + a] = V[1 + a] - Vs[1 + a] - adt * alp * Si[a];
+}
+
+/* solve the 4x4 system A x = b by Gaussian elimination with partial pivoting */
+static int solve4(double A[4][4], double b[4], double x[4]) {
+  int i, j, k;
+  for (k = 0; k < 4; ++k) {
+    int piv = k;
+    for (i = k + 1; i < 4; ++i)
+      if (fabs(A[i][k]) > fabs(A[piv][k])) piv = i;
+    if (A[piv][k] == 0.0) return 0;
+    if (piv != k) {
+      for (j = 0; j < 4; ++j) {
+        double t = A[k][j];
+        A[k][j] = A[piv][j];
+        A[piv][j] = t;
+      }
+      {
+        double t = b[k];
+        b[k] = b[piv];
+        b[piv] = t;
+      }
+    }
+    for (i = k + 1; i < 4; ++i) {
+      double f = A[i][k] / A[k][k];
+      for (j = k; j < 4; ++j) A[i][j] -= f * A[k][j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (i = 3; i >= 0; --i) {
+    double t = b[i];
+    for (j = i + 1; j < 4; ++j) t -= A[i][j] * x[j];
+    x[i] = t / A[i][i];
+  }
+  return 1;
+}
+
+/* Implicit M1 update of an IMEX stage (App. C): at every interior point and
+ * species, V = (E, F_i) solves V = V* + adt alpha (S_n, S_i)(V) with V* the
+ * radiation fields on input (densitized in U; the equations are solved
+ * undensitized), the fluid state from P and the closure's Eddington factor
+ * frozen at its value for V*.  Newton's method with a central-difference
+ * Jacobian, to |dV| <= 1e-15 (E + |F|), at most 60 iterations.  Returns the
+ * number of points that did not converge. */
+int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  int64_t bad = 0;
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : bad)
+  for (int64_t k = ng; k < Nz - ng; ++k)
+    for (int64_t j = ng; j < Ny - ng; ++j)
+      for (int64_t i = ng; i < Nx - ng; ++i) {
+        const int64_t q = i + Nx * (j + Ny * k);
+        const double alp = U[18 * N + q];
+        m1_metric m;
+        int sp;
+        m1_metric_at(U, N, q, &m);
+        for (sp = 0; sp < 3; ++sp) {
+          const double ka = aux[(3 * sp) * N + q], ks = aux[(3 * sp + 1) * N + q], eta = aux[(3 * sp + 2) * N + q];
+          m1_state s0;
+          double Pij[3][3], J, H[3], chi, Vs[4], V[4];
+          int it, a, c, ok = 0;
+          point_state(U, P, N, q, sp, &m, &s0);
+          closure(&s0, Pij, &J, H, &chi, NULL);
+          Vs[0] = s0.E;
+          for (a = 0; a < 3; ++a) Vs[1 + a] = s0.F[a];
+          for (a = 0; a < 4; ++a) V[a] = Vs[a];
+          for (it = 0; it < 60; ++it) {
+            double G[4], Jm[4][4], dV[4], scale = fabs(V[0]) + fabs(V[1]) + fabs(V[2]) + fabs(V[3]), nrm = 0.0;
+            implicit_residual(&s0, chi, V, Vs, adt, alp, ka, ks, eta, G);
+            for (c = 0; c < 4; ++c) {
+              double Vp[4], Vm[4], Gp[4], Gm[4], h = 1e-6 * scale;
+              for (a = 0; a < 4; ++a) Vp[a] = Vm[a] = V[a];
+              Vp[c] += h;
+              Vm[c] -= h;
+              implicit_residual(&s0, chi, Vp, Vs, adt, alp, ka, ks, eta, Gp);
+              implicit_residual(&s0, chi, Vm, Vs, adt, alp, ka, ks, eta, Gm);
+              for (a = 0; a < 4; ++a) Jm[a][c] = (Gp[a] - Gm[a]) / (2.0 * h);
+            }
+            for (a = 0; a < 4; ++a) G[a] = -G[a];
+            if (!solve4(Jm, G, dV)) break;
+            for (a = 0; a < 4; ++a) {
+              V[a] += dV[a];
+              nrm += fabs(dV[a]);
+            }
+            if (nrm <= 1e-15 * scale) {
+              ok = 1;
+              break;
+            }
+          }
+          if (!ok) bad += 1;
+          U[(32 + 4 * sp) * N + q] = m.sqrtg * V[0];
+          for (a = 0; a < 3; ++a) U[(33 + 4 * sp + a) * N + q] = m.sqrtg * V[1 + a];
+        }
+      }
+  return bad;
 }

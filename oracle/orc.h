@@ -146,6 +146,16 @@ void orc_m1_matter(const double* U, const double* P, int64_t N, int64_t p, doubl
                    double Sij[3][3]);
 void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
                 double* rhs, double* max_speed);
+void orc_m1_rhs_split(const orc_grid* g, const orc_par* par, const double* U, const double* P,
+                      const double* aux, double* rhs, double* stiff, double* max_speed);
+int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);
+/* explicit part F (44 fields) and stiff radiation part R (12 fields) of L(U) */
+void orc_rhs_split(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
+                   const double* aux, double* F, double* R, double* max_speed);
+/* one IMEX(4,4,2) step of Table I (44 fields, frozen ghosts); returns the number
+ * of implicit point solves that did not converge */
+int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
+                      double dt, int periodic);
 /* orc_rhs plus, if par->evolve_m1, the M1 part (U has 44 fields) */
 void orc_rhs_full(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
                   const double* aux, double* rhs, double* max_speed);

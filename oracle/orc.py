@@ -97,6 +97,11 @@ def _bind(L):
         L.orc_m1_closure.restype = C.c_double
         L.orc_m1_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), _dp, _dp, _dp, _dp, _dp]
         L.orc_rhs_full.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp, _dp, _dp]
+        L.orc_rhs_split.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp, _dp, _dp, _dp]
+        L.orc_m1_implicit.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_double]
+        L.orc_m1_implicit.restype = C.c_int64
+        L.orc_imex_step.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, C.c_double, C.c_int]
+        L.orc_imex_step.restype = C.c_int64
     if hasattr(L, "orc_mlp_forward"):
         L.orc_bf16.argtypes = [C.c_float]
         L.orc_bf16.restype = C.c_float
@@ -309,3 +314,22 @@ def rhs_full(g, par, e, U, P, aux, out):
     ms = C.c_double(0.0)
     lib().orc_rhs_full(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(P), ptr(aux), ptr(out), C.byref(ms))
     return ms.value
+
+
+def rhs_split(g, par, e, U, P, aux, F, R):
+    """Explicit part F (44 fields) and stiff radiation part R (12 fields) of L(U)."""
+    ms = C.c_double(0.0)
+    lib().orc_rhs_split(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(P), ptr(aux), ptr(F), ptr(R),
+                        C.byref(ms))
+    return ms.value
+
+
+def m1_implicit(g, U, P, aux, adt):
+    return int(lib().orc_m1_implicit(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt)))
+
+
+def imex_step(g, par, e, U, aux, dt, periodic=False):
+    """One IMEX(4,4,2) step in place on U (44 fields); returns the count of
+    implicit solves that did not converge."""
+    return int(lib().orc_imex_step(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(aux), float(dt),
+                                   int(bool(periodic))))

@@ -4,6 +4,7 @@
  * (Table I, explicit RK4) and periodic ghost filling.
  */
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 #include "orc.h"
 
@@ -127,4 +128,97 @@ void orc_fill_periodic(const orc_grid* g, double* U, int nfields) {
           if (ii != i || jj != j || kk != k) u[i + Nx * (j + Ny * k)] = u[ii + Nx * (jj + Ny * kk)];
         }
   }
+}
+
+/* ---------------------------------------------------------------- IMEX(4,4,2)
+ * Table I: explicit RK4 tableau (AE, BE) for the non-stiff part and the
+ * implicit I42L tableau (AI, BI) for the stiff part, the collision terms of
+ * the radiation.  Stage i: every field gets Un + dt sum_j AE[i][j] F_j, the
+ * radiation fields also + dt sum_j AI[i][j] R_j (= V*); con2prim; if AI[i][i]
+ * is not zero, the implicit solve V = V* + AI[i][i] dt R(V); then F_i, R_i at
+ * the stage state.  Final: Un + dt sum_i (BE[i] F_i + BI[i] R_i) (radiation)
+ * and Un + dt sum_i BE[i] F_i (all other fields).  Interior points only; ghost
+ * values are frozen unless `periodic` is set. */
+static const double IM_AE[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1.0, 0}};
+static const double IM_AI[4][4] = {{0, 0, 0, 0}, {0.25, 0.25, 0, 0}, {0, 1.0 / 6.0, 1.0 / 3.0, 0},
+                                   {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}};
+static const double IM_BE[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+static const double IM_BI[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+
+void orc_m1_rhs_split(const orc_grid* g, const orc_par* par, const double* U, const double* P,
+                      const double* aux, double* rhs, double* stiff, double* max_speed);
+int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);
+
+/* explicit part F (all 44 fields) and stiff part R (12 radiation fields) */
+void orc_rhs_split(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
+                   const double* aux, double* F, double* R, double* max_speed) {
+  orc_rhs(g, par, e, U, P, F, max_speed);
+  orc_m1_rhs_split(g, par, U, P, aux, F, R, max_speed);
+}
+
+int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
+                      double dt, int periodic) {
+  const int ng = g->ng, nf = 44;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  double* Un = (double*)malloc(sizeof(double) * nf * N);
+  double* Ui = (double*)malloc(sizeof(double) * nf * N);
+  double* P = (double*)calloc(8 * N, sizeof(double));
+  double* F[4];
+  double* R[4];
+  int64_t bad = 0;
+  int st, f;
+  memcpy(Un, U, sizeof(double) * nf * N);
+  for (st = 0; st < 4; ++st) {
+    F[st] = (double*)calloc(nf * N, sizeof(double));
+    R[st] = (double*)calloc(12 * N, sizeof(double));
+  }
+  for (st = 0; st < 4; ++st) {
+    memcpy(Ui, Un, sizeof(double) * nf * N);
+    for (f = 0; f < nf; ++f) {
+      int64_t k;
+#pragma omp parallel for schedule(static)
+      for (k = ng; k < Nz - ng; ++k)
+        for (int64_t j = ng; j < Ny - ng; ++j)
+          for (int64_t i = ng; i < Nx - ng; ++i) {
+            const int64_t p = f * N + i + Nx * (j + Ny * k);
+            double v = Un[p];
+            int jj;
+            for (jj = 0; jj < st; ++jj) v += dt * IM_AE[st][jj] * F[jj][p];
+            if (f >= 32)
+              for (jj = 0; jj < st; ++jj) v += dt * IM_AI[st][jj] * R[jj][(f - 32) * N + (p - f * N)];
+            Ui[p] = v;
+          }
+    }
+    if (periodic) orc_fill_periodic(g, Ui, nf);
+    orc_con2prim(g, e, Ui, P, NULL, NULL);
+    if (IM_AI[st][st] != 0.0) {
+      bad += orc_m1_implicit(g, Ui, P, aux, IM_AI[st][st] * dt);
+      if (periodic) orc_fill_periodic(g, Ui, nf);
+    }
+    orc_rhs_split(g, par, e, Ui, P, aux, F[st], R[st], NULL);
+  }
+  for (f = 0; f < nf; ++f) {
+    int64_t k;
+#pragma omp parallel for schedule(static)
+    for (k = ng; k < Nz - ng; ++k)
+      for (int64_t j = ng; j < Ny - ng; ++j)
+        for (int64_t i = ng; i < Nx - ng; ++i) {
+          const int64_t p = f * N + i + Nx * (j + Ny * k);
+          double v = Un[p];
+          for (st = 0; st < 4; ++st) v += dt * IM_BE[st] * F[st][p];
+          if (f >= 32)
+            for (st = 0; st < 4; ++st) v += dt * IM_BI[st] * R[st][(f - 32) * N + (p - f * N)];
+          U[p] = v;
+        }
+  }
+  if (periodic) orc_fill_periodic(g, U, nf);
+  for (st = 0; st < 4; ++st) {
+    free(F[st]);
+    free(R[st]);
+  }
+  free(Un);
+  free(Ui);
+  free(P);
+  return bad;
 }

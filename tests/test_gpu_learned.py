@@ -5,8 +5,10 @@ roundings; agreement is to the arithmetic the two sides do differently (FP32
 accumulation on the matrix cores vs exact sums), which can flip a bf16
 rounding of a hidden activation now and then.  The con2prim answer with the
 learned guess is checked against the plain bracketed solver, which stays the
-judge: mu and mu_+ to 1e-12 relative, flags equal apart from the fallback bit
-(and the eps-floor decision of the plain test), primitives to 1e-12 on
+judge: mu and mu_+ to 1e-12 relative (on all but a rare set of cells where the
+root function is flat to rounding around its root, where both answers must
+reproduce the conserved state to 1e-12), flags equal apart from the fallback
+bit (and the eps-floor decision of the plain test), primitives to 1e-12 on
 well-conditioned cells, and a backward error of 1e-12 on every cell.
 """
 import sys
@@ -194,23 +196,39 @@ def check_learned_against_plain(orc, ip, U, P, EM, out, eos_cfg):
     diff = ~same
     assert diff.mean() < 1e-3
     assert np.all(((flg ^ flp)[diff] & ~np.uint8(2)) == 0)
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    e = orc.make_eos(eos_cfg)
+
+    def backward_error(Pside, mask):
+        U2 = U.copy()
+        P2 = Pside.copy()
+        orc.prim2con(g, e, U2, P2, EM, 0)
+        C0, C2 = U[22:28][:, mask], U2[22:28][:, mask]
+        scale = np.abs(C0[0]) + np.abs(C0[2]) + np.sqrt((C0[3:6] ** 2).sum(0))
+        return np.abs(C2 - C0).max(0) / scale
+
+    # the roots agree to 1e-12 except where f is flat to rounding around its
+    # root (several answers are correct there): those must stay rare, and both
+    # answers must reproduce the conserved state to 1e-12
     solved = same & (mup[1] > 0)
-    for c in range(2):
-        rel = np.abs(mul[c][solved] - mup[c][solved]) / mup[c][solved]
-        assert rel.max() <= 1e-12, (c, rel.max())
     wc = same & (flp == 0) & (P[I.WLOR] < 2.0) & ((EM[0:3] ** 2).sum(0) < 0.1 * P[I.RHO])
+    off = np.zeros_like(solved)
+    for c in range(2):
+        rel = np.zeros(solved.shape)
+        rel[solved] = np.abs(mul[c][solved] - mup[c][solved]) / mup[c][solved]
+        assert rel[wc].max() <= 1e-12, (c, rel[wc].max())
+        off |= rel > 1e-12
+    relmu = np.abs(mul[1][solved] - mup[1][solved]) / mup[1][solved]
+    say("roots differing by more than 1e-12: %d of %d (max %.1e)" % (off.sum(), solved.sum(), relmu.max()))
+    assert off.mean() <= 1e-3
+    clean = off & (flp == 0) & (flg == 0)
+    if clean.any():
+        assert backward_error(Pl, clean).max() <= 1e-12
+        assert backward_error(Pp, clean).max() <= 1e-12
     for c in range(I.NP):
         rel = np.abs(Pl[c][wc] - Pp[c][wc]) / np.maximum(np.abs(Pp[c][wc]), 1e-300)
         assert rel.max() <= 1e-12, (c, rel.max())
-    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
-    e = orc.make_eos(eos_cfg)
-    ok = flg == 0
-    U2 = U.copy()
-    P2 = Pl.copy()
-    orc.prim2con(g, e, U2, P2, EM, 0)
-    C0, C2 = U[22:28][:, ok], U2[22:28][:, ok]
-    scale = np.abs(C0[0]) + np.abs(C0[2]) + np.sqrt((C0[3:6] ** 2).sum(0))
-    assert (np.abs(C2 - C0).max(0) / scale).max() <= 1e-12
+    assert backward_error(Pl, flg == 0).max() <= 1e-12
     assert stl[2] == fb.sum()
     return fb.mean(), stp[3], stl[3]
 
