@@ -324,6 +324,32 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
             const double* U, const double* P, const double* aux, double* rhs, double* max_speed,
             void* workspace, size_t workspace_bytes, void* stream);
 
+/* ---- IMEX(4,4,2) of Table I for the stiff radiation collisions (App. C) -----
+ * mhd_rhs_split: as mhd_rhs with MHD_EVOLVE_M1, but the radiation's collision
+ *   terms alpha sqrt(gamma) (S_n, S_i) (the stiff part) go to `stiff` (12
+ *   fields, species-major, patch layout) instead of rhs; the fluid's opposite
+ *   exchange stays in rhs (explicit).
+ * mhd_imex_combine: at the interior points of all 44 fields, stage s = 0..3:
+ *   Uout = Un + dt sum_{j<s} AE[s][j] F[j], and on the radiation fields also
+ *   + dt sum_{j<s} AI[s][j] R[j] (the explicit state V* of the stage); s = 4:
+ *   Uout = Un + dt sum_i (BE[i] F[i] + BI[i] R[i]) (radiation) and
+ *   Un + dt sum_i BE[i] F[i] (other fields).  F, R: host arrays of 4 device
+ *   pointers to stage explicit (44 fields) and stiff (12 fields) parts; only
+ *   the entries the stage reads must be set.  Uout may alias Un only at s = 4.
+ * mhd_m1_implicit: at the interior points, per species, replaces the radiation
+ *   fields V* of U by the solution V of V = V* + adt alpha (S_n, S_i)(V)
+ *   (undensitized), the fluid state from P, the closure's Eddington factor
+ *   frozen at its value for V*; Newton's method with the exact Jacobian to
+ *   |dV| <= 1e-15 (E + |F|), at most 60 iterations; nfail (device uint64, may
+ *   be NULL) is incremented per species solve that did not converge. */
+int mhd_rhs_split(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
+                  const double* P, const double* aux, double* rhs, double* stiff, double* max_speed, void* workspace,
+                  size_t workspace_bytes, void* stream);
+int mhd_imex_combine(const mhd_patch_t* patch, int stage, double dt, const double* Un, const double* const* F,
+                     const double* const* R, double* Uout, void* stream);
+int mhd_m1_implicit(const mhd_patch_t* patch, const double* aux, double* U, const double* P, double adt,
+                    uint64_t* nfail, void* stream);
+
 /* Explicit RK4 stage of Table I at the interior points of `nfields` fields:
  *   stage s (0..3): acc = (s ? acc : 0) + b_s k;  s < 3: Unext = Un + dt a_{s+1,s} k;
  *   s = 3: Unext = Un + dt acc.

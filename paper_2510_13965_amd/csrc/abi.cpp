@@ -17,7 +17,11 @@ int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const d
 int m1_workspace_fields();
 int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, hipStream_t s);
 int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
-                     double* max_speed, hipStream_t s);
+                     double* max_speed, double* stiff, hipStream_t s);
+int launch_imex_combine(const Geom& g, int stage, double dt, const double* Un, const double* const* F,
+                        const double* const* R, double* Uout, hipStream_t s);
+int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt,
+                       unsigned long long* nfail, hipStream_t s);
 int ccz4_workspace_fields();
 int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,
                double* ws, double* rhs, double* max_speed, int strip, hipStream_t s);
@@ -264,9 +268,9 @@ size_t mhd_rhs_workspace_size_m1(const mhd_patch_t* patch) {
   return mhd_rhs_workspace_size(patch) + (size_t)mhd::m1_workspace_fields() * (size_t)patch->sf * sizeof(double);
 }
 
-int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
-            const double* P, const double* aux, double* rhs, double* max_speed, void* workspace,
-            size_t workspace_bytes, void* stream) {
+static int rhs_impl(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
+                    const double* P, const double* aux, double* rhs, double* stiff, double* max_speed, void* workspace,
+                    size_t workspace_bytes, void* stream) {
   int rc;
   if ((rc = check_patch(patch, 3, MHD_NST, "mhd_rhs")) || (rc = check_eos(eos, "mhd_rhs"))) return rc;
   if (!params) return fail(MHD_EINVAL, "mhd_rhs: params is NULL");
@@ -306,9 +310,54 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
   } else {
     if ((rc = hip_check(mhd::launch_zero_interior(g, MHD_NST, MHD_NMHD, rhs, s), "mhd_rhs/zero"))) return rc;
   }
-  if (m1 && (rc = hip_check(mhd::launch_m1_update(g, U, P, aux, ws_m1, rhs, max_speed, s), "mhd_rhs/m1 update")))
+  if (m1 && (rc = hip_check(mhd::launch_m1_update(g, U, P, aux, ws_m1, rhs, max_speed, stiff, s), "mhd_rhs/m1 update")))
     return rc;
   return MHD_OK;
+}
+
+int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
+            const double* P, const double* aux, double* rhs, double* max_speed, void* workspace,
+            size_t workspace_bytes, void* stream) {
+  return rhs_impl(patch, params, eos, U, P, aux, rhs, nullptr, max_speed, workspace, workspace_bytes, stream);
+}
+
+int mhd_rhs_split(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
+                  const double* P, const double* aux, double* rhs, double* stiff, double* max_speed, void* workspace,
+                  size_t workspace_bytes, void* stream) {
+  if (!params || !(params->flags & MHD_EVOLVE_M1) || !stiff)
+    return fail(MHD_EINVAL, "mhd_rhs_split: needs MHD_EVOLVE_M1 and a stiff array");
+  return rhs_impl(patch, params, eos, U, P, aux, rhs, stiff, max_speed, workspace, workspace_bytes, stream);
+}
+
+int mhd_imex_combine(const mhd_patch_t* patch, int stage, double dt, const double* Un, const double* const* F,
+                     const double* const* R, double* Uout, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, MHD_NU_M1, "mhd_imex_combine"))) return rc;
+  if (stage < 0 || stage > 4) return fail(MHD_EINVAL, "mhd_imex_combine: stage must be 0..4");
+  if (!Un || !Uout || !F || !R) return fail(MHD_EINVAL, "mhd_imex_combine: NULL array");
+  if (!std::isfinite(dt)) return fail(MHD_EINVAL, "mhd_imex_combine: dt must be finite");
+  const int nread = stage < 4 ? stage : 4;
+  const double* f4[4] = {nullptr, nullptr, nullptr, nullptr};
+  const double* r4[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (int j = 0; j < nread; ++j) {
+    if (!F[j] || !R[j]) return fail(MHD_EINVAL, "mhd_imex_combine: stage arrays %d missing", j);
+    f4[j] = F[j];
+    r4[j] = R[j];
+  }
+  if (Uout == Un && stage < 4) return fail(MHD_EINVAL, "mhd_imex_combine: Uout may alias Un only at stage 4");
+  return hip_check(mhd::launch_imex_combine(geom_of(patch), stage, dt, Un, f4, r4, Uout, (hipStream_t)stream),
+                   "mhd_imex_combine");
+}
+
+int mhd_m1_implicit(const mhd_patch_t* patch, const double* aux, double* U, const double* P, double adt,
+                    uint64_t* nfail, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, 1, "mhd_m1_implicit"))) return rc;
+  if (!aux || !U || !P) return fail(MHD_EINVAL, "mhd_m1_implicit: aux, U and P are required");
+  if (!(adt >= 0.0) || !std::isfinite(adt)) return fail(MHD_EINVAL, "mhd_m1_implicit: adt must be finite and >= 0");
+  return hip_check(mhd::launch_m1_implicit(geom_of(patch), U, P, aux, adt,
+                                           reinterpret_cast<unsigned long long*>(nfail), (hipStream_t)stream),
+                   "mhd_m1_implicit");
 }
 
 int mhd_rk_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, const double* Un, const double* k,

@@ -1,0 +1,241 @@
+// IMEX(4,4,2) of Table I for the radiation's stiff collision terms.
+//
+//   k_imex_combine  stage s = 0..3: Ustage = Un + dt sum_{j<s} AE[s][j] F_j on
+//                   every field, + dt sum_{j<s} AI[s][j] R_j on the radiation
+//                   fields (= V*); s = 4: Un + dt sum_i (BE[i] F_i + BI[i] R_i)
+//   k_m1_implicit   per interior point and species, V = (E, F_i) solving
+//                   V = V* + adt alpha (S_n, S_i)(V) (undensitized), fluid from
+//                   the stage's primitives, the closure's Eddington factor
+//                   frozen at its value for V*; Newton's method with the exact
+//                   Jacobian (dual numbers), 4x4 elimination with partial
+//                   pivoting, to |dV| <= 1e-15 (E + |F|), at most 60 iterations
+#include "c2p_dev.hpp"
+#include "m1_dev.hpp"
+#include "prof.hpp"
+
+namespace mhd {
+
+#pragma clang fp contract(off)
+
+__constant__ double kImAE[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1.0, 0}};
+__constant__ double kImAI[4][4] = {
+    {0, 0, 0, 0}, {0.25, 0.25, 0, 0}, {0, 1.0 / 6.0, 1.0 / 3.0, 0}, {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}};
+__constant__ double kImB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+
+struct ImexArgs {
+  Geom g;
+  int stage;
+  double dt;
+  const double* Un;
+  const double* F[4];  // explicit parts of the earlier stages (44 fields)
+  const double* R[4];  // stiff parts (12 fields)
+  double* Uout;
+};
+
+// block 64x4, grid z = nz * 44 (field-major)
+__global__ void __launch_bounds__(256) k_imex_combine(ImexArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int kz = blockIdx.z % g.nz;
+  const int f = blockIdx.z / g.nz;
+  if (i >= g.nx || j >= g.ny) return;
+  const int64_t pt = g.at(i + g.ng, j + g.ng, kz + g.ng);
+  const int64_t p = (int64_t)f * g.sf + pt;
+  const int s = a.stage;
+  double v = a.Un[p];
+  if (s < 4) {
+    for (int jj = 0; jj < s; ++jj) v += a.dt * kImAE[s][jj] * a.F[jj][p];
+    if (f >= 32)
+      for (int jj = 0; jj < s; ++jj) v += a.dt * kImAI[s][jj] * a.R[jj][(int64_t)(f - 32) * g.sf + pt];
+  } else {
+    for (int st = 0; st < 4; ++st) v += a.dt * kImB[st] * a.F[st][p];
+    if (f >= 32)
+      for (int st = 0; st < 4; ++st) v += a.dt * kImB[st] * a.R[st][(int64_t)(f - 32) * g.sf + pt];
+  }
+  a.Uout[p] = v;
+}
+
+// G(V) of one species at one point for the frozen Eddington factor chi
+template <class T>
+__device__ __forceinline__ void implicit_G(const M1State& s0, const double gd[6], const double gu[6], double chi,
+                                           const T V[4], const double Vs[4], double adt, double alp, double ka,
+                                           double ks, double eta, T G[4]) {
+  const double W = s0.W, W2 = W * W;
+  const double dthick = 1.5 * (1.0 - chi), dthin = 1.0 - dthick;
+  const T E = V[0];
+  const T F[3] = {V[1], V[2], V[3]};
+  T Fu[3], F2 = F[0] * 0.0, vF = F[0] * 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    Fu[r] = F[0] * 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Fu[r] = Fu[r] + gu[sym(r, c)] * F[c];
+  }
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    F2 = F2 + Fu[r] * F[r];
+    vF = vF + F[r] * s0.v[r];
+  }
+  const T Jth = 3.0 / (2.0 * W2 + 1.0) * ((2.0 * W2 - 1.0) * E - 2.0 * W2 * vF);
+  T Hth[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+    Hth[r] = F[r] / W + W * s0.vd[r] / (2.0 * W2 + 1.0) * ((4.0 * W2 + 1.0) * vF - 4.0 * W2 * E);
+  T P[6];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = r; c < 3; ++c) {
+      const T thin = val(F2) > 0.0 ? E * F[r] * F[c] / F2 : F[0] * 0.0;
+      const T thick = 4.0 / 3.0 * Jth * W2 * s0.vd[r] * s0.vd[c] + W * (Hth[r] * s0.vd[c] + Hth[c] * s0.vd[r]) +
+                      1.0 / 3.0 * Jth * gd[sym(r, c)];
+      P[sym(r, c)] = dthin * thin + dthick * thick;
+    }
+  T Pv[3], vPv = F[0] * 0.0;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    Pv[r] = F[0] * 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Pv[r] = Pv[r] + P[sym(r, c)] * s0.v[c];
+    vPv = vPv + s0.v[r] * Pv[r];
+  }
+  const T J = W2 * (E - 2.0 * vF + vPv);
+  const T Sn = W * ((eta + ks * J) - (ka + ks) * (E - vF));
+  G[0] = V[0] - Vs[0] - adt * alp * Sn;
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    const T H = W * (F[r] - Pv[r] - J * s0.vd[r]);
+    const T Si = W * (eta - ka * J) * s0.vd[r] - (ka + ks) * H;
+    G[1 + r] = V[1 + r] - Vs[1 + r] - adt * alp * Si;
+  }
+}
+
+__device__ __forceinline__ bool solve4(double A[4][4], double b[4], double x[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int piv = k;
+#pragma unroll
+    for (int r = k + 1; r < 4; ++r)
+      if (fabs(A[r][k]) > fabs(A[piv][k])) piv = r;
+    if (A[piv][k] == 0.0) return false;
+    if (piv != k) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double t = A[k][c];
+        A[k][c] = A[piv][c];
+        A[piv][c] = t;
+      }
+      const double t = b[k];
+      b[k] = b[piv];
+      b[piv] = t;
+    }
+#pragma unroll
+    for (int r = k + 1; r < 4; ++r) {
+      const double f = A[r][k] / A[k][k];
+#pragma unroll
+      for (int c = k; c < 4; ++c) A[r][c] -= f * A[k][c];
+      b[r] -= f * b[k];
+    }
+  }
+#pragma unroll
+  for (int r = 3; r >= 0; --r) {
+    double t = b[r];
+#pragma unroll
+    for (int c = r + 1; c < 4; ++c) t -= A[r][c] * x[c];
+    x[r] = t / A[r][r];
+  }
+  return true;
+}
+
+struct ImplArgs {
+  Geom g;
+  double* U;
+  const double* __restrict__ P;
+  const double* __restrict__ aux;
+  double adt;
+  unsigned long long* nfail;
+};
+
+__global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const int64_t sf = g.sf, q = g.at(i + g.ng, j + g.ng, k + g.ng);
+  MetricR m;
+  m1_metric(a.U, sf, q, m);
+  const double alp = a.U[18 * sf + q];
+  unsigned long long bad = 0;
+#pragma unroll 1
+  for (int sp = 0; sp < 3; ++sp) {
+    const double ka = a.aux[(int64_t)(3 * sp) * sf + q], ks = a.aux[(int64_t)(3 * sp + 1) * sf + q];
+    const double eta = a.aux[(int64_t)(3 * sp + 2) * sf + q];
+    M1State s0;
+    m1_load_state(a.U, a.P, sf, q, sp, m, s0);
+    const double chi = m1_closure_chi(s0, m.gd, m.gu);
+    const double Vs[4] = {s0.E, s0.F[0], s0.F[1], s0.F[2]};
+    double V[4] = {Vs[0], Vs[1], Vs[2], Vs[3]};
+    bool ok = false;
+#pragma unroll 1
+    for (int it = 0; it < 60; ++it) {
+      const double scale = fabs(V[0]) + fabs(V[1]) + fabs(V[2]) + fabs(V[3]);
+      double Jm[4][4], rhs[4], dV[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        Dual Vd[4], Gd[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Vd[r] = Dual{V[r], r == c ? 1.0 : 0.0};
+        implicit_G<Dual>(s0, m.gd, m.gu, chi, Vd, Vs, a.adt, alp, ka, ks, eta, Gd);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          Jm[r][c] = Gd[r].d;
+          if (c == 0) rhs[r] = -Gd[r].v;
+        }
+      }
+      if (!solve4(Jm, rhs, dV)) break;
+      double nrm = 0.0;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        V[r] += dV[r];
+        nrm += fabs(dV[r]);
+      }
+      if (nrm <= 1e-15 * scale) {
+        ok = true;
+        break;
+      }
+    }
+    if (!ok) ++bad;
+    a.U[(int64_t)(32 + 4 * sp) * sf + q] = m.sqrtg * V[0];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) a.U[(int64_t)(33 + 4 * sp + r) * sf + q] = m.sqrtg * V[1 + r];
+  }
+  if (bad && a.nfail) atomicAdd(a.nfail, bad);
+}
+
+int launch_imex_combine(const Geom& g, int stage, double dt, const double* Un, const double* const* F,
+                        const double* const* R, double* Uout, hipStream_t s) {
+  ImexArgs a;
+  a.g = g;
+  a.stage = stage;
+  a.dt = dt;
+  a.Un = Un;
+  for (int st = 0; st < 4; ++st) {
+    a.F[st] = F[st];
+    a.R[st] = R[st];
+  }
+  a.Uout = Uout;
+  dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * 44);
+  MHD_LAUNCH(KID_IMEX_COMBINE, k_imex_combine, grd, dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt,
+                       unsigned long long* nfail, hipStream_t s) {
+  ImplArgs a{g, U, P, aux, adt, nfail};
+  MHD_LAUNCH(KID_M1_IMPLICIT, k_m1_implicit, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+}  // namespace mhd

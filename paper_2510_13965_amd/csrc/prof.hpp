@@ -32,6 +32,8 @@ enum KernelId : int {
   KID_C2P_FALLBACK,
   KID_M1_POINT,
   KID_M1_UPDATE,
+  KID_IMEX_COMBINE,
+  KID_M1_IMPLICIT,
   KID_COUNT
 };
 

@@ -95,6 +95,11 @@ SIGNATURES = {
     "mhd_level_autotune": (C.c_int, [_vp, C.c_double, _vp, C.POINTER(Tuning)]),
     "mhd_level_learned_workspace_size": (C.c_size_t, [_vp]),
     "mhd_level_set_learned": (C.c_int, [_vp, _vp, _vp, C.c_size_t]),
+    "mhd_rhs_split": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp, C.c_size_t, _vp]),
+    "mhd_imex_combine": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_double, _vp, C.POINTER(C.c_void_p),
+                                   C.POINTER(C.c_void_p), _vp, _vp]),
+    "mhd_m1_implicit": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, C.c_double, _vp, _vp]),
     "mhd_profile_start": (C.c_int, []),
     "mhd_profile_stop": (C.c_int, [C.POINTER(KernelTime), C.c_int, C.POINTER(C.c_int)]),
 }
@@ -278,6 +283,25 @@ def _tuning(strip=4, block_threads=256, grid_per_cu=0):
 
 def _tuning_dict(t):
     return {"strip": t.strip, "block_threads": t.block_threads, "grid_per_cu": t.grid_per_cu}
+
+
+def rhs_split(patch, params, eos, U, P, aux, out, stiff, max_speed=None, workspace=None, stream=None):
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check(lib().mhd_rhs_split(C.byref(patch), C.byref(params), C.byref(eos), _ptr(U), _ptr(P), _ptr(aux), _ptr(out),
+                               _ptr(stiff), _ptr(max_speed), _ptr(workspace), nbytes, _stream(stream)))
+
+
+def imex_combine(patch, stage, dt, Un, F, R, Uout, stream=None):
+    """F, R: lists of up to 4 device tensors (stage explicit and stiff parts)."""
+    fa = (C.c_void_p * 4)(*[(_ptr(F[j]) if j < len(F) and F[j] is not None else None) for j in range(4)])
+    ra = (C.c_void_p * 4)(*[(_ptr(R[j]) if j < len(R) and R[j] is not None else None) for j in range(4)])
+    _check(lib().mhd_imex_combine(C.byref(patch), int(stage), float(dt), _ptr(Un), fa, ra, _ptr(Uout),
+                                  _stream(stream)))
+
+
+def m1_implicit(patch, aux, U, P, adt, nfail=None, stream=None):
+    _check(lib().mhd_m1_implicit(C.byref(patch), _ptr(aux), _ptr(U), _ptr(P), float(adt), _ptr(nfail),
+                                 _stream(stream)))
 
 
 def set_tuning(strip):

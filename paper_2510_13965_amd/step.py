@@ -92,3 +92,51 @@ class LevelRun:
     @property
     def npts(self):
         return sum(b["ip"].npts for b in self.boxes)
+
+
+# implicit diagonal of Table I's I42L tableau
+IMEX_AII = (0.0, 0.25, 1.0 / 3.0, 1.0 / 6.0)
+
+
+class ImexRun:
+    """One patch with three M1 species stepped by IMEX(4,4,2) (Table I): the
+    radiation's collision terms implicit (mhd_m1_implicit), everything else
+    explicit.  Per stage: combine -> (ghost fill) -> con2prim -> implicit solve
+    -> (ghost fill) -> split RHS."""
+
+    def __init__(self, ipatch, U0, aux, eos_cfg, par_cfg, periodic=False, device="cuda", stream=None):
+        self.ip = ipatch
+        self.patch = mhd.patch_of(ipatch)
+        self.eos = mhd.make_eos(eos_cfg)
+        self.par = mhd.make_params(dict(par_cfg, evolve_m1=1))
+        self.periodic = periodic
+        self.stream = stream
+        t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
+        self.Un = t(U0)
+        self.Ust = self.Un.clone()
+        self.aux = t(aux)
+        shp = tuple(ipatch.shape)
+        self.F = [torch.zeros_like(self.Un) for _ in range(4)]
+        self.R = [torch.zeros((12,) + shp, dtype=torch.float64, device=device) for _ in range(4)]
+        self.P = torch.zeros((I.NP,) + shp, dtype=torch.float64, device=device)
+        self.flags = torch.zeros(shp, dtype=torch.uint8, device=device)
+        self.ws = mhd.workspace_for(self.patch, device, m1=True)
+        self.vmax = torch.zeros(1, dtype=torch.float64, device=device)
+        self.nfail = torch.zeros(1, dtype=torch.int64, device=device)
+
+    def step(self, dt):
+        s_ = self.stream
+        for s in range(4):
+            mhd.imex_combine(self.patch, s, dt, self.Un, self.F, self.R, self.Ust, s_)
+            if self.periodic:
+                mhd.fill_ghosts_periodic(self.patch, self.Ust, I.NU_M1, s_)
+            mhd.con2prim(self.patch, self.eos, self.Ust, self.P, self.flags, None, None, s_)
+            if IMEX_AII[s] != 0.0:
+                mhd.m1_implicit(self.patch, self.aux, self.Ust, self.P, IMEX_AII[s] * dt, self.nfail, s_)
+                if self.periodic:
+                    mhd.fill_ghosts_periodic(self.patch, self.Ust, I.NU_M1, s_)
+            mhd.rhs_split(self.patch, self.par, self.eos, self.Ust, self.P, self.aux, self.F[s], self.R[s], self.vmax,
+                          self.ws, s_)
+        mhd.imex_combine(self.patch, 4, dt, self.Un, self.F, self.R, self.Un, s_)
+        if self.periodic:
+            mhd.fill_ghosts_periodic(self.patch, self.Un, I.NU_M1, s_)

@@ -1,0 +1,129 @@
+"""GPU parity of the IMEX(4,4,2) step with the implicit M1 collision solve
+against the oracle's step (Table I, App. C), and the closed-form relaxation
+of uniform radiation.
+
+Bar: per field, |G - O| <= 4e-10 max|U^n+1 - U^n| + 8 eps max|U| over the
+interior (the step's own change sets the scale, as for the RK4 step); the
+implicit solves use the exact Jacobian on the GPU and a central-difference
+one in the oracle, and both iterate to 1e-15, so they reach the same root.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2510_13965_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    from paper_2510_13965_amd import mhd
+
+    mhd.lib()
+    return torch.device("cuda")
+
+
+def run_both(orc, ip, U44, aux, dt, periodic, par_cfg):
+    import torch
+    from paper_2510_13965_amd.step import ImexRun
+
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    e = orc.make_eos(I.EOS_IDEAL2)
+    Uo = U44.copy()
+    assert orc.imex_step(g, orc.make_par(dict(par_cfg, evolve_m1=1)), e, Uo, aux, dt, periodic=periodic) == 0
+    r = ImexRun(ip, U44, aux, I.EOS_IDEAL2, par_cfg, periodic=periodic)
+    r.step(dt)
+    torch.cuda.synchronize()
+    assert int(r.nfail.item()) == 0
+    return r.Un.cpu().numpy(), Uo
+
+
+def compare_step(ip, U0, G, O, tag):
+    sl = (slice(None),) + ip.interior()
+    worst = 0.0
+    for f in range(I.NU_M1):
+        d = np.abs(G[sl][f] - O[sl][f]).max()
+        scale = np.abs(O[sl][f] - U0[sl][f]).max()
+        bound = 4e-10 * scale + 8 * np.finfo(float).eps * np.abs(O[sl][f]).max()
+        if scale > 0:
+            worst = max(worst, d / scale)
+        assert d <= bound, (tag, f, d, scale)
+    say(tag, "worst |G-O| / max|dU| = %.1e" % worst)
+
+
+def test_imex_step_parity_periodic_flat(orc, dev):
+    say("case imex step, perturbed flat 16^3 periodic, stiff opacities")
+    ip, U, P, EM = I.c1_state(n=16, rich=True)
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    orc.prim2con(g, orc.make_eos(I.EOS_IDEAL2), U, P, EM, 0)
+    U44, aux = I.m1_fields(ip, U, P, I.SEED0 + 80)
+    aux[0::3] *= 1e3     # kappa_a up to 10: kappa dt up to 0.6
+    G, O = run_both(orc, ip, U44, aux, 0.25 * ip.dx[0], True, I.PARAMS)
+    compare_step(ip, U44, G, O, "flat")
+
+
+def test_imex_step_parity_star_frozen_ghosts(orc, dev):
+    say("case imex step, star 32^3 frozen ghosts")
+    ip, U, P, EM = I.c2_state(n=32)
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    orc.prim2con(g, orc.make_eos(I.EOS_IDEAL2), U, P, EM, 0)
+    U44, aux = I.m1_fields(ip, U, P, I.SEED0 + 81)
+    G, O = run_both(orc, ip, U44, aux, 0.25 * ip.dx[0], False, I.PARAMS)
+    compare_step(ip, U44, G, O, "star")
+
+
+def test_imex_uniform_relaxation_closed_form(dev):
+    """Uniform radiation at rest relaxing (dE/dt = eta - kappa_a E): one GPU step
+    multiplies the distance to equilibrium by R(z) of Table I's implicit tableau."""
+    import os
+    import torch
+    from fractions import Fraction
+    from paper_2510_13965_amd import mhd
+    from paper_2510_13965_amd.step import ImexRun
+
+    say("case imex uniform relaxation")
+    path = os.path.join(os.path.dirname(__file__), "golden", "table1_imex442.txt")
+    lines = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    i0 = [k for k, l in enumerate(lines) if l[0] == "implicit_A"][0]
+    A = np.array([[float(Fraction(x)) for x in lines[i0 + 1 + r]] for r in range(4)])
+    b = np.array([float(Fraction(x)) for x in [l for l in lines if l[0] == "implicit_b"][0][1:]])
+    ip = I.Patch((6, 6, 6), (0.1,) * 3, (0.0,) * 3)
+    U = np.zeros((I.NU_M1,) + ip.shape)
+    P = np.zeros((I.NP,) + ip.shape)
+    EM = np.zeros((I.NEM,) + ip.shape)
+    I.flat_spacetime(U)
+    P[I.RHO], P[I.EPS], P[I.YE] = 1e-3, 0.1, 0.1
+    Ud = torch.as_tensor(U).cuda()
+    mhd.prim2con(mhd.patch_of(ip), mhd.make_eos(I.EOS_IDEAL2), Ud, torch.as_tensor(P).cuda(),
+                 torch.as_tensor(EM).cuda(), 0)
+    U = Ud.cpu().numpy()
+    E0, eta, dt = 2e-5, 1e-7, 0.025
+    aux = np.zeros((9,) + ip.shape)
+    for kdt in (0.3, 10.0):
+        ka = kdt / dt
+        for s in range(3):
+            U[32 + 4 * s] = E0 * (s + 1)
+            aux[3 * s] = ka * (s + 1)
+            aux[3 * s + 2] = eta
+        r = ImexRun(ip, U, aux, I.EOS_IDEAL2, dict(I.PARAMS, couple_matter=0), periodic=True)
+        r.step(dt)
+        torch.cuda.synchronize()
+        out = r.Un.cpu().numpy()
+        for s in range(3):
+            k = ka * (s + 1)
+            z = -k * dt
+            R = 1.0 + z * b @ np.linalg.solve(np.eye(4) - z * A, np.ones(4))
+            want = eta / k + R * (E0 * (s + 1) - eta / k)
+            got = out[32 + 4 * s][ip.interior()]
+            tol = 64 * np.finfo(float).eps * (1.0 + abs(z)) * E0 * (s + 1)
+            assert np.abs(got - want).max() <= tol, (kdt, s, got.ravel()[0], want)
