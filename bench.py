@@ -138,12 +138,12 @@ def level_paths(torch, mhd, I, args, mlp):
     from paper_2510_13965_amd.step import LevelRun
 
     t0 = time.perf_counter()
-    boxes = I.c3_boxes(nboxes=args.level_boxes)
+    boxes = I.amr_level_boxes(nboxes=args.level_boxes)
     Ab = I.star_field_amplitude()
     eos = mhd.make_eos(I.EOS_IDEAL2)
     ips, states = [], []
     for b in boxes:
-        ip, U, P, EM = I.c3_box_state(b, Ab)
+        ip, U, P, EM = I.amr_box_state(b, Ab)
         Ud = torch.as_tensor(U).cuda()
         mhd.prim2con(mhd.patch_of(ip), eos, Ud, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
         ips.append(ip)
@@ -211,7 +211,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     mhd.lib()
-    ip, U, P, EM = I.c2_state(n=args.n)
+    ip, U, P, EM = I.tov_star_state(n=args.n)
     dev = "cuda"
     say("building the %d^3 star patch" % args.n)
     run = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS, periodic=False, device=dev)

@@ -10,7 +10,7 @@
  * operations, same order, no contraction), so the counts are those of the
  * oracle's own evaluation of the workload.
  *
- * Categories: add/sub, mul, div, sqrt, transcendental (pow, exp, log, cbrt),
+ * Categories: add/sub, mul, div, sqrt, transcendental (pow, exp, log, cbrt, tanh),
  * compare/min/max/abs, negation.  A "flop" is one of the first five.
  */
 #ifndef ORC_OPCOUNT_HPP
@@ -41,6 +41,7 @@ struct ocd {
   ocd() = default;
   constexpr ocd(double x) : v(x) {}
   explicit operator double() const { return v; }
+  explicit operator float() const { return (float)v; }
   ocd& operator+=(ocd o) { oc_tick(OC_ADD); v = v + o.v; return *this; }
   ocd& operator-=(ocd o) { oc_tick(OC_ADD); v = v - o.v; return *this; }
   ocd& operator*=(ocd o) { oc_tick(OC_MUL); v = v * o.v; return *this; }
@@ -65,6 +66,8 @@ static inline ocd cbrt(ocd a) { oc_tick(OC_TRANS); return ocd(std::cbrt(a.v)); }
 static inline ocd pow(ocd a, ocd b) { oc_tick(OC_TRANS); return ocd(std::pow(a.v, b.v)); }
 static inline ocd exp(ocd a) { oc_tick(OC_TRANS); return ocd(std::exp(a.v)); }
 static inline ocd log(ocd a) { oc_tick(OC_TRANS); return ocd(std::log(a.v)); }
+static inline ocd log10(ocd a) { oc_tick(OC_TRANS); return ocd(std::log10(a.v)); }
+static inline ocd tanh(ocd a) { oc_tick(OC_TRANS); return ocd(std::tanh(a.v)); }
 static inline ocd fabs(ocd a) { oc_tick(OC_CMP); return ocd(std::fabs(a.v)); }
 static inline ocd fmax(ocd a, ocd b) { oc_tick(OC_CMP); return ocd(std::fmax(a.v, b.v)); }
 static inline ocd fmin(ocd a, ocd b) { oc_tick(OC_CMP); return ocd(std::fmin(a.v, b.v)); }

@@ -30,7 +30,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 sys.path.insert(0, ROOT)
 
-SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c"]
+SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c", "m1.c", "mlp.c"]
 PHASES = ["other", "ccz4", "mhd_point", "mhd_recon", "mhd_update", "con2prim", "rk", "prim2con"]
 CATS = ["add", "mul", "div", "sqrt", "trans", "cmp", "neg"]
 RUNTIME = r'''
@@ -85,7 +85,7 @@ def main():
             a = np.array(list(buf), dtype=np.float64).reshape(8, 7)
             return a
 
-        ip, U, P, EM = I.c2_state(n=args.n)
+        ip, U, P, EM = I.tov_star_state(n=args.n)
         g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
         e = orc.make_eos(I.EOS_IDEAL2)
         par = orc.make_par(I.PARAMS)

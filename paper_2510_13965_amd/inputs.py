@@ -9,20 +9,22 @@ and the CPU oracle start from what it returns.
 Array layout everywhere: numpy float64, shape (nfields, Nz, Ny, Nx) over the
 padded patch (N = n + 2*ng per axis), x fastest.
 
-Workloads (seed of workload c is 2510139650 + c):
-  * C1  32^3 interior, dx = 0.25, periodic; Minkowski plus Gaussian bumps of
-        amplitude 1e-6 in the conformal metric and the lapse; ideal gas Gamma=2,
-        rho=1e-3, eps=0.1, velocity bumps of 1e-3, uniform B^z with b^2/rho=0.01.
-        ``c1_state(rich=True)`` also perturbs Khat, Theta, At_ij, Ghat^i and
-        beta^i so that every term (both upwind branches included) is exercised.
-  * C2  128^3 interior, dx = 0.25 on [-16,16]^3; TOV star K=100, Gamma=2,
+Workloads (seeds 2510139650 + k):
+  * perturbed flat patch: 32^3 interior, dx = 0.25, periodic; Minkowski plus
+        Gaussian bumps of amplitude 1e-6 in the conformal metric and the lapse;
+        ideal gas Gamma=2, rho=1e-3, eps=0.1, velocity bumps of 1e-3, uniform B^z
+        with b^2/rho=0.01.  ``perturbed_flat_state(rich=True)`` also perturbs
+        Khat, Theta, At_ij, Ghat^i and beta^i so that every term (both upwind
+        branches included) is exercised.
+  * TOV star patch: 128^3 interior, dx = 0.25 on [-16,16]^3; K=100, Gamma=2,
         rho_c=1.28e-3 in isotropic coordinates; poloidal B from
         A_phi ~ varpi^2 max(p - 0.04 p_max, 0)^2 scaled to max b^2/rho = 1e-3;
         atmosphere rho = 1e-12.
-  * C3  192 boxes, edges from {16,24,32,48,64}, three 2:1 levels, sampled from
-        the C2 star profile.
-  * C4  2^24 cells of random (rho, eps_th, W, sigma_m, metric) states for the
-        3-piece piecewise polytrope + thermal EoS.
+  * AMR level: 192 boxes, edges from {16,24,32,48,64}, three 2:1 levels,
+        sampled from the star profile.
+  * random con2prim cells: 2^24 cells of random (rho, eps_th, W, sigma_m,
+        metric) states for the 3-piece piecewise polytrope + thermal EoS.
+  * three grey M1 species on any of the patches (m1_fields).
 """
 import math
 
@@ -115,7 +117,7 @@ def flat_spacetime(U):
     U[ALPHA] = 1.0
 
 
-# ----------------------------------------------------------------------- C1
+# ----------------------------------------------------------------------- perturbed flat patch
 
 def _bumps(r, patch, X, Y, Z, amp, count=4):
     """Sum of `count` Gaussians (minimum-image periodic distance, width L/10),
@@ -135,7 +137,7 @@ def _bumps(r, patch, X, Y, Z, amp, count=4):
     return out
 
 
-def c1_state(seed=SEED0 + 1, n=32, rich=False):
+def perturbed_flat_state(seed=SEED0 + 1, n=32, rich=False):
     patch = Patch((n, n, n), (0.25,) * 3, (0.0,) * 3)
     r = rng(seed)
     Z, Y, X = patch.coords()
@@ -262,7 +264,7 @@ def _curl4(A, dx, trim):
 
 
 def star_fields(patch, tov=None, b_axis=(0.0, 0.0, 1.0), Ab=None, bmag=1e-3, rho_atm=1e-12):
-    """Spacetime, primitive and magnetic fields of the C2 star on `patch`.
+    """Spacetime, primitive and magnetic fields of the TOV star on `patch`.
 
     Returns U (spacetime part set), P (rho, eps, v=0, Ye), EM (B^i, phi=0) and the
     field amplitude Ab used (so that boxes of other patches can share it)."""
@@ -300,7 +302,7 @@ def star_fields(patch, tov=None, b_axis=(0.0, 0.0, 1.0), Ab=None, bmag=1e-3, rho
     return U, P, EM, Ab
 
 
-def c2_state(seed=SEED0 + 2, n=128):
+def tov_star_state(seed=SEED0 + 2, n=128):
     r = rng(seed)
     L = 32.0
     dx = L / n
@@ -313,9 +315,9 @@ def c2_state(seed=SEED0 + 2, n=128):
     return patch, U, P, EM
 
 
-# ----------------------------------------------------------------------- C3
+# ----------------------------------------------------------------------- AMR level
 
-def c3_boxes(seed=SEED0 + 3, nboxes=192, edges=(16, 24, 32, 48, 64)):
+def amr_level_boxes(seed=SEED0 + 3, nboxes=192, edges=(16, 24, 32, 48, 64)):
     """Box list of a batched AMR level: per box (n, dx, x0, level).
 
     Level l has dx = 1/2^l; the origin of a box is snapped to its own grid, and
@@ -336,23 +338,23 @@ def c3_boxes(seed=SEED0 + 3, nboxes=192, edges=(16, 24, 32, 48, 64)):
     return boxes
 
 
-def c3_box_state(box, Ab):
+def amr_box_state(box, Ab):
     patch = Patch(box["n"], box["dx"], box["x0"])
     U, P, EM, _ = star_fields(patch, Ab=Ab)
     return patch, U, P, EM
 
 
 def star_field_amplitude():
-    """Magnetic amplitude of the C2 star (shared by the C3 boxes)."""
+    """Magnetic amplitude of the star (shared by the AMR-level boxes)."""
     if "Ab" not in _TOV_CACHE:
         _, _, _, Ab = star_fields(Patch((32, 32, 32), (1.0,) * 3, (-15.5,) * 3))
         _TOV_CACHE["Ab"] = Ab
     return _TOV_CACHE["Ab"]
 
 
-# ----------------------------------------------------------------------- C4
+# ----------------------------------------------------------------------- random con2prim cells
 
-def c4_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None, log_rho=(-12.0, -3.0), log_eps=(-6.0, 0.0),
+def c2p_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None, log_rho=(-12.0, -3.0), log_eps=(-6.0, 0.0),
              log_sigma=(-4.0, 1.0), log_wm1=None, static_frac=0.0):
     """Random con2prim states laid out as a ghost-free patch.
 

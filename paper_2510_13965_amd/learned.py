@@ -39,10 +39,10 @@ def training_set(ncell, seed, eos_cfg=I.EOS_PWP3, device="cuda", **sampling):
     """(X, T) device tensors for `ncell` random con2prim states: raw features of
     the conserved state and the log-fraction targets of the plain solver's roots.
     Rows of atmosphere states are NaN (skipped by the kernels).  `sampling`
-    overrides the state distribution (inputs.c4_cells)."""
+    overrides the state distribution (inputs.c2p_cells)."""
     import torch
 
-    ip, U, P, EM = I.c4_cells(seed=seed, ncell=ncell, **sampling)
+    ip, U, P, EM = I.c2p_cells(seed=seed, ncell=ncell, **sampling)
     pt = mhd.patch_of(ip)
     eos = mhd.make_eos(eos_cfg)
     Ud = torch.as_tensor(U).to(device)

@@ -63,7 +63,7 @@ def compare_step(ip, U0, G, O, tag):
 
 def test_imex_step_parity_periodic_flat(orc, dev):
     say("case imex step, perturbed flat 16^3 periodic, stiff opacities")
-    ip, U, P, EM = I.c1_state(n=16, rich=True)
+    ip, U, P, EM = I.perturbed_flat_state(n=16, rich=True)
     g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
     orc.prim2con(g, orc.make_eos(I.EOS_IDEAL2), U, P, EM, 0)
     U44, aux = I.m1_fields(ip, U, P, I.SEED0 + 80)
@@ -74,7 +74,7 @@ def test_imex_step_parity_periodic_flat(orc, dev):
 
 def test_imex_step_parity_star_frozen_ghosts(orc, dev):
     say("case imex step, star 32^3 frozen ghosts")
-    ip, U, P, EM = I.c2_state(n=32)
+    ip, U, P, EM = I.tov_star_state(n=32)
     g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
     orc.prim2con(g, orc.make_eos(I.EOS_IDEAL2), U, P, EM, 0)
     U44, aux = I.m1_fields(ip, U, P, I.SEED0 + 81)

@@ -136,7 +136,7 @@ def test_mlp_features_parity(orc, dev):
     from paper_2510_13965_amd import mhd
 
     say("case mlp features 2^12")
-    ip, U, P, EM = I.c4_cells(ncell=1 << 12, seed=77)
+    ip, U, P, EM = I.c2p_cells(ncell=1 << 12, seed=77)
     g = orc.make_grid(ip.n, ip.dx, ng=0)
     e = orc.make_eos(I.EOS_PWP3)
     orc.prim2con(g, e, U, P, EM, 1)
@@ -239,7 +239,7 @@ def test_learned_c2p_untrained_is_plain(orc, dev):
     import torch
 
     say("case learned c2p, random weights, 2^14")
-    ip, U, P, EM = I.c4_cells(ncell=1 << 14, seed=91)
+    ip, U, P, EM = I.c2p_cells(ncell=1 << 14, seed=91)
     g = orc.make_grid(ip.n, ip.dx, ng=0)
     orc.prim2con(g, orc.make_eos(I.EOS_PWP3), U, P, EM, 1)
     prm = torch.as_tensor(rand_params(8, scale=0.05)).cuda()
@@ -259,7 +259,7 @@ def test_learned_c2p_trained_parity_and_gain(orc, dev):
     prm, hist = learned.train(X, T, seed=3, epochs=40, batch=1024)
     say("training loss per epoch: first %.3e last %.3e" % (hist[0], hist[-1]))
     assert hist[-1] < 0.2 * hist[0]
-    ip, U, P, EM = I.c4_cells(ncell=1 << 16, seed=I.SEED0 + 41)
+    ip, U, P, EM = I.c2p_cells(ncell=1 << 16, seed=I.SEED0 + 41)
     g = orc.make_grid(ip.n, ip.dx, ng=0)
     orc.prim2con(g, orc.make_eos(I.EOS_PWP3), U, P, EM, 1)
     out = c2p_both(ip, U, prm, I.EOS_PWP3)

@@ -38,12 +38,12 @@ def level_states(dev):
     import torch
     from paper_2510_13965_amd import mhd
 
-    boxes = I.c3_boxes(seed=I.SEED0 + 30, nboxes=8, edges=(16, 24, 32))
+    boxes = I.amr_level_boxes(seed=I.SEED0 + 30, nboxes=8, edges=(16, 24, 32))
     Ab = I.star_field_amplitude()
     eos = mhd.make_eos(I.EOS_IDEAL2)
     out = []
     for b in boxes:
-        ip, U, P, EM = I.c3_box_state(b, Ab)
+        ip, U, P, EM = I.amr_box_state(b, Ab)
         Ud = torch.as_tensor(U).cuda()
         mhd.prim2con(mhd.patch_of(ip), eos, Ud, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
         out.append((ip, Ud.cpu().numpy()))

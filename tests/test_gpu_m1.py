@@ -82,7 +82,7 @@ def compare(ip, G, O, tag):
 
 def test_m1_rhs_parity_perturbed_flat(orc, dev):
     say("case m1 rhs, perturbed flat 24^3")
-    ip, U, P, EM = I.c1_state(n=24, rich=True)
+    ip, U, P, EM = I.perturbed_flat_state(n=24, rich=True)
     U44, aux = with_m1(orc, ip, U, P, EM, seed=I.SEED0 + 60)
     O, mso = oracle_full(orc, ip, U44, aux)
     G, msg = gpu_full(ip, U44, aux)
@@ -92,7 +92,7 @@ def test_m1_rhs_parity_perturbed_flat(orc, dev):
 
 def test_m1_rhs_parity_star(orc, dev):
     say("case m1 rhs, star 40^3")
-    ip, U, P, EM = I.c2_state(n=40)
+    ip, U, P, EM = I.tov_star_state(n=40)
     U44, aux = with_m1(orc, ip, U, P, EM, seed=I.SEED0 + 61)
     O, mso = oracle_full(orc, ip, U44, aux)
     G, msg = gpu_full(ip, U44, aux)
@@ -106,7 +106,7 @@ def test_m1_rk4_step_parity(orc, dev):
     from paper_2510_13965_amd.step import PatchRun
 
     say("case m1 rk4 step, perturbed flat 20^3")
-    ip, U, P, EM = I.c1_state(n=20, rich=True)
+    ip, U, P, EM = I.perturbed_flat_state(n=20, rich=True)
     U44, aux = with_m1(orc, ip, U, P, EM, seed=I.SEED0 + 62)
     dt = 0.25 * ip.dx[0]
     g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)

@@ -124,7 +124,7 @@ def prepared(orc, ip, U, P, EM, eos_cfg=I.EOS_IDEAL2):
 @pytest.mark.parametrize("case", ["c1", "c1_rich", "c1_harmonic_nomatter"])
 def test_rhs_parity_c1(orc, dev, case):
     say("case", case)
-    ip, U, P, EM = I.c1_state(rich=(case != "c1"))
+    ip, U, P, EM = I.perturbed_flat_state(rich=(case != "c1"))
     U = prepared(orc, ip, U, P, EM)
     par = dict(I.PARAMS)
     if case == "c1_harmonic_nomatter":
@@ -145,7 +145,7 @@ def test_rhs_parity_c1(orc, dev, case):
 
 def test_rhs_parity_c2_full(orc, dev):
     say("case c2 128^3")
-    ip, U, P, EM = I.c2_state()
+    ip, U, P, EM = I.tov_star_state()
     U = prepared(orc, ip, U, P, EM)
     Uo, Po, flo, muo = oracle_prims(orc, ip, U)
     O, ms_o = oracle_rhs(orc, ip, Uo, Po, I.PARAMS)
@@ -231,7 +231,7 @@ def test_con2prim_parity_random_states(orc, dev):
     primitives agree to 1e-12 on well-conditioned cells and every cell's
     primitives reproduce the conserved input to 1e-12 (backward error)."""
     say("case c2p random 2^16")
-    ip, U, P, EM = I.c4_cells(ncell=1 << 16, seed=4242)
+    ip, U, P, EM = I.c2p_cells(ncell=1 << 16, seed=4242)
     g = orc.make_grid(ip.n, ip.dx, ng=0)
     e = orc.make_eos(I.EOS_PWP3)
     orc.prim2con(g, e, U, P, EM, 1)
@@ -374,10 +374,10 @@ def test_rk4_step_parity(orc, dev, case):
 
     say("case rk4 step", case)
     if case == "c1":
-        ip, U, P, EM = I.c1_state(rich=True)
+        ip, U, P, EM = I.perturbed_flat_state(rich=True)
         periodic = True
     else:
-        ip, U, P, EM = I.c2_state(n=48)
+        ip, U, P, EM = I.tov_star_state(n=48)
         periodic = False
     U = prepared(orc, ip, U, P, EM)
     dt = 0.25 * ip.dx[0]

@@ -112,7 +112,7 @@ def _roundtrip(orc, eos, patch, U, P, EM, eps_mode):
 
 
 def test_roundtrip_well_conditioned(orc, eos_ideal):
-    patch, U, P, EM = I.c1_state(n=8)
+    patch, U, P, EM = I.perturbed_flat_state(n=8)
     g, U0, P0, U1, Pr, flags, mu, nf = _roundtrip(orc, eos_ideal, patch, U, P, EM, 0)
     assert nf == 0 and not flags.any()
     for c in (I.RHO, I.EPS, I.PRESS, I.VX, I.VY, I.VZ, I.WLOR, I.YE):
@@ -122,7 +122,7 @@ def test_roundtrip_well_conditioned(orc, eos_ideal):
 
 
 def test_backward_error_random_states(orc, eos_pwp):
-    patch, U, P, EM = I.c4_cells(ncell=1 << 14, seed=12345)
+    patch, U, P, EM = I.c2p_cells(ncell=1 << 14, seed=12345)
     g, U0, P0, U1, Pr, flags, mu, nf = _roundtrip(orc, eos_pwp, patch, U, P, EM, 1)
     ok = flags == 0
     assert ok.mean() > 0.95
@@ -150,7 +150,7 @@ def test_root_is_root(orc, eos_pwp):
     """At the returned mu, f changes sign within a few ulp (checked by
     re-solving with brackets pinched around mu is not exposed; instead perturb
     the conserved data so the solution moves smoothly: mu must be continuous)."""
-    patch, U, P, EM = I.c4_cells(ncell=64, seed=99)
+    patch, U, P, EM = I.c2p_cells(ncell=64, seed=99)
     g, U0, P0, U1, Pr, flags, mu, nf = _roundtrip(orc, eos_pwp, patch, U, P, EM, 1)
     U2 = U0.copy()
     U2[I.TAUBAR] *= 1 + 1e-9

@@ -73,7 +73,7 @@ def test_uniform_relaxation_matches_stability_function(kdt):
 
 
 def test_no_collisions_is_rk4():
-    ip, U, P, EM = I.c1_state(n=8, rich=True)
+    ip, U, P, EM = I.perturbed_flat_state(n=8, rich=True)
     g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
     e = orc.make_eos(I.EOS_IDEAL2)
     orc.prim2con(g, e, U, P, EM, 0)
@@ -101,7 +101,7 @@ def test_no_collisions_is_rk4():
 
 
 def test_implicit_solves_converge_on_rough_fields():
-    ip, U, P, EM = I.c1_state(n=8, rich=True)
+    ip, U, P, EM = I.perturbed_flat_state(n=8, rich=True)
     g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
     e = orc.make_eos(I.EOS_IDEAL2)
     orc.prim2con(g, e, U, P, EM, 0)
