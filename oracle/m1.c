@@ -293,6 +293,7 @@ static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, 
   double vmax = 0.0;
   int64_t p;
 
+  ORC_PHASE(ORC_PH_M1_POINT);
 #pragma omp parallel for schedule(static)
   for (p = 0; p < N; ++p) {
     m1_metric m;
@@ -319,6 +320,7 @@ static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, 
     }
   }
 
+  ORC_PHASE(ORC_PH_M1_UPD);
 #pragma omp parallel for collapse(2) schedule(static) reduction(max : vmax)
   for (int64_t k = ng; k < Nz - ng; ++k)
     for (int64_t j = ng; j < Ny - ng; ++j)
@@ -350,14 +352,19 @@ static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, 
               const double* f = FL + ((sp * 3 + d) * 4 + c) * N;
               const double* kap = aux + (3 * sp) * N;
               const double* kas = aux + (3 * sp + 1) * N;
-              const double fr = holo(u, f, lam, kap, kas, q, st[d], g->dx[d]);
-              const double fl = holo(u, f, lam, kap, kas, q - st[d], st[d], g->dx[d]);
+              double fr, fl;
+              ORC_PHASE(ORC_PH_M1_HOLO);
+              fr = holo(u, f, lam, kap, kas, q, st[d], g->dx[d]);
+              fl = holo(u, f, lam, kap, kas, q - st[d], st[d], g->dx[d]);
+              ORC_PHASE(ORC_PH_M1_UPD);
               out[c] -= (fr - fl) / g->dx[d];
             }
           }
           /* geometric sources */
+          ORC_PHASE(ORC_PH_M1_RECL);
           point_state(U, P, N, q, sp, &m, &s);
           closure(&s, Pij, &J, H, &chi, NULL);
+          ORC_PHASE(ORC_PH_M1_UPD);
           for (a = 0; a < 3; ++a)
             for (b = 0; b < 3; ++b) {
               double t = 0.0;
@@ -403,6 +410,7 @@ static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, 
           for (c = 0; c < 4; ++c) rhs[(32 + 4 * sp + c) * N + q] = out[c];
         }
       }
+  ORC_PHASE(ORC_PH_OTHER);
   free(FL);
   free(LM);
   if (max_speed) *max_speed = fmax(*max_speed, vmax);

@@ -28,7 +28,7 @@
 enum { OC_ADD, OC_MUL, OC_DIV, OC_SQRT, OC_TRANS, OC_CMP, OC_NEG, OC_NCAT };
 
 extern "C" {
-extern long long orc_opc[8][OC_NCAT];
+extern long long orc_opc[16][OC_NCAT];
 extern int orc_opc_phase;
 }
 

@@ -6,13 +6,16 @@ double operation counts itself into the phase the oracle names with
 ORC_PHASE), runs one evaluation of each step on the 128^3 TOV workload
 (single thread), and prints per-unit counts as JSON:
 
-  con2prim, prim2con, MHD point fluxes: per padded point
-  CCZ4, MHD conservative update:         per interior point
+  con2prim, prim2con, MHD/M1 point fluxes: per padded point
+  CCZ4, MHD/M1 conservative update:         per interior point
   RK stage:                               per interior point and field
 
-The oracle evaluates each MHD interface twice (once from each neighbouring
-point); the algorithmic count takes every interface once, i.e. the counted
-reconstruction work times (n+1)/(2n) per axis line.
+The oracle evaluates each MHD and M1 interface twice (once from each
+neighbouring point); the algorithmic count takes every interface once, i.e.
+the counted interface work times (n+1)/(2n) per axis line.  The M1 counts come
+from one evaluation with three grey species on the same star (M1 point work
+per padded point; M1 update per interior point, without the oracle's second
+closure evaluation at the point, which the algorithmic count takes once).
 
 Usage: python oracle/opcount.py [--n 128]
 """
@@ -31,18 +34,20 @@ ROOT = os.path.dirname(HERE)
 sys.path.insert(0, ROOT)
 
 SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c", "m1.c", "mlp.c"]
-PHASES = ["other", "ccz4", "mhd_point", "mhd_recon", "mhd_update", "con2prim", "rk", "prim2con"]
+PHASES = ["other", "ccz4", "mhd_point", "mhd_recon", "mhd_update", "con2prim", "rk", "prim2con",
+          "m1_point", "m1_holo", "m1_update", "m1_reclosure"]
+NROW = 16
 CATS = ["add", "mul", "div", "sqrt", "trans", "cmp", "neg"]
 RUNTIME = r'''
 extern "C" {
-long long orc_opc[8][7];
+long long orc_opc[16][7];
 int orc_opc_phase;
 void orc_opc_read(long long* out) {
-  for (int p = 0; p < 8; ++p)
+  for (int p = 0; p < 16; ++p)
     for (int c = 0; c < 7; ++c) out[p * 7 + c] = orc_opc[p][c];
 }
 void orc_opc_reset(void) {
-  for (int p = 0; p < 8; ++p)
+  for (int p = 0; p < 16; ++p)
     for (int c = 0; c < 7; ++c) orc_opc[p][c] = 0;
   orc_opc_phase = 0;
 }
@@ -77,13 +82,13 @@ def main():
         so = build(td)
         orc.use_library(so)
         L = C.CDLL(so)
-        buf = (C.c_longlong * 56)()
+        buf = (C.c_longlong * (NROW * 7))()
 
         def take():
             L.orc_opc_read(buf)
             L.orc_opc_reset()
-            a = np.array(list(buf), dtype=np.float64).reshape(8, 7)
-            return a
+            a = np.array(list(buf), dtype=np.float64).reshape(NROW, 7)
+            return a[:len(PHASES)]
 
         ip, U, P, EM = I.tov_star_state(n=args.n)
         g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
@@ -105,9 +110,15 @@ def main():
         for st in range(4):
             orc.rk4_stage_interior(g, I.NU, st, 0.25 * ip.dx[0], U, k, acc, Us if st < 3 else U.copy())
         c_rk = take()
+        # grey M1, three species, on the same star
+        U44, aux = I.m1_fields(ip, U, Pr, I.SEED0 + 61)
+        k44 = np.zeros_like(U44)
+        orc.rhs_full(g, orc.make_par(dict(I.PARAMS, evolve_m1=1)), e, U44, Pr, aux, k44)
+        c_m1 = take()
 
     nint, npad, n = ip.ninterior, ip.npts, args.n
     tot = c_p2c + c_c2p + c_rhs + c_rk
+    m1 = c_m1
 
     def per(ph, unit):
         row = tot[PHASES.index(ph)] / unit
@@ -119,6 +130,16 @@ def main():
     iface = (n + 1) / (2.0 * n)
     upd = per("mhd_update", nint)
     upd_alg = {c: round(upd[c] + recon[c] * iface, 2) for c in upd}
+
+    def per_m1(ph, unit):
+        row = m1[PHASES.index(ph)] / unit
+        d = {c: round(float(v), 2) for c, v in zip(CATS, row)}
+        d["flop"] = round(float(row[:5].sum()), 2)
+        return d
+
+    holo = per_m1("m1_holo", nint)
+    m1u = per_m1("m1_update", nint)
+    m1u_alg = {c: round(m1u[c] + holo[c] * iface, 2) for c in m1u}
     out = {
         "workload": "TOV star, %d^3 interior, dx=%.4g, ideal gas Gamma=2, one evaluation of each step" % (n, ip.dx[0]),
         "interior_points": nint, "padded_points": npad,
@@ -127,7 +148,9 @@ def main():
         "per_padded_point": {"con2prim": per("con2prim", npad), "prim2con": per("prim2con", npad),
                              "mhd_point_3axes": per("mhd_point", npad)},
         "per_interior_point": {"ccz4": per("ccz4", nint), "mhd_recon_as_evaluated": recon,
-                               "mhd_update_algorithmic": upd_alg},
+                               "mhd_update_algorithmic": upd_alg,
+                               "m1_holo_as_evaluated": holo, "m1_update_algorithmic": m1u_alg},
+        "per_padded_point_m1": {"m1_point_3species_3axes": per_m1("m1_point", npad)},
         "per_interior_point_and_field": {"rk_stage": per("rk", nint * I.NU * 4)},
     }
     print(json.dumps(out, indent=1))

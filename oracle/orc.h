@@ -49,7 +49,11 @@ extern "C" { /* the op-counting build compiles these sources as C++ */
 #define ORC_PH_C2P 5       /* con2prim incl. rewriting corrected points */
 #define ORC_PH_RK 6        /* RK stage */
 #define ORC_PH_P2C 7       /* prim -> cons */
-#define ORC_NPHASE 8
+#define ORC_PH_M1_POINT 8  /* M1 closure, point fluxes and speeds */
+#define ORC_PH_M1_HOLO 9   /* M1 HO/LO flux at one interface */
+#define ORC_PH_M1_UPD 10   /* M1 flux difference, geometric and collision sources */
+#define ORC_PH_M1_RECL 11  /* closure re-evaluated for the sources (computed once per point above) */
+#define ORC_NPHASE 12
 
 #define ORC_NST 22
 #define ORC_NMHD 10
