@@ -126,9 +126,8 @@ def m1_path(torch, mhd, I, ip, U, P, EM, args):
     prof = mhd.profile_stop()
     fin = bool(torch.isfinite(run.Un).all().item())
     say("m1 path: %.3f ms/step" % ms)
-    per = {k: round(t / n, 4) for k, (n, t) in prof.items()}
     return {"zone_updates_per_s": round(ip.ninterior * 4 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-            "evolved_fields": 44, "finite": fin, "ms_per_launch": per}
+            "evolved_fields": 44, "finite": fin, "kernels": kernel_table(prof, ip, args.steps + 1, nfields=44)}
 
 
 def level_paths(torch, mhd, I, args, mlp):
@@ -284,13 +283,18 @@ def main():
 # (the oracle's own evaluation with an op-counting scalar type; add/sub, mul,
 # div, sqrt and pow/exp/log count one flop each).  Units: interior points for
 # the RHS kernels, padded points for con2prim and the point fluxes, interior
-# point-fields for the RK stage.  The MHD update counts every interface once.
+# point-fields for the RK stage.  The MHD and M1 updates count every interface
+# once; the M1 point kernel (closure root, point fluxes and speeds of three
+# species on three axes) and the M1 update were counted with three grey species
+# on the same star.
 FLOP_PER_UNIT = {
     "k_con2prim": 188.85,
     "k_mhd_point": 1608.0,
     "k_mhd_update": 5136.11,
     "ccz4 (4 kernels)": 10396.0,
     "k_rk4_stage": 4.75,
+    "k_m1_point": 15301.03,
+    "k_m1_update": 2855.5,
 }
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc (FETCH_SIZE x 2
 # + WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read and write 1 GiB),
@@ -309,11 +313,11 @@ def sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def kernel_table(prof, ip, steps):
+def kernel_table(prof, ip, steps, nfields=32):
     """Per-kernel launches and event-timed durations, with the achieved FP64
     rate of the algorithmic flops where the count exists."""
     units = {"k_con2prim": ip.npts, "k_mhd_point": ip.npts, "k_mhd_update": ip.ninterior,
-             "k_rk4_stage": ip.ninterior * 32}
+             "k_rk4_stage": ip.ninterior * nfields, "k_m1_point": ip.npts, "k_m1_update": ip.ninterior}
     tab = {}
     for k, (n, t) in prof.items():
         e = {"launches": n, "ms_per_launch": round(t / n, 4), "ms_per_step": round(t / steps, 4)}
