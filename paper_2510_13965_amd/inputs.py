@@ -447,11 +447,15 @@ def m1_fields(patch, U32, P, seed):
     Ebar, Fbar_i per species) and the 9 aux fields (kappa_a, kappa_s, eta).
 
     Ebar = 10^(-10 + 6 s(x)) with s a smooth field in [0, 1] (so Ebar spans
-    [1e-10, 1e-4]); Fbar_i = f(x) Ebar d_i/|d| with f smooth in [0, 0.95] and d a
-    smooth direction field (|F|/E <= 0.95 wherever chi <= 1 and the conformal
-    metric is flat, as on the star and the perturbed flat patches); kappa_a,
-    kappa_s log-uniform in [1e-8, 1e-2] per point and species; eta = kappa_a
-    E_eq with E_eq = 1e-2 rho eps."""
+    [1e-10, 1e-4]); Fbar_i = f(x) Ebar d_i/|d| with d a smooth direction field
+    and f = 0.95 (w s'(x) + 1 - w), s' smooth in [0, 1] and w = min(rho/1e-4, 1):
+    random flux factors in dense matter, near free streaming where it thins out (|F|/E <= 0.95 wherever chi <= 1 and the conformal
+    metric is flat, as on the star and the perturbed flat patches).
+    Opacities scale with the density, as matter opacities do: kappa_a, kappa_s
+    = khat rho / 1e-3 with khat log-uniform in [1e-3, 1] per point and species
+    (so radiation streams freely through the atmosphere and kappa dt stays
+    well inside the explicit RK4 stability interval at the star's densities);
+    eta = kappa_a E_eq with E_eq = 1e-2 rho eps."""
     r = rng(seed)
     Z, Y, X = patch.coords()
     U = np.zeros((NU_M1,) + patch.shape)
@@ -459,14 +463,16 @@ def m1_fields(patch, U32, P, seed):
     aux = np.zeros((NAUX,) + patch.shape)
     for s in range(3):
         Eb = 10.0 ** (-10.0 + 6.0 * _smooth01(r, patch, X, Y, Z))
-        frac = 0.95 * _smooth01(r, patch, X, Y, Z)
+        # free streaming (|F|/E -> 0.95) where the matter thins out
+        wm = np.minimum(P[RHO] / 1e-4, 1.0)
+        frac = 0.95 * (wm * _smooth01(r, patch, X, Y, Z) + (1.0 - wm))
         d = np.array([2.0 * _smooth01(r, patch, X, Y, Z) - 1.0 for _ in range(3)]) + 1e-3
         d /= np.sqrt((d * d).sum(0))
         U[32 + 4 * s] = Eb
         for a in range(3):
             U[33 + 4 * s + a] = frac * Eb * d[a]
-        ka = 10.0 ** r.uniform(-8.0, -2.0, patch.shape)
-        ks = 10.0 ** r.uniform(-8.0, -2.0, patch.shape)
+        ka = 10.0 ** r.uniform(-3.0, 0.0, patch.shape) * (P[RHO] / 1e-3)
+        ks = 10.0 ** r.uniform(-3.0, 0.0, patch.shape) * (P[RHO] / 1e-3)
         aux[3 * s] = ka
         aux[3 * s + 1] = ks
         aux[3 * s + 2] = ka * 1e-2 * P[RHO] * P[EPS]

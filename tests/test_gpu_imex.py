@@ -67,7 +67,7 @@ def test_imex_step_parity_periodic_flat(orc, dev):
     g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
     orc.prim2con(g, orc.make_eos(I.EOS_IDEAL2), U, P, EM, 0)
     U44, aux = I.m1_fields(ip, U, P, I.SEED0 + 80)
-    aux[0::3] *= 1e3     # kappa_a up to 10: kappa dt up to 0.6
+    aux[0::3] *= 10.0    # kappa_a up to 10: kappa dt up to 0.6
     G, O = run_both(orc, ip, U44, aux, 0.25 * ip.dx[0], True, I.PARAMS)
     compare_step(ip, U44, G, O, "flat")
 

@@ -106,7 +106,7 @@ def test_implicit_solves_converge_on_rough_fields():
     e = orc.make_eos(I.EOS_IDEAL2)
     orc.prim2con(g, e, U, P, EM, 0)
     U44, aux = I.m1_fields(ip, U, P, 78)
-    aux[0::3] *= 1e4   # stiff absorption
+    aux[0::3] *= 1e2   # stiff absorption: kappa_a up to 100
     par = orc.make_par(dict(I.PARAMS, evolve_m1=1))
     assert orc.imex_step(g, par, e, U44, aux, 0.25 * ip.dx[0]) == 0
     assert np.isfinite(U44).all()
