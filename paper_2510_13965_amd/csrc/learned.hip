@@ -525,8 +525,9 @@ struct LearnedArgs {
 
 constexpr int kNewtonIt = 3;
 
-// Newton on F from x0 with at most kNewtonIt updates; accepted when |F(x)| <=
-// tol(x) (then one more correction is applied), 0 < x <= hi, and F changes
+// Newton on F from x0 with at most kNewtonIt updates (iterates clamped to hi);
+// accepted when |F(x)| <= tol(x) (then one more correction is applied),
+// 0 < x <= hi, and F changes
 // sign across [x (1 - 5e-13), min(x (1 + 5e-13), hi)] (F increases through
 // its only root in the bracket), which puts x within 5e-13 relative of the
 // root.  nev counts the function evaluations.
@@ -550,8 +551,10 @@ __device__ __forceinline__ bool newton_polish(const FnD& F, const Fn& Fv, double
       return true;
     }
     if (it == kNewtonIt || !(r.d != 0.0)) return false;
-    x = x - r.v / r.d;
-    if (!(x > 0.0 && x <= hi)) return false;
+    // an update past the bracket's upper end restarts from that end, where F
+    // is known to be positive (roots close to it are common)
+    x = fmin(x - r.v / r.d, hi);
+    if (!(x > 0.0)) return false;
   }
   return false;
 }
