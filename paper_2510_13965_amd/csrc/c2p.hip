@@ -9,8 +9,8 @@
 // interpolation / secant steps safeguarded by bisection) until the bracket is
 // a few ulp wide; primitives from mu; then the error policy.
 //
-// One thread per padded point.  Iteration counts differ from lane to lane, so
-// the kernel is divergence bound; the learned-guess path in learned.hip
+// Threads stride over the padded points.  Iteration counts differ from lane
+// to lane, so the kernel is divergence bound; the learned-guess path in learned.hip
 // replaces most of the Brent iterations with three Newton steps.
 #include "c2p_dev.hpp"
 #include "prof.hpp"
@@ -27,45 +27,50 @@ struct C2pArgs {
   int64_t* __restrict__ stats;
 };
 
-// padded indices; every lane of the wavefront calls this (statistics are a
-// wavefront reduction)
-__device__ __forceinline__ void con2prim_at(const C2pArgs& a, const mhd_eos_t& eos, int i, int j, int k, bool live) {
+// padded indices; adds the point's statistics to the counters
+__device__ __forceinline__ void con2prim_at(const C2pArgs& a, const mhd_eos_t& eos, int i, int j, int k,
+                                            int64_t& nfatal, int64_t& ncorr, int64_t& nit) {
   const Geom& g = a.g;
-  int64_t nfatal = 0, ncorr = 0, nit = 0;
-  if (live) {
-    const int64_t p = g.at(i, j, k);
-    C2pPoint pt;
-    load_point(a.U, g.sf, p, pt);
-    C2pOut o;
-    c2p_plain(eos, pt, o);
-    store_point(a.U, a.P, a.flags, a.mu, g.sf, p, pt, o);
-    nfatal = (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
-    ncorr = (o.flags & C2P_CORRECTED) ? 1 : 0;
-    nit = o.iters;
-  }
-  if (a.stats) wave_add_stats(a.stats, nfatal, ncorr, 0, nit);
+  const int64_t p = g.at(i, j, k);
+  C2pPoint pt;
+  load_point(a.U, g.sf, p, pt);
+  C2pOut o;
+  c2p_plain(eos, pt, o);
+  store_point(a.U, a.P, a.flags, a.mu, g.sf, p, pt, o);
+  nfatal += (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
+  ncorr += (o.flags & C2P_CORRECTED) ? 1 : 0;
+  nit += o.iters;
 }
 
-__global__ void __launch_bounds__(256) k_con2prim(C2pArgs a) {
+// grid-stride over the padded points in memory order
+__global__ void __launch_bounds__(256) k_con2prim(C2pArgs a, int64_t npts) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(a.eos, seos);
   const Geom& g = a.g;
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  con2prim_at(a, a.eos, i, j, k, i < Nx && j < Ny);
+  int64_t nfatal = 0, ncorr = 0, nit = 0;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npts; t += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t % Nx), j = (int)((t / Nx) % Ny), k = (int)(t / ((int64_t)Nx * Ny));
+    con2prim_at(a, eos, i, j, k, nfatal, ncorr, nit);
+  }
+  if (a.stats) block_add_stats(a.stats, nfatal, ncorr, 0, nit);
 }
 
 __global__ void __launch_bounds__(256) k_con2prim_lv(LevelArgs L) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(L.eos, seos);
+  int64_t nfatal = 0, ncorr = 0, nit = 0;
   for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    C2pArgs a;  // eos stays in the kernel arguments (read with dynamic indices)
+    C2pArgs a;  // the EoS is read from LDS
     a.g = B.g;
     a.U = L.src ? B.Us : B.U;
     a.P = B.P;
     a.flags = B.flags;
     a.mu = nullptr;
     a.stats = L.stats;
-    con2prim_at(a, L.eos, i, j, k, live);
+    if (live) con2prim_at(a, eos, i, j, k, nfatal, ncorr, nit);
   });
+  if (L.stats) block_add_stats(L.stats, nfatal, ncorr, 0, nit);
 }
 
 int launch_con2prim_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
@@ -117,8 +122,9 @@ __global__ void __launch_bounds__(256) k_prim2con(P2cArgs a) {
 int launch_con2prim(const Geom& g, const mhd_eos_t& eos, double* U, double* P, uint8_t* flags, double* mu,
                     int64_t* stats, hipStream_t s) {
   C2pArgs a{g, eos, U, P, flags, mu, stats};
-  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
-  MHD_LAUNCH(KID_CON2PRIM, k_con2prim, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
+  const int64_t npts = (int64_t)(g.nx + 2 * g.ng) * (g.ny + 2 * g.ng) * (g.nz + 2 * g.ng);
+  const int64_t nblk = (npts + 255) / 256;
+  MHD_LAUNCH(KID_CON2PRIM, k_con2prim, dim3((unsigned)(nblk < 2048 ? nblk : 2048)), dim3(256), 0, s, a, npts);
   return (int)hipGetLastError();
 }
 

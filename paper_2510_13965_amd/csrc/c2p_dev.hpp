@@ -394,9 +394,22 @@ __device__ __forceinline__ void store_point(double* __restrict__ U, double* __re
   }
 }
 
-// per-wavefront sums, one atomic per counter per wavefront
-__device__ __forceinline__ void wave_add_stats(int64_t* stats, int64_t nfatal, int64_t ncorr, int64_t nfb,
-                                               int64_t nit) {
+// The EoS copied to LDS by the block (every thread calls this): its piece
+// tables are read with lane-dependent indices, which kernel arguments would
+// serve through a private copy per lane.
+__device__ __forceinline__ const mhd_eos_t& stage_eos(const mhd_eos_t& e, mhd_eos_t& lds) {
+  if (threadIdx.x + threadIdx.y * blockDim.x == 0) lds = e;
+  __syncthreads();
+  return lds;
+}
+
+// Block-wide sums of the statistics, then at most one atomic per counter per
+// block: atomics on one address are serialised in L2, so one per wavefront
+// would dominate the cost of a cheap launch.  Every thread of the block (at
+// most 256 threads) must call this, once, after its last point.
+__device__ __forceinline__ void block_add_stats(int64_t* stats, int64_t nfatal, int64_t ncorr, int64_t nfb,
+                                                int64_t nit) {
+  __shared__ int64_t red[4][4];
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     nfatal += __shfl_xor(nfatal, off, 64);
@@ -404,12 +417,25 @@ __device__ __forceinline__ void wave_add_stats(int64_t* stats, int64_t nfatal, i
     nfb += __shfl_xor(nfb, off, 64);
     nit += __shfl_xor(nit, off, 64);
   }
-  const int lane = (threadIdx.x + threadIdx.y * blockDim.x) % 64;
-  if (lane == 0) {
-    if (nfatal) atomicAdd((unsigned long long*)&stats[MHD_STAT_FATAL], (unsigned long long)nfatal);
-    if (ncorr) atomicAdd((unsigned long long*)&stats[MHD_STAT_CORRECTED], (unsigned long long)ncorr);
-    if (nfb) atomicAdd((unsigned long long*)&stats[MHD_STAT_FALLBACK], (unsigned long long)nfb);
-    if (nit) atomicAdd((unsigned long long*)&stats[MHD_STAT_ITERATIONS], (unsigned long long)nit);
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int w = tid / 64;
+  if (tid % 64 == 0) {
+    red[w][0] = nfatal;
+    red[w][1] = ncorr;
+    red[w][2] = nfb;
+    red[w][3] = nit;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = (int)((blockDim.x * blockDim.y + 63) / 64);
+    int64_t sum[4] = {0, 0, 0, 0};
+    for (int v = 0; v < nw; ++v)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sum[c] += red[v][c];
+    if (sum[0]) atomicAdd((unsigned long long*)&stats[MHD_STAT_FATAL], (unsigned long long)sum[0]);
+    if (sum[1]) atomicAdd((unsigned long long*)&stats[MHD_STAT_CORRECTED], (unsigned long long)sum[1]);
+    if (sum[2]) atomicAdd((unsigned long long*)&stats[MHD_STAT_FALLBACK], (unsigned long long)sum[2]);
+    if (sum[3]) atomicAdd((unsigned long long*)&stats[MHD_STAT_ITERATIONS], (unsigned long long)sum[3]);
   }
 }
 

@@ -661,17 +661,26 @@ __device__ __forceinline__ void queue_append(bool take, T entry, uint32_t* count
   if (take) queue[base + __popcll(mask & ((1ull << l) - 1ull))] = entry;
 }
 
+// blocks stride over chunks of 256 padded points (the trip count is uniform
+// over the block: the network runs on whole wavefronts)
 __global__ void __launch_bounds__(256) k_c2p_learned(LearnedArgs a) {
   __shared__ MlpLds s;
   mlp_stage(a.prm, s);
   __syncthreads();
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool inside = t < a.npts;
-  const int i = inside ? (int)(t % a.Nx) : 0, j = inside ? (int)((t / a.Nx) % a.Ny) : 0;
-  const int k = inside ? (int)(t / ((int64_t)a.Nx * a.Ny)) : 0;
-  const LearnedOut r = learned_point(s, a.eos, a.g, a.U, a.P, a.flags, a.mu, i, j, k, inside);
-  queue_append<uint32_t>(r.fallback, (uint32_t)t, a.qcount, a.queue);
-  if (a.stats) wave_add_stats(a.stats, r.nfatal, r.ncorr, r.fallback ? 1 : 0, r.nit);
+  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.npts; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = base + threadIdx.x;
+    const bool inside = t < a.npts;
+    const int i = inside ? (int)(t % a.Nx) : 0, j = inside ? (int)((t / a.Nx) % a.Ny) : 0;
+    const int k = inside ? (int)(t / ((int64_t)a.Nx * a.Ny)) : 0;
+    const LearnedOut r = learned_point(s, a.eos, a.g, a.U, a.P, a.flags, a.mu, i, j, k, inside);
+    queue_append<uint32_t>(r.fallback, (uint32_t)t, a.qcount, a.queue);
+    nfatal += r.nfatal;
+    ncorr += r.ncorr;
+    nfb += r.fallback ? 1 : 0;
+    nit += r.nit;
+  }
+  if (a.stats) block_add_stats(a.stats, nfatal, ncorr, nfb, nit);
 }
 
 // level version: queue entries are (box << 32) | linear padded point of the box
@@ -679,17 +688,24 @@ __global__ void __launch_bounds__(256) k_c2p_learned_lv(LevelArgs L) {
   __shared__ MlpLds s;
   mlp_stage(L.mlp, s);
   __syncthreads();
+  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
   for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
     const LearnedOut r = learned_point(s, L.eos, B.g, L.src ? B.Us : B.U, B.P, B.flags, nullptr, i, j, k, live);
     const int Nx = B.g.nx + 2 * B.g.ng, Ny = B.g.ny + 2 * B.g.ng;
     const uint64_t box = (uint64_t)(&B - L.boxes);
     const uint64_t entry = (box << 32) | (uint64_t)((int64_t)i + (int64_t)Nx * ((int64_t)j + (int64_t)Ny * k));
     queue_append<uint64_t>(r.fallback, entry, L.qcount, L.queue);
-    if (L.stats) wave_add_stats(L.stats, r.nfatal, r.ncorr, r.fallback ? 1 : 0, r.nit);
+    nfatal += r.nfatal;
+    ncorr += r.ncorr;
+    nfb += r.fallback ? 1 : 0;
+    nit += r.nit;
   });
+  if (L.stats) block_add_stats(L.stats, nfatal, ncorr, nfb, nit);
 }
 
 __global__ void __launch_bounds__(256) k_c2p_fallback_lv(LevelArgs L) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(L.eos, seos);
   const uint32_t nq = *L.qcount;
   int64_t nfatal = 0, ncorr = 0, nit = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
@@ -703,18 +719,20 @@ __global__ void __launch_bounds__(256) k_c2p_fallback_lv(LevelArgs L) {
     C2pPoint pt;
     load_point(U, B.g.sf, p, pt);
     C2pOut o;
-    c2p_plain(L.eos, pt, o);
+    c2p_plain(eos, pt, o);
     o.flags |= MHD_FLAG_FALLBACK;
     store_point(U, B.P, B.flags, nullptr, B.g.sf, p, pt, o);
     nfatal += (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
     ncorr += (o.flags & C2P_CORRECTED) ? 1 : 0;
     nit += o.iters;
   }
-  if (L.stats) wave_add_stats(L.stats, nfatal, ncorr, 0, nit);
+  if (L.stats) block_add_stats(L.stats, nfatal, ncorr, 0, nit);
 }
 
 // the bracketed solver on the queued points (grid-strided over the queue)
 __global__ void __launch_bounds__(256) k_c2p_fallback(LearnedArgs a) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(a.eos, seos);
   const uint32_t nq = *a.qcount;
   int64_t nfatal = 0, ncorr = 0, nit = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
@@ -724,14 +742,14 @@ __global__ void __launch_bounds__(256) k_c2p_fallback(LearnedArgs a) {
     C2pPoint pt;
     load_point(a.U, a.g.sf, p, pt);
     C2pOut o;
-    c2p_plain(a.eos, pt, o);
+    c2p_plain(eos, pt, o);
     o.flags |= MHD_FLAG_FALLBACK;
     store_point(a.U, a.P, a.flags, a.mu, a.g.sf, p, pt, o);
     nfatal += (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
     ncorr += (o.flags & C2P_CORRECTED) ? 1 : 0;
     nit += o.iters;
   }
-  if (a.stats) wave_add_stats(a.stats, nfatal, ncorr, 0, nit);
+  if (a.stats) block_add_stats(a.stats, nfatal, ncorr, 0, nit);
 }
 
 __global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
@@ -787,8 +805,9 @@ int launch_con2prim_learned(const Geom& g, const mhd_eos_t& eos, const float* pr
   uint32_t* queue = qcount + 64;  // 256-byte offset
   LearnedArgs a{g, eos, prm, U, P, flags, mu, stats, qcount, queue, Nx, Ny, (int64_t)Nx * Ny * Nz};
   MHD_LAUNCH(KID_ZERO, k_zero_u32, dim3(1), dim3(1), 0, s, qcount);
-  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_learned, dim3((unsigned)((a.npts + 255) / 256)), dim3(256), 0, s, a);
   const int64_t fb_blocks = (a.npts + 255) / 256;
+  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_learned, dim3((unsigned)(fb_blocks < 2048 ? fb_blocks : 2048)), dim3(256), 0, s,
+             a);
   MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback, dim3((unsigned)(fb_blocks < 2048 ? fb_blocks : 2048)), dim3(256), 0, s,
              a);
   return (int)hipGetLastError();
