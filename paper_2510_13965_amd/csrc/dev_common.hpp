@@ -70,6 +70,24 @@ __device__ __forceinline__ TileXYZ tile_of_block(int nbx, int nby, int nbz, int 
   return tile_of_index(id, nbx, nby, nbz, strip);
 }
 
+// Maximum of a non-negative value over the block, then one atomic max (on the
+// bit pattern) per block: atomics on one address are serialised in L2.  Every
+// thread of the block (at most 256 threads) calls this once.
+__device__ __forceinline__ void block_max_to(unsigned long long* dst, double v) {
+  __shared__ double red[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  if (tid % 64 == 0) red[tid / 64] = v;
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = (int)((blockDim.x * blockDim.y + 63) / 64);
+    double m = red[0];
+    for (int w = 1; w < nw; ++w) m = fmax(m, red[w]);
+    atomicMax(dst, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
 // ------------------------------------------------------------------ batched levels
 //
 // A level is a list of boxes (patches of any shape) processed by persistent

@@ -202,10 +202,9 @@ struct MhdUpdArgs {
   unsigned long long* max_speed;  // bit pattern of a non-negative double
 };
 
-// interior indices (i, j, k); every lane of the wavefront calls this (the
-// speed maximum is a wavefront reduction), lanes without a point with live =
-// false and a valid k
-__device__ __forceinline__ void mhd_update_at(const MhdUpdArgs& a, int i, int j, int k, bool live) {
+// interior indices (i, j, k); lanes without a point come with live = false
+// and a valid k.  Returns the largest point speed at the point (0 if not live).
+__device__ __forceinline__ double mhd_update_at(const MhdUpdArgs& a, int i, int j, int k, bool live) {
   const Geom& g = a.g;
   const int64_t sf = g.sf;
   const int64_t p = live ? g.at(i + g.ng, j + g.ng, k + g.ng) : g.at(g.ng, g.ng, k + g.ng);
@@ -371,14 +370,7 @@ __device__ __forceinline__ void mhd_update_at(const MhdUpdArgs& a, int i, int j,
 #pragma unroll
     for (int f = 0; f < 10; ++f) a.rhs[(int64_t)(22 + f) * sf + p] = out[f];
   }
-  if (a.max_speed) {
-    double v = live ? vmax : 0.0;
-    // wavefront max, then one atomic per wavefront
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0)
-      atomicMax(a.max_speed, (unsigned long long)__double_as_longlong(v));
-  }
+  return live ? vmax : 0.0;
 }
 
 __global__ void __launch_bounds__(256) k_mhd_point(MhdPointArgs a) {
@@ -390,6 +382,9 @@ __global__ void __launch_bounds__(256) k_mhd_point(MhdPointArgs a) {
   mhd_point_at(a, a.par, a.eos, i, j, k);
 }
 
+// persistent: each XCD takes a contiguous range of the 64x4 tiles in the
+// strip order and its blocks stride through it; the speed maximum is kept per
+// thread and reduced once per block
 __global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
   const Geom& g = a.g;
   const TileXYZ t = tile_of_block(a.nbx, a.nby, a.nbz, a.strip);
@@ -397,7 +392,8 @@ __global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
   const int j = t.by * 4 + threadIdx.y;
   const int k = t.bz < 0 ? 0 : t.bz;
   const bool live = (t.bx >= 0 && i < g.nx && j < g.ny);
-  mhd_update_at(a, i, j, k, live);
+  const double vmax = mhd_update_at(a, i, j, k, live);
+  if (a.max_speed) block_max_to(a.max_speed, vmax);
 }
 
 __global__ void __launch_bounds__(256) k_mhd_point_lv(LevelArgs L) {
@@ -413,10 +409,12 @@ __global__ void __launch_bounds__(256) k_mhd_point_lv(LevelArgs L) {
 }
 
 __global__ void __launch_bounds__(256) k_mhd_update_lv(LevelArgs L) {
+  double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     const MhdUpdArgs a{B.g, 0, 0, 0, 0, L.par, L.src ? B.Us : B.U, B.P, B.ws, B.k, L.max_speed};
-    mhd_update_at(a, i, j, k, live);
+    vmax = fmax(vmax, mhd_update_at(a, i, j, k, live));
   });
+  if (L.max_speed) block_max_to(L.max_speed, vmax);
 }
 
 int launch_mhd_level(const LevelArgs& L, int grid_pad, int grid_int, int block, hipStream_t s) {

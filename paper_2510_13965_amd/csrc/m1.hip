@@ -101,8 +101,8 @@ __device__ __forceinline__ double m1_holo(const double* __restrict__ u, const do
   return fho - A * (1.0 - phi) * (fho - flo);
 }
 
-// interior indices; every lane of the wavefront calls this (speed reduction)
-__device__ __forceinline__ void m1_update_at(const M1Args& a, int i, int j, int k, bool live) {
+// interior indices; returns the largest M1 point speed at the point (0 if not live)
+__device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, int k, bool live) {
   const Geom& g = a.g;
   const int64_t sf = g.sf;
   const int64_t q = live ? g.at(i + g.ng, j + g.ng, k + g.ng) : g.at(g.ng, g.ng, k + g.ng);
@@ -233,13 +233,7 @@ __device__ __forceinline__ void m1_update_at(const M1Args& a, int i, int j, int 
       for (int c = 0; c < 4; ++c) a.rhs[(int64_t)(32 + 4 * sp + c) * sf + q] = out[c];
     }
   }
-  if (a.max_speed) {
-    double v = vmax;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0)
-      atomicMax(a.max_speed, (unsigned long long)__double_as_longlong(v));
-  }
+  return vmax;
 }
 
 __global__ void __launch_bounds__(256) k_m1_update(M1Args a) {
@@ -247,7 +241,8 @@ __global__ void __launch_bounds__(256) k_m1_update(M1Args a) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z;
-  m1_update_at(a, i, j, k, i < g.nx && j < g.ny);
+  const double vmax = m1_update_at(a, i, j, k, i < g.nx && j < g.ny);
+  if (a.max_speed) block_max_to(a.max_speed, vmax);
 }
 
 int m1_workspace_fields() { return kM1Fields; }
