@@ -199,8 +199,11 @@ int mhd_con2prim(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, doub
  * scalars of the state: log10 D, log10 q, log10 r^2, log10 calB^2,
  * (r.calB)^2 / (r^2 calB^2), log10(1+q), log10 r^2/(1+q)^2, log10 calB^2/(1+q)
  * (q = tau/D, r_i = S_i/D, calB^i = B^i/sqrt(D); tiny floors keep the logs
- * finite).  Outputs: log(mu_+ h0) and log(mu / mu_+) (log fractions of the
- * upper ends of the two brackets).
+ * finite).  Outputs: corrections y0, y1 to closed-form approximations b0, b1
+ * of log(mu_+ h0) and log(mu / mu_+) (log fractions of the upper ends of the
+ * two brackets): b0 = log h0 - log(h0^2 + r^2)/2 (exact without magnetic
+ * field), b1 = -log(1 + q) + log(h0^2 + r^2)/2 (mu ~ 1/(1 + q)); the guesses
+ * are mu_+ = exp(min(b0 + y0, 0))/h0 and mu = mu_+ exp(min(b1 + y1, 0)).
  * Parameter block (float32, device, MHD_MLP_NBLOCK floats): W1[64][8] at 0,
  * b1[64] at 512, W2[64][64] at 576, b2[64] at 4672, W3[2][64] at 4736, b3[2] at
  * 4864 (the MHD_MLP_NPARAM trainable values), feature mean[8] at 4866 and
@@ -211,8 +214,9 @@ int mhd_con2prim(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, doub
 /* con2prim (App. D) with the learned guess: per padded point, the network
  * guesses mu_+ and mu; each is polished by at most 3 Newton iterations in FP64
  * and accepted when the residual is <= 1e-12 (|f_a|, and |f| relative to mu)
- * with 0 < mu <= mu_+ and the function changes sign across mu (1 -+ 5e-13),
- * so an accepted root is within 5e-13 relative of the bracketed one.  Rejected points are queued and finished by the same
+ * with 0 < mu <= mu_+ and the function has the opposite sign 5e-13 (relative)
+ * away on the side the residual points to, so an accepted root is within
+ * 5e-13 relative of the bracketed one.  Rejected points are queued and finished by the same
  * bracketed solver as mhd_con2prim (their flag gets MHD_FLAG_FALLBACK).  The
  * error policy, outputs and U rewrite are those of mhd_con2prim; stats also
  * counts MHD_STAT_FALLBACK points and, in MHD_STAT_ITERATIONS, Newton
@@ -228,7 +232,7 @@ int mhd_con2prim_learned(const mhd_patch_t* patch, const mhd_eos_t* eos, const f
  * mhd_mlp_features: X[N][8] raw features (float32) of every padded point in
  *   linear padded order (i fastest); points with D < rho_min get NaN rows.
  *   If mu (2 fields mu_+, mu, as written by mhd_con2prim) and T are non-NULL,
- *   T[N][2] gets the targets log(mu_+ h0), log(mu/mu_+).
+ *   T[N][2] gets the targets log(mu_+ h0) - b0, log(mu/mu_+) - b1.
  * mhd_mlp_normalize: mean and inverse std of each feature over the non-NaN rows
  *   of X[n][8], written into the parameter block.
  * mhd_mlp_forward: Y[n][2] network outputs for raw features X[n][8].

@@ -362,7 +362,7 @@ void orc_c2p_features(const orc_grid* g, const orc_eos* e, const double* U, cons
   int64_t N = npts(g), p;
 #pragma omp parallel for schedule(static)
   for (p = 0; p < N; ++p) {
-    double gdn[6], gup[6], sg, cons[6], B[3], x[8], m[2], t[2];
+    double gdn[6], gup[6], sg, cons[6], B[3], x[8], m[2], t[2], b[2];
     int i;
     metric_at(U, p, N, gdn, gup, &sg);
     for (i = 0; i < 6; ++i) cons[i] = U[(22 + i) * N + p] / sg;
@@ -377,7 +377,8 @@ void orc_c2p_features(const orc_grid* g, const orc_eos* e, const double* U, cons
     if (T && mu) {
       m[0] = mu[p];
       m[1] = mu[N + p];
-      orc_mlp_targets(e->h0, m, t);
+      orc_mlp_baseline(e->h0, cons, gup, b);
+      orc_mlp_targets(e->h0, b, m, t);
       T[p * 2] = (float)t[0];
       T[p * 2 + 1] = (float)t[1];
     }

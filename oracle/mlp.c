@@ -9,7 +9,8 @@
  *
  *   features   8 metric-invariant scalars of one state (con2prim depends on
  *              the metric only through q, r^2, calB^2, (r.calB), App. D step 1)
- *   targets    log(mu_+ h0) and log(mu / mu_+) of the plain solver's roots
+ *   targets    log(mu_+ h0) and log(mu / mu_+) of the plain solver's roots, less
+ *              closed-form approximations of both (orc_mlp_baseline)
  *   forward    y = W3 relu(W2 relu(W1 z + b1) + b2) + b3, z the standardized
  *              features
  *   gradient   of L = 1/(2n) sum_samples sum_o (y_o - t_o)^2 by backpropagation
@@ -92,11 +93,31 @@ void orc_mlp_features(const double cons[6], const double B[3], const double gdn[
   x[7] = log10(B2 / onep + 1e-30);
 }
 
-/* the roots as fractions of their upper bounds, in log space:
- * log(mu_+ h0) and log(mu / mu_+), both <= 0 */
-void orc_mlp_targets(double h0, const double mu[2], double t[2]) {
-  t[0] = log(mu[0] * h0);
-  t[1] = log(mu[1] / mu[0]);
+/* Closed-form approximations of the two log fractions, which the network
+ * corrects.  Without a magnetic field (calB = 0, so rbar^2 = r^2 for every mu,
+ * App. D) the auxiliary root solves mu sqrt(h0^2 + r^2) = 1 exactly:
+ *   b0 = log(h0) - log(h0^2 + r^2) / 2.
+ * The second root mu = 1/(h W) is taken as 1/(1 + q), since D (1 + q) = tau + D
+ * is the energy density, about rho h W^2 for a cold, weakly magnetised fluid:
+ *   b1 = -log(1 + q) + log(h0^2 + r^2) / 2.
+ * cons = (D, Y_e D, tau, S_i) undensitized, gup the inverse physical metric. */
+void orc_mlp_baseline(double h0, const double cons[6], const double gup[6], double b[2]) {
+  const double D = cons[0], q = cons[2] / D;
+  static const int sym[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}}; /* xx xy xz yy yz zz */
+  double r[3], r2 = 0.0;
+  int i, j;
+  for (i = 0; i < 3; ++i) r[i] = cons[3 + i] / D;
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) r2 += gup[sym[i][j]] * r[i] * r[j];
+  b[0] = log(h0) - 0.5 * log(h0 * h0 + r2);
+  b[1] = -log(1.0 + q) + 0.5 * log(h0 * h0 + r2);
+}
+
+/* the roots as fractions of their upper bounds, in log space (log(mu_+ h0)
+ * and log(mu / mu_+), both <= 0), less the baseline b */
+void orc_mlp_targets(double h0, const double b[2], const double mu[2], double t[2]) {
+  t[0] = log(mu[0] * h0) - b[0];
+  t[1] = log(mu[1] / mu[0]) - b[1];
 }
 
 /* one sample through the network; keeps the intermediate values for backprop */

@@ -131,7 +131,8 @@ unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3]
 float orc_bf16(float x);
 void orc_mlp_features(const double cons[6], const double B[3], const double gdn[6],
                       const double gup[6], double x[8]);
-void orc_mlp_targets(double h0, const double mu[2], double t[2]);
+void orc_mlp_baseline(double h0, const double cons[6], const double gup[6], double b[2]);
+void orc_mlp_targets(double h0, const double b[2], const double mu[2], double t[2]);
 /* features (and, if mu != NULL, targets) at every padded point; X is [N][8],
  * T is [N][2], binary32; points with D < rho_min get NaN rows */
 void orc_c2p_features(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,

@@ -106,7 +106,8 @@ def _bind(L):
         L.orc_bf16.argtypes = [C.c_float]
         L.orc_bf16.restype = C.c_float
         L.orc_mlp_features.argtypes = [_dp, _dp, _dp, _dp, _dp]
-        L.orc_mlp_targets.argtypes = [C.c_double, _dp, _dp]
+        L.orc_mlp_baseline.argtypes = [C.c_double, _dp, _dp, _dp]
+        L.orc_mlp_targets.argtypes = [C.c_double, _dp, _dp, _dp]
         L.orc_c2p_features.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _fp, _fp]
         L.orc_mlp_forward.argtypes = [_dp, _fp, C.c_int64, C.c_int, _dp]
         L.orc_mlp_grad.argtypes = [_dp, _fp, _fp, C.c_int64, C.c_int, _dp]
@@ -247,9 +248,17 @@ def mlp_features(cons, B, gdn, gup):
     return x
 
 
-def mlp_targets(h0, mu):
+def mlp_baseline(h0, cons, gup):
+    b = np.zeros(2)
+    lib().orc_mlp_baseline(float(h0), ptr(np.ascontiguousarray(cons, dtype=np.float64)),
+                           ptr(np.ascontiguousarray(gup, dtype=np.float64)), ptr(b))
+    return b
+
+
+def mlp_targets(h0, b, mu):
     t = np.zeros(2)
-    lib().orc_mlp_targets(float(h0), ptr(np.ascontiguousarray(mu, dtype=np.float64)), ptr(t))
+    lib().orc_mlp_targets(float(h0), ptr(np.ascontiguousarray(b, dtype=np.float64)),
+                          ptr(np.ascontiguousarray(mu, dtype=np.float64)), ptr(t))
     return t
 
 

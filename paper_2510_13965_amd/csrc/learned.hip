@@ -4,7 +4,8 @@
 // f(mu) = 0 on (0, mu_+] by bracketed iterations.  Here a small MLP
 // (8 -> 64 -> 64 -> 2, ReLU) maps 8 metric-invariant scalars of the state
 // (log D, log q, log r^2, log calB^2, (r.calB)^2/(r^2 calB^2), log(1+q),
-// log r^2/(1+q)^2, log calB^2/(1+q)) to log(mu_+ h0) and log(mu/mu_+);
+// log r^2/(1+q)^2, log calB^2/(1+q)) to corrections of closed-form
+// approximations of log(mu_+ h0) and log(mu/mu_+) (c2p_baseline);
 // Newton's method in FP64 polishes each guess for at most three iterations,
 // and a point is accepted only if the residual falls below 1e-12 (f_a
 // absolute, f relative to mu) with 0 < mu <= mu_+.  Every other point goes to
@@ -179,6 +180,17 @@ __device__ __forceinline__ void c2p_features(const C2pInv& c, double x[8]) {
   x[7] = log10(c.B2 / onep + 1e-30);
 }
 
+// Closed-form approximations of the two log fractions, corrected by the
+// network: exact for the auxiliary root without magnetic field (rbar = r, so
+// mu_+ = 1/sqrt(h0^2 + r^2)); mu ~ 1/(1 + q) for the second root (D (1 + q)
+// is the energy density, about rho h W^2 for a cold, weakly magnetised fluid).
+__device__ __forceinline__ void c2p_baseline(const C2pInv& c, double h0, double b[2]) {
+#pragma clang fp contract(off)
+  const double l = 0.5 * log(h0 * h0 + c.r2);
+  b[0] = log(h0) - l;
+  b[1] = -log(1.0 + c.q) + l;
+}
+
 __device__ __forceinline__ void standardize(const MlpLds& s, const float x[8], float z[8]) {
 #pragma clang fp contract(off)
 #pragma unroll
@@ -220,8 +232,10 @@ __global__ void __launch_bounds__(256) k_mlp_features(FeatArgs a) {
   for (int q = 0; q < 8; ++q) a.X[t * 8 + q] = (float)x[q];
   if (a.T && a.mu) {
     const double mup = a.mu[p], mu = a.mu[a.g.sf + p];
-    a.T[t * 2] = (float)log(mup * a.eos.h0);
-    a.T[t * 2 + 1] = (float)log(mu / mup);
+    double b[2];
+    c2p_baseline(c, a.eos.h0, b);
+    a.T[t * 2] = (float)(log(mup * a.eos.h0) - b[0]);
+    a.T[t * 2 + 1] = (float)(log(mu / mup) - b[1]);
   }
 }
 
@@ -525,12 +539,12 @@ struct LearnedArgs {
 
 constexpr int kNewtonIt = 3;
 
-// Newton on F from x0 with at most kNewtonIt updates (iterates clamped to hi);
-// accepted when |F(x)| <= tol(x) (then one more correction is applied),
-// 0 < x <= hi, and F changes
-// sign across [x (1 - 5e-13), min(x (1 + 5e-13), hi)] (F increases through
-// its only root in the bracket), which puts x within 5e-13 relative of the
-// root.  nev counts the function evaluations.
+// Newton on F from x0 with at most kNewtonIt updates (iterates clamped to hi).
+// A point x is accepted when |F(x)| <= tol(x) and F has the opposite sign at
+// x (1 -+ 5e-13) on the side where the root lies (F increases through its
+// only root in the bracket; F(hi) > 0 is known): the root is then within
+// 5e-13 relative of x, and the result is the Newton correction of x kept
+// inside that interval.  nev counts the function evaluations.
 template <class FnD, class Fn>
 __device__ __forceinline__ bool newton_polish(const FnD& F, const Fn& Fv, double x, double hi, bool rel, double& out,
                                               int& nev) {
@@ -569,7 +583,7 @@ struct FDual {
   __device__ Dual operator()(Dual mu) const { return f_t<Dual>(e, c, mu); }
 };
 
-// network output y (a log fraction) -> fraction of the bracket's upper end, in (0, 1]
+// log fraction (baseline + network output) -> fraction of the bracket's upper end, in (0, 1]
 __device__ __forceinline__ double frac_of(double y) { return exp(fmin(y, 0.0)); }
 
 struct LearnedOut {
@@ -594,17 +608,19 @@ __device__ __forceinline__ LearnedOut learned_point(const MlpLds& s, const mhd_e
     load_point(U, g.sf, p, pt);
     solve = c2p_setup(eos, pt, c);
   }
-  // network guess (whole wave, dead lanes with zero inputs)
-  float z[8] = {0, 0, 0, 0, 0, 0, 0, 0}, y[2];
-  if (solve) {
-    double x[8];
-    c2p_features(c, x);
-    float xf[8];
+  // network guess (whole wave, dead lanes with zero inputs); skipped by
+  // wavefronts without a state to solve (atmosphere, padding)
+  float y[2] = {0.0f, 0.0f};
+  if (__any(solve)) {
+    float z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (solve) {
+      double x[8];
+      c2p_features(c, x);
+      float xf[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) xf[q] = (float)x[q];
-    standardize(s, xf, z);
-  }
-  {
+      for (int q = 0; q < 8; ++q) xf[q] = (float)x[q];
+      standardize(s, xf, z);
+    }
     MlpFwd f;
     mlp_forward(s, z, f, y);
   }
@@ -621,17 +637,19 @@ __device__ __forceinline__ LearnedOut learned_point(const MlpLds& s, const mhd_e
     prim_to_cons(pt.gd, o.prim[0], o.prim[1], o.prim[2], zv, o.prim[7], pt.B, o.cons, Wn);
   } else {
     int nev = 0;
+    double b[2];
+    c2p_baseline(c, c.h0, b);
     const double hi = 1.0 / c.h0;
     const double fhi = fa_t<double>(c, hi);
     double mup = hi;
     bool ok = true;
-    if (fhi > 0.0) ok = newton_polish(FaDual{c}, FaFn{c}, frac_of((double)y[0]) * hi, hi, false, mup, nev);
+    if (fhi > 0.0) ok = newton_polish(FaDual{c}, FaFn{c}, frac_of(b[0] + (double)y[0]) * hi, hi, false, mup, nev);
     double m = mup;
     if (ok) {
       const FFn fp{eos, c};
       const double f1 = fp(mup);
       ++nev;
-      if (f1 > 0.0) ok = newton_polish(FDual{eos, c}, fp, frac_of((double)y[1]) * mup, mup, true, m, nev);
+      if (f1 > 0.0) ok = newton_polish(FDual{eos, c}, fp, frac_of(b[1] + (double)y[1]) * mup, mup, true, m, nev);
     }
     r.nit = nev + 1;  // root-function evaluations, f_a(1/h0) included
     if (!ok) {

@@ -37,7 +37,8 @@ STAR_SAMPLING = dict(log_rho=(-12.0, -2.5), log_eps=(-11.0, 0.0), log_sigma=(-7.
 
 def training_set(ncell, seed, eos_cfg=I.EOS_PWP3, device="cuda", **sampling):
     """(X, T) device tensors for `ncell` random con2prim states: raw features of
-    the conserved state and the log-fraction targets of the plain solver's roots.
+    the conserved state and the targets (log fractions of the plain solver's roots
+    less their closed-form baselines).
     Rows of atmosphere states are NaN (skipped by the kernels).  `sampling`
     overrides the state distribution (inputs.c2p_cells)."""
     import torch

@@ -16,6 +16,7 @@ import numpy as np
 import pytest
 
 from oracle import orc
+from paper_2510_13965_amd import inputs as I
 
 OFF = orc.MLP_OFF
 
@@ -211,9 +212,63 @@ def test_features_frame_invariant():
 
 
 def test_targets_invert_to_roots():
+    b = np.array([-0.3, 0.05])
     for mu in ([0.7, 0.3], [0.999, 0.5], [1e-3, 1e-3 * 0.25], [1.0, 1.0]):
-        t = orc.mlp_targets(1.0, np.array(mu))
-        assert np.exp(t[0]) == pytest.approx(mu[0], rel=1e-14)
-        assert np.exp(t[1]) * mu[0] == pytest.approx(mu[1], rel=1e-14)
-    t = orc.mlp_targets(2.0, np.array([0.25, 0.2]))
+        t = orc.mlp_targets(1.0, b, np.array(mu))
+        assert np.exp(t[0] + b[0]) == pytest.approx(mu[0], rel=1e-14)
+        assert np.exp(t[1] + b[1]) * mu[0] == pytest.approx(mu[1], rel=1e-14)
+    t = orc.mlp_targets(2.0, np.zeros(2), np.array([0.25, 0.2]))
     assert t[0] == pytest.approx(math.log(0.5)) and t[1] == pytest.approx(math.log(0.8))
+
+
+def _textbook_state(rho, eps, Gam, v_up, gdn3):
+    """Undensitized (D, Y_e D, tau, S_i) of an ideal-gas fluid without field:
+    D = rho W, S_i = rho h W^2 v_i, tau = rho h W^2 - p - D."""
+    p = (Gam - 1) * rho * eps
+    vd = gdn3 @ v_up
+    W = 1 / math.sqrt(1 - v_up @ vd)
+    hs = 1 + eps + p / rho
+    D = rho * W
+    return np.array([D, 0.1 * D, rho * hs * W * W - p - D, *(rho * hs * W * W * vd)]), p, hs, W
+
+
+def test_baseline_exact_without_field():
+    """App. D: with calB = 0, rbar(mu) = r for every mu, so the auxiliary root is
+    mu_+ = 1/sqrt(h0^2 + r^2) and the first target (log fraction less the
+    baseline) vanishes to the root solver's accuracy.  For a fluid at rest
+    (r = 0, mu_+ = 1/h0) mu = 1/h while 1 + q = 1 + eps, so the second target is
+    log((1 + eps)/h) in closed form.  The roots come from the oracle's own
+    bracketed solver, so this also pins its auxiliary root."""
+    e = orc.make_eos(I.EOS_IDEAL2)
+    r = np.random.default_rng(61)
+    def pack(M):
+        return np.array([M[0, 0], M[0, 1], M[0, 2], M[1, 1], M[1, 2], M[2, 2]])
+    for n in range(40):
+        G = np.eye(3) + 0.1 * r.normal(size=(3, 3))
+        G = G @ G.T
+        Gi = np.linalg.inv(G)
+        rho = 10 ** r.uniform(-8, -3)
+        eps = 10 ** r.uniform(-4, 0)
+        still = n % 4 == 0
+        v = np.zeros(3) if still else r.normal(size=3)
+        if not still:
+            v *= r.uniform(0.05, 0.95) / math.sqrt(v @ G @ v)
+        cons, p, hs, W = _textbook_state(rho, eps, 2.0, v, G)
+        _, prim, mu, _ = orc.c2p_point(e, cons, np.zeros(3), pack(G), pack(Gi), 1.0)
+        b = orc.mlp_baseline(1.0, cons, pack(Gi))
+        t = orc.mlp_targets(1.0, b, mu)
+        assert abs(t[0]) <= 2e-14, (n, t)
+        if still:
+            assert t[1] == pytest.approx(math.log((1 + eps) / hs), rel=1e-10, abs=1e-14), (n, t)
+
+
+def test_baseline_mu_plus_for_moving_fluid_flat():
+    """Flat metric, B = 0, moving fluid: b0 = -log(1 + r^2)/2 with r = h W |v|
+    (h0 = 1), written out from the textbook state."""
+    cons, p, hs, W = _textbook_state(1e-4, 0.3, 2.0, np.array([0.3, -0.2, 0.1]), np.eye(3))
+    gup = np.array([1.0, 0, 0, 1.0, 0, 1.0])
+    b = orc.mlp_baseline(1.0, cons, gup)
+    r2 = (hs * W) ** 2 * 0.14
+    assert b[0] == pytest.approx(-0.5 * math.log(1 + r2), rel=1e-13)
+    q = cons[2] / cons[0]
+    assert b[1] == pytest.approx(-math.log(1 + q) + 0.5 * math.log(1 + r2), rel=1e-13)
