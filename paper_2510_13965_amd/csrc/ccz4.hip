@@ -78,7 +78,7 @@ struct Conf {
 };
 
 __device__ __forceinline__ void conf_point(const double* __restrict__ U, const PointIdx& q, const Geom& g, Conf& c) {
-  const int64_t sf = q.sf, p = q.p;
+  const int64_t sf = q.sf;
 #pragma unroll
   for (int a = 0; a < 6; ++a) c.gt[a] = ldf(U + (a) * sf, q.voff);
   c.det = sym_inv(c.gt, c.gtu);
@@ -114,7 +114,7 @@ struct Matter {
 __device__ __forceinline__ void matter_point(const double* __restrict__ U, const double* __restrict__ P,
                                              const double* __restrict__ m1P, const PointIdx& q, const Conf& c,
                                              double chi, bool want_sij, Matter& m) {
-  const int64_t sf = q.sf, p = q.p;
+  const int64_t sf = q.sf;
   const double ichi = 1.0 / chi;
   const double isg = 1.0 / sqrt(c.det * ichi * ichi * ichi);
   double Sf[3];  // fluid momentum (the fluid stress needs it alone)

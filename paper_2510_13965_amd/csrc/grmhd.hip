@@ -26,8 +26,9 @@ namespace mhd {
 // the MP5 reconstruction are therefore evaluated in a fixed order of plain
 // IEEE operations, FMA contraction off, with the divisions the formulas
 // contain (metric inverse by the determinant, undensitizing by sqrt(gamma),
-// the 1/60 of the interpolant, 1/dx of the difference); any FP64
-// implementation following the same order gets identical results.
+// the 1/60 of the interpolant, computed as a correctly rounded quotient with
+// div_rn, 1/dx of the difference); any FP64 implementation following the same
+// order gets identical results.
 #pragma clang fp contract(off)
 
 // ------------------------------------------------------------------ MP5 (Sec. 3.3)
@@ -44,7 +45,7 @@ __device__ __forceinline__ double minmod4(double a, double b, double c, double d
 
 // value at i+1/2 from F_{i-2} .. F_{i+2} (= a b c d e)
 __device__ __forceinline__ double mp5(double a, double b, double c, double d, double e, double alpha) {
-  const double unl = (2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e) / 60.0;
+  const double unl = div_rn(2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e, 60.0, 1.0 / 60.0);
   const double dm = c - b;
   const double fmp = c + minmod2(d - c, alpha * dm);
   if ((unl - c) * (unl - fmp) < 0.0) return unl;
@@ -218,10 +219,9 @@ __device__ __forceinline__ double mhd_update_at(const MhdUpdArgs& a, int i, int 
   for (int f = 0; f < 10; ++f) out[f] = 0.0;
   double vmax = 0.0;
 
-#pragma unroll
+#pragma unroll 1
   for (int d = 0; d < 3; ++d) {
     const int64_t s = g.stride(d);
-    const double ih = g.idx[d];
     const double* __restrict__ lam = a.W + (int64_t)(d * 11 + 10) * sf + p;
     double l[7];
 #pragma unroll

@@ -141,7 +141,7 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
           const double* f = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + c) * sf;
           const double fr = m1_holo(u, f, lam, ka, ks, q, st, g.h[d]);
           const double fl = m1_holo(u, f, lam, ka, ks, q - st, st, g.h[d]);
-          out[c] -= (fr - fl) / g.h[d];
+          out[c] -= div_rn(fr - fl, g.h[d], g.idx[d]);
         }
       }
       // closure quantities at the point
