@@ -324,6 +324,27 @@ __global__ void __launch_bounds__(256) k_ccz4_stencil_lds(Ccz4Args a, StencilTil
 // 21-23 d_i d_k beta^k
 constexpr int kD2Fields = 24;
 
+// -1/2 gt^{mn} d_m d_n gt_ij from the six second derivatives of one gt_ij
+// (fixed evaluation order, no contraction: both d2 kernels give the same bits)
+__device__ __forceinline__ double d2_gt_contract(const double gtu[6], double xx, double yy, double zz, double xy,
+                                                 double xz, double yz) {
+#pragma clang fp contract(off)
+  double r = -0.5 * (gtu[0] * xx + gtu[3] * yy + gtu[5] * zz);
+  r -= gtu[1] * xy;
+  r -= gtu[2] * xz;
+  r -= gtu[4] * yz;
+  return r;
+}
+
+// gt^{jk} d_j d_k beta^i from the six second derivatives v (symmetric storage)
+__device__ __forceinline__ double d2_beta_lap(const double gtu[6], const double v[6]) {
+#pragma clang fp contract(off)
+  double lap = 0.0;
+#pragma unroll
+  for (int b = 0; b < 6; ++b) lap += wsym(b) * gtu[b] * v[b];
+  return lap;
+}
+
 __device__ __forceinline__ void ccz4_d2_at(const Ccz4Args& a, double* __restrict__ W, const PointIdx& q) {
   const Geom& g = a.g;
   const double* __restrict__ U = a.U;
@@ -336,12 +357,10 @@ __device__ __forceinline__ void ccz4_d2_at(const Ccz4Args& a, double* __restrict
 #pragma unroll 1
   for (int b = 0; b < 6; ++b) {
     const double* u = U + (int64_t)b * sf;
-    double r = -0.5 * (gtu[0] * fd2(u, q.st[0], q.voff, g.i12s[0]) + gtu[3] * fd2(u, q.st[1], q.voff, g.i12s[1]) +
-                       gtu[5] * fd2(u, q.st[2], q.voff, g.i12s[2]));
-    r -= gtu[1] * fd11(u, q.st[0], q.st[1], q.voff, g.i12[0], g.i12[1]);
-    r -= gtu[2] * fd11(u, q.st[0], q.st[2], q.voff, g.i12[0], g.i12[2]);
-    r -= gtu[4] * fd11(u, q.st[1], q.st[2], q.voff, g.i12[1], g.i12[2]);
-    Wp[(int64_t)b * sf] = r;
+    Wp[(int64_t)b * sf] = d2_gt_contract(
+        gtu, fd2(u, q.st[0], q.voff, g.i12s[0]), fd2(u, q.st[1], q.voff, g.i12s[1]),
+        fd2(u, q.st[2], q.voff, g.i12s[2]), fd11(u, q.st[0], q.st[1], q.voff, g.i12[0], g.i12[1]),
+        fd11(u, q.st[0], q.st[2], q.voff, g.i12[0], g.i12[2]), fd11(u, q.st[1], q.st[2], q.voff, g.i12[1], g.i12[2]));
   }
 #pragma unroll 1
   for (int fi = 0; fi < 2; ++fi) {
@@ -365,15 +384,183 @@ __device__ __forceinline__ void ccz4_d2_at(const Ccz4Args& a, double* __restrict
       for (int e = d; e < 3; ++e)
         v[sym(d, e)] = (d == e) ? fd2(u, q.st[d], q.voff, g.i12s[d])
                                 : fd11(u, q.st[d], q.st[e], q.voff, g.i12[d], g.i12[e]);
-    double lap = 0.0;
-#pragma unroll
-    for (int b = 0; b < 6; ++b) lap += wsym(b) * gtu[b] * v[b];
-    Wp[(int64_t)(18 + ci) * sf] = lap;
+    Wp[(int64_t)(18 + ci) * sf] = d2_beta_lap(gtu, v);
 #pragma unroll
     for (int j = 0; j < 3; ++j) ddivb[j] += (ci == 0) ? v[sym(j, 0)] : ((ci == 1) ? v[sym(j, 1)] : v[sym(j, 2)]);
   }
 #pragma unroll
   for (int j = 0; j < 3; ++j) Wp[(int64_t)(21 + j) * sf] = ddivb[j];
+}
+
+// ------------------------------------------------------------------ second derivatives, LDS-staged
+//
+// The same derivatives and contractions from staged values: a block owns a
+// 64x4 (x,y) tile and streams it along z, field by field, staging each plane
+// with a two-point halo (corners included) in LDS, two planes ahead of the
+// output plane.  When plane z' is staged the thread forms D_x u and D_y u at
+// its point (queued over five planes, for the xz and yz mixed derivatives),
+// and the in-plane d_xx, d_yy and d_xy (held two steps, until the z
+// neighbours are staged); d_zz comes from a five-plane queue of u.  About
+// four global loads per point and field replace the ~63 of the per-point
+// kernel.  Every derivative is the per-point kernel's expression, operation
+// for operation.
+
+constexpr int kD2ZC = 8, kD2H = 2, kD2LX = 64 + 2 * kD2H, kD2LY = 4 + 2 * kD2H;
+constexpr int kD2NH = kD2LX * kD2LY - 64 * 4;  // halo slots per plane
+
+struct D2Tile {
+  int nbx, nby, nzc;  // tiles in x, y and z chunks of kD2ZC planes
+};
+
+// centred first derivative from five values v[m] = u_{m-2} (as fd1)
+__device__ __forceinline__ double d1of5(double m2, double m1, double p1, double p2, double ih12) {
+#pragma clang fp contract(off)
+  return (8.0 * (p1 - m1) - (p2 - m2)) * ih12;
+}
+// centred second derivative from five values (as fd2)
+__device__ __forceinline__ double d2of5(double m2, double m1, double c, double p1, double p2, double ih2_12) {
+#pragma clang fp contract(off)
+  return (16.0 * (p1 + m1) - (p2 + m2) - 30.0 * c) * ih2_12;
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_d2_lds(Ccz4Args a, double* __restrict__ W, D2Tile T) {
+#pragma clang fp contract(off)
+  __shared__ double lds[2][kD2LY][kD2LX];
+  const Geom& g = a.g;
+  const TileXYZ t = tile_of_block(T.nbx, T.nby, T.nzc, a.strip);
+  if (t.bx < 0) return;  // whole block
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
+  const int i = t.bx * 64 + tx, j = t.by * 4 + ty;
+  const int z0 = t.bz * kD2ZC, nzb = min(kD2ZC, g.nz - z0);
+  const bool col = i < g.nx + g.ng && j < g.ny + g.ng;
+  const bool live = i < g.nx && j < g.ny;
+  const int64_t sf = g.sf, sz = g.sz;
+  const int64_t pc = col ? g.at(i + g.ng, j + g.ng, g.ng + z0) : 0;  // column at plane z0
+  const double* __restrict__ U = a.U;
+  int hx[2], hy[2];
+  bool hok[2];
+  int64_t hp[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int h = tid + 256 * r;
+    int lx = 0, ly = 0;
+    if (h < 2 * kD2LX) {
+      ly = h / kD2LX;
+      lx = h % kD2LX;
+    } else if (h < 4 * kD2LX) {
+      ly = kD2H + 4 + (h - 2 * kD2LX) / kD2LX;
+      lx = (h - 2 * kD2LX) % kD2LX;
+    } else if (h < kD2NH) {
+      const int q = h - 4 * kD2LX, c = q % 4;
+      ly = kD2H + q / 4;
+      lx = c < 2 ? c : 64 + c;
+    }
+    const int gi = t.bx * 64 + lx - kD2H, gj = t.by * 4 + ly - kD2H;
+    hx[r] = lx;
+    hy[r] = ly;
+    hok[r] = h < kD2NH && gi >= -g.ng && gj >= -g.ng && gi < g.nx + g.ng && gj < g.ny + g.ng;
+    hp[r] = hok[r] ? g.at(gi + g.ng, gj + g.ng, g.ng + z0) : 0;
+  }
+  const int nst = nzb + 4;  // staged planes z0-2 .. z0+nzb+1
+  // fields in the order of the per-point kernel: gt_ij, chi, alpha, beta^i
+  const int fld[11] = {0, 1, 2, 3, 4, 5, 12, 18, 19, 20, 21};
+  // pipeline: own and halo values of the next staged plane
+  double own = col ? U[pc - 2 * sz] : 0.0, hv[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) hv[r] = hok[r] ? U[hp[r] - 2 * sz] : 0.0;
+  int buf = 0;
+#pragma unroll 1
+  for (int fi = 0; fi < 11; ++fi) {
+    const double* __restrict__ u = U + (int64_t)fld[fi] * sf;
+    double qu[5] = {0, 0, 0, 0, 0}, qx[5] = {0, 0, 0, 0, 0}, qy[5] = {0, 0, 0, 0, 0};
+    double hxx[3] = {0, 0, 0}, hyy[3] = {0, 0, 0}, hxy[3] = {0, 0, 0};
+#pragma unroll 1
+    for (int st = 0; st < nst; ++st) {
+      const int zs = st - 2;  // staged plane, relative to z0
+      lds[buf][ty + kD2H][tx + kD2H] = own;
+#pragma unroll
+      for (int r = 0; r < 2; ++r)
+        if (hok[r]) lds[buf][hy[r]][hx[r]] = hv[r];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) qu[m] = qu[m + 1];
+      qu[4] = own;
+      if (st + 1 < nst) {
+        own = col ? u[pc + (int64_t)(zs + 1) * sz] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) hv[r] = hok[r] ? u[hp[r] + (int64_t)(zs + 1) * sz] : 0.0;
+      } else if (fi + 1 < 11) {
+        const double* __restrict__ un = U + (int64_t)fld[fi + 1] * sf;
+        own = col ? un[pc - 2 * sz] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 2; ++r) hv[r] = hok[r] ? un[hp[r] - 2 * sz] : 0.0;
+      }
+      __syncthreads();
+      if (live) {
+        const double(*L)[kD2LX] = lds[buf];
+        const int cy = ty + kD2H, cx = tx + kD2H;
+        // D_x u and D_y u at the staged plane
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          qx[m] = qx[m + 1];
+          qy[m] = qy[m + 1];
+        }
+        qx[4] = d1of5(L[cy][cx - 2], L[cy][cx - 1], L[cy][cx + 1], L[cy][cx + 2], g.i12[0]);
+        qy[4] = d1of5(L[cy - 2][cx], L[cy - 1][cx], L[cy + 1][cx], L[cy + 2][cx], g.i12[1]);
+        // in-plane second derivatives of the staged plane, held two steps
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+          hxx[m] = hxx[m + 1];
+          hyy[m] = hyy[m + 1];
+          hxy[m] = hxy[m + 1];
+        }
+        hxx[2] = d2of5(L[cy][cx - 2], L[cy][cx - 1], L[cy][cx], L[cy][cx + 1], L[cy][cx + 2], g.i12s[0]);
+        hyy[2] = d2of5(L[cy - 2][cx], L[cy - 1][cx], L[cy][cx], L[cy + 1][cx], L[cy + 2][cx], g.i12s[1]);
+        {
+          const double a1 = d1of5(L[cy + 1][cx - 2], L[cy + 1][cx - 1], L[cy + 1][cx + 1], L[cy + 1][cx + 2], g.i12[0]);
+          const double b1 = d1of5(L[cy - 1][cx - 2], L[cy - 1][cx - 1], L[cy - 1][cx + 1], L[cy - 1][cx + 2], g.i12[0]);
+          const double a2 = d1of5(L[cy + 2][cx - 2], L[cy + 2][cx - 1], L[cy + 2][cx + 1], L[cy + 2][cx + 2], g.i12[0]);
+          const double b2 = d1of5(L[cy - 2][cx - 2], L[cy - 2][cx - 1], L[cy - 2][cx + 1], L[cy - 2][cx + 2], g.i12[0]);
+          hxy[2] = (8.0 * (a1 - b1) - (a2 - b2)) * g.i12[1];
+        }
+        if (st >= 4) {  // output plane z = zs - 2
+          const int64_t po = pc + (int64_t)(zs - 2) * sz;
+          const double xx = hxx[0], yy = hyy[0], xy = hxy[0];
+          const double zz = d2of5(qu[0], qu[1], qu[2], qu[3], qu[4], g.i12s[2]);
+          const double xz = (8.0 * (qx[3] - qx[1]) - (qx[4] - qx[0])) * g.i12[2];
+          const double yz = (8.0 * (qy[3] - qy[1]) - (qy[4] - qy[0])) * g.i12[2];
+          double* __restrict__ Wp = W + po;
+          if (fi == 6 || fi == 7) {  // chi, alpha: 6 values each
+            double* o = Wp + (int64_t)(6 + 6 * (fi - 6)) * sf;
+            o[0 * sf] = xx;
+            o[1 * sf] = xy;
+            o[2 * sf] = xz;
+            o[3 * sf] = yy;
+            o[4 * sf] = yz;
+            o[5 * sf] = zz;
+          } else {
+            double gt[6], gtu[6];
+#pragma unroll
+            for (int b = 0; b < 6; ++b) gt[b] = U[(int64_t)b * sf + po];
+            sym_inv(gt, gtu);
+            if (fi < 6) {
+              Wp[(int64_t)fi * sf] = d2_gt_contract(gtu, xx, yy, zz, xy, xz, yz);
+            } else {  // beta^ci
+              const int ci = fi - 8;
+              const double v[6] = {xx, xy, xz, yy, yz, zz};
+              Wp[(int64_t)(18 + ci) * sf] = d2_beta_lap(gtu, v);
+#pragma unroll
+              for (int jj = 0; jj < 3; ++jj) {
+                const double add = v[sym(jj, ci)];
+                double* dv = Wp + (int64_t)(21 + jj) * sf;
+                *dv = (ci == 0 ? 0.0 : *dv) + add;
+              }
+            }
+          }
+        }
+      }
+      buf ^= 1;
+    }
+  }
 }
 
 // ------------------------------------------------------------------ At_ij, Khat, Theta
@@ -681,12 +868,6 @@ __global__ void __launch_bounds__(256) k_ccz4_stencil_lv(LevelArgs L) {
   });
 }
 
-__global__ void __launch_bounds__(256) k_ccz4_d2(Ccz4Args a, double* __restrict__ W) {
-  const PointIdx q = point_index(a);
-  if (!q.live) return;
-  ccz4_d2_at(a, W, q);
-}
-
 __global__ void __launch_bounds__(256) k_ccz4_d2_lv(LevelArgs L) {
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
@@ -739,7 +920,11 @@ int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const d
     const int nst = nbx * nby * T.nzc;
     MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lds, dim3(8 * ((nst + 7) / 8)), blk, 0, s, as, T);
   }
-  MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2, grd, blk, 0, s, a, ws);
+  {
+    const D2Tile T{nbx, nby, (g.nz + kD2ZC - 1) / kD2ZC};
+    const int nd2 = nbx * nby * T.nzc;
+    MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2_lds, dim3(8 * ((nd2 + 7) / 8)), blk, 0, s, a, ws, T);
+  }
   MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv, grd, blk, 0, s, a, (const double*)ws);
   MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge, grd, blk, 0, s, a, (const double*)ws);
   return (int)hipGetLastError();
