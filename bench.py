@@ -130,6 +130,35 @@ def m1_path(torch, mhd, I, ip, U, P, EM, args):
             "evolved_fields": 44, "finite": fin, "kernels": kernel_table(prof, ip, args.steps + 1, nfields=44)}
 
 
+def imex_path(torch, mhd, I, ip, U, P, EM, args):
+    """The same star and radiation as the M1 path, opacities x1000 (kappa dt up
+    to ~80 at the centre, far past the explicit stability limit), stepped by
+    IMEX(4,4,2) with the implicit collision solve."""
+    from paper_2510_13965_amd.step import ImexRun, PatchRun
+
+    t0 = time.perf_counter()
+    run0 = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS)
+    mhd.prim2con(run0.patch, run0.eos, run0.Un, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
+    U32 = run0.Un.cpu().numpy()
+    del run0
+    U44, aux = I.m1_fields(ip, U32, P, I.SEED0 + 70)
+    aux[0::3] *= 1e3
+    aux[1::3] *= 1e3
+    aux[2::3] *= 1e3
+    run = ImexRun(ip, U44, aux, I.EOS_IDEAL2, I.PARAMS)
+    del U44, aux
+    dt = 0.25 * ip.dx[0]
+    say("imex path: built in %.1f s" % (time.perf_counter() - t0))
+    mhd.profile_start()
+    ms = time_steps(torch, lambda: run.step(dt), max(2, args.steps // 2), 1)
+    prof = mhd.profile_stop()
+    fin = bool(torch.isfinite(run.Un).all().item())
+    say("imex path: %.3f ms/step" % ms)
+    return {"zone_updates_per_s": round(ip.ninterior * 4 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
+            "evolved_fields": 44, "finite": fin, "implicit_solves_not_converged": int(run.nfail.item()),
+            "kernels": {k: {"launches": n, "ms_per_launch": round(t / n, 4)} for k, (n, t) in prof.items()}}
+
+
 def level_paths(torch, mhd, I, args, mlp):
     """The AMR-level workload: uneven boxes (edges 16..64) on three 2:1 levels of
     the star; per-box launches vs one batched level (autotuned), eager, as a
@@ -266,6 +295,7 @@ def main():
         paths["learned"] = learned_path(torch, mhd, I, run, step, args, nint)
     if not args.no_m1:
         paths["m1"] = m1_path(torch, mhd, I, ip, U, P, EM, args)
+        paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
     if not args.no_level:
         level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
     if "learned" in paths:

@@ -84,19 +84,31 @@ __global__ void __launch_bounds__(256) k_m1_point(M1Args a) {
   m1_point_at(a, i, j, k);
 }
 
+// Lax-Friedrichs speed and the thick-limit weight A = tanh(1/(kappa h)) at the
+// interface between p and p + st; both are shared by the four fields of a
+// species, so they are evaluated once per interface
+struct M1Iface {
+  double lh, A;
+};
+__device__ __forceinline__ M1Iface m1_iface(const double* __restrict__ lam, const double* __restrict__ ka,
+                                            const double* __restrict__ ks, int64_t p, int64_t st, double h) {
+  M1Iface r;
+  r.lh = fmax(lam[p], lam[p + st]);
+  const double kap = 0.5 * (ka[p] + ka[p + st] + ks[p] + ks[p + st]);
+  r.A = kap > 0.0 ? tanh(1.0 / (kap * h)) : 1.0;
+  return r;
+}
+
 // interface value between p and p + st of one field
-__device__ __forceinline__ double m1_holo(const double* __restrict__ u, const double* __restrict__ f,
-                                          const double* __restrict__ lam, const double* __restrict__ ka,
-                                          const double* __restrict__ ks, int64_t p, int64_t st, double h) {
+__device__ __forceinline__ double m1_holo(const double* __restrict__ u, const double* __restrict__ f, const M1Iface& w,
+                                          int64_t p, int64_t st) {
   const double um = u[p - st], u0 = u[p], u1 = u[p + st], u2 = u[p + 2 * st];
   const double fho = 0.5 * (f[p] + f[p + st]);
-  const double lh = fmax(lam[p], lam[p + st]);
-  const double flo = fho - 0.5 * lh * (u1 - u0);
+  const double flo = fho - 0.5 * w.lh * (u1 - u0);
   const double du = u1 - u0;
   double phi = 0.0;
   if (du != 0.0) phi = fmax(0.0, fmin(1.0, fmin(2.0 * (u0 - um) / du, 2.0 * (u2 - u1) / du)));
-  const double kap = 0.5 * (ka[p] + ka[p + st] + ks[p] + ks[p + st]);
-  double A = kap > 0.0 ? tanh(1.0 / (kap * h)) : 1.0;
+  double A = w.A;
   if ((u0 - um) * du < 0.0 && du * (u2 - u1) < 0.0) A = 1.0;
   return fho - A * (1.0 - phi) * (fho - flo);
 }
@@ -114,6 +126,37 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
     m1_metric(U, sf, q, m);
     const double chi = U[12 * sf + q];
     const double alp = U[18 * sf + q], Kh = U[13 * sf + q], Th = U[14 * sf + q];
+    // flux differences of the three species first (the metric derivatives of
+    // the sources are not live meanwhile); each output then gets its
+    // geometric and collision terms in the same order as before
+    double outs[3][4];
+#pragma unroll 1
+    for (int sp = 0; sp < 3; ++sp) {
+      double out[4] = {0.0, 0.0, 0.0, 0.0};
+      const double* ka = a.aux + (int64_t)(3 * sp) * sf;
+      const double* ks = a.aux + (int64_t)(3 * sp + 1) * sf;
+#pragma unroll 1
+      for (int d = 0; d < 3; ++d) {
+        const int64_t st = g.stride(d);
+        const double* lam = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + 4) * sf;
+        vmax = fmax(vmax, lam[q]);
+        const M1Iface wr = m1_iface(lam, ka, ks, q, st, g.h[d]), wl = m1_iface(lam, ka, ks, q - st, st, g.h[d]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const double* u = U + (int64_t)(32 + 4 * sp + c) * sf;
+          const double* f = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + c) * sf;
+          const double fr = m1_holo(u, f, wr, q, st);
+          const double fl = m1_holo(u, f, wl, q - st, st);
+          out[c] -= div_rn(fr - fl, g.h[d], g.idx[d]);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        if (sp == 0) outs[0][c] = out[c];
+        else if (sp == 1) outs[1][c] = out[c];
+        else outs[2][c] = out[c];
+      }
+    }
     double dalp[3], dchi[3], dbeta[3][3], dgt[3][6];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -127,23 +170,11 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
     }
 #pragma unroll 1
     for (int sp = 0; sp < 3; ++sp) {
-      double out[4] = {0.0, 0.0, 0.0, 0.0};
+      double out[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) out[c] = sp == 0 ? outs[0][c] : (sp == 1 ? outs[1][c] : outs[2][c]);
       const double* ka = a.aux + (int64_t)(3 * sp) * sf;
       const double* ks = a.aux + (int64_t)(3 * sp + 1) * sf;
-#pragma unroll 1
-      for (int d = 0; d < 3; ++d) {
-        const int64_t st = g.stride(d);
-        const double* lam = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + 4) * sf;
-        vmax = fmax(vmax, lam[q]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double* u = U + (int64_t)(32 + 4 * sp + c) * sf;
-          const double* f = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + c) * sf;
-          const double fr = m1_holo(u, f, lam, ka, ks, q, st, g.h[d]);
-          const double fl = m1_holo(u, f, lam, ka, ks, q - st, st, g.h[d]);
-          out[c] -= div_rn(fr - fl, g.h[d], g.idx[d]);
-        }
-      }
       // closure quantities at the point
       M1State s;
       m1_load_state(U, a.P, sf, q, sp, m, s);
@@ -236,7 +267,7 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
   return vmax;
 }
 
-__global__ void __launch_bounds__(256) k_m1_update(M1Args a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update(M1Args a) {
   const Geom& g = a.g;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
