@@ -45,6 +45,10 @@ __device__ __forceinline__ double minmod4(double a, double b, double c, double d
 
 // value at i+1/2 from F_{i-2} .. F_{i+2} (= a b c d e)
 __device__ __forceinline__ double mp5(double a, double b, double c, double d, double e, double alpha) {
+  // identical inputs: the limiter below returns c exactly (every difference is 0,
+  // so lo = hi = c and the final correction is minmod2(., 0) = 0); zero
+  // magnetic and cleaning fields outside matter take this exit
+  if (a == c && b == c && d == c && e == c) return c;
   const double unl = div_rn(2.0 * a - 13.0 * b + 47.0 * c + 27.0 * d - 3.0 * e, 60.0, 1.0 / 60.0);
   const double dm = c - b;
   const double fmp = c + minmod2(d - c, alpha * dm);
