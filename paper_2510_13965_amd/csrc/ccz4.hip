@@ -1,23 +1,25 @@
-// CCZ4 right-hand side (Sec. 2.1) at the interior points of one patch.
+// CCZ4 right-hand side (Sec. 2.1) at the interior points of a patch or of the
+// boxes of a level.
 //
 // The point algebra needs well over 256 live FP64 values when evaluated in one
 // piece, so it is split into kernels that each stay within the register file:
-//   k_ccz4_stencil  advection terms beta^k d_k u with the one-sided stencils and
-//                   Kreiss-Oliger dissipation for all 22 fields (Sec. 3.2);
-//                   writes the 22 RHS fields;
-//   k_ccz4_d2       the second derivatives, contracted where possible:
+//   k_ccz4_stencil_lds  advection terms beta^k d_k u with the one-sided
+//                   stencils and Kreiss-Oliger dissipation for all 22 fields
+//                   (Sec. 3.2), staged through LDS; writes the 22 RHS fields;
+//   k_ccz4_d2_lds   the second derivatives, contracted where possible:
 //                   -1/2 gt^{mn} d_m d_n gt_ij, d_i d_j chi, d_i d_j alpha,
 //                   gt^{jk} d_j d_k beta^i and d_i d_k beta^k, into 24 workspace
-//                   fields (one field at a time, so few loads are in flight);
+//                   fields, staged through LDS;
 //   k_ccz4_curv     d_t At_ij, d_t Khat, d_t Theta: the Ricci split
 //                   R_ij + 2 D_(i Z_j) = Rhat_ij + Rhat^chi_ij, D_i D_j alpha and
 //                   the Laplacian of the lapse, matter S_ij, tau (= E), S;
 //                   adds into the RHS;
 //   k_ccz4_gauge    d_t gt_ij, d_t chi, d_t Ghat^i and the gauge (1+log or
 //                   harmonic slicing, Gamma-freezing shift); adds into the RHS.
-// One thread per interior point; 64x4 blocks put a wavefront on 64 consecutive
-// x so every stencil row load is a coalesced 512-byte access and y/z
-// neighbours come from L1/L2.
+// The LDS-staged kernels stream (x,y) tiles along z: 64x4 on a patch, 16x16 on
+// the boxes of a level.  The other two run one thread per interior point;
+// 64x4 blocks put a wavefront on 64 consecutive x so every stencil row load is
+// a coalesced 512-byte access and y/z neighbours come from L1/L2.
 #include "dev_common.hpp"
 #include "prof.hpp"
 
@@ -158,23 +160,6 @@ __device__ __forceinline__ void matter_point(const double* __restrict__ U, const
   m.Str *= chi;
 }
 
-// ------------------------------------------------------------------ advection + KO
-
-__device__ __forceinline__ void ccz4_stencil_at(const Ccz4Args& a, const PointIdx& q) {
-  const Geom& g = a.g;
-  const double* __restrict__ U = a.U;
-  const double beta[3] = {ldf(U + (19) * q.sf, q.voff), ldf(U + (20) * q.sf, q.voff), ldf(U + (21) * q.sf, q.voff)};
-  const double sko[3] = {a.par.sigma_ko * (1.0 / 64.0) * g.idx[0], a.par.sigma_ko * (1.0 / 64.0) * g.idx[1],
-                         a.par.sigma_ko * (1.0 / 64.0) * g.idx[2]};
-#pragma unroll 2
-  for (int f = 0; f < 22; ++f) {
-    const double* u = U + (int64_t)f * q.sf;
-    double s = 0.0;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) s += fdadv(u, q.st[d], q.voff, g.i12[d], beta[d]) + fdko(u, q.st[d], q.voff, sko[d]);
-    a.rhs[(int64_t)f * q.sf + q.p] = s;
-  }
-}
 
 
 // ------------------------------------------------------------------ advection + KO, LDS-staged
@@ -188,8 +173,8 @@ __device__ __forceinline__ void ccz4_stencil_at(const Ccz4Args& a, const PointId
 // replace the ~19 stencil loads of the per-point kernel.  The arithmetic is the per-point kernel's, operation
 // for operation, so both give identical bits.
 
-constexpr int kStTX = 64, kStTY = 4, kStH = 3;
-constexpr int kStLX = kStTX + 2 * kStH, kStLY = kStTY + 2 * kStH;
+constexpr int kStTX = 64, kStTY = 4, kStH = 3;  // patch tiles; halo of the 7-point stencils
+constexpr int kLvT = kLevelLdsTile;             // level tiles are kLvT x kLvT
 
 // beta * D^upwind u from the seven values v[m] = u_{m-3} (as fdadv)
 __device__ __forceinline__ double adv7(const double v[7], double ih12, double beta) {
@@ -215,29 +200,30 @@ struct StencilTile {
   int nbx, nby, nzc;  // tiles in x, y and z chunks of kStZC planes
 };
 
-__global__ void __launch_bounds__(256) k_ccz4_stencil_lds(Ccz4Args a, StencilTile T) {
+// one TX x TY tile through one chunk of z planes (the whole block calls this)
+template <int TX, int TY>
+__device__ __forceinline__ void stencil_lds_tile(const Geom& g, const mhd_params_t& par, const double* __restrict__ U,
+                                                 double* __restrict__ rhs, int tbx, int tby, int tbz,
+                                                 double (&lds)[2][TY + 2 * kStH][TX + 2 * kStH]) {
 #pragma clang fp contract(off)
-  __shared__ double lds[2][kStLY][kStLX];
-  const Geom& g = a.g;
-  const TileXYZ t = tile_of_block(T.nbx, T.nby, T.nzc, a.strip);
-  if (t.bx < 0) return;  // whole block: no barrier is skipped by part of it
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + kStTX * ty;
-  const int i = t.bx * kStTX + tx, j = t.by * kStTY + ty;
-  const int z0 = t.bz * kStZC, nzb = min(kStZC, g.nz - z0);  // planes z0 .. z0+nzb-1 of the interior
+  constexpr int NXH = 2 * kStH * TY, NH = NXH + 2 * kStH * TX;  // x-halo and all halo slots
+  static_assert(NH <= 512, "two halo rounds per thread");
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+  const int i = tbx * TX + tx, j = tby * TY + ty;
+  const int z0 = tbz * kStZC, nzb = min(kStZC, g.nz - z0);  // planes z0 .. z0+nzb-1 of the interior
   const bool col = i < g.nx + g.ng && j < g.ny + g.ng;      // the column exists in the padded patch
   const bool live = i < g.nx && j < g.ny;
   const int64_t sf = g.sf, sz = g.sz;
   const int64_t pc = col ? g.at(i + g.ng, j + g.ng, g.ng + z0) : 0;  // column at plane z0
-  const double* __restrict__ U = a.U;
-  const double sko[3] = {a.par.sigma_ko * (1.0 / 64.0) * g.idx[0], a.par.sigma_ko * (1.0 / 64.0) * g.idx[1],
-                         a.par.sigma_ko * (1.0 / 64.0) * g.idx[2]};
+  const double sko[3] = {par.sigma_ko * (1.0 / 64.0) * g.idx[0], par.sigma_ko * (1.0 / 64.0) * g.idx[1],
+                         par.sigma_ko * (1.0 / 64.0) * g.idx[2]};
   // the shift of the chunk's planes
   double bta[3][kStZC];
 #pragma unroll
   for (int zz = 0; zz < kStZC; ++zz)
 #pragma unroll
     for (int d = 0; d < 3; ++d) bta[d][zz] = (live && zz < nzb) ? U[(int64_t)(19 + d) * sf + pc + zz * sz] : 0.0;
-  // halo slots: 0..23 x-halo (3 left, 3 right, 4 rows), 24..407 y-halo (3 below, 3 above, 64 columns)
+  // halo slots: x-halo (3 left, 3 right, TY rows), then y-halo (3 below, 3 above, TX columns)
   int hx[2], hy[2];
   bool hok[2];
   int64_t hp[2];
@@ -245,19 +231,19 @@ __global__ void __launch_bounds__(256) k_ccz4_stencil_lds(Ccz4Args a, StencilTil
   for (int r = 0; r < 2; ++r) {
     const int h = tid + 256 * r;
     int lx = 0, ly = 0;
-    if (h < 24) {
-      const int side = h / 12, rr = h % 12;
-      ly = kStH + rr / 3;
-      lx = side == 0 ? rr % 3 : kStH + kStTX + rr % 3;
-    } else if (h < 24 + 384) {
-      const int q = h - 24, side = q / 192, rr = q % 192;
-      lx = kStH + rr % 64;
-      ly = side == 0 ? rr / 64 : kStH + kStTY + rr / 64;
+    if (h < NXH) {
+      const int side = h / (kStH * TY), rr = h % (kStH * TY);
+      ly = kStH + rr / kStH;
+      lx = side == 0 ? rr % kStH : kStH + TX + rr % kStH;
+    } else if (h < NH) {
+      const int q = h - NXH, side = q / (kStH * TX), rr = q % (kStH * TX);
+      lx = kStH + rr % TX;
+      ly = side == 0 ? rr / TX : kStH + TY + rr / TX;
     }
-    const int gi = t.bx * kStTX + lx - kStH, gj = t.by * kStTY + ly - kStH;  // interior indices
+    const int gi = tbx * TX + lx - kStH, gj = tby * TY + ly - kStH;  // interior indices
     hx[r] = lx;
     hy[r] = ly;
-    hok[r] = h < 408 && gi >= -g.ng && gj >= -g.ng && gi < g.nx + g.ng && gj < g.ny + g.ng;
+    hok[r] = h < NH && gi >= -g.ng && gj >= -g.ng && gi < g.nx + g.ng && gj < g.ny + g.ng;
     hp[r] = hok[r] ? g.at(gi + g.ng, gj + g.ng, g.ng + z0) : 0;
   }
   // software pipeline: the values of the next plane (the column's plane z+4
@@ -309,12 +295,46 @@ __global__ void __launch_bounds__(256) k_ccz4_stencil_lds(Ccz4Args a, StencilTil
           sacc += adv7(vx, g.i12[0], bta[0][zz]) + ko7(vx, sko[0]);
           sacc += adv7(vy, g.i12[1], bta[1][zz]) + ko7(vy, sko[1]);
           sacc += adv7(q, g.i12[2], bta[2][zz]) + ko7(q, sko[2]);
-          a.rhs[(int64_t)f * sf + pc + zz * sz] = sacc;
+          rhs[(int64_t)f * sf + pc + zz * sz] = sacc;
         }
         buf ^= 1;
       }
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_stencil_lds(Ccz4Args a, StencilTile T) {
+  __shared__ double lds[2][kStTY + 2 * kStH][kStTX + 2 * kStH];
+  const TileXYZ t = tile_of_block(T.nbx, T.nby, T.nzc, a.strip);
+  if (t.bx < 0) return;  // whole block
+  stencil_lds_tile<kStTX, kStTY>(a.g, a.par, a.U, a.rhs, t.bx, t.by, t.bz, lds);
+}
+
+// level: one block per tile of the boxes' LDS tile space (16x16 tiles, so
+// boxes of edge 16..64 keep most lanes busy), in XCD-contiguous ranges
+__device__ __forceinline__ bool level_lds_tile(const LevelArgs& L, int& box, TileXYZ& t) {
+  const int64_t per = (L.ntile_lds + 7) / 8;
+  const int64_t id = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (id >= L.ntile_lds) return false;
+  int lo = 0, hi = L.nboxes - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (L.boxes[mid].t0_lds <= id) lo = mid;
+    else hi = mid - 1;
+  }
+  const BoxDev& B = L.boxes[lo];
+  box = lo;
+  t = tile_of_index((int)(id - B.t0_lds), B.ntx_lds, B.nty_lds, B.nzc_lds, L.strip);
+  return true;
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_stencil_lds_lv(LevelArgs L) {
+  __shared__ double lds[2][kLvT + 2 * kStH][kLvT + 2 * kStH];
+  int b;
+  TileXYZ t;
+  if (!level_lds_tile(L, b, t)) return;  // whole block
+  const BoxDev& B = L.boxes[b];
+  stencil_lds_tile<kLvT, kLvT>(B.g, L.par, L.src ? B.Us : B.U, B.k, t.bx, t.by, t.bz, lds);
 }
 
 // ------------------------------------------------------------------ second derivatives
@@ -345,52 +365,6 @@ __device__ __forceinline__ double d2_beta_lap(const double gtu[6], const double 
   return lap;
 }
 
-__device__ __forceinline__ void ccz4_d2_at(const Ccz4Args& a, double* __restrict__ W, const PointIdx& q) {
-  const Geom& g = a.g;
-  const double* __restrict__ U = a.U;
-  const int64_t sf = q.sf;
-  double gt[6], gtu[6];
-#pragma unroll
-  for (int b = 0; b < 6; ++b) gt[b] = ldf(U + b * sf, q.voff);
-  sym_inv(gt, gtu);
-  double* __restrict__ Wp = W + q.p;
-#pragma unroll 1
-  for (int b = 0; b < 6; ++b) {
-    const double* u = U + (int64_t)b * sf;
-    Wp[(int64_t)b * sf] = d2_gt_contract(
-        gtu, fd2(u, q.st[0], q.voff, g.i12s[0]), fd2(u, q.st[1], q.voff, g.i12s[1]),
-        fd2(u, q.st[2], q.voff, g.i12s[2]), fd11(u, q.st[0], q.st[1], q.voff, g.i12[0], g.i12[1]),
-        fd11(u, q.st[0], q.st[2], q.voff, g.i12[0], g.i12[2]), fd11(u, q.st[1], q.st[2], q.voff, g.i12[1], g.i12[2]));
-  }
-#pragma unroll 1
-  for (int fi = 0; fi < 2; ++fi) {
-    const double* u = U + (int64_t)(fi == 0 ? 12 : 18) * sf;
-    double* o = Wp + (int64_t)(6 + 6 * fi) * sf;
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int e = d; e < 3; ++e)
-        o[(int64_t)sym(d, e) * sf] = (d == e) ? fd2(u, q.st[d], q.voff, g.i12s[d])
-                                              : fd11(u, q.st[d], q.st[e], q.voff, g.i12[d], g.i12[e]);
-  }
-  double ddivb[3] = {0.0, 0.0, 0.0};
-#pragma unroll 1
-  for (int ci = 0; ci < 3; ++ci) {
-    const double* u = U + (int64_t)(19 + ci) * sf;
-    double v[6];
-#pragma unroll
-    for (int d = 0; d < 3; ++d)
-#pragma unroll
-      for (int e = d; e < 3; ++e)
-        v[sym(d, e)] = (d == e) ? fd2(u, q.st[d], q.voff, g.i12s[d])
-                                : fd11(u, q.st[d], q.st[e], q.voff, g.i12[d], g.i12[e]);
-    Wp[(int64_t)(18 + ci) * sf] = d2_beta_lap(gtu, v);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) ddivb[j] += (ci == 0) ? v[sym(j, 0)] : ((ci == 1) ? v[sym(j, 1)] : v[sym(j, 2)]);
-  }
-#pragma unroll
-  for (int j = 0; j < 3; ++j) Wp[(int64_t)(21 + j) * sf] = ddivb[j];
-}
 
 // ------------------------------------------------------------------ second derivatives, LDS-staged
 //
@@ -405,8 +379,7 @@ __device__ __forceinline__ void ccz4_d2_at(const Ccz4Args& a, double* __restrict
 // kernel.  Every derivative is the per-point kernel's expression, operation
 // for operation.
 
-constexpr int kD2ZC = 8, kD2H = 2, kD2LX = 64 + 2 * kD2H, kD2LY = 4 + 2 * kD2H;
-constexpr int kD2NH = kD2LX * kD2LY - 64 * 4;  // halo slots per plane
+constexpr int kD2ZC = 8, kD2H = 2;  // z planes per block; halo of the 5-point stencils
 
 struct D2Tile {
   int nbx, nby, nzc;  // tiles in x, y and z chunks of kD2ZC planes
@@ -423,20 +396,21 @@ __device__ __forceinline__ double d2of5(double m2, double m1, double c, double p
   return (16.0 * (p1 + m1) - (p2 + m2) - 30.0 * c) * ih2_12;
 }
 
-__global__ void __launch_bounds__(256) k_ccz4_d2_lds(Ccz4Args a, double* __restrict__ W, D2Tile T) {
+// one TX x TY tile through one chunk of z planes (the whole block calls this)
+template <int TX, int TY>
+__device__ __forceinline__ void d2_lds_tile(const Geom& g, const double* __restrict__ U, double* __restrict__ W,
+                                            int tbx, int tby, int tbz,
+                                            double (&lds)[2][TY + 2 * kD2H][TX + 2 * kD2H]) {
 #pragma clang fp contract(off)
-  __shared__ double lds[2][kD2LY][kD2LX];
-  const Geom& g = a.g;
-  const TileXYZ t = tile_of_block(T.nbx, T.nby, T.nzc, a.strip);
-  if (t.bx < 0) return;  // whole block
-  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + 64 * ty;
-  const int i = t.bx * 64 + tx, j = t.by * 4 + ty;
-  const int z0 = t.bz * kD2ZC, nzb = min(kD2ZC, g.nz - z0);
+  constexpr int LX = TX + 2 * kD2H, NH = LX * (TY + 2 * kD2H) - TX * TY;  // halo slots per plane
+  static_assert(NH <= 512, "two halo rounds per thread");
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = tx + TX * ty;
+  const int i = tbx * TX + tx, j = tby * TY + ty;
+  const int z0 = tbz * kD2ZC, nzb = min(kD2ZC, g.nz - z0);
   const bool col = i < g.nx + g.ng && j < g.ny + g.ng;
   const bool live = i < g.nx && j < g.ny;
   const int64_t sf = g.sf, sz = g.sz;
   const int64_t pc = col ? g.at(i + g.ng, j + g.ng, g.ng + z0) : 0;  // column at plane z0
-  const double* __restrict__ U = a.U;
   int hx[2], hy[2];
   bool hok[2];
   int64_t hp[2];
@@ -444,21 +418,21 @@ __global__ void __launch_bounds__(256) k_ccz4_d2_lds(Ccz4Args a, double* __restr
   for (int r = 0; r < 2; ++r) {
     const int h = tid + 256 * r;
     int lx = 0, ly = 0;
-    if (h < 2 * kD2LX) {
-      ly = h / kD2LX;
-      lx = h % kD2LX;
-    } else if (h < 4 * kD2LX) {
-      ly = kD2H + 4 + (h - 2 * kD2LX) / kD2LX;
-      lx = (h - 2 * kD2LX) % kD2LX;
-    } else if (h < kD2NH) {
-      const int q = h - 4 * kD2LX, c = q % 4;
+    if (h < 2 * LX) {
+      ly = h / LX;
+      lx = h % LX;
+    } else if (h < 4 * LX) {
+      ly = kD2H + TY + (h - 2 * LX) / LX;
+      lx = (h - 2 * LX) % LX;
+    } else if (h < NH) {
+      const int q = h - 4 * LX, c = q % 4;
       ly = kD2H + q / 4;
-      lx = c < 2 ? c : 64 + c;
+      lx = c < 2 ? c : TX + c;
     }
-    const int gi = t.bx * 64 + lx - kD2H, gj = t.by * 4 + ly - kD2H;
+    const int gi = tbx * TX + lx - kD2H, gj = tby * TY + ly - kD2H;
     hx[r] = lx;
     hy[r] = ly;
-    hok[r] = h < kD2NH && gi >= -g.ng && gj >= -g.ng && gi < g.nx + g.ng && gj < g.ny + g.ng;
+    hok[r] = h < NH && gi >= -g.ng && gj >= -g.ng && gi < g.nx + g.ng && gj < g.ny + g.ng;
     hp[r] = hok[r] ? g.at(gi + g.ng, gj + g.ng, g.ng + z0) : 0;
   }
   const int nst = nzb + 4;  // staged planes z0-2 .. z0+nzb+1
@@ -496,7 +470,7 @@ __global__ void __launch_bounds__(256) k_ccz4_d2_lds(Ccz4Args a, double* __restr
       }
       __syncthreads();
       if (live) {
-        const double(*L)[kD2LX] = lds[buf];
+        const double(*L)[LX] = lds[buf];
         const int cy = ty + kD2H, cx = tx + kD2H;
         // D_x u and D_y u at the staged plane
 #pragma unroll
@@ -561,6 +535,22 @@ __global__ void __launch_bounds__(256) k_ccz4_d2_lds(Ccz4Args a, double* __restr
       buf ^= 1;
     }
   }
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_d2_lds(Ccz4Args a, double* __restrict__ W, D2Tile T) {
+  __shared__ double lds[2][4 + 2 * kD2H][64 + 2 * kD2H];
+  const TileXYZ t = tile_of_block(T.nbx, T.nby, T.nzc, a.strip);
+  if (t.bx < 0) return;  // whole block
+  d2_lds_tile<64, 4>(a.g, a.U, W, t.bx, t.by, t.bz, lds);
+}
+
+__global__ void __launch_bounds__(256) k_ccz4_d2_lds_lv(LevelArgs L) {
+  __shared__ double lds[2][kLvT + 2 * kD2H][kLvT + 2 * kD2H];
+  int b;
+  TileXYZ t;
+  if (!level_lds_tile(L, b, t)) return;  // whole block
+  const BoxDev& B = L.boxes[b];
+  d2_lds_tile<kLvT, kLvT>(B.g, L.src ? B.Us : B.U, B.ws + 33 * B.g.sf, t.bx, t.by, t.bz, lds);
 }
 
 // ------------------------------------------------------------------ At_ij, Khat, Theta
@@ -860,22 +850,6 @@ __device__ __forceinline__ void ccz4_gauge_at(const Ccz4Args& a, const double* _
 
 // ------------------------------------------------------------------ kernels
 
-__global__ void __launch_bounds__(256) k_ccz4_stencil_lv(LevelArgs L) {
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    if (!live) return;
-    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0};
-    ccz4_stencil_at(a, point_at(B.g, i, j, k));
-  });
-}
-
-__global__ void __launch_bounds__(256) k_ccz4_d2_lv(LevelArgs L) {
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    if (!live) return;
-    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0};
-    ccz4_d2_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
-  });
-}
-
 __global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __restrict__ W) {
   const PointIdx q = point_index(a);
   if (!q.live) return;
@@ -930,9 +904,11 @@ int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const d
   return (int)hipGetLastError();
 }
 
-int launch_ccz4_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
-  MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lv, dim3(grid), dim3(block), 0, s, L);
-  MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2_lv, dim3(grid), dim3(block), 0, s, L);
+int launch_ccz4_level(const LevelArgs& L, int grid, int block, int grid_lds, hipStream_t s) {
+  static_assert(kStZC == kLevelLdsZ && kD2ZC == kLevelLdsZ, "one LDS tile space for both staged kernels");
+  const dim3 blk_lds(kLvT, kLvT, 1);
+  MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lds_lv, dim3(grid_lds), blk_lds, 0, s, L);
+  MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2_lds_lv, dim3(grid_lds), blk_lds, 0, s, L);
   MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv_lv, dim3(grid), dim3(block), 0, s, L);
   MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge_lv, dim3(grid), dim3(block), 0, s, L);
   return (int)hipGetLastError();

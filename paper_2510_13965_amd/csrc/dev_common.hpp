@@ -111,6 +111,10 @@ __device__ __forceinline__ void block_max_to(unsigned long long* dst, double v) 
 // Every XCD takes a contiguous range of the global space.  The per-point work
 // is the same device code as the single-patch kernels, so results are bitwise
 // those of per-box launches.
+// LDS-staged level kernels: kLevelLdsTile x kLevelLdsTile (x,y) tiles streamed
+// through chunks of kLevelLdsZ z planes
+constexpr int kLevelLdsTile = 16, kLevelLdsZ = 8;
+
 struct BoxDev {
   Geom g;
   double* U;    // state at t^n
@@ -122,6 +126,8 @@ struct BoxDev {
   uint8_t* flags;
   int cpp_int, cpp_pad;    // chunks per interior / padded z plane
   int64_t t0_int, t0_pad;  // first global tile id of the box in each space
+  int ntx_lds, nty_lds, nzc_lds;  // LDS-staged kernels: (x, y) tiles and z chunks of the box
+  int64_t t0_lds;                 // first global id of the box in the LDS tile space
 };
 
 struct LevelArgs {
@@ -130,7 +136,7 @@ struct LevelArgs {
   int strip;
   int src;  // 0: evaluate at U, 1: at Us
   int stage;
-  int64_t ntile_int, ntile_pad;
+  int64_t ntile_int, ntile_pad, ntile_lds;
   double dt;
   mhd_params_t par;
   mhd_eos_t eos;

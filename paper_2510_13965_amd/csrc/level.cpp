@@ -14,7 +14,7 @@
 
 namespace mhd {
 int launch_con2prim_level(const LevelArgs& L, int grid, int block, hipStream_t s);
-int launch_ccz4_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int launch_ccz4_level(const LevelArgs& L, int grid, int block, int grid_lds, hipStream_t s);
 int launch_mhd_level(const LevelArgs& L, int grid_pad, int grid_int, int block, hipStream_t s);
 int launch_rk4_level(const LevelArgs& L, int grid, int block, hipStream_t s);
 int launch_zero_u64(unsigned long long* p, hipStream_t s);
@@ -32,7 +32,7 @@ struct mhd_level {
   mhd_params_t par;
   mhd_eos_t eos;
   mhd_tuning_t tun;
-  int64_t ntile_int = 0, ntile_pad = 0;
+  int64_t ntile_int = 0, ntile_pad = 0, ntile_lds = 0;
   int ncu = 256;
   // graph of one RK4 step, valid for (dt, max_speed)
   hipStream_t cap = nullptr;
@@ -58,7 +58,7 @@ int layout(mhd_level_t* lv) {
   int rc0 = abi_hip((int)hipDeviceSynchronize(), "mhd_level: synchronize");
   if (rc0) return rc0;
   const int T = block_threads(lv->tun);
-  int64_t ti = 0, tp = 0;
+  int64_t ti = 0, tp = 0, tl = 0;
   for (size_t b = 0; b < lv->boxes.size(); ++b) {
     mhd::BoxDev& B = lv->host[b];
     const mhd::Geom& g = B.g;
@@ -70,11 +70,17 @@ int layout(mhd_level_t* lv) {
     B.t0_pad = tp;
     ti += (int64_t)B.cpp_int * g.nz;
     tp += (int64_t)B.cpp_pad * (g.nz + 2 * g.ng);
+    B.ntx_lds = (g.nx + mhd::kLevelLdsTile - 1) / mhd::kLevelLdsTile;
+    B.nty_lds = (g.ny + mhd::kLevelLdsTile - 1) / mhd::kLevelLdsTile;
+    B.nzc_lds = (g.nz + mhd::kLevelLdsZ - 1) / mhd::kLevelLdsZ;
+    B.t0_lds = tl;
+    tl += (int64_t)B.ntx_lds * B.nty_lds * B.nzc_lds;
   }
-  if (ti >= ((int64_t)1 << 31) || tp >= ((int64_t)1 << 31))
+  if (ti >= ((int64_t)1 << 31) || tp >= ((int64_t)1 << 31) || tl >= ((int64_t)1 << 31))
     return abi_fail(MHD_EINVAL, "mhd_level: too many tiles for one launch");
   lv->ntile_int = ti;
   lv->ntile_pad = tp;
+  lv->ntile_lds = tl;
   if (lv->exec) {
     (void)hipGraphExecDestroy(lv->exec);
     lv->exec = nullptr;
@@ -101,6 +107,7 @@ mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, dou
   L.stage = stage;
   L.ntile_int = lv->ntile_int;
   L.ntile_pad = lv->ntile_pad;
+  L.ntile_lds = lv->ntile_lds;
   L.dt = dt;
   L.par = lv->par;
   L.eos = lv->eos;
@@ -124,7 +131,7 @@ int enqueue_rhs(const mhd_level_t* lv, int src, double* max_speed, int64_t* stat
   } else if ((rc = mhd::launch_con2prim_level(L, gp, T, s))) {
     return rc;
   }
-  if ((rc = mhd::launch_ccz4_level(L, gi, T, s))) return rc;
+  if ((rc = mhd::launch_ccz4_level(L, gi, T, (int)((lv->ntile_lds + 7) / 8 * 8), s))) return rc;
   return mhd::launch_mhd_level(L, gp, gi, T, s);
 }
 
