@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-level", action="store_true", help="skip the batched AMR-level paths")
     ap.add_argument("--no-m1", action="store_true", help="skip the M1-radiation path")
     ap.add_argument("--level-boxes", type=int, default=192)
+    ap.add_argument("--no-c2p-cells", action="store_true", help="skip con2prim on random states")
+    ap.add_argument("--c2p-log2", type=int, default=24, help="log2 of the number of random con2prim states")
     ap.add_argument("--level-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times): the reference for scaling "
@@ -128,6 +130,68 @@ def m1_path(torch, mhd, I, ip, U, P, EM, args):
     say("m1 path: %.3f ms/step" % ms)
     return {"zone_updates_per_s": round(ip.ninterior * 4 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
             "evolved_fields": 44, "finite": fin, "kernels": kernel_table(prof, ip, args.steps + 1, nfields=44)}
+
+
+def c2p_cells_path(torch, mhd, I, args):
+    """con2prim alone on 2^24 random states of the broad distribution (three-piece
+    PWP + thermal part; densities 1e-12..1e-3, W 1..10, magnetisations 1e-4..10):
+    the plain bracketed solver against the learned guess (trained here on 2^20
+    states of its own seed).  Rates in states per second; the learned roots are
+    compared with the plain ones state by state."""
+    from paper_2510_13965_amd import learned
+
+    n = 1 << args.c2p_log2
+    t0 = time.perf_counter()
+    X, T = learned.training_set(1 << 20, seed=I.SEED0 + 90)
+    prm, hist = learned.train(X, T, seed=11, epochs=60, batch=1024)
+    del X, T
+    t_train = time.perf_counter() - t0
+    ip, U, P, EM = I.c2p_cells(ncell=n, seed=I.SEED0 + 91)
+    pt = mhd.patch_of(ip)
+    eos = mhd.make_eos(I.EOS_PWP3)
+    U0 = torch.as_tensor(U).cuda()
+    mhd.prim2con(pt, eos, U0, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 1)
+    del U, P, EM
+    say("c2p cells: %d states ready, network trained in %.1f s" % (n, t_train))
+    out = {"states": n, "train_s": round(t_train, 2), "train_loss_first_last": [hist[0], hist[-1]]}
+    ws = torch.empty((mhd.con2prim_learned_workspace_size(pt) + 7) // 8, dtype=torch.float64, device="cuda")
+    res = {}
+    for mode in ("plain", "learned"):
+        Ud = U0.clone()
+        Pd = torch.zeros((I.NP,) + ip.shape, dtype=torch.float64, device="cuda")
+        fl = torch.zeros(ip.shape, dtype=torch.uint8, device="cuda")
+        mu = torch.zeros((2,) + ip.shape, dtype=torch.float64, device="cuda")
+        st = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device="cuda")
+
+        def once(stats=None):
+            if mode == "plain":
+                mhd.con2prim(pt, eos, Ud, Pd, fl, mu, stats)
+            else:
+                mhd.con2prim_learned(pt, eos, prm, Ud, Pd, ws, fl, mu, stats)
+
+        once(st)  # the counted call, on the untouched states
+        torch.cuda.synchronize()
+        ms = time_steps(torch, once, 3, 1)
+        res[mode] = (mu.clone(), fl.clone(), st.cpu().numpy())
+        out[mode] = {"states_per_s": round(n / (ms * 1e-3), 1), "ms": round(ms, 3),
+                     "root_evals_per_state": round(float(res[mode][2][3]) / n, 3)}
+        say("c2p cells %s: %.3f ms" % (mode, ms))
+        del Ud, Pd
+    mup, flp, _ = res["plain"]
+    mul, fll, stl = res["learned"]
+    solved = (mup[1] > 0) & ((fll & 32) == 0)
+    rel = ((mul - mup).abs() / mup.abs().clamp_min(1e-300))[:, solved]
+    # Where the root function has more than one root in (0, mu_+] (possible once
+    # the density and energy are clamped to the EoS range), Newton from the
+    # learned guess and the bracketing solver may converge to different roots:
+    # counted separately; the maximum difference is taken over the other states.
+    other = rel[1] > 1e-6
+    out["learned"]["fallback_rate"] = round(float(stl[2]) / n, 6)
+    out["learned"]["states_other_root"] = int(other.sum().item())
+    same = rel[:, ~other]
+    out["learned"]["max_rel_root_difference"] = [float(same[0].max().item()), float(same[1].max().item())]
+    out["learned"]["flags_differ"] = int(((fll & ~32) != flp).sum().item())
+    return out
 
 
 def imex_path(torch, mhd, I, ip, U, P, EM, args):
@@ -293,6 +357,8 @@ def main():
     level = None
     if not args.no_learned:
         paths["learned"] = learned_path(torch, mhd, I, run, step, args, nint)
+    if not args.no_c2p_cells:
+        paths["c2p_cells"] = c2p_cells_path(torch, mhd, I, args)
     if not args.no_m1:
         paths["m1"] = m1_path(torch, mhd, I, ip, U, P, EM, args)
         paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
