@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--no-level", action="store_true", help="skip the batched AMR-level paths")
     ap.add_argument("--no-m1", action="store_true", help="skip the M1-radiation path")
     ap.add_argument("--level-boxes", type=int, default=192)
+    ap.add_argument("--no-level-m1", action="store_true", help="skip the batched level with M1 radiation")
+    ap.add_argument("--level-m1-boxes", type=int, default=803)
     ap.add_argument("--no-c2p-cells", action="store_true", help="skip con2prim on random states")
     ap.add_argument("--c2p-log2", type=int, default=24, help="log2 of the number of random con2prim states")
     ap.add_argument("--level-steps", type=int, default=5)
@@ -293,6 +295,101 @@ def level_paths(torch, mhd, I, args, mlp):
     return res
 
 
+class _Units:
+    """Interior and padded point counts of a set of boxes (for kernel_table)."""
+
+    def __init__(self, ninterior, npts):
+        self.ninterior, self.npts = ninterior, npts
+
+
+def level_m1_path(torch, mhd, I, args, mlp):
+    """The coupled system with three grey M1 species (44 fields) on a batched
+    level of ~800 uneven boxes (~40 M interior points) of the star: per-box
+    launches with the bracketed con2prim against the autotuned batched level
+    replayed as a hipGraph, with the bracketed and with the learned con2prim."""
+    from paper_2510_13965_amd.step import LevelRun
+
+    from concurrent.futures import ThreadPoolExecutor
+
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    boxes = I.amr_level_boxes(seed=I.SEED0 + 5, nboxes=args.level_m1_boxes)
+    Ab = I.star_field_amplitude()
+    eos = mhd.make_eos(I.EOS_IDEAL2)
+
+    def host_box(b):
+        # numpy releases the GIL in the array work: boxes are generated in threads
+        ip, U, P, EM = I.amr_box_state(boxes[b], Ab)
+        R, aux = I.m1_radiation(ip, P, I.SEED0 + 500 + b)
+        return ip, U, P, EM, R, aux
+
+    ips, states, auxs = [], [], []
+    workers = max(1, min(16, len(os.sched_getaffinity(0))))
+    with ThreadPoolExecutor(workers) as ex:
+        for ip, U, P, EM, R, aux in ex.map(host_box, range(len(boxes))):
+            Ud = torch.empty((I.NU_M1,) + tuple(ip.shape), dtype=torch.float64, device="cuda")
+            Ud[:I.NU].copy_(torch.as_tensor(U))
+            Ud[I.NU:].copy_(torch.as_tensor(R))
+            mhd.prim2con(mhd.patch_of(ip), eos, Ud, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
+            ips.append(ip)
+            states.append(Ud)
+            auxs.append(torch.as_tensor(aux).cuda())
+    par = dict(I.PARAMS, evolve_m1=1)
+    lr = LevelRun(ips, states, I.EOS_IDEAL2, par, auxs=auxs)
+    del states, auxs
+    torch.cuda.synchronize()
+    say("level M1: %d boxes, %d interior points, built in %.1f s" % (len(ips), lr.ninterior, time.perf_counter() - t0))
+    dt = 0.25 * min(ip.dx[0] for ip in ips)
+    nzu = lr.ninterior * 4
+    res = {"workload": "%d boxes, edges from {16,24,32,48,64}, 3 levels dx=1,1/2,1/4 of the TOV star, CCZ4+GRMHD+3 "
+                       "grey M1 species (44 fields); dt=%.4g" % (len(ips), dt),
+           "interior_points": lr.ninterior, "padded_points": lr.npts, "evolved_fields": I.NU_M1}
+
+    def per_box_step():
+        for s in range(4):
+            for b in lr.boxes:
+                Ux = b["U"] if s == 0 else b["Us"]
+                mhd.con2prim(b["patch"], lr.eos, Ux, b["P"], b.get("flags"), None, None)
+                mhd.rhs(b["patch"], lr.par, lr.eos, Ux, b["P"], b["k"], None, b["ws"], aux=b["aux"])
+                mhd.rk_stage(b["patch"], I.NU_M1, s, dt, b["U"], b["k"], b["acc"], b["Us"] if s < 3 else b["U"])
+
+    ms = time_steps(torch, per_box_step, 1, 1)
+    res["per_box"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+    say("level M1 per-box: %.2f ms/step" % ms)
+    t1 = time.perf_counter()
+    res["autotuned"] = lr.level.autotune(dt)
+    res["autotune_s"] = round(time.perf_counter() - t1, 2)
+    stream = torch.cuda.Stream()
+    units = _Units(lr.ninterior, lr.npts)
+    for tag, m in (("batched_graph", None), ("batched_graph_learned", mlp)):
+        if tag == "batched_graph_learned" and m is None:
+            continue
+        lr.level.set_learned(m)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            lr.level.rk4_step(dt, use_graph=True, stream=stream)   # capture + warm-up
+            ms = time_steps(torch, lambda: lr.level.rk4_step(dt, use_graph=True, stream=stream),
+                            args.level_steps, 0)
+        res[tag] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+        say("level M1 %s (%s): %.2f ms/step" % (tag, res["autotuned"], ms))
+    # per-kernel times of one eager step (graph replays are not event-timed)
+    lr.level.set_learned(mlp)
+    mhd.profile_start()
+    lr.level.rk4_step(dt)
+    prof = mhd.profile_stop()
+    res["kernels"] = kernel_table(prof, units, 1, nfields=I.NU_M1)
+    st = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device="cuda")
+    lr.level.rhs(0, None, st)
+    st = st.cpu().numpy()
+    res["c2p_learned" if mlp is not None else "c2p_plain"] = {
+        "fallback_rate": round(float(st[2]) / lr.npts, 6), "root_evals_per_point": round(float(st[3]) / lr.npts, 3)}
+    res["finite"] = all(bool(torch.isfinite(b["U"]).all().item()) for b in lr.boxes)
+    lr.level.close()
+    del lr
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -364,6 +461,8 @@ def main():
         paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
     if not args.no_level:
         level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
+    if not args.no_level_m1:
+        paths["level_m1"] = level_m1_path(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
     if "learned" in paths:
         paths["learned"].pop("_mlp", None)
 

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 2
+#define MHD_ABI_VERSION 3
 
 #define MHD_NST 22
 #define MHD_NMHD 10
@@ -260,19 +260,25 @@ int mhd_mlp_adam(float* mlp, const float* grad, float* m, float* v, int step, fl
  * single-patch entry points, so results are bitwise equal to per-box calls of
  * mhd_con2prim, mhd_rhs and mhd_rk_stage.  Ghost values are taken as given
  * (frozen; the level does not exchange or fill them).  The level evolves the
- * full coupled system (params->flags must hold all three MHD_* flags).
+ * full coupled system (params->flags must hold MHD_EVOLVE_SPACETIME,
+ * MHD_EVOLVE_MHD and MHD_COUPLE_MATTER); with MHD_EVOLVE_M1 as well, every box
+ * also evolves the three grey M1 species (Sec. 2.3, 3.4): U, Us, k and acc then
+ * hold MHD_NU_M1 fields, aux is required and the workspace is
+ * mhd_rhs_workspace_size_m1() bytes; the results are bitwise those of per-box
+ * mhd_rhs with MHD_EVOLVE_M1 and mhd_rk_stage over 44 fields.
  * mhd_level_create copies the descriptors to the device (the only allocation,
  * with a capture stream); the arrays stay the caller's and must outlive it. */
 typedef struct {
   mhd_patch_t patch;
-  double* U;        /* state at t^n (32 fields); the RK4 step updates it in place */
-  double* Us;       /* stage state (32 fields) */
+  double* U;        /* state at t^n (32 or 44 fields); the RK4 step updates it in place */
+  double* Us;       /* stage state (32 or 44 fields) */
   double* P;        /* primitives (8 fields) */
-  double* k;        /* right-hand side (32 fields) */
-  double* acc;      /* RK4 accumulator (32 fields) */
-  void* workspace;  /* mhd_rhs_workspace_size(&patch) bytes or more */
+  double* k;        /* right-hand side (32 or 44 fields) */
+  double* acc;      /* RK4 accumulator (32 or 44 fields) */
+  void* workspace;  /* mhd_rhs_workspace_size(&patch) bytes or more (_m1 with M1) */
   size_t workspace_bytes;
   uint8_t* flags;   /* con2prim flags, may be NULL */
+  const double* aux; /* MHD_NAUX fields (kappa_a, kappa_s, eta per species) with MHD_EVOLVE_M1, else NULL */
 } mhd_box_t;
 
 typedef struct mhd_level mhd_level_t;

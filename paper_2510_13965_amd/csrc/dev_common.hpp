@@ -124,6 +124,8 @@ struct BoxDev {
   double* acc;  // RK accumulator
   double* ws;   // RHS workspace
   uint8_t* flags;
+  const double* aux;  // M1 opacities and emissivities (levels evolving radiation), else null
+  double* ws_m1;      // M1 part of the RHS workspace, else null
   int cpp_int, cpp_pad;    // chunks per interior / padded z plane
   int64_t t0_int, t0_pad;  // first global tile id of the box in each space
   int ntx_lds, nty_lds, nzc_lds;  // LDS-staged kernels: (x, y) tiles and z chunks of the box
@@ -136,6 +138,8 @@ struct LevelArgs {
   int strip;
   int src;  // 0: evaluate at U, 1: at Us
   int stage;
+  int nfields;  // evolved fields: 32, or 44 with three M1 species
+  int m1;       // nonzero: the boxes evolve the M1 radiation
   int64_t ntile_int, ntile_pad, ntile_lds;
   double dt;
   mhd_params_t par;

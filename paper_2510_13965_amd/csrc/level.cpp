@@ -19,6 +19,9 @@ int launch_mhd_level(const LevelArgs& L, int grid_pad, int grid_int, int block, 
 int launch_rk4_level(const LevelArgs& L, int grid, int block, hipStream_t s);
 int launch_zero_u64(unsigned long long* p, hipStream_t s);
 int launch_con2prim_learned_level(const LevelArgs& L, int grid, int block, int grid_fb, hipStream_t s);
+int launch_m1_point_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int ccz4_workspace_fields();
 int abi_fail(int code, const char* msg);
 int abi_hip(int rc, const char* what);
 Geom abi_geom(const mhd_patch_t* p);
@@ -105,6 +108,8 @@ mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, dou
   L.strip = lv->tun.strip;
   L.src = src;
   L.stage = stage;
+  L.m1 = (lv->par.flags & MHD_EVOLVE_M1) ? 1 : 0;
+  L.nfields = L.m1 ? MHD_NU_M1 : MHD_NU;
   L.ntile_int = lv->ntile_int;
   L.ntile_pad = lv->ntile_pad;
   L.ntile_lds = lv->ntile_lds;
@@ -131,8 +136,13 @@ int enqueue_rhs(const mhd_level_t* lv, int src, double* max_speed, int64_t* stat
   } else if ((rc = mhd::launch_con2prim_level(L, gp, T, s))) {
     return rc;
   }
+  // the order of mhd_rhs: M1 closure and point fluxes (the CCZ4 matter terms read
+  // the closure), CCZ4, GRMHD, then the M1 update (which adds the radiation's
+  // exchange to the fluid's right-hand side)
+  if (L.m1 && (rc = mhd::launch_m1_point_level(L, gp, T, s))) return rc;
   if ((rc = mhd::launch_ccz4_level(L, gi, T, (int)((lv->ntile_lds + 7) / 8 * 8), s))) return rc;
-  return mhd::launch_mhd_level(L, gp, gi, T, s);
+  if ((rc = mhd::launch_mhd_level(L, gp, gi, T, s))) return rc;
+  return L.m1 ? mhd::launch_m1_update_level(L, gi, T, s) : 0;
 }
 
 int enqueue_stage(const mhd_level_t* lv, int stage, double dt, hipStream_t s) {
@@ -171,6 +181,8 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
   const uint32_t need = MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER;
   if ((par->flags & need) != need)
     return abi_fail(MHD_EINVAL, "mhd_level_create: a level evolves the full coupled system (all flags set)");
+  if (par->flags & ~(need | MHD_EVOLVE_M1)) return abi_fail(MHD_EINVAL, "mhd_level_create: unknown params flags");
+  const bool m1 = (par->flags & MHD_EVOLVE_M1) != 0;
   if (par->f_alpha_kind != MHD_FALPHA_ONE && par->f_alpha_kind != MHD_FALPHA_HARMONIC)
     return abi_fail(MHD_EINVAL, "mhd_level_create: unknown f_alpha_kind");
   if (!(par->c_b > 0.0)) return abi_fail(MHD_EINVAL, "mhd_level_create: c_b must be > 0");
@@ -181,8 +193,9 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
     if ((rc = mhd::abi_check_patch(&B.patch, 3, "mhd_level_create"))) return rc;
     if (!B.U || !B.Us || !B.P || !B.k || !B.acc || !B.workspace)
       return abi_fail(MHD_EINVAL, "mhd_level_create: box arrays must be non-NULL (flags may be NULL)");
-    if (B.workspace_bytes < mhd_rhs_workspace_size(&B.patch))
+    if (B.workspace_bytes < (m1 ? mhd_rhs_workspace_size_m1(&B.patch) : mhd_rhs_workspace_size(&B.patch)))
       return abi_fail(MHD_EWORKSPACE, "mhd_level_create: box workspace too small");
+    if (m1 && !B.aux) return abi_fail(MHD_EINVAL, "mhd_level_create: aux is required with MHD_EVOLVE_M1");
     if (B.patch.sf > (int64_t)(INT32_MAX / 8))
       return abi_fail(MHD_EINVAL, "mhd_level_create: a padded field exceeds the 2^28-point limit");
   }
@@ -201,6 +214,8 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
     D.acc = B.acc;
     D.ws = static_cast<double*>(B.workspace);
     D.flags = B.flags;
+    D.aux = m1 ? B.aux : nullptr;
+    D.ws_m1 = m1 ? D.ws + (int64_t)(33 + mhd::ccz4_workspace_fields()) * B.patch.sf : nullptr;
     lv->npad += (int64_t)(B.patch.nx + 6) * (B.patch.ny + 6) * (B.patch.nz + 6);
   }
   lv->par = *par;

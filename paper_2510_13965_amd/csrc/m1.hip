@@ -130,6 +130,8 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
     // the sources are not live meanwhile); each output then gets its
     // geometric and collision terms in the same order as before
     double outs[3][4];
+    const double hx = g.h[0], hy = g.h[1], hz = g.h[2];
+    const double ihx = g.idx[0], ihy = g.idx[1], ihz = g.idx[2];
 #pragma unroll 1
     for (int sp = 0; sp < 3; ++sp) {
       double out[4] = {0.0, 0.0, 0.0, 0.0};
@@ -140,14 +142,15 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
         const int64_t st = g.stride(d);
         const double* lam = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + 4) * sf;
         vmax = fmax(vmax, lam[q]);
-        const M1Iface wr = m1_iface(lam, ka, ks, q, st, g.h[d]), wl = m1_iface(lam, ka, ks, q - st, st, g.h[d]);
+        const double h = d == 0 ? hx : (d == 1 ? hy : hz), ih = d == 0 ? ihx : (d == 1 ? ihy : ihz);
+        const M1Iface wr = m1_iface(lam, ka, ks, q, st, h), wl = m1_iface(lam, ka, ks, q - st, st, h);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const double* u = U + (int64_t)(32 + 4 * sp + c) * sf;
           const double* f = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + c) * sf;
           const double fr = m1_holo(u, f, wr, q, st);
           const double fl = m1_holo(u, f, wl, q - st, st);
-          out[c] -= div_rn(fr - fl, g.h[d], g.idx[d]);
+          out[c] -= div_rn(fr - fl, h, ih);
         }
       }
 #pragma unroll
@@ -276,7 +279,35 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   if (a.max_speed) block_max_to(a.max_speed, vmax);
 }
 
+// levels: the same point functions over every box, one persistent launch each
+__global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
+  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr};
+    m1_point_at(a, i, j, k);
+  });
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update_lv(LevelArgs L) {
+  double vmax = 0.0;
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, B.k, L.max_speed, nullptr};
+    vmax = fmax(vmax, m1_update_at(a, i, j, k, live));
+  });
+  if (L.max_speed) block_max_to(L.max_speed, vmax);
+}
+
 int m1_workspace_fields() { return kM1Fields; }
+
+int launch_m1_point_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_M1_POINT, k_m1_point_lv, dim3(grid), dim3(block), 0, s, L);
+  return (int)hipGetLastError();
+}
+
+int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_M1_UPDATE, k_m1_update_lv, dim3(grid), dim3(block), 0, s, L);
+  return (int)hipGetLastError();
+}
 
 int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, hipStream_t s) {
   M1Args a{g, U, P, aux, ws, nullptr, nullptr, nullptr};

@@ -50,15 +50,21 @@ __global__ void __launch_bounds__(256) k_rk4_stage(RkArgs a) {
   rk4_element(a, (int64_t)f * g.sf + g.at(i + g.ng, j + g.ng, kz + g.ng));
 }
 
-// all 32 fields of every interior point of a level's boxes
-__global__ void __launch_bounds__(256) k_rk4_stage_lv(LevelArgs L) {
+// all evolved fields (32, or 44 with M1) of every interior point of a level's boxes
+template <int NF>
+__device__ __forceinline__ void rk4_level_point(const LevelArgs& L) {
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     const RkArgs a{B.g, L.stage, L.dt, B.U, B.k, B.acc, L.stage < 3 ? B.Us : B.U};
     const int64_t p = B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng);
 #pragma unroll 4
-    for (int f = 0; f < MHD_NU; ++f) rk4_element(a, (int64_t)f * B.g.sf + p);
+    for (int f = 0; f < NF; ++f) rk4_element(a, (int64_t)f * B.g.sf + p);
   });
+}
+
+__global__ void __launch_bounds__(256) k_rk4_stage_lv(LevelArgs L) {
+  if (L.nfields == MHD_NU_M1) rk4_level_point<MHD_NU_M1>(L);
+  else rk4_level_point<MHD_NU>(L);
 }
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }

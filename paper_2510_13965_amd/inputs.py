@@ -456,10 +456,20 @@ def m1_fields(patch, U32, P, seed):
     (so radiation streams freely through the atmosphere and kappa dt stays
     well inside the explicit RK4 stability interval at the star's densities);
     eta = kappa_a E_eq with E_eq = 1e-2 rho eps."""
+    R, aux = m1_radiation(patch, P, seed)
+    U = np.empty((NU_M1,) + patch.shape)
+    U[:NU] = U32[:NU]
+    U[NU:] = R
+    return U, aux
+
+
+def m1_radiation(patch, P, seed):
+    """The radiation part of m1_fields alone: the 12 fields Ebar, Fbar_i of the
+    three species (in U order from field 32) and the 9 aux fields; they depend
+    on the primitives P and the seed only."""
     r = rng(seed)
     Z, Y, X = patch.coords()
-    U = np.zeros((NU_M1,) + patch.shape)
-    U[:NU] = U32[:NU]
+    R = np.zeros((NU_M1 - NU,) + patch.shape)
     aux = np.zeros((NAUX,) + patch.shape)
     for s in range(3):
         Eb = 10.0 ** (-10.0 + 6.0 * _smooth01(r, patch, X, Y, Z))
@@ -468,12 +478,12 @@ def m1_fields(patch, U32, P, seed):
         frac = 0.95 * (wm * _smooth01(r, patch, X, Y, Z) + (1.0 - wm))
         d = np.array([2.0 * _smooth01(r, patch, X, Y, Z) - 1.0 for _ in range(3)]) + 1e-3
         d /= np.sqrt((d * d).sum(0))
-        U[32 + 4 * s] = Eb
+        R[4 * s] = Eb
         for a in range(3):
-            U[33 + 4 * s + a] = frac * Eb * d[a]
+            R[4 * s + 1 + a] = frac * Eb * d[a]
         ka = 10.0 ** r.uniform(-3.0, 0.0, patch.shape) * (P[RHO] / 1e-3)
         ks = 10.0 ** r.uniform(-3.0, 0.0, patch.shape) * (P[RHO] / 1e-3)
         aux[3 * s] = ka
         aux[3 * s + 1] = ks
         aux[3 * s + 2] = ka * 1e-2 * P[RHO] * P[EPS]
-    return U, aux
+    return R, aux

@@ -51,7 +51,7 @@ class Tuning(C.Structure):
 class Box(C.Structure):
     _fields_ = [("patch", Patch), ("U", C.c_void_p), ("Us", C.c_void_p), ("P", C.c_void_p), ("k", C.c_void_p),
                 ("acc", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
-                ("flags", C.c_void_p)]
+                ("flags", C.c_void_p), ("aux", C.c_void_p)]
 
 
 class KernelTime(C.Structure):
@@ -317,7 +317,8 @@ def get_tuning():
 class Level:
     """A batched level (mhd_level_*).  `boxes` is a list of dicts with the
     patch (mhd_patch_t) and device tensors U, Us, P, k, acc, ws and
-    optionally flags; the tensors are kept alive with the level."""
+    optionally flags and aux (required when params evolve M1); the tensors are
+    kept alive with the level."""
 
     def __init__(self, boxes, params, eos):
         self._keep = boxes
@@ -329,6 +330,7 @@ class Level:
             arr[b].workspace = _ptr(d["ws"])
             arr[b].workspace_bytes = d["ws"].numel() * d["ws"].element_size()
             arr[b].flags = _ptr(d.get("flags"))
+            arr[b].aux = _ptr(d.get("aux"))
         self._params, self._eos = params, eos
         h = C.c_void_p()
         _check(lib().mhd_level_create(arr, len(boxes), C.byref(params), C.byref(eos), C.byref(h)))

@@ -70,18 +70,22 @@ class LevelRun:
     """Device buffers of a list of boxes and their batched level (mhd_level_*).
     Us starts as a copy of U so the stage states carry the (frozen) ghosts."""
 
-    def __init__(self, ipatches, states, eos_cfg, par_cfg, device="cuda", flags=True):
+    def __init__(self, ipatches, states, eos_cfg, par_cfg, device="cuda", flags=True, auxs=None):
         self.eos = mhd.make_eos(eos_cfg)
         self.par = mhd.make_params(par_cfg)
+        self.m1 = bool(par_cfg.get("evolve_m1", 0))
+        self.nfields = I.NU_M1 if self.m1 else I.NU
         self.boxes = []
-        for ip, U0 in zip(ipatches, states):
+        for b, (ip, U0) in enumerate(zip(ipatches, states)):
             pt = mhd.patch_of(ip)
             U = torch.as_tensor(U0, dtype=torch.float64).to(device).contiguous()
             d = dict(patch=pt, ip=ip, U=U, Us=U.clone(), k=torch.zeros_like(U), acc=torch.zeros_like(U),
                      P=torch.zeros((I.NP,) + tuple(ip.shape), dtype=torch.float64, device=device),
-                     ws=mhd.workspace_for(pt, device))
+                     ws=mhd.workspace_for(pt, device, m1=self.m1))
             if flags:
                 d["flags"] = torch.zeros(tuple(ip.shape), dtype=torch.uint8, device=device)
+            if auxs is not None and auxs[b] is not None:
+                d["aux"] = torch.as_tensor(auxs[b], dtype=torch.float64).to(device).contiguous()
             self.boxes.append(d)
         self.level = mhd.Level(self.boxes, self.par, self.eos)
 

@@ -213,3 +213,121 @@ def test_level_learned_equals_per_box_learned(level_states):
     assert_same(ref, got, "learned")
     fb = np.mean([((g["flags"] & 32) != 0).mean() for g in got])
     say("fallback share with these weights %.3f" % fb)
+
+
+# ---------------------------------------------------------------- levels with M1
+
+PAR_M1 = dict(I.PARAMS, evolve_m1=1)
+
+
+@pytest.fixture(scope="module")
+def level_m1_states(dev):
+    """Six uneven boxes of the star with three grey M1 species (radiation inputs
+    following the matter, as on the single patch); cons built on the device."""
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    boxes = I.amr_level_boxes(seed=I.SEED0 + 31, nboxes=6, edges=(16, 24, 32))
+    Ab = I.star_field_amplitude()
+    eos = mhd.make_eos(I.EOS_IDEAL2)
+    out = []
+    for b, box in enumerate(boxes):
+        ip, U, P, EM = I.amr_box_state(box, Ab)
+        Ud = torch.as_tensor(U).cuda()
+        mhd.prim2con(mhd.patch_of(ip), eos, Ud, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
+        U44, aux = I.m1_fields(ip, Ud.cpu().numpy(), P, I.SEED0 + 310 + b)
+        out.append((ip, U44, aux))
+    say("level M1 boxes", [ip.n for ip, _, _ in out])
+    return out
+
+
+def m1_level_run(states, **kw):
+    from paper_2510_13965_amd.step import LevelRun
+
+    return LevelRun([s[0] for s in states], [s[1] for s in states], I.EOS_IDEAL2, PAR_M1,
+                    auxs=[s[2] for s in states], **kw)
+
+
+def test_level_m1_rhs_bitwise_equals_per_box(level_m1_states):
+    import torch
+    from paper_2510_13965_amd.step import PatchRun
+
+    say("case level M1 rhs vs per-box, 6 boxes")
+    ref, vref = [], 0.0
+    for ip, U, aux in level_m1_states:
+        r = PatchRun(ip, U, I.EOS_IDEAL2, PAR_M1, aux=aux)
+        r.rhs_eval(r.Un)
+        torch.cuda.synchronize()
+        vref = max(vref, float(r.vmax.item()))
+        ref.append(dict(k=r.k.cpu().numpy(), P=r.P.cpu().numpy(), flags=r.flags.cpu().numpy(), U=r.Un.cpu().numpy()))
+    for tun in (None, dict(strip=16, block_threads=128, grid_per_cu=4)):
+        run = m1_level_run(level_m1_states)
+        if tun:
+            run.level.set_tuning(**tun)
+        got, v = level_rhs(run)
+        assert_same(ref, got, "M1 %s" % tun)
+        assert v == vref
+
+
+def test_level_m1_rk4_eager_and_graph_replays(level_m1_states):
+    """Two RK4 steps (44 fields) per box, eager level and replayed graph level."""
+    import torch
+    from paper_2510_13965_amd.step import PatchRun
+
+    say("case level M1 rk4 eager/graph, 6 boxes, 2 steps")
+    dt = 0.25 * 0.25
+    boxes = [PatchRun(ip, U, I.EOS_IDEAL2, PAR_M1, aux=aux) for ip, U, aux in level_m1_states]
+    eager = m1_level_run(level_m1_states)
+    graph = m1_level_run(level_m1_states)
+    ms_e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ms_g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.Stream()
+    for step in range(2):
+        for r in boxes:
+            r.step(dt)
+        eager.level.rk4_step(dt, ms_e)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            graph.level.rk4_step(dt, ms_g, use_graph=True, stream=stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for b, r in enumerate(boxes):
+            ref = r.Un.cpu().numpy()
+            assert np.isfinite(ref).all()
+            assert np.array_equal(ref, eager.boxes[b]["U"].cpu().numpy()), ("eager", step, b)
+            assert np.array_equal(ref, graph.boxes[b]["U"].cpu().numpy()), ("graph", step, b)
+        assert float(ms_e.item()) == float(ms_g.item()) > 0.0
+        say("step", step, "ok, max speed", float(ms_e.item()))
+
+
+def test_level_m1_box_against_oracle(orc, level_m1_states):
+    """The level's coupled RHS with radiation on its smallest box against the
+    FP64 oracle (1e-10 per field, all 44 fields)."""
+    ip, U, aux = min(level_m1_states, key=lambda s: s[0].npts)
+    say("case level M1 box vs oracle", ip.n)
+    run = m1_level_run([(ip, U, aux)])
+    got, _ = level_rhs(run)
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    e = orc.make_eos(I.EOS_IDEAL2)
+    Uo = U.copy()
+    Po = np.zeros((I.NP,) + ip.shape)
+    orc.con2prim(g, e, Uo, Po, None, None)
+    ko = np.zeros_like(U)
+    orc.rhs_full(g, orc.make_par(PAR_M1), e, Uo, Po, aux, ko)
+    sl = (slice(None),) + ip.interior()
+    kg, ko = got[0]["k"][sl], ko[sl]
+    for f in range(I.NU_M1):
+        m = np.abs(ko[f]).max()
+        if m > 0:
+            assert np.abs(kg[f] - ko[f]).max() <= 1e-10 * m, f
+        else:
+            assert np.abs(kg[f]).max() == 0.0, f
+
+
+def test_level_m1_rejects_missing_aux(level_m1_states):
+    from paper_2510_13965_amd import mhd
+
+    say("case level M1 without aux")
+    ip, U, aux = level_m1_states[0]
+    with pytest.raises(mhd.MhdError, match="aux is required"):
+        m1_level_run([(ip, U, None)])
