@@ -33,14 +33,18 @@ namespace mhd {
 
 // ------------------------------------------------------------------ MP5 (Sec. 3.3)
 
+// minmod of 2 and 4 arguments: the argument of least magnitude when all share a
+// strict sign, else 0; taken from the extremes (the smallest is the answer when it
+// is positive, the largest when it is negative), which gives the same bits as the
+// case-by-case definition with fewer compares and selects
 __device__ __forceinline__ double minmod2(double a, double b) {
-  return (a > 0.0 && b > 0.0) ? fmin(a, b) : ((a < 0.0 && b < 0.0) ? fmax(a, b) : 0.0);
+  const double lo = fmin(a, b), hi = fmax(a, b);
+  return lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
 }
 
 __device__ __forceinline__ double minmod4(double a, double b, double c, double d) {
-  if (a > 0.0 && b > 0.0 && c > 0.0 && d > 0.0) return fmin(fmin(a, b), fmin(c, d));
-  if (a < 0.0 && b < 0.0 && c < 0.0 && d < 0.0) return fmax(fmax(a, b), fmax(c, d));
-  return 0.0;
+  const double lo = fmin(fmin(a, b), fmin(c, d)), hi = fmax(fmax(a, b), fmax(c, d));
+  return lo > 0.0 ? lo : (hi < 0.0 ? hi : 0.0);
 }
 
 // value at i+1/2 from F_{i-2} .. F_{i+2} (= a b c d e)
@@ -223,6 +227,10 @@ __device__ __forceinline__ double mhd_update_at(const MhdUpdArgs& a, int i, int 
   for (int f = 0; f < 10; ++f) out[f] = 0.0;
   double vmax = 0.0;
 
+  // spacings as values: selecting among fields of a local copy of the geometry
+  // (level kernels build one per box) would keep that copy in private memory
+  const double hx = g.h[0], hy = g.h[1], hz = g.h[2];
+  const double ihx = g.idx[0], ihy = g.idx[1], ihz = g.idx[2];
 #pragma unroll 1
   for (int d = 0; d < 3; ++d) {
     const int64_t s = g.stride(d);
@@ -237,7 +245,8 @@ __device__ __forceinline__ double mhd_update_at(const MhdUpdArgs& a, int i, int 
       lL = fmax(lL, l[m]);
       lR = fmax(lR, l[m + 1]);
     }
-    const double hd = d == 0 ? g.h[0] : (d == 1 ? g.h[1] : g.h[2]);
+    const double hd = d == 0 ? hx : (d == 1 ? hy : hz);
+    const double ihd = d == 0 ? ihx : (d == 1 ? ihy : ihz);
 #pragma unroll
     for (int f = 0; f < 10; ++f) {
       const double* __restrict__ Fp = a.W + (int64_t)(d * 11 + f) * sf + p;
@@ -263,7 +272,7 @@ __device__ __forceinline__ double mhd_update_at(const MhdUpdArgs& a, int i, int 
       // interface i-1/2: F^+ on i-3..i+1 (m = 0..4), F^- mirrored on i+2..i-2 (m = 5..1)
       const double fl = 0.5 * (mp5(pL[0], pL[1], pL[2], pL[3], pL[4], alpha_mp5) +
                                mp5(mL[5], mL[4], mL[3], mL[2], mL[1], alpha_mp5));
-      out[f] -= (fr - fl) / hd;
+      out[f] -= div_rn(fr - fl, hd, ihd);
     }
   }
 
