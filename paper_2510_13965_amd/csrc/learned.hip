@@ -680,8 +680,11 @@ __device__ __forceinline__ void queue_append(bool take, T entry, uint32_t* count
 }
 
 // blocks stride over chunks of 256 padded points (the trip count is uniform
-// over the block: the network runs on whole wavefronts)
-__global__ void __launch_bounds__(256) k_c2p_learned(LearnedArgs a) {
+// over the block: the network runs on whole wavefronts).  Two waves per SIMD:
+// left alone, the matrix-core accumulators (AGPRs) come on top of ~230 VGPRs
+// and the kernel runs one wave per SIMD, which leaves the root-function
+// evaluations' latency unhidden
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_c2p_learned(LearnedArgs a) {
   __shared__ MlpLds s;
   mlp_stage(a.prm, s);
   __syncthreads();
@@ -702,7 +705,7 @@ __global__ void __launch_bounds__(256) k_c2p_learned(LearnedArgs a) {
 }
 
 // level version: queue entries are (box << 32) | linear padded point of the box
-__global__ void __launch_bounds__(256) k_c2p_learned_lv(LevelArgs L) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_c2p_learned_lv(LevelArgs L) {
   __shared__ MlpLds s;
   mlp_stage(L.mlp, s);
   __syncthreads();
