@@ -502,7 +502,7 @@ FLOP_PER_UNIT = {
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc (FETCH_SIZE x 2
 # + WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read and write 1 GiB),
 # valid only for the kernel sources they were taken on (sha256 of these files).
-TRAFFIC = {"k_mhd_update": (2794033517.0, "97a507f899b69ebd")}
+TRAFFIC = {"k_mhd_update": (2720399695.0, "d42fc845224e47b9")}
 TRAFFIC_SOURCES = {"k_mhd_update": ["paper_2510_13965_amd/csrc/grmhd.hip", "paper_2510_13965_amd/csrc/dev_common.hpp"]}
 
 
