@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-m1", action="store_true", help="skip the M1-radiation path")
     ap.add_argument("--level-boxes", type=int, default=192)
     ap.add_argument("--no-level-m1", action="store_true", help="skip the batched level with M1 radiation")
+    ap.add_argument("--no-level-imex", action="store_true", help="skip the batched level stepped by IMEX(4,4,2)")
     ap.add_argument("--level-m1-boxes", type=int, default=803)
     ap.add_argument("--no-c2p-cells", action="store_true", help="skip con2prim on random states")
     ap.add_argument("--c2p-log2", type=int, default=24, help="log2 of the number of random con2prim states")
@@ -390,6 +391,66 @@ def level_m1_path(torch, mhd, I, args, mlp):
     return res
 
 
+def level_imex_path(torch, mhd, I, args):
+    """The 192-box level of the star with three grey M1 species, opacities and
+    emissivities x100 (kappa dt up to ~8 at the centre, past the explicit RK4
+    stability limit), stepped by IMEX(4,4,2): per-box launches (one ImexRun per
+    box) against the batched level, eager and as a replayed hipGraph."""
+    from paper_2510_13965_amd.step import ImexRun, LevelRun
+
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    boxes = I.amr_level_boxes(nboxes=args.level_boxes)
+    Ab = I.star_field_amplitude()
+    eos = mhd.make_eos(I.EOS_IDEAL2)
+    ips, states, auxs = [], [], []
+    for b, box in enumerate(boxes):
+        ip, U, P, EM = I.amr_box_state(box, Ab)
+        R, aux = I.m1_radiation(ip, P, I.SEED0 + 700 + b)
+        Ud = torch.empty((I.NU_M1,) + tuple(ip.shape), dtype=torch.float64, device="cuda")
+        Ud[:I.NU].copy_(torch.as_tensor(U))
+        Ud[I.NU:].copy_(torch.as_tensor(R))
+        mhd.prim2con(mhd.patch_of(ip), eos, Ud, torch.as_tensor(P).cuda(), torch.as_tensor(EM).cuda(), 0)
+        ips.append(ip)
+        states.append(Ud)
+        auxs.append(torch.as_tensor(aux * 1e2).cuda())
+    lr = LevelRun(ips, states, I.EOS_IDEAL2, dict(I.PARAMS, evolve_m1=1), auxs=auxs, imex=True)
+    torch.cuda.synchronize()
+    say("level IMEX: %d boxes, %d interior points, built in %.1f s" % (len(ips), lr.ninterior, time.perf_counter() - t0))
+    dt = 0.25 * min(ip.dx[0] for ip in ips)
+    nzu = lr.ninterior * 4
+    res = {"workload": "%d boxes of the star (as the batched level) + 3 grey M1 species, opacities x100, "
+                       "IMEX(4,4,2); dt=%.4g" % (len(ips), dt), "interior_points": lr.ninterior}
+    runs = [ImexRun(ip, U.clone(), aux, I.EOS_IDEAL2, I.PARAMS) for ip, U, aux in zip(ips, states, auxs)]
+    del states, auxs
+    ms = time_steps(torch, lambda: [r.step(dt) for r in runs], 1, 1)
+    res["per_box"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+    say("level IMEX per-box: %.2f ms/step" % ms)
+    del runs
+    res["autotuned"] = lr.level.autotune(dt)
+    nf = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ms = time_steps(torch, lambda: lr.level.imex_step(dt, None, nf), args.level_steps, 1)
+    res["batched_eager"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+    stream = torch.cuda.Stream()
+    stream.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(stream):
+        ms = time_steps(torch, lambda: lr.level.imex_step(dt, None, nf, use_graph=True, stream=stream),
+                        args.level_steps, 1)
+    res["batched_graph"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
+    say("level IMEX batched graph (%s): %.2f ms/step" % (res["autotuned"], ms))
+    torch.cuda.synchronize()
+    mhd.profile_start()
+    lr.level.imex_step(dt, None, nf)
+    prof = mhd.profile_stop()
+    res["kernels"] = kernel_table(prof, _Units(lr.ninterior, lr.npts), 1, nfields=I.NU_M1)
+    res["implicit_solves_not_converged"] = int(nf.item())
+    res["finite"] = all(bool(torch.isfinite(b["U"]).all().item()) for b in lr.boxes)
+    lr.level.close()
+    del lr
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -461,6 +522,8 @@ def main():
         paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
     if not args.no_level:
         level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
+    if not args.no_level_imex:
+        paths["level_imex"] = level_imex_path(torch, mhd, I, args)
     if not args.no_level_m1:
         paths["level_m1"] = level_m1_path(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
     if "learned" in paths:

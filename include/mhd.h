@@ -312,6 +312,29 @@ int mhd_level_autotune(mhd_level_t* level, double dt, void* stream, mhd_tuning_t
 size_t mhd_level_learned_workspace_size(const mhd_level_t* level);
 int mhd_level_set_learned(mhd_level_t* level, const float* mlp, void* workspace, size_t workspace_bytes);
 
+/* IMEX(4,4,2) on a batched level (Table I; App. C), for a level that evolves M1.
+ * mhd_level_set_imex: per box (same order as at creation), the explicit parts
+ *   F[s] (MHD_NU_M1 fields) and stiff parts R[s] (12 fields) of the four
+ *   stages, device arrays in the box's patch layout, caller-owned, outliving
+ *   their use; boxes = NULL detaches them.  Waits for the device.
+ * mhd_level_imex_step: one step of size dt of every box, per box and stage the
+ *   sequence of the single-patch entry points (mhd_imex_combine into Us,
+ *   mhd_con2prim or the learned guess, mhd_m1_implicit with a_ii dt where
+ *   a_ii != 0, mhd_rhs_split into F[s] and R[s]), then the final combination
+ *   into U (advanced in place); results are bitwise those per-box calls.
+ *   Ghosts stay frozen.  max_speed (may be NULL) is zeroed and then receives the
+ *   maximum over the four evaluations; nfail (device uint64, may be NULL) is
+ *   incremented per collision solve that did not converge.  use_graph != 0:
+ *   captured once (again when dt, max_speed or nfail change) and replayed. */
+typedef struct {
+  double* F[4];
+  double* R[4];
+} mhd_imex_box_t;
+
+int mhd_level_set_imex(mhd_level_t* level, const mhd_imex_box_t* boxes, int nboxes);
+int mhd_level_imex_step(mhd_level_t* level, double dt, double* max_speed, uint64_t* nfail, int use_graph,
+                        void* stream);
+
 /* Workspace bytes mhd_rhs needs for this patch (point fluxes and speeds). */
 size_t mhd_rhs_workspace_size(const mhd_patch_t* patch);
 

@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(256) k_ccz4_stencil_lds_lv(LevelArgs L) {
   TileXYZ t;
   if (!level_lds_tile(L, b, t)) return;  // whole block
   const BoxDev& B = L.boxes[b];
-  stencil_lds_tile<kLvT, kLvT>(B.g, L.par, L.src ? B.Us : B.U, B.k, t.bx, t.by, t.bz, lds);
+  stencil_lds_tile<kLvT, kLvT>(B.g, L.par, L.src ? B.Us : B.U, level_rhs(B, L), t.bx, t.by, t.bz, lds);
 }
 
 // ------------------------------------------------------------------ second derivatives
@@ -859,7 +859,7 @@ __global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __r
 __global__ void __launch_bounds__(256) k_ccz4_curv_lv(LevelArgs L) {
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
     ccz4_curv_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
   });
 }
@@ -873,7 +873,7 @@ __global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __
 __global__ void __launch_bounds__(256) k_ccz4_gauge_lv(LevelArgs L) {
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, B.k, 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
     ccz4_gauge_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
   });
 }

@@ -126,6 +126,8 @@ struct BoxDev {
   uint8_t* flags;
   const double* aux;  // M1 opacities and emissivities (levels evolving radiation), else null
   double* ws_m1;      // M1 part of the RHS workspace, else null
+  double* F[4];       // IMEX: explicit parts of the four stages (44 fields), else null
+  double* R[4];       // IMEX: stiff parts of the four stages (12 fields), else null
   int cpp_int, cpp_pad;    // chunks per interior / padded z plane
   int64_t t0_int, t0_pad;  // first global tile id of the box in each space
   int ntx_lds, nty_lds, nzc_lds;  // LDS-staged kernels: (x, y) tiles and z chunks of the box
@@ -140,6 +142,9 @@ struct LevelArgs {
   int stage;
   int nfields;  // evolved fields: 32, or 44 with three M1 species
   int m1;       // nonzero: the boxes evolve the M1 radiation
+  int slot;     // right-hand side into k (-1) or, in an IMEX stage, into F[slot] with the stiff part in R[slot]
+  double adt;   // IMEX: implicit step a_ii dt of the collision solve
+  unsigned long long* nfail;  // IMEX: count of collision solves that did not converge (may be null)
   int64_t ntile_int, ntile_pad, ntile_lds;
   double dt;
   mhd_params_t par;
@@ -151,6 +156,15 @@ struct LevelArgs {
   uint32_t* qcount;
   uint64_t* queue;
 };
+
+// where the right-hand-side kernels of a level write: k, or an IMEX stage's
+// explicit part (and its stiff part, for the radiation)
+__device__ __forceinline__ double* level_rhs(const BoxDev& B, const LevelArgs& L) {
+  return L.slot < 0 ? B.k : B.F[L.slot];
+}
+__device__ __forceinline__ double* level_stiff(const BoxDev& B, const LevelArgs& L) {
+  return L.slot < 0 ? nullptr : B.R[L.slot];
+}
 
 __device__ __forceinline__ int find_box(const LevelArgs& L, int64_t id, bool padded) {
   int lo = 0, hi = L.nboxes - 1;

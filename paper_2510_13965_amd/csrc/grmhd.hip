@@ -424,7 +424,7 @@ __global__ void __launch_bounds__(256) k_mhd_point_lv(LevelArgs L) {
 __global__ void __launch_bounds__(256) k_mhd_update_lv(LevelArgs L) {
   double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    const MhdUpdArgs a{B.g, 0, 0, 0, 0, L.par, L.src ? B.Us : B.U, B.P, B.ws, B.k, L.max_speed};
+    const MhdUpdArgs a{B.g, 0, 0, 0, 0, L.par, L.src ? B.Us : B.U, B.P, B.ws, level_rhs(B, L), L.max_speed};
     vmax = fmax(vmax, mhd_update_at(a, i, j, k, live));
   });
   if (L.max_speed) block_max_to(L.max_speed, vmax);

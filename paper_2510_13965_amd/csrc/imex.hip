@@ -33,6 +33,24 @@ struct ImexArgs {
 };
 
 // block 64x4, grid z = nz * 44 (field-major)
+// one element of stage `s` of Table I's IMEX combination: field f (0..43) at
+// point pt; the stiff parts exist for the radiation fields (f >= 32) only
+__device__ __forceinline__ void imex_element(int s, double dt, const double* Un, const double* const* F,
+                                             const double* const* R, double* Uout, int f, int64_t pt, int64_t sf) {
+  const int64_t p = (int64_t)f * sf + pt;
+  double v = Un[p];
+  if (s < 4) {
+    for (int jj = 0; jj < s; ++jj) v += dt * kImAE[s][jj] * F[jj][p];
+    if (f >= 32)
+      for (int jj = 0; jj < s; ++jj) v += dt * kImAI[s][jj] * R[jj][(int64_t)(f - 32) * sf + pt];
+  } else {
+    for (int st = 0; st < 4; ++st) v += dt * kImB[st] * F[st][p];
+    if (f >= 32)
+      for (int st = 0; st < 4; ++st) v += dt * kImB[st] * R[st][(int64_t)(f - 32) * sf + pt];
+  }
+  Uout[p] = v;
+}
+
 __global__ void __launch_bounds__(256) k_imex_combine(ImexArgs a) {
   const Geom& g = a.g;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -40,23 +58,22 @@ __global__ void __launch_bounds__(256) k_imex_combine(ImexArgs a) {
   const int kz = blockIdx.z % g.nz;
   const int f = blockIdx.z / g.nz;
   if (i >= g.nx || j >= g.ny) return;
-  const int64_t pt = g.at(i + g.ng, j + g.ng, kz + g.ng);
-  const int64_t p = (int64_t)f * g.sf + pt;
-  const int s = a.stage;
-  double v = a.Un[p];
-  if (s < 4) {
-    for (int jj = 0; jj < s; ++jj) v += a.dt * kImAE[s][jj] * a.F[jj][p];
-    if (f >= 32)
-      for (int jj = 0; jj < s; ++jj) v += a.dt * kImAI[s][jj] * a.R[jj][(int64_t)(f - 32) * g.sf + pt];
-  } else {
-    for (int st = 0; st < 4; ++st) v += a.dt * kImB[st] * a.F[st][p];
-    if (f >= 32)
-      for (int st = 0; st < 4; ++st) v += a.dt * kImB[st] * a.R[st][(int64_t)(f - 32) * g.sf + pt];
-  }
-  a.Uout[p] = v;
+  imex_element(a.stage, a.dt, a.Un, a.F, a.R, a.Uout, f, g.at(i + g.ng, j + g.ng, kz + g.ng), g.sf);
 }
 
-// G(V) of one species at one point for the frozen Eddington factor chi
+// every field of every interior point of a level's boxes; stage 4 writes U
+__global__ void __launch_bounds__(256) k_imex_combine_lv(LevelArgs L) {
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    const int64_t pt = B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng);
+    double* out = L.stage < 4 ? B.Us : B.U;
+    const double* const* F = B.F;
+    const double* const* R = B.R;
+#pragma unroll 4
+    for (int f = 0; f < MHD_NU_M1; ++f) imex_element(L.stage, L.dt, B.U, F, R, out, f, pt, B.g.sf);
+  });
+}
+
 template <class T>
 __device__ __forceinline__ void implicit_G(const M1State& s0, const double gd[6], const double gu[6], double chi,
                                            const T V[4], const double Vs[4], double adt, double alp, double ka,
@@ -157,23 +174,21 @@ struct ImplArgs {
   unsigned long long* nfail;
 };
 
-__global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
-  const Geom& g = a.g;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
-  const int k = blockIdx.z;
-  if (i >= g.nx || j >= g.ny) return;
-  const int64_t sf = g.sf, q = g.at(i + g.ng, j + g.ng, k + g.ng);
+// the implicit collision solve of the three species at interior point q (padded
+// index); returns the number of species solves that did not converge
+__device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const double* __restrict__ P,
+                                                           const double* __restrict__ aux, int64_t sf, int64_t q,
+                                                           double adt) {
   MetricR m;
-  m1_metric(a.U, sf, q, m);
-  const double alp = a.U[18 * sf + q];
+  m1_metric(U, sf, q, m);
+  const double alp = U[18 * sf + q];
   unsigned long long bad = 0;
 #pragma unroll 1
   for (int sp = 0; sp < 3; ++sp) {
-    const double ka = a.aux[(int64_t)(3 * sp) * sf + q], ks = a.aux[(int64_t)(3 * sp + 1) * sf + q];
-    const double eta = a.aux[(int64_t)(3 * sp + 2) * sf + q];
+    const double ka = aux[(int64_t)(3 * sp) * sf + q], ks = aux[(int64_t)(3 * sp + 1) * sf + q];
+    const double eta = aux[(int64_t)(3 * sp + 2) * sf + q];
     M1State s0;
-    m1_load_state(a.U, a.P, sf, q, sp, m, s0);
+    m1_load_state(U, P, sf, q, sp, m, s0);
     const double chi = m1_closure_chi(s0, m.gd, m.gu);
     const double Vs[4] = {s0.E, s0.F[0], s0.F[1], s0.F[2]};
     double V[4] = {Vs[0], Vs[1], Vs[2], Vs[3]};
@@ -187,7 +202,7 @@ __global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
         Dual Vd[4], Gd[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) Vd[r] = Dual{V[r], r == c ? 1.0 : 0.0};
-        implicit_G<Dual>(s0, m.gd, m.gu, chi, Vd, Vs, a.adt, alp, ka, ks, eta, Gd);
+        implicit_G<Dual>(s0, m.gd, m.gu, chi, Vd, Vs, adt, alp, ka, ks, eta, Gd);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           Jm[r][c] = Gd[r].d;
@@ -207,11 +222,32 @@ __global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
       }
     }
     if (!ok) ++bad;
-    a.U[(int64_t)(32 + 4 * sp) * sf + q] = m.sqrtg * V[0];
+    U[(int64_t)(32 + 4 * sp) * sf + q] = m.sqrtg * V[0];
 #pragma unroll
-    for (int r = 0; r < 3; ++r) a.U[(int64_t)(33 + 4 * sp + r) * sf + q] = m.sqrtg * V[1 + r];
+    for (int r = 0; r < 3; ++r) U[(int64_t)(33 + 4 * sp + r) * sf + q] = m.sqrtg * V[1 + r];
   }
+  return bad;
+}
+
+__global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int k = blockIdx.z;
+  if (i >= g.nx || j >= g.ny) return;
+  const unsigned long long bad = m1_implicit_at(a.U, a.P, a.aux, g.sf, g.at(i + g.ng, j + g.ng, k + g.ng), a.adt);
   if (bad && a.nfail) atomicAdd(a.nfail, bad);
+}
+
+// the stage state Us of every box (non-converged solves are rare: one atomic
+// per thread that has any)
+__global__ void __launch_bounds__(256) k_m1_implicit_lv(LevelArgs L) {
+  unsigned long long bad = 0;
+  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+    if (!live) return;
+    bad += m1_implicit_at(B.Us, B.P, B.aux, B.g.sf, B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng), L.adt);
+  });
+  if (bad && L.nfail) atomicAdd(L.nfail, bad);
 }
 
 int launch_imex_combine(const Geom& g, int stage, double dt, const double* Un, const double* const* F,
@@ -228,6 +264,16 @@ int launch_imex_combine(const Geom& g, int stage, double dt, const double* Un, c
   a.Uout = Uout;
   dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * 44);
   MHD_LAUNCH(KID_IMEX_COMBINE, k_imex_combine, grd, dim3(64, 4, 1), 0, s, a);
+  return (int)hipGetLastError();
+}
+
+int launch_imex_combine_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_IMEX_COMBINE, k_imex_combine_lv, dim3(grid), dim3(block), 0, s, L);
+  return (int)hipGetLastError();
+}
+
+int launch_m1_implicit_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
+  MHD_LAUNCH(KID_M1_IMPLICIT, k_m1_implicit_lv, dim3(grid), dim3(block), 0, s, L);
   return (int)hipGetLastError();
 }
 

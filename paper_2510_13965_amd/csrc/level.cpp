@@ -21,6 +21,8 @@ int launch_zero_u64(unsigned long long* p, hipStream_t s);
 int launch_con2prim_learned_level(const LevelArgs& L, int grid, int block, int grid_fb, hipStream_t s);
 int launch_m1_point_level(const LevelArgs& L, int grid, int block, hipStream_t s);
 int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int launch_imex_combine_level(const LevelArgs& L, int grid, int block, hipStream_t s);
+int launch_m1_implicit_level(const LevelArgs& L, int grid, int block, hipStream_t s);
 int ccz4_workspace_fields();
 int abi_fail(int code, const char* msg);
 int abi_hip(int rc, const char* what);
@@ -37,11 +39,17 @@ struct mhd_level {
   mhd_tuning_t tun;
   int64_t ntile_int = 0, ntile_pad = 0, ntile_lds = 0;
   int ncu = 256;
-  // graph of one RK4 step, valid for (dt, max_speed)
+  // graphs of one RK4 step and of one IMEX step, each valid for the arguments
+  // it was captured with
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    double dt = 0.0;
+    const void* a = nullptr;
+    const void* b = nullptr;
+  };
   hipStream_t cap = nullptr;
-  hipGraphExec_t exec = nullptr;
-  double g_dt = 0.0;
-  double* g_ms = nullptr;
+  Graph g_rk, g_imex;
+  bool imex = false;  // per-box IMEX stage arrays attached
   // learned con2prim guess (nullptr: bracketed solver) and its fallback queue
   const float* mlp = nullptr;
   void* lws = nullptr;
@@ -54,6 +62,13 @@ using mhd::abi_fail;
 using mhd::abi_hip;
 
 int block_threads(const mhd_tuning_t& t) { return t.block_threads ? t.block_threads : 256; }
+
+void drop_graphs(mhd_level_t* lv) {
+  for (mhd_level::Graph* g : {&lv->g_rk, &lv->g_imex}) {
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    *g = mhd_level::Graph{};
+  }
+}
 
 // tile prefix sums for the current chunk size, uploaded to the device array
 int layout(mhd_level_t* lv) {
@@ -84,10 +99,7 @@ int layout(mhd_level_t* lv) {
   lv->ntile_int = ti;
   lv->ntile_pad = tp;
   lv->ntile_lds = tl;
-  if (lv->exec) {
-    (void)hipGraphExecDestroy(lv->exec);
-    lv->exec = nullptr;
-  }
+  drop_graphs(lv);
   return abi_hip((int)hipMemcpy(lv->dev, lv->host.data(), sizeof(mhd::BoxDev) * lv->host.size(), hipMemcpyHostToDevice),
                  "mhd_level: upload");
 }
@@ -108,6 +120,9 @@ mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, dou
   L.strip = lv->tun.strip;
   L.src = src;
   L.stage = stage;
+  L.slot = -1;
+  L.adt = 0.0;
+  L.nfail = nullptr;
   L.m1 = (lv->par.flags & MHD_EVOLVE_M1) ? 1 : 0;
   L.nfields = L.m1 ? MHD_NU_M1 : MHD_NU;
   L.ntile_int = lv->ntile_int;
@@ -124,18 +139,26 @@ mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, dou
   return L;
 }
 
-// con2prim + RHS of every box at U (src 0) or Us (src 1)
-int enqueue_rhs(const mhd_level_t* lv, int src, double* max_speed, int64_t* stats, hipStream_t s) {
-  const mhd::LevelArgs L = args_of(lv, src, 0, 0.0, max_speed, stats);
+// con2prim of every box at U (src 0) or Us (src 1)
+int enqueue_c2p(const mhd_level_t* lv, int src, int64_t* stats, hipStream_t s) {
+  const mhd::LevelArgs L = args_of(lv, src, 0, 0.0, nullptr, stats);
+  const int T = block_threads(lv->tun);
+  const int gp = grid_for(lv, lv->ntile_pad);
+  if (lv->mlp) {
+    const int64_t fb = (lv->npad + 255) / 256;
+    return mhd::launch_con2prim_learned_level(L, gp, T, (int)(fb < 2048 ? fb : 2048), s);
+  }
+  return mhd::launch_con2prim_level(L, gp, T, s);
+}
+
+// L(U) of every box at U (src 0) or Us (src 1), into k (slot -1) or into the
+// IMEX stage arrays F[slot], R[slot]
+int enqueue_rhs_only(const mhd_level_t* lv, int src, double* max_speed, int slot, hipStream_t s) {
+  mhd::LevelArgs L = args_of(lv, src, 0, 0.0, max_speed, nullptr);
+  L.slot = slot;
   const int T = block_threads(lv->tun);
   const int gi = grid_for(lv, lv->ntile_int), gp = grid_for(lv, lv->ntile_pad);
   int rc;
-  if (lv->mlp) {
-    const int64_t fb = (lv->npad + 255) / 256;
-    if ((rc = mhd::launch_con2prim_learned_level(L, gp, T, (int)(fb < 2048 ? fb : 2048), s))) return rc;
-  } else if ((rc = mhd::launch_con2prim_level(L, gp, T, s))) {
-    return rc;
-  }
   // the order of mhd_rhs: M1 closure and point fluxes (the CCZ4 matter terms read
   // the closure), CCZ4, GRMHD, then the M1 update (which adds the radiation's
   // exchange to the fluid's right-hand side)
@@ -143,6 +166,68 @@ int enqueue_rhs(const mhd_level_t* lv, int src, double* max_speed, int64_t* stat
   if ((rc = mhd::launch_ccz4_level(L, gi, T, (int)((lv->ntile_lds + 7) / 8 * 8), s))) return rc;
   if ((rc = mhd::launch_mhd_level(L, gp, gi, T, s))) return rc;
   return L.m1 ? mhd::launch_m1_update_level(L, gi, T, s) : 0;
+}
+
+// con2prim + RHS of every box at U (src 0) or Us (src 1)
+int enqueue_rhs(const mhd_level_t* lv, int src, double* max_speed, int64_t* stats, hipStream_t s) {
+  const int rc = enqueue_c2p(lv, src, stats, s);
+  return rc ? rc : enqueue_rhs_only(lv, src, max_speed, -1, s);
+}
+
+// implicit diagonal of Table I's I42L tableau
+constexpr double kImexAii[4] = {0.0, 0.25, 1.0 / 3.0, 1.0 / 6.0};
+
+// one IMEX(4,4,2) step (Table I): per stage, the combination into Us, con2prim,
+// the implicit collision solve (a_ii != 0), and the split RHS into F[s], R[s];
+// then the final combination into U
+int enqueue_imex_step(const mhd_level_t* lv, double dt, double* max_speed, uint64_t* nfail, hipStream_t s) {
+  int rc;
+  if (max_speed && (rc = mhd::launch_zero_u64(reinterpret_cast<unsigned long long*>(max_speed), s))) return rc;
+  const int T = block_threads(lv->tun);
+  const int gi = grid_for(lv, lv->ntile_int);
+  for (int st = 0; st <= 4; ++st) {
+    const mhd::LevelArgs C = args_of(lv, 1, st, dt, nullptr, nullptr);
+    if ((rc = mhd::launch_imex_combine_level(C, gi, T, s))) return rc;
+    if (st == 4) break;
+    if ((rc = enqueue_c2p(lv, 1, nullptr, s))) return rc;
+    if (kImexAii[st] != 0.0) {
+      mhd::LevelArgs I = args_of(lv, 1, st, dt, nullptr, nullptr);
+      I.adt = kImexAii[st] * dt;
+      I.nfail = reinterpret_cast<unsigned long long*>(nfail);
+      if ((rc = mhd::launch_m1_implicit_level(I, gi, T, s))) return rc;
+    }
+    if ((rc = enqueue_rhs_only(lv, 1, max_speed, st, s))) return rc;
+  }
+  return 0;
+}
+
+// replays `g` (captured again when its arguments changed) on `s`
+template <class Enqueue>
+int graph_launch(mhd_level_t* lv, mhd_level::Graph& g, double dt, const void* a, const void* b, hipStream_t s,
+                 Enqueue&& enqueue) {
+  if (!g.exec || g.dt != dt || g.a != a || g.b != b) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = mhd_level::Graph{};
+    hipGraph_t graph = nullptr;
+    int rc = abi_hip((int)hipStreamBeginCapture(lv->cap, hipStreamCaptureModeThreadLocal), "mhd_level: capture");
+    if (rc) return rc;
+    const int erc = enqueue(lv->cap);
+    const hipError_t e2 = hipStreamEndCapture(lv->cap, &graph);
+    if (erc || e2 != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return abi_hip(erc ? erc : (int)e2, "mhd_level: capture of the step");
+    }
+    const hipError_t e3 = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e3 != hipSuccess) {
+      g.exec = nullptr;
+      return abi_hip((int)e3, "mhd_level: graph instantiate");
+    }
+    g.dt = dt;
+    g.a = a;
+    g.b = b;
+  }
+  return abi_hip((int)hipGraphLaunch(g.exec, s), "mhd_level: graph launch");
 }
 
 int enqueue_stage(const mhd_level_t* lv, int stage, double dt, hipStream_t s) {
@@ -239,7 +324,7 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
 
 int mhd_level_destroy(mhd_level_t* lv) {
   if (!lv) return MHD_OK;
-  if (lv->exec) (void)hipGraphExecDestroy(lv->exec);
+  drop_graphs(lv);
   if (lv->cap) (void)hipStreamDestroy(lv->cap);
   if (lv->dev) (void)hipFree(lv->dev);
   delete lv;
@@ -276,10 +361,7 @@ int mhd_level_set_learned(mhd_level_t* lv, const float* mlp, void* workspace, si
   if (rc) return rc;
   lv->mlp = mlp;
   lv->lws = mlp ? workspace : nullptr;
-  if (lv->exec) {
-    (void)hipGraphExecDestroy(lv->exec);
-    lv->exec = nullptr;
-  }
+  drop_graphs(lv);
   return MHD_OK;
 }
 
@@ -294,30 +376,37 @@ int mhd_level_rk4_step(mhd_level_t* lv, double dt, double* max_speed, int use_gr
   if (!(dt == dt) || dt > 1e300 || dt < -1e300) return abi_fail(MHD_EINVAL, "mhd_level_rk4_step: dt must be finite");
   hipStream_t s = (hipStream_t)stream;
   if (!use_graph) return abi_hip(enqueue_step(lv, dt, max_speed, s), "mhd_level_rk4_step");
-  if (!lv->exec || lv->g_dt != dt || lv->g_ms != max_speed) {
-    if (lv->exec) {
-      (void)hipGraphExecDestroy(lv->exec);
-      lv->exec = nullptr;
+  return graph_launch(lv, lv->g_rk, dt, max_speed, nullptr, s,
+                      [&](hipStream_t cs) { return enqueue_step(lv, dt, max_speed, cs); });
+}
+
+int mhd_level_set_imex(mhd_level_t* lv, const mhd_imex_box_t* boxes, int nboxes) {
+  if (!lv) return abi_fail(MHD_EINVAL, "mhd_level_set_imex: NULL level");
+  if (!(lv->par.flags & MHD_EVOLVE_M1)) return abi_fail(MHD_EINVAL, "mhd_level_set_imex: the level must evolve M1");
+  if (boxes && nboxes != (int)lv->boxes.size())
+    return abi_fail(MHD_EINVAL, "mhd_level_set_imex: one entry per box of the level is needed");
+  if (boxes)
+    for (int b = 0; b < nboxes; ++b)
+      for (int st = 0; st < 4; ++st)
+        if (!boxes[b].F[st] || !boxes[b].R[st])
+          return abi_fail(MHD_EINVAL, "mhd_level_set_imex: every F[s] and R[s] must be non-NULL");
+  for (size_t b = 0; b < lv->host.size(); ++b)
+    for (int st = 0; st < 4; ++st) {
+      lv->host[b].F[st] = boxes ? boxes[b].F[st] : nullptr;
+      lv->host[b].R[st] = boxes ? boxes[b].R[st] : nullptr;
     }
-    hipGraph_t graph = nullptr;
-    int rc = abi_hip((int)hipStreamBeginCapture(lv->cap, hipStreamCaptureModeThreadLocal), "mhd_level: capture");
-    if (rc) return rc;
-    const int erc = enqueue_step(lv, dt, max_speed, lv->cap);
-    const hipError_t e2 = hipStreamEndCapture(lv->cap, &graph);
-    if (erc || e2 != hipSuccess || !graph) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return abi_hip(erc ? erc : (int)e2, "mhd_level: capture of the RK4 step");
-    }
-    const hipError_t e3 = hipGraphInstantiate(&lv->exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e3 != hipSuccess) {
-      lv->exec = nullptr;
-      return abi_hip((int)e3, "mhd_level: graph instantiate");
-    }
-    lv->g_dt = dt;
-    lv->g_ms = max_speed;
-  }
-  return abi_hip((int)hipGraphLaunch(lv->exec, s), "mhd_level: graph launch");
+  lv->imex = boxes != nullptr;
+  return layout(lv);  // waits for the device, uploads the descriptors, drops the graphs
+}
+
+int mhd_level_imex_step(mhd_level_t* lv, double dt, double* max_speed, uint64_t* nfail, int use_graph, void* stream) {
+  if (!lv) return abi_fail(MHD_EINVAL, "mhd_level_imex_step: NULL level");
+  if (!lv->imex) return abi_fail(MHD_EINVAL, "mhd_level_imex_step: no IMEX stage arrays (mhd_level_set_imex)");
+  if (!(dt == dt) || dt > 1e300 || dt < -1e300) return abi_fail(MHD_EINVAL, "mhd_level_imex_step: dt must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  if (!use_graph) return abi_hip(enqueue_imex_step(lv, dt, max_speed, nfail, s), "mhd_level_imex_step");
+  return graph_launch(lv, lv->g_imex, dt, max_speed, nfail, s,
+                      [&](hipStream_t cs) { return enqueue_imex_step(lv, dt, max_speed, nfail, cs); });
 }
 
 int mhd_level_autotune(mhd_level_t* lv, double dt, void* stream, mhd_tuning_t* chosen) {

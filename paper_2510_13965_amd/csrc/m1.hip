@@ -291,7 +291,7 @@ __global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update_lv(LevelArgs L) {
   double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, B.k, L.max_speed, nullptr};
+    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs(B, L), L.max_speed, level_stiff(B, L)};
     vmax = fmax(vmax, m1_update_at(a, i, j, k, live));
   });
   if (L.max_speed) block_max_to(L.max_speed, vmax);

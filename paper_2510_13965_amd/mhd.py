@@ -54,6 +54,10 @@ class Box(C.Structure):
                 ("flags", C.c_void_p), ("aux", C.c_void_p)]
 
 
+class ImexBox(C.Structure):
+    _fields_ = [("F", C.c_void_p * 4), ("R", C.c_void_p * 4)]
+
+
 class KernelTime(C.Structure):
     _fields_ = [("name", C.c_char * 40), ("launches", C.c_int64), ("total_ms", C.c_double)]
 
@@ -95,6 +99,8 @@ SIGNATURES = {
     "mhd_level_autotune": (C.c_int, [_vp, C.c_double, _vp, C.POINTER(Tuning)]),
     "mhd_level_learned_workspace_size": (C.c_size_t, [_vp]),
     "mhd_level_set_learned": (C.c_int, [_vp, _vp, _vp, C.c_size_t]),
+    "mhd_level_set_imex": (C.c_int, [_vp, C.POINTER(ImexBox), C.c_int]),
+    "mhd_level_imex_step": (C.c_int, [_vp, C.c_double, _vp, _vp, C.c_int, _vp]),
     "mhd_rhs_split": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, C.c_size_t, _vp]),
     "mhd_imex_combine": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_double, _vp, C.POINTER(C.c_void_p),
@@ -375,10 +381,49 @@ class Level:
         self._mlp = mlp
         _check(lib().mhd_level_set_learned(self.h, _ptr(mlp), _ptr(self._lws), self._lws.numel() * 8))
 
-    def autotune(self, dt, stream=None):
+    def set_imex(self, stages):
+        """IMEX stage arrays per box: stages[b] = (F, R), four device tensors each
+        (F: 44 fields, R: 12 fields, the box's shape); None detaches them."""
+        if stages is None:
+            _check(lib().mhd_level_set_imex(self.h, None, 0))
+            self._imex = None
+            return
+        arr = (ImexBox * len(stages))()
+        for b, (F, R) in enumerate(stages):
+            for st in range(4):
+                arr[b].F[st] = _ptr(F[st])
+                arr[b].R[st] = _ptr(R[st])
+        self._imex = stages
+        _check(lib().mhd_level_set_imex(self.h, arr, len(stages)))
+
+    def imex_step(self, dt, max_speed=None, nfail=None, use_graph=False, stream=None):
+        _check(lib().mhd_level_imex_step(self.h, float(dt), _ptr(max_speed), _ptr(nfail), int(bool(use_graph)),
+                                         _stream(stream)))
+
+    def autotune(self, dt, stream=None, cache=None):
+        """Time the candidate launch shapes and keep the fastest (mhd_level_autotune).
+        cache: path of an on-disk tuning cache (tuning.TuningCache); a level with
+        the same device, library version, radiation switch and box shapes reuses
+        the stored choice without timing anything."""
+        key = None
+        if cache is not None:
+            import torch
+
+            from .tuning import TuningCache, cache_key
+
+            dims = [(b["patch"].nx, b["patch"].ny, b["patch"].nz) for b in self._keep]
+            key = cache_key(dims, self._params.flags & EVOLVE_M1, torch.cuda.get_device_name(),
+                            lib().mhd_abi_version())
+            hit = TuningCache(cache).get(key)
+            if hit is not None:
+                self.set_tuning(**hit)
+                return self.get_tuning()
         t = Tuning()
         _check(lib().mhd_level_autotune(self.h, float(dt), _stream(stream), C.byref(t)))
-        return _tuning_dict(t)
+        chosen = _tuning_dict(t)
+        if key is not None:
+            TuningCache(cache).put(key, chosen)
+        return chosen
 
 
 def profile_start():

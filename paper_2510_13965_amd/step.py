@@ -70,7 +70,7 @@ class LevelRun:
     """Device buffers of a list of boxes and their batched level (mhd_level_*).
     Us starts as a copy of U so the stage states carry the (frozen) ghosts."""
 
-    def __init__(self, ipatches, states, eos_cfg, par_cfg, device="cuda", flags=True, auxs=None):
+    def __init__(self, ipatches, states, eos_cfg, par_cfg, device="cuda", flags=True, auxs=None, imex=False):
         self.eos = mhd.make_eos(eos_cfg)
         self.par = mhd.make_params(par_cfg)
         self.m1 = bool(par_cfg.get("evolve_m1", 0))
@@ -86,8 +86,14 @@ class LevelRun:
                 d["flags"] = torch.zeros(tuple(ip.shape), dtype=torch.uint8, device=device)
             if auxs is not None and auxs[b] is not None:
                 d["aux"] = torch.as_tensor(auxs[b], dtype=torch.float64).to(device).contiguous()
+            if imex:
+                shp = tuple(ip.shape)
+                d["F"] = [torch.zeros_like(U) for _ in range(4)]
+                d["R"] = [torch.zeros((12,) + shp, dtype=torch.float64, device=device) for _ in range(4)]
             self.boxes.append(d)
         self.level = mhd.Level(self.boxes, self.par, self.eos)
+        if imex:
+            self.level.set_imex([(b["F"], b["R"]) for b in self.boxes])
 
     @property
     def ninterior(self):

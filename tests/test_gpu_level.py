@@ -160,6 +160,30 @@ def test_level_autotune_keeps_results(level_states):
     assert_same(ref, got, "after autotune")
 
 
+def test_level_autotune_cache(level_states, tmp_path):
+    """A second level of the same box shapes takes the cached choice without
+    timing anything, and its results are unchanged."""
+    import time
+
+    import torch
+    from paper_2510_13965_amd.step import LevelRun
+
+    say("case level autotune cache")
+    cache = tmp_path / "tuning.json"
+    ips, Us = [ip for ip, _ in level_states], [U for _, U in level_states]
+    t1 = LevelRun(ips, Us, I.EOS_IDEAL2, I.PARAMS).level.autotune(0.0625, cache=cache)
+    assert cache.exists()
+    run = LevelRun(ips, Us, I.EOS_IDEAL2, I.PARAMS)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    t2 = run.level.autotune(0.0625, cache=cache)
+    assert time.perf_counter() - w0 < 0.5
+    assert t2 == t1 == run.level.get_tuning()
+    ref, vref = per_box_rhs(level_states)
+    got, v = level_rhs(run)
+    assert_same(ref, got, "cached tuning")
+
+
 def test_level_box_against_oracle(orc, level_states):
     """The level's RHS on its smallest box against the FP64 oracle (1e-10 per field)."""
     from paper_2510_13965_amd.step import LevelRun
@@ -331,3 +355,56 @@ def test_level_m1_rejects_missing_aux(level_m1_states):
     ip, U, aux = level_m1_states[0]
     with pytest.raises(mhd.MhdError, match="aux is required"):
         m1_level_run([(ip, U, None)])
+
+
+def test_level_imex_bitwise_equals_per_box(level_m1_states):
+    """IMEX(4,4,2) steps of the batched level (opacities and emissivities x100,
+    kappa dt up to ~8: past the explicit stability limit), eager and as a
+    replayed graph, against per-box ImexRun steps: bitwise."""
+    import torch
+    from paper_2510_13965_amd.step import ImexRun
+
+    say("case level IMEX vs per-box IMEX, 6 boxes, 3 steps")
+    dt = 0.25 * 0.25
+    states = [(ip, U, aux * 1e2) for ip, U, aux in level_m1_states]
+    boxes = [ImexRun(ip, U, aux, I.EOS_IDEAL2, I.PARAMS) for ip, U, aux in states]
+    eager = m1_level_run(states, imex=True)
+    graph = m1_level_run(states, imex=True)
+    ms_e = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ms_g = torch.zeros(1, dtype=torch.float64, device="cuda")
+    nf_e = torch.zeros(1, dtype=torch.int64, device="cuda")
+    nf_g = torch.zeros(1, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.Stream()
+    for step in range(3):
+        for r in boxes:
+            r.step(dt)
+        eager.level.imex_step(dt, ms_e, nf_e)
+        stream.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(stream):
+            graph.level.imex_step(dt, ms_g, nf_g, use_graph=True, stream=stream)
+        stream.synchronize()
+        torch.cuda.synchronize()
+        for b, r in enumerate(boxes):
+            ref = r.Un.cpu().numpy()
+            assert np.isfinite(ref).all()
+            assert np.array_equal(ref, eager.boxes[b]["U"].cpu().numpy()), ("eager", step, b)
+            assert np.array_equal(ref, graph.boxes[b]["U"].cpu().numpy()), ("graph", step, b)
+        if step == 0:
+            assert float(ms_e.item()) == max(float(r.vmax.item()) for r in boxes) > 0.0
+        assert float(ms_e.item()) == float(ms_g.item())
+        nf_ref = sum(int(r.nfail.item()) for r in boxes)
+        assert int(nf_e.item()) == int(nf_g.item()) == nf_ref
+        say("step", step, "ok, max speed", float(ms_e.item()), "unconverged solves", nf_ref)
+
+
+def test_level_imex_needs_m1_and_stage_arrays(level_states, level_m1_states):
+    from paper_2510_13965_amd import mhd
+    from paper_2510_13965_amd.step import LevelRun
+
+    say("case level IMEX argument checks")
+    run = LevelRun([s[0] for s in level_states[:1]], [s[1] for s in level_states[:1]], I.EOS_IDEAL2, I.PARAMS)
+    with pytest.raises(mhd.MhdError, match="must evolve M1"):
+        run.level.set_imex([([None] * 4, [None] * 4)])
+    m1 = m1_level_run(level_m1_states[:1])
+    with pytest.raises(mhd.MhdError, match="no IMEX stage arrays"):
+        m1.level.imex_step(0.0625)
