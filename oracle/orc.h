@@ -179,6 +179,17 @@ void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt
 /* ---- ghost fill ---- */
 void orc_fill_periodic(const orc_grid* g, double* U, int nfields);
 
+/* ---- mesh-refinement glue (amr.c): 2:1 vertex-centred prolongation by the
+ * six-point Lagrange interpolation, restriction by copy, RK4 dense output ---- */
+void orc_lagrange_half(double w[6]);
+int orc_prolong(const orc_grid* gc, const double* Uc, const orc_grid* gf, double* Uf, int nfields,
+                const int off[3], const int lo[3], const int hi[3]);
+int orc_restrict(const orc_grid* gf, const double* Uf, const orc_grid* gc, double* Uc, int nfields,
+                 const int off[3], const int lo[3], const int hi[3]);
+void orc_dense_weights(double theta, int m, double b[4]);
+void orc_dense_output(const orc_grid* g, int nfields, double theta, double dt, int m, const double* Un,
+                      const double* L0, const double* L1, const double* L2, const double* L3, double* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -89,6 +89,16 @@ def _bind(L):
     L.orc_rk4_stage_interior.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, C.c_double,
                                          _dp, _dp, _dp, _dp]
     L.orc_fill_periodic.argtypes = [C.POINTER(Grid), _dp, C.c_int]
+    if hasattr(L, "orc_prolong"):
+        _i3 = C.POINTER(C.c_int)
+        L.orc_lagrange_half.argtypes = [_dp]
+        L.orc_prolong.argtypes = [C.POINTER(Grid), _dp, C.POINTER(Grid), _dp, C.c_int, _i3, _i3, _i3]
+        L.orc_prolong.restype = C.c_int
+        L.orc_restrict.argtypes = [C.POINTER(Grid), _dp, C.POINTER(Grid), _dp, C.c_int, _i3, _i3, _i3]
+        L.orc_restrict.restype = C.c_int
+        L.orc_dense_weights.argtypes = [C.c_double, C.c_int, _dp]
+        L.orc_dense_output.argtypes = [C.POINTER(Grid), C.c_int, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp,
+                                       _dp, _dp, _dp]
     if hasattr(L, "orc_m1_rhs"):
         L.orc_m1_eddington.argtypes = [C.c_double]
         L.orc_m1_eddington.restype = C.c_double
@@ -194,6 +204,39 @@ def rk4_stage(stage, dt, Un, k, acc, Unext):
 
 def fill_periodic(g, U, nfields):
     lib().orc_fill_periodic(C.byref(g), ptr(U), nfields)
+
+
+def _int3(v):
+    return (C.c_int * 3)(*[int(x) for x in v])
+
+
+def lagrange_half():
+    w = np.zeros(6)
+    lib().orc_lagrange_half(ptr(w))
+    return w
+
+
+def prolong(gc, Uc, gf, Uf, nfields, off, lo, hi):
+    """Fine padded box [lo, hi) of Uf from Uc (fine index = 2 coarse index + off); 0 or -1."""
+    return lib().orc_prolong(C.byref(gc), ptr(Uc), C.byref(gf), ptr(Uf), int(nfields), _int3(off), _int3(lo),
+                             _int3(hi))
+
+
+def restrict(gf, Uf, gc, Uc, nfields, off, lo, hi):
+    """Coarse padded box [lo, hi) of Uc copied from Uf; 0 or -1."""
+    return lib().orc_restrict(C.byref(gf), ptr(Uf), C.byref(gc), ptr(Uc), int(nfields), _int3(off), _int3(lo),
+                              _int3(hi))
+
+
+def dense_weights(theta, m):
+    b = np.zeros(4)
+    lib().orc_dense_weights(float(theta), int(m), ptr(b))
+    return b
+
+
+def dense_output(g, nfields, theta, dt, m, Un, L, out):
+    lib().orc_dense_output(C.byref(g), int(nfields), float(theta), float(dt), int(m), ptr(Un), ptr(L[0]), ptr(L[1]),
+                           ptr(L[2]), ptr(L[3]), ptr(out))
 
 
 def c2p_point(e, cons, B, gdn, gup, alpha):
