@@ -393,6 +393,35 @@ int mhd_rk_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, co
 /* Periodic ghost fill of `nfields` fields (edges and corners included). */
 int mhd_fill_ghosts_periodic(const mhd_patch_t* patch, double* U, int nfields, void* stream);
 
+/* ---- mesh-refinement glue (Sec. 4.2; Sec. 3.1 dense output) ----------------
+ * Two patches of a 2:1 vertex-centred hierarchy: the coarse spacing is twice
+ * the fine one on every axis, and fine padded index I coincides with coarse
+ * padded index i when I = 2 i + offset (per axis; offset is a host int32[3],
+ * any sign).  Boxes are host int32[3] half-open ranges [lo, hi) of padded
+ * indices.  The arrays hold nfields fields in their patch's layout and must not
+ * alias.
+ * mhd_prolong: every fine point of the box takes the symmetric six-point
+ *   Lagrange interpolation of the coarse data (coincident points are copies,
+ *   half points (3, -25, 150, 150, -25, 3)/256 over the six nearest coarse
+ *   nodes), as a tensor product applied along x, then y, then z; polynomials
+ *   of degree <= 5 in each variable are reproduced.  Rejected (MHD_EINVAL)
+ *   when a needed coarse node lies outside the padded coarse patch.
+ * mhd_restrict: restriction by direct copy: every coarse point of the box
+ *   takes the coincident fine value, Uc(i) = Uf(2 i + offset).
+ * mhd_dense_output: at the interior points, from the right-hand sides L[j]
+ *   (host array of 4 device pointers) of the four stages of an RK4 step of
+ *   size dt that started from Un, with k_j = dt L_j: deriv = 0 gives
+ *   U(t^n + theta dt) = Un + sum_j b_j(theta) k_j, deriv = 1..3 the deriv-th
+ *   time derivative (1/dt^deriv) sum_j b_j^(deriv)(theta) k_j (Un unused, may
+ *   be NULL), for the third-order interpolant b_1 = t - 3/2 t^2 + 2/3 t^3,
+ *   b_2 = b_3 = t^2 - 2/3 t^3, b_4 = -1/2 t^2 + 2/3 t^3.  out may alias Un. */
+int mhd_prolong(const mhd_patch_t* coarse, const double* Uc, const mhd_patch_t* fine, double* Uf, int nfields,
+                const int32_t* offset, const int32_t* lo, const int32_t* hi, void* stream);
+int mhd_restrict(const mhd_patch_t* fine, const double* Uf, const mhd_patch_t* coarse, double* Uc, int nfields,
+                 const int32_t* offset, const int32_t* lo, const int32_t* hi, void* stream);
+int mhd_dense_output(const mhd_patch_t* patch, int nfields, double theta, double dt, int deriv, const double* Un,
+                     const double* const* L, double* out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -3,6 +3,7 @@
 // caller's.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -38,6 +39,12 @@ int launch_mlp_features(const Geom& g, const mhd_eos_t& eos, const double* U, co
 int launch_mlp_normalize(float* prm, const float* X, int64_t n, hipStream_t s);
 int launch_mlp_forward(const float* prm, const float* X, int64_t n, float* Y, hipStream_t s);
 int mlp_grad_blocks(int64_t n);
+int launch_prolong(const Geom& gc, const double* Uc, const Geom& gf, double* Uf, int nfields, const int off[3],
+                   const int lo[3], const int n[3], hipStream_t s);
+int launch_restrict(const Geom& gf, const double* Uf, const Geom& gc, double* Uc, int nfields, const int off[3],
+                    const int lo[3], const int n[3], hipStream_t s);
+int launch_dense_output(const Geom& g, int nfields, double dt, const double b[4], int add_un, double dtm,
+                        const double* Un, const double* const* L, double* out, hipStream_t s);
 int launch_mlp_grad(const float* prm, const float* X, const float* T, int64_t n, float* grad, float* loss, void* ws,
                     hipStream_t s);
 int launch_mlp_adam(float* prm, const float* grad, float* m, float* v, int step, float lr, float b1, float b2,
@@ -371,6 +378,127 @@ int mhd_rk_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, co
   if (!std::isfinite(dt)) return fail(MHD_EINVAL, "mhd_rk_stage: dt must be finite");
   return hip_check(mhd::launch_rk4_stage(geom_of(patch), nfields, stage, dt, Un, k, acc, Unext, (hipStream_t)stream),
                    "mhd_rk_stage");
+}
+
+// padded extent of a patch along axis a
+static int64_t padded(const mhd_patch_t* p, int a) {
+  const int n = a == 0 ? p->nx : (a == 1 ? p->ny : p->nz);
+  return (int64_t)n + 2 * p->ng;
+}
+
+static double spacing(const mhd_patch_t* p, int a) { return a == 0 ? p->dx : (a == 1 ? p->dy : p->dz); }
+
+// floor(t / 2) for any sign
+static int64_t floor_half(int64_t t) { return t >= 0 ? t / 2 : -((-t + 1) / 2); }
+
+int mhd_prolong(const mhd_patch_t* coarse, const double* Uc, const mhd_patch_t* fine, double* Uf, int nfields,
+                const int32_t* offset, const int32_t* lo, const int32_t* hi, void* stream) {
+  int rc;
+  const char* fn = "mhd_prolong";
+  if ((rc = check_patch(coarse, -1, 1, fn)) || (rc = check_patch(fine, -1, 1, fn))) return rc;
+  if (nfields < 1 || !Uc || !Uf || !offset || !lo || !hi)
+    return fail(MHD_EINVAL, "%s: need nfields >= 1 and non-NULL arrays", fn);
+  if (Uc == Uf) return fail(MHD_EINVAL, "%s: coarse and fine arrays must differ", fn);
+  int o3[3], l3[3], n3[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(spacing(coarse, a) == 2.0 * spacing(fine, a)))
+      return fail(MHD_EINVAL, "%s: the coarse spacing must be twice the fine one on every axis", fn);
+    if (lo[a] < 0 || hi[a] <= lo[a] || hi[a] > padded(fine, a))
+      return fail(MHD_EINVAL, "%s: fine box [%d, %d) out of the padded fine patch on axis %d", fn, lo[a], hi[a], a);
+    // coarse nodes needed over the box: copies at even t = I - off, six points around odd t
+    const int64_t t0 = (int64_t)lo[a] - offset[a], t1 = (int64_t)hi[a] - 1 - offset[a];
+    int64_t need_lo = INT64_MAX, need_hi = INT64_MIN;
+    for (int64_t t : {t0, t0 + 1, t1 - 1, t1}) {
+      if (t < t0 || t > t1) continue;
+      const int64_t first = (t % 2 == 0) ? floor_half(t) : floor_half(t - 1) - 2;
+      const int64_t last = (t % 2 == 0) ? floor_half(t) : floor_half(t - 1) + 3;
+      need_lo = first < need_lo ? first : need_lo;
+      need_hi = last > need_hi ? last : need_hi;
+    }
+    if (need_lo < 0 || need_hi >= padded(coarse, a))
+      return fail(MHD_EINVAL, "%s: the box needs coarse nodes %lld..%lld on axis %d, outside the padded coarse patch",
+                  fn, (long long)need_lo, (long long)need_hi, a);
+    o3[a] = offset[a];
+    l3[a] = lo[a];
+    n3[a] = hi[a] - lo[a];
+  }
+  if ((n3[1] + 3) / 4 > kMaxGridYZ || n3[2] > kMaxGridYZ) return fail(MHD_EINVAL, "%s: box too large for one launch", fn);
+  return hip_check(mhd::launch_prolong(geom_of(coarse), Uc, geom_of(fine), Uf, nfields, o3, l3, n3, (hipStream_t)stream),
+                   fn);
+}
+
+int mhd_restrict(const mhd_patch_t* fine, const double* Uf, const mhd_patch_t* coarse, double* Uc, int nfields,
+                 const int32_t* offset, const int32_t* lo, const int32_t* hi, void* stream) {
+  int rc;
+  const char* fn = "mhd_restrict";
+  if ((rc = check_patch(coarse, -1, 1, fn)) || (rc = check_patch(fine, -1, 1, fn))) return rc;
+  if (nfields < 1 || !Uc || !Uf || !offset || !lo || !hi)
+    return fail(MHD_EINVAL, "%s: need nfields >= 1 and non-NULL arrays", fn);
+  if (Uc == Uf) return fail(MHD_EINVAL, "%s: coarse and fine arrays must differ", fn);
+  int o3[3], l3[3], n3[3];
+  for (int a = 0; a < 3; ++a) {
+    if (!(spacing(coarse, a) == 2.0 * spacing(fine, a)))
+      return fail(MHD_EINVAL, "%s: the coarse spacing must be twice the fine one on every axis", fn);
+    if (lo[a] < 0 || hi[a] <= lo[a] || hi[a] > padded(coarse, a))
+      return fail(MHD_EINVAL, "%s: coarse box [%d, %d) out of the padded coarse patch on axis %d", fn, lo[a], hi[a], a);
+    const int64_t f0 = 2 * (int64_t)lo[a] + offset[a], f1 = 2 * ((int64_t)hi[a] - 1) + offset[a];
+    if (f0 < 0 || f1 >= padded(fine, a))
+      return fail(MHD_EINVAL, "%s: the box maps to fine points %lld..%lld on axis %d, outside the padded fine patch",
+                  fn, (long long)f0, (long long)f1, a);
+    o3[a] = offset[a];
+    l3[a] = lo[a];
+    n3[a] = hi[a] - lo[a];
+  }
+  if ((n3[1] + 3) / 4 > kMaxGridYZ || n3[2] > kMaxGridYZ) return fail(MHD_EINVAL, "%s: box too large for one launch", fn);
+  return hip_check(mhd::launch_restrict(geom_of(fine), Uf, geom_of(coarse), Uc, nfields, o3, l3, n3, (hipStream_t)stream),
+                   fn);
+}
+
+int mhd_dense_output(const mhd_patch_t* patch, int nfields, double theta, double dt, int deriv, const double* Un,
+                     const double* const* L, double* out, void* stream) {
+  int rc;
+  const char* fn = "mhd_dense_output";
+  if ((rc = check_patch(patch, -1, nfields > 0 ? nfields : 1, fn))) return rc;
+  if (nfields < 1 || !L || !out) return fail(MHD_EINVAL, "%s: need nfields >= 1, L and out", fn);
+  if (deriv < 0 || deriv > 3) return fail(MHD_EINVAL, "%s: deriv must be 0..3", fn);
+  if (deriv == 0 && !Un) return fail(MHD_EINVAL, "%s: Un is required for the value (deriv 0)", fn);
+  if (!std::isfinite(theta) || !std::isfinite(dt) || (deriv > 0 && dt == 0.0))
+    return fail(MHD_EINVAL, "%s: theta and dt must be finite (dt != 0 for derivatives)", fn);
+  const double* l4[4];
+  for (int j = 0; j < 4; ++j) {
+    if (!L[j] || L[j] == out) return fail(MHD_EINVAL, "%s: stage array %d missing or aliasing out", fn, j);
+    l4[j] = L[j];
+  }
+  // b_j(theta) of RK4's third-order dense output and their theta-derivatives
+  // (Sec. 3.1): b1 = t - 3/2 t^2 + 2/3 t^3, b2 = b3 = t^2 - 2/3 t^3,
+  // b4 = -1/2 t^2 + 2/3 t^3
+  const double t = theta, t2 = t * t, t3 = t2 * t;
+  double b[4];
+  switch (deriv) {
+    case 0:
+      b[0] = t - 1.5 * t2 + 2.0 / 3.0 * t3;
+      b[1] = b[2] = t2 - 2.0 / 3.0 * t3;
+      b[3] = -0.5 * t2 + 2.0 / 3.0 * t3;
+      break;
+    case 1:
+      b[0] = 1.0 - 3.0 * t + 2.0 * t2;
+      b[1] = b[2] = 2.0 * t - 2.0 * t2;
+      b[3] = -t + 2.0 * t2;
+      break;
+    case 2:
+      b[0] = -3.0 + 4.0 * t;
+      b[1] = b[2] = 2.0 - 4.0 * t;
+      b[3] = -1.0 + 4.0 * t;
+      break;
+    default:
+      b[0] = 4.0;
+      b[1] = b[2] = -4.0;
+      b[3] = 4.0;
+  }
+  const double dtm = deriv == 0 ? 1.0 : std::pow(dt, (double)deriv);
+  return hip_check(mhd::launch_dense_output(geom_of(patch), nfields, dt, b, deriv == 0 ? 1 : 0, dtm, Un, l4, out,
+                                            (hipStream_t)stream),
+                   fn);
 }
 
 int mhd_fill_ghosts_periodic(const mhd_patch_t* patch, double* U, int nfields, void* stream) {

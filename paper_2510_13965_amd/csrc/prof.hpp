@@ -34,6 +34,9 @@ enum KernelId : int {
   KID_M1_UPDATE,
   KID_IMEX_COMBINE,
   KID_M1_IMPLICIT,
+  KID_PROLONG,
+  KID_RESTRICT,
+  KID_DENSE,
   KID_COUNT
 };
 

@@ -100,6 +100,10 @@ SIGNATURES = {
     "mhd_level_learned_workspace_size": (C.c_size_t, [_vp]),
     "mhd_level_set_learned": (C.c_int, [_vp, _vp, _vp, C.c_size_t]),
     "mhd_level_set_imex": (C.c_int, [_vp, C.POINTER(ImexBox), C.c_int]),
+    "mhd_prolong": (C.c_int, [C.POINTER(Patch), _vp, C.POINTER(Patch), _vp, C.c_int, _vp, _vp, _vp, _vp]),
+    "mhd_restrict": (C.c_int, [C.POINTER(Patch), _vp, C.POINTER(Patch), _vp, C.c_int, _vp, _vp, _vp, _vp]),
+    "mhd_dense_output": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_double, C.c_double, C.c_int, _vp,
+                                   C.POINTER(C.c_void_p), _vp, _vp]),
     "mhd_level_imex_step": (C.c_int, [_vp, C.c_double, _vp, _vp, C.c_int, _vp]),
     "mhd_rhs_split": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, C.c_size_t, _vp]),
@@ -424,6 +428,31 @@ class Level:
         if key is not None:
             TuningCache(cache).put(key, chosen)
         return chosen
+
+
+def _i3(v):
+    return (C.c_int32 * 3)(*[int(x) for x in v])
+
+
+def prolong(coarse, Uc, fine, Uf, nfields, offset, lo, hi, stream=None):
+    """Fine padded box [lo, hi) of Uf from Uc (mhd_prolong); offset: fine index of coarse index 0."""
+    o, l, h = _i3(offset), _i3(lo), _i3(hi)
+    _check(lib().mhd_prolong(C.byref(coarse), _ptr(Uc), C.byref(fine), _ptr(Uf), int(nfields), C.cast(o, _vp),
+                             C.cast(l, _vp), C.cast(h, _vp), _stream(stream)))
+
+
+def restrict(fine, Uf, coarse, Uc, nfields, offset, lo, hi, stream=None):
+    """Coarse padded box [lo, hi) of Uc copied from the coincident fine points (mhd_restrict)."""
+    o, l, h = _i3(offset), _i3(lo), _i3(hi)
+    _check(lib().mhd_restrict(C.byref(fine), _ptr(Uf), C.byref(coarse), _ptr(Uc), int(nfields), C.cast(o, _vp),
+                              C.cast(l, _vp), C.cast(h, _vp), _stream(stream)))
+
+
+def dense_output(patch, nfields, theta, dt, deriv, Un, L, out, stream=None):
+    """RK4 dense output (deriv 0) or its deriv-th time derivative from the four stage RHS arrays L."""
+    arr = (C.c_void_p * 4)(*[_ptr(x) for x in L])
+    _check(lib().mhd_dense_output(C.byref(patch), int(nfields), float(theta), float(dt), int(deriv), _ptr(Un), arr,
+                                  _ptr(out), _stream(stream)))
 
 
 def profile_start():
