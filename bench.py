@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--level-boxes", type=int, default=192)
     ap.add_argument("--no-level-m1", action="store_true", help="skip the batched level with M1 radiation")
     ap.add_argument("--no-level-imex", action="store_true", help="skip the batched level stepped by IMEX(4,4,2)")
+    ap.add_argument("--no-glue", action="store_true", help="skip the prolongation/restriction/dense-output timings")
     ap.add_argument("--level-m1-boxes", type=int, default=803)
     ap.add_argument("--no-c2p-cells", action="store_true", help="skip con2prim on random states")
     ap.add_argument("--c2p-log2", type=int, default=24, help="log2 of the number of random con2prim states")
@@ -451,6 +452,53 @@ def level_imex_path(torch, mhd, I, args):
     return res
 
 
+def glue_path(torch, mhd, I, args):
+    """Mesh-refinement glue on star-sized data (32 fields): a fine 128^3 patch
+    (dx 0.25, 3 ghosts) filled entirely by prolongation from its 2:1 parent
+    (70^3 interior, dx 0.5), the restriction of the fine data back onto the 65^3
+    coincident parent points, and the RK4 dense output (and its first
+    derivative) on the fine patch.  Per-call times and HBM rates of the
+    algorithmic bytes (every input value read once, every output written once)."""
+    import numpy as np
+
+    nf = I.NU
+    ipf = I.Patch((128, 128, 128), (0.25,) * 3, (-16.0,) * 3, 3)
+    ipc = I.Patch((70, 70, 70), (0.5,) * 3, (-17.5,) * 3, 3)
+    Uc, _, _, _ = I.star_fields(ipc)
+    pc, pf = mhd.patch_of(ipc), mhd.patch_of(ipf)
+    # coarse padded index 0 at x = -19, fine padded index 0 at x = -16.75: the
+    # coarse point i coincides with the fine point 2 i - 9
+    off = (-9, -9, -9)
+    Ucd = torch.as_tensor(Uc).cuda()
+    Uf = torch.zeros((nf,) + ipf.shape, dtype=torch.float64, device="cuda")
+    nfine = ipf.npts
+    lo, hi = (0, 0, 0), tuple(n + 6 for n in ipf.n)
+    ms = time_steps(torch, lambda: mhd.prolong(pc, Ucd, pf, Uf, nf, off, lo, hi), 10, 2)
+    # reads: the coarse points under the fine patch; writes: every fine point
+    ncoarse_read = ((134 + 1) // 2 + 5) ** 3
+    b = 8.0 * nf * (nfine + ncoarse_read)
+    res = {"workload": "128^3 fine patch (+3 ghosts) of the star from its 2:1 parent, 32 fields",
+           "prolong": {"ms": round(ms, 4), "gbs": round(b / (ms * 1e-3) / 1e9, 1), "algorithmic_bytes": b}}
+    clo = [max(0, (1 - o) // 2) for o in off]
+    chi = [min(n + 6, (134 - 1 - o) // 2 + 1) for n, o in zip(ipc.n, off)]
+    npts_r = int(np.prod([h - l for l, h in zip(clo, chi)]))
+    Ub = Ucd.clone()
+    ms = time_steps(torch, lambda: mhd.restrict(pf, Uf, pc, Ub, nf, off, clo, chi), 10, 2)
+    b = 8.0 * nf * 2 * npts_r
+    res["restrict"] = {"ms": round(ms, 4), "gbs": round(b / (ms * 1e-3) / 1e9, 1), "points": npts_r}
+    L = [torch.rand_like(Uf) for _ in range(4)]
+    out = torch.empty_like(Uf)
+    for m in (0, 1):
+        ms = time_steps(torch, lambda: mhd.dense_output(pf, nf, 0.5, 0.0625, m, Uf, L, out), 10, 2)
+        b = 8.0 * nf * ipf.ninterior * (6 if m == 0 else 5)
+        res["dense_output_d%d" % m] = {"ms": round(ms, 4), "gbs": round(b / (ms * 1e-3) / 1e9, 1)}
+    say("glue: prolong %.3f ms (%.0f GB/s), restrict %.3f ms, dense output %.3f ms" % (
+        res["prolong"]["ms"], res["prolong"]["gbs"], res["restrict"]["ms"], res["dense_output_d0"]["ms"]))
+    del Ucd, Uf, Ub, L, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -522,6 +570,8 @@ def main():
         paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
     if not args.no_level:
         level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
+    if not args.no_glue:
+        paths["glue"] = glue_path(torch, mhd, I, args)
     if not args.no_level_imex:
         paths["level_imex"] = level_imex_path(torch, mhd, I, args)
     if not args.no_level_m1:
