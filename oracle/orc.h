@@ -176,6 +176,13 @@ void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt
                             const double* Un, const double* k, double* acc,
                             double* Unext);
 
+/* SSP-RK(3,3) (Sec. 3.1): the printed tableau, and one stage combination in
+ * Butcher form from the stored stage right-hand sides (K1, K2 may be NULL when
+ * the stage does not read them) */
+void orc_ssprk3_tableau(double A[9], double b[3]);
+void orc_ssprk3_combine(const orc_grid* g, int nfields, int stage, double dt, const double* Un,
+                        const double* K0, const double* K1, const double* K2, double* Unext);
+
 /* ---- ghost fill ---- */
 void orc_fill_periodic(const orc_grid* g, double* U, int nfields);
 

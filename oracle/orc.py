@@ -89,6 +89,9 @@ def _bind(L):
     L.orc_rk4_stage_interior.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, C.c_double,
                                          _dp, _dp, _dp, _dp]
     L.orc_fill_periodic.argtypes = [C.POINTER(Grid), _dp, C.c_int]
+    if hasattr(L, "orc_ssprk3_combine"):
+        L.orc_ssprk3_tableau.argtypes = [_dp, _dp]
+        L.orc_ssprk3_combine.argtypes = [C.POINTER(Grid), C.c_int, C.c_int, C.c_double, _dp, _dp, _dp, _dp, _dp]
     if hasattr(L, "orc_prolong"):
         _i3 = C.POINTER(C.c_int)
         L.orc_lagrange_half.argtypes = [_dp]
@@ -204,6 +207,19 @@ def rk4_stage(stage, dt, Un, k, acc, Unext):
 
 def fill_periodic(g, U, nfields):
     lib().orc_fill_periodic(C.byref(g), ptr(U), nfields)
+
+
+def ssprk3_tableau():
+    A, b = np.zeros(9), np.zeros(3)
+    lib().orc_ssprk3_tableau(ptr(A), ptr(b))
+    return A.reshape(3, 3), b
+
+
+def ssprk3_combine(g, nfields, stage, dt, Un, K, Unext):
+    """Stage `stage` of SSP-RK(3,3) in Butcher form from the stage RHS list K."""
+    ks = [ptr(x) if x is not None else None for x in (list(K) + [None, None, None])[:3]]
+    lib().orc_ssprk3_combine(C.byref(g), int(nfields), int(stage), float(dt), ptr(Un), ks[0], ks[1], ks[2],
+                             ptr(Unext))
 
 
 def _int3(v):

@@ -90,6 +90,39 @@ void orc_rk4_stage(int stage, double dt, int64_t n, const double* Un, const doub
   ORC_PHASE(ORC_PH_OTHER);
 }
 
+/* SSP-RK(3,3) of Shu and Osher (Sec. 3.1, explicit half of IMEX(3,3,2)) in
+ * its Butcher form: with K[j] the right-hand sides of the earlier stages,
+ * stage s = 0, 1 gives the next stage state Un + dt sum_{j<=s} a_{s+1,j} K[j],
+ * s = 2 the step Un + dt sum_j b_j K[j], at the interior points. */
+static const double SSP_A[3][3] = {{0.0, 0.0, 0.0}, {1.0, 0.0, 0.0}, {0.25, 0.25, 0.0}};
+static const double SSP_B[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+
+void orc_ssprk3_tableau(double A[9], double b[3]) {
+  int i, j;
+  for (i = 0; i < 3; ++i) {
+    for (j = 0; j < 3; ++j) A[3 * i + j] = SSP_A[i][j];
+    b[i] = SSP_B[i];
+  }
+}
+
+void orc_ssprk3_combine(const orc_grid* g, int nfields, int stage, double dt, const double* Un,
+                        const double* K0, const double* K1, const double* K2, double* Unext) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  const double* K[3] = {K0, K1, K2};
+  int f, j;
+  for (f = 0; f < nfields; ++f)
+    for (int64_t kk = ng; kk < Nz - ng; ++kk)
+      for (int64_t jj = ng; jj < Ny - ng; ++jj)
+        for (int64_t i = ng; i < Nx - ng; ++i) {
+          const int64_t p = f * N + i + Nx * (jj + Ny * kk);
+          double s = 0.0;
+          for (j = 0; j <= stage; ++j) s += (stage < 2 ? SSP_A[stage + 1][j] : SSP_B[j]) * K[j][p];
+          Unext[p] = Un[p] + dt * s;
+        }
+}
+
 void orc_rk4_stage_interior(const orc_grid* g, int nfields, int stage, double dt,
                             const double* Un, const double* k, double* acc, double* Unext) {
   const int ng = g->ng;
