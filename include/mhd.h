@@ -390,6 +390,16 @@ int mhd_m1_implicit(const mhd_patch_t* patch, const double* aux, double* U, cons
 int mhd_rk_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, const double* Un,
                  const double* k, double* acc, double* Unext, void* stream);
 
+/* Explicit SSP-RK(3,3) stage of Shu and Osher (Sec. 3.1, the explicit half of
+ * IMEX(3,3,2); c = (0, 1, 1/2), A = ((0), (1), (1/4, 1/4)), b = (1/6, 1/6, 2/3))
+ * at the interior points of `nfields` fields:
+ *   stage 0: acc = k/6, Unext = Un + dt k;
+ *   stage 1: acc += k/6, Unext = Un + dt (3/2) acc  (= Un + dt (k0 + k1)/4);
+ *   stage 2: Unext = Un + dt (acc + 2/3 k).
+ * Unext may alias Un only for stage 2. */
+int mhd_ssprk3_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, const double* Un,
+                     const double* k, double* acc, double* Unext, void* stream);
+
 /* Periodic ghost fill of `nfields` fields (edges and corners included). */
 int mhd_fill_ghosts_periodic(const mhd_patch_t* patch, double* U, int nfields, void* stream);
 

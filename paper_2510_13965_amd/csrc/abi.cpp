@@ -33,6 +33,8 @@ int launch_prim2con(const Geom& g, const mhd_eos_t& eos, double* U, double* P, c
 int launch_rk4_stage(const Geom& g, int nfields, int stage, double dt, const double* Un, const double* k, double* acc,
                      double* Unext, hipStream_t s);
 int launch_ghosts_periodic(const Geom& g, double* U, int nfields, hipStream_t s);
+int launch_ssprk3_stage(const Geom& g, int nfields, int stage, double dt, const double* Un, const double* k,
+                        double* acc, double* Unext, hipStream_t s);
 int launch_zero_interior(const Geom& g, int f0, int nfields, double* A, hipStream_t s);
 int launch_mlp_features(const Geom& g, const mhd_eos_t& eos, const double* U, const double* mu, float* X, float* T,
                         hipStream_t s);
@@ -378,6 +380,19 @@ int mhd_rk_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, co
   if (!std::isfinite(dt)) return fail(MHD_EINVAL, "mhd_rk_stage: dt must be finite");
   return hip_check(mhd::launch_rk4_stage(geom_of(patch), nfields, stage, dt, Un, k, acc, Unext, (hipStream_t)stream),
                    "mhd_rk_stage");
+}
+
+int mhd_ssprk3_stage(const mhd_patch_t* patch, int nfields, int stage, double dt, const double* Un, const double* k,
+                     double* acc, double* Unext, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, nfields > 0 ? nfields : 1, "mhd_ssprk3_stage"))) return rc;
+  if (nfields < 1) return fail(MHD_EINVAL, "mhd_ssprk3_stage: nfields must be >= 1");
+  if (stage < 0 || stage > 2) return fail(MHD_EINVAL, "mhd_ssprk3_stage: stage must be 0..2");
+  if (!Un || !k || !acc || !Unext) return fail(MHD_EINVAL, "mhd_ssprk3_stage: NULL array");
+  if (Unext == Un && stage != 2) return fail(MHD_EINVAL, "mhd_ssprk3_stage: Unext may alias Un only at stage 2");
+  if (!std::isfinite(dt)) return fail(MHD_EINVAL, "mhd_ssprk3_stage: dt must be finite");
+  return hip_check(mhd::launch_ssprk3_stage(geom_of(patch), nfields, stage, dt, Un, k, acc, Unext, (hipStream_t)stream),
+                   "mhd_ssprk3_stage");
 }
 
 // padded extent of a patch along axis a

@@ -37,6 +37,7 @@ enum KernelId : int {
   KID_PROLONG,
   KID_RESTRICT,
   KID_DENSE,
+  KID_SSPRK3_STAGE,
   KID_COUNT
 };
 

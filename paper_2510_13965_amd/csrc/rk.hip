@@ -39,6 +39,38 @@ __device__ __forceinline__ void rk4_element(const RkArgs& a, int64_t p) {
   }
 }
 
+// SSP-RK(3,3) of Shu and Osher (Sec. 3.1; the explicit half of IMEX(3,3,2)):
+// c = (0, 1, 1/2), A = ((0), (1), (1/4, 1/4)), b = (1/6, 1/6, 2/3).  Stored as
+// acc = sum of b_j k_j so far, which after stage 1 is (k0 + k1)/6, so the third
+// stage state Un + dt (k0 + k1)/4 is Un + dt (3/2) acc:
+//   s = 0: acc = k/6;        Unext = Un + dt k
+//   s = 1: acc = acc + k/6;  Unext = Un + dt (3/2 acc)
+//   s = 2: Unext = Un + dt (acc + 2/3 k)
+__device__ __forceinline__ void ssprk3_element(const RkArgs& a, int64_t p) {
+  const double kv = a.k[p];
+  const int s = a.stage;
+  if (s == 0) {
+    a.acc[p] = kv / 6.0;
+    a.Unext[p] = a.Un[p] + a.dt * kv;
+  } else if (s == 1) {
+    const double acc = a.acc[p] + kv / 6.0;
+    a.acc[p] = acc;
+    a.Unext[p] = a.Un[p] + a.dt * (1.5 * acc);
+  } else {
+    a.Unext[p] = a.Un[p] + a.dt * (a.acc[p] + 2.0 / 3.0 * kv);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_ssprk3_stage(RkArgs a) {
+  const Geom& g = a.g;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+  const int kz = blockIdx.z % g.nz;
+  const int f = blockIdx.z / g.nz;
+  if (i >= g.nx || j >= g.ny) return;
+  ssprk3_element(a, (int64_t)f * g.sf + g.at(i + g.ng, j + g.ng, kz + g.ng));
+}
+
 // block 64x4: x = 64 consecutive points of a row, y = 4 rows; grid z = k * nfields + f
 __global__ void __launch_bounds__(256) k_rk4_stage(RkArgs a) {
   const Geom& g = a.g;
@@ -68,6 +100,14 @@ __global__ void __launch_bounds__(256) k_rk4_stage_lv(LevelArgs L) {
 }
 
 __global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+int launch_ssprk3_stage(const Geom& g, int nfields, int stage, double dt, const double* Un, const double* k,
+                        double* acc, double* Unext, hipStream_t s) {
+  const RkArgs a{g, stage, dt, Un, k, acc, Unext};
+  MHD_LAUNCH(KID_SSPRK3_STAGE, k_ssprk3_stage, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * nfields), dim3(64, 4, 1), 0,
+             s, a);
+  return (int)hipGetLastError();
+}
 
 int launch_rk4_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
   MHD_LAUNCH(KID_RK4_STAGE, k_rk4_stage_lv, dim3(grid), dim3(block), 0, s, L);

@@ -100,6 +100,7 @@ SIGNATURES = {
     "mhd_level_learned_workspace_size": (C.c_size_t, [_vp]),
     "mhd_level_set_learned": (C.c_int, [_vp, _vp, _vp, C.c_size_t]),
     "mhd_level_set_imex": (C.c_int, [_vp, C.POINTER(ImexBox), C.c_int]),
+    "mhd_ssprk3_stage": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_double, _vp, _vp, _vp, _vp, _vp]),
     "mhd_prolong": (C.c_int, [C.POINTER(Patch), _vp, C.POINTER(Patch), _vp, C.c_int, _vp, _vp, _vp, _vp]),
     "mhd_restrict": (C.c_int, [C.POINTER(Patch), _vp, C.POINTER(Patch), _vp, C.c_int, _vp, _vp, _vp, _vp]),
     "mhd_dense_output": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_double, C.c_double, C.c_int, _vp,
@@ -428,6 +429,11 @@ class Level:
         if key is not None:
             TuningCache(cache).put(key, chosen)
         return chosen
+
+
+def ssprk3_stage(patch, nfields, stage, dt, Un, k, acc, Unext, stream=None):
+    _check(lib().mhd_ssprk3_stage(C.byref(patch), int(nfields), int(stage), float(dt), _ptr(Un), _ptr(k), _ptr(acc),
+                                  _ptr(Unext), _stream(stream)))
 
 
 def _i3(v):

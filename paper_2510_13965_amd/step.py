@@ -66,6 +66,16 @@ class PatchRun:
             mhd.fill_ghosts_periodic(self.patch, self.Un, self.nfields, self.stream)
 
 
+    def step_ssprk3(self, dt):
+        """One SSP-RK(3,3) step (Sec. 3.1), stage structure as in step()."""
+        for s in range(3):
+            self.rhs_eval(self.Un if s == 0 else self.Us)
+            nxt = self.Us if s < 2 else self.Un
+            mhd.ssprk3_stage(self.patch, self.nfields, s, dt, self.Un, self.k, self.acc, nxt, self.stream)
+        if self.periodic:
+            mhd.fill_ghosts_periodic(self.patch, self.Un, self.nfields, self.stream)
+
+
 class LevelRun:
     """Device buffers of a list of boxes and their batched level (mhd_level_*).
     Us starts as a copy of U so the stage states carry the (frozen) ghosts."""

@@ -395,6 +395,61 @@ def test_rk4_step_parity(orc, dev, case):
         assert err <= bound, (case, f, err, bound)
 
 
+def _oracle_ssprk3_step(orc, ip, U, par, dt, periodic, eos_cfg=I.EOS_IDEAL2):
+    """The oracle's SSP-RK(3,3) step in Butcher form (stage right-hand sides
+    stored), with the device driver's stage sequence."""
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    e = orc.make_eos(eos_cfg)
+    p = orc.make_par(par)
+    Un = U.copy()
+    Us = U.copy()
+    K = []
+    P = np.zeros((I.NP,) + ip.shape)
+    for s in range(3):
+        X = Un if s == 0 else Us
+        if periodic:
+            orc.fill_periodic(g, X, I.NU)
+        orc.con2prim(g, e, X, P, None, None)
+        k = np.zeros_like(U)
+        orc.rhs(g, p, e, X, P, k)
+        K.append(k)
+        nxt = Us.copy() if s < 2 else Un
+        orc.ssprk3_combine(g, I.NU, s, dt, Un, K, nxt)
+        if s < 2:
+            Us = nxt
+    if periodic:
+        orc.fill_periodic(g, Un, I.NU)
+    return Un
+
+
+@pytest.mark.parametrize("case", ["c1", "c2_48"])
+def test_ssprk3_step_parity(orc, dev, case):
+    """SSP-RK(3,3) step (Sec. 3.1): the device's accumulator form against the
+    oracle's Butcher form, to the RHS bar on the increment."""
+    import torch
+    from paper_2510_13965_amd.step import PatchRun
+
+    say("case ssprk3 step", case)
+    if case == "c1":
+        ip, U, P, EM = I.perturbed_flat_state(rich=True)
+        periodic = True
+    else:
+        ip, U, P, EM = I.tov_star_state(n=48)
+        periodic = False
+    U = prepared(orc, ip, U, P, EM)
+    dt = 0.25 * ip.dx[0]
+    Uo = _oracle_ssprk3_step(orc, ip, U, I.PARAMS, dt, periodic)
+    run = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS, periodic=periodic)
+    run.step_ssprk3(dt)
+    torch.cuda.synchronize()
+    Ug = run.Un.cpu().numpy()
+    for f in range(32):
+        do = interior(ip, Uo - U)[f]
+        err = np.abs(interior(ip, Ug)[f] - interior(ip, Uo)[f]).max()
+        bound = 4e-10 * np.abs(do).max() + 8 * np.finfo(float).eps * np.abs(interior(ip, Uo)[f]).max()
+        assert err <= bound, (case, f, err, bound)
+
+
 # ---------------------------------------------------------------- argument errors
 
 def test_abi_rejects_bad_arguments(dev):
@@ -415,5 +470,9 @@ def test_abi_rejects_bad_arguments(dev):
                 torch.zeros(1, dtype=torch.float64, device="cuda"))
     with pytest.raises(mhd.MhdError, match="stage"):
         mhd.rk_stage(pt, 4, 7, 0.1, U, U, U, U)
+    with pytest.raises(mhd.MhdError, match="stage must be 0..2"):
+        mhd.ssprk3_stage(pt, 4, 3, 0.1, U, U, U, U)
+    with pytest.raises(mhd.MhdError, match="alias Un only at stage 2"):
+        mhd.ssprk3_stage(pt, 4, 1, 0.1, U, U, U, U)
     with pytest.raises(mhd.MhdError, match="device tensors"):
         mhd.fill_ghosts_periodic(pt, U.cpu(), 4)
