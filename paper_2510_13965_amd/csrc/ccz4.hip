@@ -328,13 +328,14 @@ __device__ __forceinline__ bool level_lds_tile(const LevelArgs& L, int& box, Til
   return true;
 }
 
+template <bool IMEX>
 __global__ void __launch_bounds__(256) k_ccz4_stencil_lds_lv(LevelArgs L) {
   __shared__ double lds[2][kLvT + 2 * kStH][kLvT + 2 * kStH];
   int b;
   TileXYZ t;
   if (!level_lds_tile(L, b, t)) return;  // whole block
   const BoxDev& B = L.boxes[b];
-  stencil_lds_tile<kLvT, kLvT>(B.g, L.par, L.src ? B.Us : B.U, level_rhs(B, L), t.bx, t.by, t.bz, lds);
+  stencil_lds_tile<kLvT, kLvT>(B.g, L.par, L.src ? B.Us : B.U, level_rhs<IMEX>(B, L), t.bx, t.by, t.bz, lds);
 }
 
 // ------------------------------------------------------------------ second derivatives
@@ -856,10 +857,11 @@ __global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __r
   ccz4_curv_at(a, W, q);
 }
 
+template <bool IMEX>
 __global__ void __launch_bounds__(256) k_ccz4_curv_lv(LevelArgs L) {
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs<IMEX>(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
     ccz4_curv_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
   });
 }
@@ -870,10 +872,11 @@ __global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __
   ccz4_gauge_at(a, W, q);
 }
 
+template <bool IMEX>
 __global__ void __launch_bounds__(256) k_ccz4_gauge_lv(LevelArgs L) {
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
+    const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs<IMEX>(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
     ccz4_gauge_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
   });
 }
@@ -907,10 +910,18 @@ int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const d
 int launch_ccz4_level(const LevelArgs& L, int grid, int block, int grid_lds, hipStream_t s) {
   static_assert(kStZC == kLevelLdsZ && kD2ZC == kLevelLdsZ, "one LDS tile space for both staged kernels");
   const dim3 blk_lds(kLvT, kLvT, 1);
-  MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lds_lv, dim3(grid_lds), blk_lds, 0, s, L);
+  if (L.slot >= 0)
+    MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lds_lv<true>, dim3(grid_lds), blk_lds, 0, s, L);
+  else
+    MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lds_lv<false>, dim3(grid_lds), blk_lds, 0, s, L);
   MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2_lds_lv, dim3(grid_lds), blk_lds, 0, s, L);
-  MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv_lv, dim3(grid), dim3(block), 0, s, L);
-  MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge_lv, dim3(grid), dim3(block), 0, s, L);
+  if (L.slot >= 0) {
+    MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv_lv<true>, dim3(grid), dim3(block), 0, s, L);
+    MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge_lv<true>, dim3(grid), dim3(block), 0, s, L);
+  } else {
+    MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv_lv<false>, dim3(grid), dim3(block), 0, s, L);
+    MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge_lv<false>, dim3(grid), dim3(block), 0, s, L);
+  }
   return (int)hipGetLastError();
 }
 

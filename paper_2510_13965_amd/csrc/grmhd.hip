@@ -421,10 +421,11 @@ __global__ void __launch_bounds__(256) k_mhd_point_lv(LevelArgs L) {
   });
 }
 
+template <bool IMEX>
 __global__ void __launch_bounds__(256) k_mhd_update_lv(LevelArgs L) {
   double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    const MhdUpdArgs a{B.g, 0, 0, 0, 0, L.par, L.src ? B.Us : B.U, B.P, B.ws, level_rhs(B, L), L.max_speed};
+    const MhdUpdArgs a{B.g, 0, 0, 0, 0, L.par, L.src ? B.Us : B.U, B.P, B.ws, level_rhs<IMEX>(B, L), L.max_speed};
     vmax = fmax(vmax, mhd_update_at(a, i, j, k, live));
   });
   if (L.max_speed) block_max_to(L.max_speed, vmax);
@@ -432,7 +433,10 @@ __global__ void __launch_bounds__(256) k_mhd_update_lv(LevelArgs L) {
 
 int launch_mhd_level(const LevelArgs& L, int grid_pad, int grid_int, int block, hipStream_t s) {
   MHD_LAUNCH(KID_MHD_POINT, k_mhd_point_lv, dim3(grid_pad), dim3(block), 0, s, L);
-  MHD_LAUNCH(KID_MHD_UPDATE, k_mhd_update_lv, dim3(grid_int), dim3(block), 0, s, L);
+  if (L.slot >= 0)
+    MHD_LAUNCH(KID_MHD_UPDATE, k_mhd_update_lv<true>, dim3(grid_int), dim3(block), 0, s, L);
+  else
+    MHD_LAUNCH(KID_MHD_UPDATE, k_mhd_update_lv<false>, dim3(grid_int), dim3(block), 0, s, L);
   return (int)hipGetLastError();
 }
 

@@ -288,10 +288,11 @@ __global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
   });
 }
 
+template <bool IMEX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update_lv(LevelArgs L) {
   double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs(B, L), L.max_speed, level_stiff(B, L)};
+    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs<IMEX>(B, L), L.max_speed, level_stiff<IMEX>(B, L)};
     vmax = fmax(vmax, m1_update_at(a, i, j, k, live));
   });
   if (L.max_speed) block_max_to(L.max_speed, vmax);
@@ -305,7 +306,10 @@ int launch_m1_point_level(const LevelArgs& L, int grid, int block, hipStream_t s
 }
 
 int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
-  MHD_LAUNCH(KID_M1_UPDATE, k_m1_update_lv, dim3(grid), dim3(block), 0, s, L);
+  if (L.slot >= 0)
+    MHD_LAUNCH(KID_M1_UPDATE, k_m1_update_lv<true>, dim3(grid), dim3(block), 0, s, L);
+  else
+    MHD_LAUNCH(KID_M1_UPDATE, k_m1_update_lv<false>, dim3(grid), dim3(block), 0, s, L);
   return (int)hipGetLastError();
 }
 
