@@ -615,7 +615,7 @@ FLOP_PER_UNIT = {
 # HBM bytes per launch of the dominant kernel from rocprofv3 --pmc (FETCH_SIZE x 2
 # + WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read and write 1 GiB),
 # valid only for the kernel sources they were taken on (sha256 of these files).
-TRAFFIC = {"k_mhd_update": (2721545025.0, "f3f368c0fd332f5f")}
+TRAFFIC = {"k_mhd_update": (2698185360.0, "6d780a4bcdb13c60")}
 TRAFFIC_SOURCES = {"k_mhd_update": ["paper_2510_13965_amd/csrc/grmhd.hip", "paper_2510_13965_amd/csrc/dev_common.hpp"]}
 
 
