@@ -255,7 +255,7 @@ int mhd_mlp_adam(float* mlp, const float* grad, float* m, float* v, int step, fl
 /* ---- batched levels ---------------------------------------------------------
  * All boxes of one refinement level (patches of any shape, ng = 3, each with its
  * own arrays) go through one persistent kernel per phase of the right-hand
- * side; an RK4 step is 33 launches whatever the number of boxes, and can be
+ * side; an RK4 step is 33 launches (41 with M1) whatever the number of boxes, and can be
  * replayed as one hipGraph.  Per point the arithmetic is that of the
  * single-patch entry points, so results are bitwise equal to per-box calls of
  * mhd_con2prim, mhd_rhs and mhd_rk_stage.  Ghost values are taken as given
