@@ -197,6 +197,12 @@ void orc_dense_weights(double theta, int m, double b[4]);
 void orc_dense_output(const orc_grid* g, int nfields, double theta, double dt, int m, const double* Un,
                       const double* L0, const double* L1, const double* L2, const double* L3, double* out);
 
+/* ---- constraint monitors (diag.c): energy and momentum constraints, Z4
+ * variables, baryonic mass, cleaning field ---- */
+void orc_constraints_point(const double* U, int64_t N, int64_t p, const int64_t st[3], const double h[3],
+                           double out[5], double* sqrtg, double gdn[3][3]);
+void orc_constraints(const orc_grid* g, const double* U, double* C, double* sums);
+
 #ifdef __cplusplus
 }
 #endif

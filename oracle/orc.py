@@ -102,6 +102,8 @@ def _bind(L):
         L.orc_dense_weights.argtypes = [C.c_double, C.c_int, _dp]
         L.orc_dense_output.argtypes = [C.POINTER(Grid), C.c_int, C.c_double, C.c_double, C.c_int, _dp, _dp, _dp,
                                        _dp, _dp, _dp]
+    if hasattr(L, "orc_constraints"):
+        L.orc_constraints.argtypes = [C.POINTER(Grid), _dp, _dp, _dp]
     if hasattr(L, "orc_m1_rhs"):
         L.orc_m1_eddington.argtypes = [C.c_double]
         L.orc_m1_eddington.restype = C.c_double
@@ -253,6 +255,18 @@ def dense_weights(theta, m):
 def dense_output(g, nfields, theta, dt, m, Un, L, out):
     lib().orc_dense_output(C.byref(g), int(nfields), float(theta), float(dt), int(m), ptr(Un), ptr(L[0]), ptr(L[1]),
                            ptr(L[2]), ptr(L[3]), ptr(out))
+
+
+def constraints(g, U):
+    """Constraint monitors over the interior of the padded patch of grid g:
+    returns (C, sums), C = (5, padded) with H, M_1..3, Z_i Z^i at interior
+    points (zero elsewhere), sums = 7 (nz + 1) volume integrals (totals first,
+    then one row per interior plane)."""
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    out = np.zeros((5,) + U.shape[1:])
+    sums = np.zeros(7 * (g.n[2] + 1))
+    lib().orc_constraints(C.byref(g), ptr(U), ptr(out), ptr(sums))
+    return out, sums
 
 
 def c2p_point(e, cons, B, gdn, gup, alpha):
