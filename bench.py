@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--level-boxes", type=int, default=192)
     ap.add_argument("--no-level-m1", action="store_true", help="skip the batched level with M1 radiation")
     ap.add_argument("--no-level-imex", action="store_true", help="skip the batched level stepped by IMEX(4,4,2)")
+    ap.add_argument("--no-diag", action="store_true", help="skip the constraint-monitor timing")
     ap.add_argument("--no-glue", action="store_true", help="skip the prolongation/restriction/dense-output timings")
     ap.add_argument("--level-m1-boxes", type=int, default=803)
     ap.add_argument("--no-c2p-cells", action="store_true", help="skip con2prim on random states")
@@ -499,6 +500,34 @@ def glue_path(torch, mhd, I, args):
     return res
 
 
+def diag_path(torch, mhd, I, run, ip):
+    """Constraint monitors on the evolved star patch (the state the plain path
+    left): per-call time of mhd_constraints, per-kernel event times, the HBM
+    rate of the algorithmic bytes of the point kernel (23 evolved fields read
+    once, 5 monitor fields written once, per interior point) and the monitor
+    values themselves."""
+    C5 = torch.zeros((5,) + ip.shape, dtype=torch.float64, device="cuda")
+    sums = torch.zeros(7 * (ip.n[2] + 1), dtype=torch.float64, device="cuda")
+    ms = time_steps(torch, lambda: mhd.constraints(run.patch, run.Un, C5, sums), 5, 1)
+    mhd.profile_start()
+    for _ in range(5):
+        mhd.constraints(run.patch, run.Un, C5, sums)
+    torch.cuda.synchronize()
+    prof = mhd.profile_stop()
+    kern = {k: round(t / n, 4) for k, (n, t) in prof.items()}
+    b = 8.0 * (23 + 5) * ip.ninterior
+    t = kern.get("k_constraints")
+    s = sums[:7].cpu().tolist()
+    res = {"workload": "constraint monitors of the evolved %d^3 star patch" % ip.n[0], "ms": round(ms, 4),
+           "kernels_ms": kern, "k_constraints_gbs": round(b / (t * 1e-3) / 1e9, 1) if t else None,
+           "algorithmic_bytes": b,
+           "monitors": {"H_L2": s[0] ** 0.5, "M_L2": s[1] ** 0.5, "baryon_mass": s[2], "Theta_L2": s[3] ** 0.5,
+                        "Z_L2": s[4] ** 0.5, "phi_L2": s[5] ** 0.5, "B_L2": s[6] ** 0.5}}
+    say("constraints: %.3f ms per call (H_L2 %.3e, baryonic mass %.6f)" % (ms, res["monitors"]["H_L2"], s[2]))
+    del C5, sums
+    return res
+
+
 def main():
     args = parse()
     if args.copy_calibration:
@@ -570,6 +599,8 @@ def main():
         paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
     if not args.no_level:
         level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
+    if not args.no_diag:
+        paths["constraints"] = diag_path(torch, mhd, I, run, ip)
     if not args.no_glue:
         paths["glue"] = glue_path(torch, mhd, I, args)
     if not args.no_level_imex:

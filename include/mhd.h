@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 3
+#define MHD_ABI_VERSION 4
 
 #define MHD_NST 22
 #define MHD_NMHD 10
@@ -431,6 +431,29 @@ int mhd_restrict(const mhd_patch_t* fine, const double* Uf, const mhd_patch_t* c
                  const int32_t* offset, const int32_t* lo, const int32_t* hi, void* stream);
 int mhd_dense_output(const mhd_patch_t* patch, int nfields, double theta, double dt, int deriv, const double* Un,
                      const double* const* L, double* out, void* stream);
+
+/* ---- constraint monitors (Sec. 2.1 constraints; Sec. 5 accuracy checks) ----
+ * At every interior point of the patch (ghost width >= 2, the 4th-order
+ * centred stencils of Sec. 3.2 reach two points out), from the 32 evolved
+ * fields U:
+ *   C[0] = H   = R + K^2 - K_ij K^ij - 16 pi E          (energy constraint)
+ *   C[1..3] = M_i = D_j K^j_i - d_i K - 8 pi S_i         (momentum constraint)
+ *   C[4] = Z_i Z^i,  Z^i = chi (Ghat^i - Gt^i) / 2,  Gt^i = gt^ij gt^kl d_l gt_jk
+ * with the physical metric gamma_ij = gt_ij / chi, K_ij = (At_ij + gt_ij K/3)/chi,
+ * K = Khat + 2 Theta, E = (taubar + Dbar)/sqrt(gamma), S_i = Sbar_i/sqrt(gamma),
+ * R the Ricci scalar of gamma_ij; every derivative is the 4th-order centred
+ * operator on the evolved fields, products by the product rule.  C is a device
+ * array of 5 fields in the patch layout (interior points written, the rest
+ * untouched); it must not alias U.
+ * sums: device array of 7 (nz + 1) doubles.  sums[7 + 7 k + q] is the volume
+ * integral (sum times dx dy dz) over interior plane k of
+ *   q = 0: H^2,  1: M_1^2 + M_2^2 + M_3^2,  2: Dbar (baryonic mass),
+ *   3: Theta^2,  4: Z_i Z^i,  5: phi^2 = (phibar/sqrt(gamma))^2,
+ *   6: gamma_ij B^i B^j with B^i = Bbar^i/sqrt(gamma),
+ * and sums[q] the total over the planes (so sqrt(sums[0]) is the L2 norm of
+ * H over the patch).  Reductions run in a fixed order: the same input gives
+ * the same bits on every call.  Three kernels, enqueued on `stream`. */
+int mhd_constraints(const mhd_patch_t* patch, const double* U, double* C, double* sums, void* stream);
 
 #ifdef __cplusplus
 }

@@ -45,6 +45,7 @@ int launch_prolong(const Geom& gc, const double* Uc, const Geom& gf, double* Uf,
                    const int lo[3], const int n[3], hipStream_t s);
 int launch_restrict(const Geom& gf, const double* Uf, const Geom& gc, double* Uc, int nfields, const int off[3],
                     const int lo[3], const int n[3], hipStream_t s);
+int launch_constraints(const Geom& g, const double* U, double* C, double* sums, hipStream_t s);
 int launch_dense_output(const Geom& g, int nfields, double dt, const double b[4], int add_un, double dtm,
                         const double* Un, const double* const* L, double* out, hipStream_t s);
 int launch_mlp_grad(const float* prm, const float* X, const float* T, int64_t n, float* grad, float* loss, void* ws,
@@ -523,6 +524,19 @@ int mhd_fill_ghosts_periodic(const mhd_patch_t* patch, double* U, int nfields, v
   if (patch->ng == 0) return MHD_OK;
   return hip_check(mhd::launch_ghosts_periodic(geom_of(patch), U, nfields, (hipStream_t)stream),
                    "mhd_fill_ghosts_periodic");
+}
+
+int mhd_constraints(const mhd_patch_t* patch, const double* U, double* C, double* sums, void* stream) {
+  int rc;
+  const char* fn = "mhd_constraints";
+  if ((rc = check_patch(patch, -1, 1, fn))) return rc;
+  if (patch->ng < 2) return fail(MHD_EINVAL, "%s: ghost width must be >= 2 (got %d)", fn, patch->ng);
+  if (!U || !C || !sums) return fail(MHD_EINVAL, "%s: U, C and sums are required", fn);
+  if (C == U) return fail(MHD_EINVAL, "%s: C must not alias U", fn);
+  if (patch->sf > (int64_t)(INT32_MAX / 8))
+    return fail(MHD_EINVAL, "%s: a padded field of %lld points exceeds the 2^28-point limit of one launch", fn,
+                (long long)patch->sf);
+  return hip_check(mhd::launch_constraints(geom_of(patch), U, C, sums, (hipStream_t)stream), fn);
 }
 
 }  // extern "C"

@@ -38,6 +38,9 @@ enum KernelId : int {
   KID_RESTRICT,
   KID_DENSE,
   KID_SSPRK3_STAGE,
+  KID_CONSTRAINTS,
+  KID_CONSTRAINT_PLANES,
+  KID_CONSTRAINT_TOTAL,
   KID_COUNT
 };
 

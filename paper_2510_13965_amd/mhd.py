@@ -111,6 +111,7 @@ SIGNATURES = {
     "mhd_imex_combine": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_double, _vp, C.POINTER(C.c_void_p),
                                    C.POINTER(C.c_void_p), _vp, _vp]),
     "mhd_m1_implicit": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, C.c_double, _vp, _vp]),
+    "mhd_constraints": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, _vp]),
     "mhd_profile_start": (C.c_int, []),
     "mhd_profile_stop": (C.c_int, [C.POINTER(KernelTime), C.c_int, C.POINTER(C.c_int)]),
 }
@@ -459,6 +460,13 @@ def dense_output(patch, nfields, theta, dt, deriv, Un, L, out, stream=None):
     arr = (C.c_void_p * 4)(*[_ptr(x) for x in L])
     _check(lib().mhd_dense_output(C.byref(patch), int(nfields), float(theta), float(dt), int(deriv), _ptr(Un), arr,
                                   _ptr(out), _stream(stream)))
+
+
+def constraints(patch, U, C5, sums, stream=None):
+    """Constraint monitors (mhd_constraints): H, M_i, Z_i Z^i into the 5-field
+    array C5 at interior points, volume integrals into the device array sums of
+    7 (nz + 1) doubles (totals first, then one row per interior plane)."""
+    _check(lib().mhd_constraints(C.byref(patch), _ptr(U), _ptr(C5), _ptr(sums), _stream(stream)))
 
 
 def profile_start():
