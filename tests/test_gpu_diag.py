@@ -138,6 +138,31 @@ def test_tov_star(orc, dev, n):
         assert abs(sg[2] - 1.506) < 2e-3, sg[2]
 
 
+def test_baryonic_mass_conserved_on_a_periodic_patch(orc, dev):
+    """The fluid update is in flux form: on a periodic patch the fluxes of the
+    conserved density telescope and the baryonic mass is constant up to
+    rounding (the oracle's own RK4 step keeps it to 2e-16 on this state).
+    Three GPU steps, the monitor read by the GPU."""
+    import torch
+    from paper_2510_13965_amd.step import PatchRun
+
+    say("case constraints: baryonic mass over three periodic RK4 steps")
+    ip, U, P, EM = I.perturbed_flat_state(rich=True)
+    U = prepared(orc, ip, U, P, EM)
+    run = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS, periodic=True)
+    masses = []
+    for _ in range(4):
+        torch.cuda.synchronize()
+        _, s = gpu_constraints(ip, run.Un.cpu().numpy())
+        masses.append(s[2])
+        run.step(0.25 * ip.dx[0])
+    torch.cuda.synchronize()
+    assert bool(torch.isfinite(run.Un).all().item())
+    m0 = masses[0]
+    assert all(abs(m - m0) <= 1e-14 * m0 for m in masses), masses
+    say("baryonic mass over the steps", masses)
+
+
 def test_rejects_bad_arguments(dev):
     import torch
     from paper_2510_13965_amd import mhd
