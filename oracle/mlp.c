@@ -4,7 +4,7 @@
  * The paper recovers primitives by two bracketed root solves (App. D).  The
  * learned variant predicts starting guesses for both roots with a small MLP
  * 8 -> 64 -> 64 -> 2 (ReLU) and polishes them by Newton's method; the plain
- * solver stays the judge of the answer.  This file is the plain FP64 version
+ * solver decides the answer.  This file is the plain FP64 version
  * of the network part:
  *
  *   features   8 metric-invariant scalars of one state (con2prim depends on

@@ -9,8 +9,8 @@
 // Newton's method in FP64 polishes each guess for at most three iterations,
 // and a point is accepted only if the residual falls below 1e-12 (f_a
 // absolute, f relative to mu) with 0 < mu <= mu_+.  Every other point goes to
-// a queue that the bracketed solver then finishes, so the plain solver stays
-// the judge and the answer is the root either way.
+// a queue that the bracketed solver then finishes, so the plain solver
+// decides and the answer is the root either way.
 //
 // Network arithmetic: the two hidden layers run on the bf16 matrix cores
 // (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with inputs, weights and
