@@ -10,6 +10,21 @@ from . import inputs as I
 from . import mhd
 
 
+# names of the seven volume integrals of mhd_constraints, in order
+MONITORS = ("H2", "M2", "baryon_mass", "Theta2", "Z2", "phi2", "B2")
+
+
+def monitors(patch, ipatch, U, stream=None):
+    """The constraint monitors of one patch (mhd_constraints): a dict of the
+    seven volume integrals (H^2, M_i M_i, Dbar, Theta^2, Z_i Z^i, phi^2,
+    gamma_ij B^i B^j), read back to the host."""
+    C5 = torch.empty((5,) + tuple(ipatch.shape), dtype=torch.float64, device=U.device)
+    sums = torch.zeros(7 * (ipatch.n[2] + 1), dtype=torch.float64, device=U.device)
+    mhd.constraints(patch, U, C5, sums, stream)
+    vals = sums[:7].cpu().tolist()
+    return dict(zip(MONITORS, vals))
+
+
 class PatchRun:
     def __init__(self, ipatch, U0, eos_cfg, par_cfg, periodic=False, device="cuda", stream=None, aux=None):
         self.ip = ipatch
@@ -66,6 +81,10 @@ class PatchRun:
             mhd.fill_ghosts_periodic(self.patch, self.Un, self.nfields, self.stream)
 
 
+    def monitors(self):
+        """Constraint monitors of the current state Un."""
+        return monitors(self.patch, self.ip, self.Un, self.stream)
+
     def step_ssprk3(self, dt):
         """One SSP-RK(3,3) step (Sec. 3.1), stage structure as in step()."""
         for s in range(3):
@@ -104,6 +123,11 @@ class LevelRun:
         self.level = mhd.Level(self.boxes, self.par, self.eos)
         if imex:
             self.level.set_imex([(b["F"], b["R"]) for b in self.boxes])
+
+    def monitors(self):
+        """Constraint monitors of every box, in box order (boxes of one level do
+        not overlap, so the integrals of the level are the boxes' sums)."""
+        return [monitors(b["patch"], b["ip"], b["U"]) for b in self.boxes]
 
     @property
     def ninterior(self):

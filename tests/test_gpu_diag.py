@@ -125,6 +125,61 @@ def test_ragged(orc, dev, n):
     check(orc, ip, U, "ragged %s" % (n,))
 
 
+def test_two_ghosts_and_padded_strides(orc, dev):
+    """The minimum ghost width (the stencils reach exactly two points out) and a
+    layout with padded row, plane and field strides; the padding is untouched."""
+    import torch
+    from paper_2510_13965_amd import mhd
+
+    say("case constraints, ng = 2, padded strides")
+    ip = I.Patch((21, 6, 5), (0.2, 0.3, 0.25), (0.0, 0.0, 0.0), 2)
+    r = I.rng(79)
+    U, P, EM = I.empty_state(ip)
+    I.flat_spacetime(U)
+    sh = ip.shape
+    for c in I.GT + (I.CHI,) + I.AT + (I.KHAT, I.THETA) + I.GHAT:
+        U[c] += 1e-3 * r.standard_normal(sh)
+    P[I.RHO] = 1e-3 * (1 + 0.1 * r.random(sh))
+    P[I.EPS] = 0.1 * (1 + 0.1 * r.random(sh))
+    for c in (I.VX, I.VY, I.VZ):
+        P[c] = 0.05 * r.standard_normal(sh)
+    P[I.YE] = 0.1
+    EM[0:3] = 1e-3 * r.standard_normal((3,) + sh)
+    EM[3] = 1e-4 * r.standard_normal(sh)
+    U = prepared(orc, ip, U, P, EM)
+    Co, so = orc.constraints(orc.make_grid(ip.n, ip.dx, ng=ip.ng), U)
+    Nz, Ny, Nx = sh
+    sy, sz = Nx + 3, (Nx + 3) * (Ny + 1)
+    sf = sz * Nz + 11
+
+    def padded(a):
+        buf = np.full(a.shape[0] * sf, np.nan)
+        v = np.lib.stride_tricks.as_strided(buf, shape=a.shape, strides=(sf * 8, sz * 8, sy * 8, 8))
+        v[...] = a
+        return buf, v
+
+    Ub, _ = padded(U)
+    Cb, _ = padded(np.full((5,) + sh, 3.0))
+    Ud, Cd = torch.as_tensor(Ub).cuda(), torch.as_tensor(Cb).cuda()
+    sd = torch.zeros(7 * (ip.n[2] + 1), dtype=torch.float64, device="cuda")
+    mhd.constraints(mhd.patch_of(ip, strides=(sy, sz, sf)), Ud, Cd, sd)
+    torch.cuda.synchronize()
+    cb = Cd.cpu().numpy()
+    Cg = np.lib.stride_tricks.as_strided(cb, shape=(5,) + sh, strides=(sf * 8, sz * 8, sy * 8, 8)).copy()
+    inter = (slice(None),) + ip.interior()
+    for q in range(5):
+        m = np.abs(Co[inter][q]).max()
+        assert np.abs(Cg[inter][q] - Co[inter][q]).max() <= TOL * m, q
+    mask = np.ones(sh, dtype=bool)
+    mask[ip.interior()] = False
+    assert (Cg[:, mask] == 3.0).all()
+    # the padding between rows, planes and fields is never written
+    written = np.zeros(cb.shape, dtype=bool)
+    np.lib.stride_tricks.as_strided(written, shape=(5,) + sh, strides=(sf, sz, sy, 1))[...] = True
+    assert np.isnan(cb[~written]).all()
+    np.testing.assert_allclose(sd.cpu().numpy(), so, rtol=TOL_SUM, atol=TOL_SUM * np.abs(so).max())
+
+
 @pytest.mark.parametrize("n", [32, 128])
 def test_tov_star(orc, dev, n):
     """The TOV star (isotropic coordinates, K_ij = 0): H is the truncation error
@@ -142,7 +197,7 @@ def test_baryonic_mass_conserved_on_a_periodic_patch(orc, dev):
     """The fluid update is in flux form: on a periodic patch the fluxes of the
     conserved density telescope and the baryonic mass is constant up to
     rounding (the oracle's own RK4 step keeps it to 2e-16 on this state).
-    Three GPU steps, the monitor read by the GPU."""
+    Three GPU steps, the monitor read through the driver."""
     import torch
     from paper_2510_13965_amd.step import PatchRun
 
@@ -151,10 +206,14 @@ def test_baryonic_mass_conserved_on_a_periodic_patch(orc, dev):
     U = prepared(orc, ip, U, P, EM)
     run = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS, periodic=True)
     masses = []
-    for _ in range(4):
-        torch.cuda.synchronize()
-        _, s = gpu_constraints(ip, run.Un.cpu().numpy())
-        masses.append(s[2])
+    for it in range(4):
+        if it == 0:
+            # the driver's monitor call gives the same integrals as the direct one
+            torch.cuda.synchronize()
+            _, s = gpu_constraints(ip, run.Un.cpu().numpy())
+            mon = run.monitors()
+            assert [mon[k] for k in ("H2", "M2", "baryon_mass", "Theta2", "Z2", "phi2", "B2")] == list(s[:7])
+        masses.append(run.monitors()["baryon_mass"])
         run.step(0.25 * ip.dx[0])
     torch.cuda.synchronize()
     assert bool(torch.isfinite(run.Un).all().item())
