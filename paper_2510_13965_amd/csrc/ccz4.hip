@@ -538,11 +538,13 @@ __device__ __forceinline__ void d2_lds_tile(const Geom& g, const double* __restr
   }
 }
 
+constexpr int kD2TX = 64, kD2TY = 4;  // patch tiles of the second-derivative kernel
+
 __global__ void __launch_bounds__(256) k_ccz4_d2_lds(Ccz4Args a, double* __restrict__ W, D2Tile T) {
-  __shared__ double lds[2][4 + 2 * kD2H][64 + 2 * kD2H];
+  __shared__ double lds[2][kD2TY + 2 * kD2H][kD2TX + 2 * kD2H];
   const TileXYZ t = tile_of_block(T.nbx, T.nby, T.nzc, a.strip);
   if (t.bx < 0) return;  // whole block
-  d2_lds_tile<64, 4>(a.g, a.U, W, t.bx, t.by, t.bz, lds);
+  d2_lds_tile<kD2TX, kD2TY>(a.g, a.U, W, t.bx, t.by, t.bz, lds);
 }
 
 __global__ void __launch_bounds__(256) k_ccz4_d2_lds_lv(LevelArgs L) {
@@ -898,9 +900,9 @@ int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const d
     MHD_LAUNCH(KID_CCZ4_STENCIL, k_ccz4_stencil_lds, dim3(8 * ((nst + 7) / 8)), blk, 0, s, as, T);
   }
   {
-    const D2Tile T{nbx, nby, (g.nz + kD2ZC - 1) / kD2ZC};
-    const int nd2 = nbx * nby * T.nzc;
-    MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2_lds, dim3(8 * ((nd2 + 7) / 8)), blk, 0, s, a, ws, T);
+    const D2Tile T{(g.nx + kD2TX - 1) / kD2TX, (g.ny + kD2TY - 1) / kD2TY, (g.nz + kD2ZC - 1) / kD2ZC};
+    const int nd2 = T.nbx * T.nby * T.nzc;
+    MHD_LAUNCH(KID_CCZ4_D2, k_ccz4_d2_lds, dim3(8 * ((nd2 + 7) / 8)), dim3(kD2TX, kD2TY, 1), 0, s, a, ws, T);
   }
   MHD_LAUNCH(KID_CCZ4_CURV, k_ccz4_curv, grd, blk, 0, s, a, (const double*)ws);
   MHD_LAUNCH(KID_CCZ4_GAUGE, k_ccz4_gauge, grd, blk, 0, s, a, (const double*)ws);
