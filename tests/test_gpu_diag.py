@@ -222,6 +222,23 @@ def test_baryonic_mass_conserved_on_a_periodic_patch(orc, dev):
     say("baryonic mass over the steps", masses)
 
 
+def test_level_monitors_per_box(orc, dev):
+    """LevelRun.monitors: one entry per box, equal to the direct call on that box."""
+    from paper_2510_13965_amd.step import MONITORS, LevelRun
+
+    say("case constraints: level monitors per box")
+    ip1, U1, P1, EM1 = I.perturbed_flat_state(rich=True, n=16)
+    U1 = prepared(orc, ip1, U1, P1, EM1)
+    ip2, U2, P2, EM2 = I.tov_star_state(n=32)
+    U2 = prepared(orc, ip2, U2, P2, EM2)
+    run = LevelRun([ip1, ip2], [U1, U2], I.EOS_IDEAL2, I.PARAMS)
+    mons = run.monitors()
+    assert len(mons) == 2
+    for ip, U, m in ((ip1, U1, mons[0]), (ip2, U2, mons[1])):
+        _, s = gpu_constraints(ip, U)
+        assert [m[k] for k in MONITORS] == list(s[:7])
+
+
 def test_rejects_bad_arguments(dev):
     import torch
     from paper_2510_13965_amd import mhd
