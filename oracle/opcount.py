@@ -9,6 +9,7 @@ ORC_PHASE), runs one evaluation of each step on the 128^3 TOV workload
   con2prim, prim2con, MHD/M1 point fluxes: per padded point
   CCZ4, MHD/M1 conservative update:         per interior point
   RK stage:                               per interior point and field
+  constraint monitors (residuals + integrals): per interior point
 
 The oracle evaluates each MHD and M1 interface twice (once from each
 neighbouring point); the algorithmic count takes every interface once, i.e.
@@ -33,7 +34,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 sys.path.insert(0, ROOT)
 
-SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c", "m1.c", "mlp.c"]
+SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c", "m1.c", "mlp.c", "diag.c"]
 PHASES = ["other", "ccz4", "mhd_point", "mhd_recon", "mhd_update", "con2prim", "rk", "prim2con",
           "m1_point", "m1_holo", "m1_update", "m1_reclosure"]
 NROW = 16
@@ -115,6 +116,9 @@ def main():
         k44 = np.zeros_like(U44)
         orc.rhs_full(g, orc.make_par(dict(I.PARAMS, evolve_m1=1)), e, U44, Pr, aux, k44)
         c_m1 = take()
+        # constraint monitors of the star (every phase counter: the monitors set none)
+        orc.constraints(g, U)
+        c_diag = take().sum(axis=0, keepdims=True)
 
     nint, npad, n = ip.ninterior, ip.npts, args.n
     tot = c_p2c + c_c2p + c_rhs + c_rk
@@ -153,6 +157,10 @@ def main():
         "per_padded_point_m1": {"m1_point_3species_3axes": per_m1("m1_point", npad)},
         "per_interior_point_and_field": {"rk_stage": per("rk", nint * I.NU * 4)},
     }
+    row = c_diag[0] / nint
+    diag = {c: round(float(v), 2) for c, v in zip(CATS, row)}
+    diag["flop"] = round(float(row[:5].sum()), 2)
+    out["per_interior_point"]["constraint_monitors"] = diag
     print(json.dumps(out, indent=1))
 
 
