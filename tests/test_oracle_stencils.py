@@ -187,3 +187,47 @@ def test_mp5_smooth_extremum_not_clipped(orc):
             unl = sum(float(w[m - 2]) * f5[m] for m in range(5))
             got = orc.mp5(f5)
             assert got == pytest.approx(unl, rel=1e-13, abs=1e-15), (h, x0)
+
+
+# Limited MP5 values worked by hand from the bounds of Sec. 3.3 (alpha = 4).
+# F = (F_{i-2}, F_{i-1}, F_i, F_{i+1}, F_{i+2}); D+ = F_{i+1} - F_i, D- = F_i - F_{i-1};
+# d_{i-1}, d_i, d_{i+1} are the second differences centred on i-1, i, i+1.
+MP5_LIMITED = [
+    # (-4, 3, 6, 6, -5): unlimited 412/60 = 103/15; f^MP = 6 + minmod(0, 12) = 6, so the
+    # test (103/15 - 6)^2 < 0 fails and the limiter acts.  d = (-4, -3, -11):
+    # d^M4_{i+1/2} = minmod(-12+11, -44+3, -3, -11) = -1, d^M4_{i-1/2} = minmod(-16+3, -12+4, -4, -3) = -3.
+    # f^UL = 6 + 12 = 18, f^MD = 6 + 1/2 = 13/2, f^LC = 6 + 3/2 + (4/3)(-3) = 7/2.
+    # f^min = max(min(6, 6, 13/2), min(6, 18, 7/2)) = 6, f^max = min(13/2, 18) = 13/2:
+    # the result is f^MD.
+    ((-4, 3, 6, 6, -5), Fraction(13, 2)),
+    # (1, -3, -5, 0, 3): unlimited -203/60; f^MP = -5 + minmod(5, -8) = -5, limiter acts.
+    # d = (2, 7, -2): d^M4_{i+1/2} = minmod(30, -15, 7, -2) = 0 (mixed signs),
+    # d^M4_{i-1/2} = minmod(1, 26, 2, 7) = 1.  f^UL = -13, f^MD = -5/2, f^LC = -5 - 1 + 4/3 = -14/3.
+    # f^min = max(-5, -13) = -5, f^max = min(max(-5, 0, -5/2), max(-5, -13, -14/3)) = -14/3:
+    # the result is f^LC, through the 4/3 curvature term.
+    ((1, -3, -5, 0, 3), Fraction(-14, 3)),
+    # (6, 6, 5, -5, -2): unlimited 40/60 = 2/3; f^MP = 5 + minmod(-10, -4) = 1 and
+    # (2/3 - 5)(2/3 - 1) > 0, limiter acts.  d = (-1, -9, 13): both d^M4 are 0 (mixed signs).
+    # f^UL = 5 - 4 = 1, f^MD = 0, f^LC = 9/2; f^min = max(-5, 1) = 1, f^max = min(5, 5) = 5:
+    # the result is f^UL.
+    ((6, 6, 5, -5, -2), Fraction(1)),
+    # (-5, 1, 4, -2, -6): unlimited 129/60 = 43/20; f^MP = 4 + minmod(-6, 12) = 4, limiter acts.
+    # d = (-3, -9, 2): d^M4_{i+1/2} = 0, d^M4_{i-1/2} = minmod(-3, -33, -3, -9) = -3.
+    # f^UL = 16, f^MD = 1, f^LC = 4 + 3/2 - 4 = 3/2; f^min = max(-2, 3/2) = 3/2, f^max = min(4, 16) = 4:
+    # 43/20 lies inside [3/2, 4] and is kept (a wrong f^LC above 43/20 would move it).
+    ((-5, 1, 4, -2, -6), Fraction(43, 20)),
+]
+
+
+def check_mp5_limited(orc):
+    for f5, want in MP5_LIMITED:
+        got = orc.mp5(np.array(f5, dtype=float))
+        assert got == pytest.approx(float(want), rel=2e-16, abs=0), (f5, got, want)
+        # mirrored data (the right-state reconstruction reads the stencil reversed and
+        # negated values flip every bound): R(-F) = -R(F)
+        got_neg = orc.mp5(-np.array(f5, dtype=float))
+        assert got_neg == pytest.approx(-float(want), rel=2e-16, abs=0), (f5, got_neg)
+
+
+def test_mp5_limited_values(orc):
+    check_mp5_limited(orc)
