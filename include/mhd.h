@@ -228,6 +228,23 @@ int mhd_con2prim_learned(const mhd_patch_t* patch, const mhd_eos_t* eos, const f
                          uint8_t* flags, double* mu, int64_t* stats, void* workspace, size_t workspace_bytes,
                          void* stream);
 
+/* Allocation-free variant of mhd_con2prim_learned, for callers that cannot
+ * allocate device memory (code under stream or graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same kernels, arguments, outputs
+ * and results as mhd_con2prim_learned, without the workspace: the fallback
+ * queue is a file-scope device array of the library, 256 + 4 * 2^22 bytes
+ * (16 MiB) per device, held from the first call on a device until the process
+ * ends.  The padded patch must have at most 2^22 points (4 194 304; a 155^3
+ * padded patch fits), else MHD_EINVAL.  The call allocates nothing; its first
+ * call on a device looks up the array's address (MHD_EHIP if that fails) with
+ * that device current, and the stream must belong to the current device.
+ * Every call on a device shares that device's queue, whose count the call
+ * clears by a kernel on `stream` before use: calls that overlap on one device
+ * (different streams, or threads without ordering between their streams)
+ * race and give wrong answers. */
+int mhd_con2prim_learned_noalloc(const mhd_patch_t* patch, const mhd_eos_t* eos, const float* mlp, double* U,
+                                 double* P, uint8_t* flags, double* mu, int64_t* stats, void* stream);
+
 /* Training set-up and steps (device arrays, row-major):
  * mhd_mlp_features: X[N][8] raw features (float32) of every padded point in
  *   linear padded order (i fastest); points with D < rho_min get NaN rows.

@@ -54,6 +54,9 @@ int launch_mlp_adam(float* prm, const float* grad, float* m, float* v, int step,
                     float eps, hipStream_t s);
 int launch_con2prim_learned(const Geom& g, const mhd_eos_t& eos, const float* prm, double* U, double* P,
                             uint8_t* flags, double* mu, int64_t* stats, void* ws, hipStream_t s);
+int64_t noalloc_max_points();
+int launch_con2prim_learned_noalloc(const Geom& g, const mhd_eos_t& eos, const float* prm, double* U, double* P,
+                                    uint8_t* flags, double* mu, int64_t* stats, hipStream_t s);
 }  // namespace mhd
 
 namespace {
@@ -222,6 +225,21 @@ int mhd_con2prim_learned(const mhd_patch_t* patch, const mhd_eos_t* eos, const f
   return hip_check(mhd::launch_con2prim_learned(geom_of(patch), *eos, mlp, U, P, flags, mu, stats, workspace,
                                                 (hipStream_t)stream),
                    "mhd_con2prim_learned");
+}
+
+int mhd_con2prim_learned_noalloc(const mhd_patch_t* patch, const mhd_eos_t* eos, const float* mlp, double* U,
+                                 double* P, uint8_t* flags, double* mu, int64_t* stats, void* stream) {
+  int rc;
+  if ((rc = check_patch(patch, -1, 1, "mhd_con2prim_learned_noalloc")) ||
+      (rc = check_eos(eos, "mhd_con2prim_learned_noalloc")))
+    return rc;
+  if (!U || !P || !mlp) return fail(MHD_EINVAL, "mhd_con2prim_learned_noalloc: U, P and mlp must be non-NULL");
+  if (padded_points(patch) > mhd::noalloc_max_points())
+    return fail(MHD_EINVAL, "mhd_con2prim_learned_noalloc: the padded patch has %lld points, at most %lld allowed",
+                (long long)padded_points(patch), (long long)mhd::noalloc_max_points());
+  return hip_check(mhd::launch_con2prim_learned_noalloc(geom_of(patch), *eos, mlp, U, P, flags, mu, stats,
+                                                        (hipStream_t)stream),
+                   "mhd_con2prim_learned_noalloc");
 }
 
 int mhd_mlp_features(const mhd_patch_t* patch, const mhd_eos_t* eos, const double* U, const double* mu, float* X,

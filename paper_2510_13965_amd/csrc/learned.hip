@@ -26,6 +26,8 @@
 // kappa = 16 ks + 8 g + j (g = l/32) stands for hidden unit pi(kappa), the
 // unit the lane already holds in accumulator slot idx = 8 ks + j, and the
 // weight matrix is loaded with its columns permuted by pi.
+#include <mutex>
+
 #include "c2p_dev.hpp"
 #include "prof.hpp"
 
@@ -832,6 +834,53 @@ int launch_con2prim_learned(const Geom& g, const mhd_eos_t& eos, const float* pr
   MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback, dim3((unsigned)(fb_blocks < 2048 ? fb_blocks : 2048)), dim3(256), 0, s,
              a);
   return (int)hipGetLastError();
+}
+
+// ---------------------------------------------- allocation-free entry point
+// The fallback queue of mhd_con2prim_learned_noalloc lives in this file-scope
+// device array: a count word padded to 256 bytes, then one 4-byte slot per
+// padded point for patches of at most kNoAllocMaxPoints padded points
+// (16 MiB + 256 B per device, held until the process ends).  In host code the
+// array's name is not a device address: the address comes from
+// hipGetSymbolAddress, taken once per device with that device current, and
+// only that address is passed to kernels.  Every call on a device shares its
+// array; calls that overlap on one device race.
+constexpr int64_t kNoAllocMaxPoints = int64_t(1) << 22;
+static __device__ __align__(256) uint32_t scratch[64 + kNoAllocMaxPoints];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+int64_t noalloc_max_points() { return kNoAllocMaxPoints; }
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device).  Returns a hipError_t.
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return (int)e;
+  if (dev < 0 || dev >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return (int)e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return (int)hipSuccess;
+}
+
+int launch_con2prim_learned_noalloc(const Geom& g, const mhd_eos_t& eos, const float* prm, double* U, double* P,
+                                    uint8_t* flags, double* mu, int64_t* stats, hipStream_t s) {
+  void* ws = nullptr;
+  const int e = noalloc_scratch(&ws);
+  if (e != (int)hipSuccess) return e;
+  // same kernels as mhd_con2prim_learned; the first one clears the queue count
+  return launch_con2prim_learned(g, eos, prm, U, P, flags, mu, stats, ws, s);
 }
 
 int launch_con2prim_learned_level(const LevelArgs& L, int grid, int block, int grid_fb, hipStream_t s) {

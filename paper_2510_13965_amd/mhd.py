@@ -81,6 +81,8 @@ SIGNATURES = {
     "mhd_set_tuning": (C.c_int, [C.POINTER(Tuning)]),
     "mhd_get_tuning": (C.c_int, [C.POINTER(Tuning)]),
     "mhd_con2prim_learned_workspace_size": (C.c_size_t, [C.POINTER(Patch)]),
+    "mhd_con2prim_learned_noalloc": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
+                                               _vp]),
     "mhd_con2prim_learned": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp, _vp,
                                        C.c_size_t, _vp]),
     "mhd_mlp_features": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp]),
@@ -255,6 +257,11 @@ def con2prim_learned(patch, eos, mlp, U, P, workspace, flags=None, mu=None, stat
     nbytes = workspace.numel() * workspace.element_size()
     _check(lib().mhd_con2prim_learned(C.byref(patch), C.byref(eos), _ptr(mlp), _ptr(U), _ptr(P), _ptr(flags), _ptr(mu),
                                       _ptr(stats), _ptr(workspace), nbytes, _stream(stream)))
+
+
+def con2prim_learned_noalloc(patch, eos, mlp, U, P, flags=None, mu=None, stats=None, stream=None):
+    _check(lib().mhd_con2prim_learned_noalloc(C.byref(patch), C.byref(eos), _ptr(mlp), _ptr(U), _ptr(P), _ptr(flags),
+                                              _ptr(mu), _ptr(stats), _stream(stream)))
 
 
 def mlp_features(patch, eos, U, X, mu=None, T=None, stream=None):

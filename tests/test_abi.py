@@ -82,3 +82,18 @@ def test_argument_errors_before_device_work(lib):
                      None, C.c_void_p(8), 1 << 40, None)
     assert rc == -1 and b"aux" in lib.mhd_last_error()
     assert lib.mhd_rhs_workspace_size_m1(C.byref(p)) > lib.mhd_rhs_workspace_size(C.byref(p))
+
+
+def test_noalloc_con2prim_rejects_oversized_patch(lib):
+    """The allocation-free con2prim checks the patch against its fixed queue
+    (at most 2^22 padded points) before any device work."""
+    from paper_2510_13965_amd import mhd
+
+    e = mhd.make_eos(I.EOS_PWP3)
+    p = mhd.make_patch((156, 156, 156), (0.1, 0.1, 0.1), ng=3)   # 162^3 > 2^22 padded points
+    rc = lib.mhd_con2prim_learned_noalloc(C.byref(p), C.byref(e), C.c_void_p(8), C.c_void_p(8), C.c_void_p(8),
+                                          None, None, None, None)
+    assert rc == -1 and b"at most 4194304" in lib.mhd_last_error()
+    rc = lib.mhd_con2prim_learned_noalloc(C.byref(p), C.byref(e), None, C.c_void_p(8), C.c_void_p(8),
+                                          None, None, None, None)
+    assert rc == -1 and b"non-NULL" in lib.mhd_last_error()
