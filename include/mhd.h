@@ -189,7 +189,13 @@ int mhd_prim2con(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, doub
  * (U[22..27]) rewritten from the corrected primitives.
  * In/out: U.  Out: P (8 fields), flags (uint8 per padded point, may be NULL),
  *   mu (2 fields mu_+, mu with stride patch->sf, may be NULL),
- *   stats (MHD_NSTAT int64 device counters, accumulated, may be NULL). */
+ *   stats (MHD_NSTAT int64 device counters, accumulated, may be NULL).
+ * Returns MHD_OK or an error code, not the number of fatal points: a count
+ * returned to the host would need a device-to-host copy and a stream
+ * synchronisation on every call (no asynchronous steps, no graph capture).
+ * Points the paper treats as fatal (App. D: density above rho_max) get
+ * MHD_FLAG_FATAL and are counted in stats[MHD_STAT_FATAL]; the caller reads
+ * the counter when it decides to stop. */
 int mhd_con2prim(const mhd_patch_t* patch, const mhd_eos_t* eos, double* U, double* P,
                  uint8_t* flags, double* mu, int64_t* stats, void* stream);
 
@@ -389,9 +395,13 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
  * mhd_m1_implicit: at the interior points, per species, replaces the radiation
  *   fields V* of U by the solution V of V = V* + adt alpha (S_n, S_i)(V)
  *   (undensitized), the fluid state from P, the closure's Eddington factor
- *   frozen at its value for V*; Newton's method with the exact Jacobian to
- *   |dV| <= 1e-15 (E + |F|), at most 60 iterations; nfail (device uint64, may
- *   be NULL) is incremented per species solve that did not converge. */
+ *   frozen at its value for V*; Newton's method with the exact Jacobian, at
+ *   most 60 iterations, converged at |dV| <= 1e-15 (E + |F|) or once an update
+ *   no larger than 1e-9 (E + |F|) is not below half of the previous one (the
+ *   rounding floor: App. C leaves the stopping rule open).  A solve that does
+ *   not converge (singular Jacobian, or 60 iterations) keeps the first Newton
+ *   iterate, App. C's linearised implicit update about V*; nfail (device
+ *   uint64, may be NULL) is incremented per such species solve. */
 int mhd_rhs_split(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
                   const double* P, const double* aux, double* rhs, double* stiff, double* max_speed, void* workspace,
                   size_t workspace_bytes, void* stream);

@@ -484,8 +484,13 @@ static int solve4(double A[4][4], double b[4], double x[4]) {
  * radiation fields on input (densitized in U; the equations are solved
  * undensitized), the fluid state from P and the closure's Eddington factor
  * frozen at its value for V*.  Newton's method with a central-difference
- * Jacobian, to |dV| <= 1e-15 (E + |F|), at most 60 iterations.  Returns the
- * number of points that did not converge. */
+ * Jacobian, at most 60 iterations.  Converged when |dV| <= 1e-15 (E + |F|), or
+ * when an update no larger than 1e-9 (E + |F|) is not below half of the one
+ * before it: Newton has stopped contracting and rounding decides the last
+ * digits (App. C leaves the stopping rule open).  A solve that does not
+ * converge keeps the first Newton iterate, which is App. C's linearised
+ * implicit update about V' = V* (one solve with the Jacobian at V*).  Returns
+ * the number of solves that did not converge. */
 int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt) {
   const int ng = g->ng;
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
@@ -510,6 +515,8 @@ int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const dou
           Vs[0] = s0.E;
           for (a = 0; a < 3; ++a) Vs[1 + a] = s0.F[a];
           for (a = 0; a < 4; ++a) V[a] = Vs[a];
+          double prev = HUGE_VAL, V1[4];
+          for (a = 0; a < 4; ++a) V1[a] = Vs[a];
           for (it = 0; it < 60; ++it) {
             double G[4], Jm[4][4], dV[4], scale = fabs(V[0]) + fabs(V[1]) + fabs(V[2]) + fabs(V[3]), nrm = 0.0;
             implicit_residual(&s0, chi, V, Vs, adt, alp, ka, ks, eta, G);
@@ -528,15 +535,146 @@ int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const dou
               V[a] += dV[a];
               nrm += fabs(dV[a]);
             }
-            if (nrm <= 1e-15 * scale) {
+            if (it == 0)
+              for (a = 0; a < 4; ++a) V1[a] = V[a];
+            if (nrm <= 1e-15 * scale || (nrm <= 1e-9 * scale && nrm >= 0.5 * prev)) {
               ok = 1;
               break;
             }
+            prev = nrm;
           }
-          if (!ok) bad += 1;
+          if (!ok) {
+            bad += 1;
+            for (a = 0; a < 4; ++a) V[a] = V1[a];
+          }
           U[(32 + 4 * sp) * N + q] = m.sqrtg * V[0];
           for (a = 0; a < 3; ++a) U[(33 + 4 * sp + a) * N + q] = m.sqrtg * V[1 + a];
         }
       }
   return bad;
+}
+
+/* ---- neutrino number densities (Sec. 2.3; App. C) --------------------------
+ * Per species s the evolved field is Nbar = sqrt(gamma) N at U index 44 + s;
+ * the number absorption coefficient kappa0_a and emissivity eta0 sit at
+ * aux[(9 + 2 s) N + p] and aux[(10 + 2 s) N + p].  With J and H_i of the
+ * Minerbo closure at the point, the number current N^a = n (u^a + H^a/J)
+ * gives the d_k-flux
+ *   Fbar_N^k = (-W beta^k + alpha W v^k + alpha H^k/J) Nbar/Gamma,
+ *   Gamma = W (E - F_i v^i)/J,
+ * where H^k is the spatial component of the four-vector
+ * H^a = -(H^b n_b) n^a + gamma^a_b H^b, i.e. H^k = gamma^kj H_j + H_n beta^k/alpha
+ * with H_n = H^b n_b = W (J - E + F_i v^i) (the relations below the M1
+ * equations in Sec. 2.3);
+ * and the source alpha sqrt(gamma) C with C = eta0 - kappa0_a N/Gamma.  The
+ * electron fraction gains -alpha sqrt(gamma) m_b (C_0 - C_1) (species 0 the
+ * electron neutrino, 1 its antineutrino).
+ * Readings: H^k as above (with the spatial projection alone the shift term
+ * would not reduce to -beta^k Nbar); Nbar's interfaces take the HO/LO splitting of the energy moments
+ * (Sec. 3.4) with the species' point speed and its kappa_a + kappa_s in the
+ * opacity switch (the text gives one scheme for the radiation fields); the
+ * electron-fraction source stays explicit, as the fluid's energy and momentum
+ * exchange does. */
+void orc_m1n_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
+                 double* rhs, double* stiff) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+  const int64_t st[3] = {1, Nx, Nx * Ny};
+  double* FN = (double*)malloc(sizeof(double) * 3 * 3 * N);
+  double* LM = (double*)malloc(sizeof(double) * 3 * 3 * N);
+  double* GM = (double*)malloc(sizeof(double) * 3 * N);
+  int64_t p;
+
+#pragma omp parallel for schedule(static)
+  for (p = 0; p < N; ++p) {
+    m1_metric m;
+    int sp, d, j;
+    const double alp = U[18 * N + p];
+    m1_metric_at(U, N, p, &m);
+    for (sp = 0; sp < 3; ++sp) {
+      m1_state s;
+      double Pij[3][3], J, H[3], chi, Hu[3], gam;
+      const double Nb = U[(44 + sp) * N + p];
+      point_state(U, P, N, p, sp, &m, &s);
+      closure(&s, Pij, &J, H, &chi, NULL);
+      for (d = 0; d < 3; ++d) {
+        Hu[d] = s.W * (J - s.E + s.vF) * U[(19 + d) * N + p] / alp;
+        for (j = 0; j < 3; ++j) Hu[d] += m.gup[d][j] * H[j];
+      }
+      gam = s.W * (s.E - s.vF) / J;
+      GM[sp * N + p] = gam;
+      for (d = 0; d < 3; ++d) {
+        const double bd = U[(19 + d) * N + p];
+        FN[(sp * 3 + d) * N + p] = (-s.W * bd + alp * s.W * s.v[d] + alp * Hu[d] / J) * Nb / gam;
+        LM[(sp * 3 + d) * N + p] = speed(&s, chi, alp, bd, d);
+      }
+    }
+  }
+
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int64_t k = ng; k < Nz - ng; ++k)
+    for (int64_t j = ng; j < Ny - ng; ++j)
+      for (int64_t i = ng; i < Nx - ng; ++i) {
+        const int64_t q = i + Nx * (j + Ny * k);
+        const double alp = U[18 * N + q];
+        m1_metric m;
+        double C[3];
+        int sp, d;
+        m1_metric_at(U, N, q, &m);
+        for (sp = 0; sp < 3; ++sp) {
+          const double* u = U + (44 + sp) * N;
+          const double* kap = aux + (3 * sp) * N;
+          const double* kas = aux + (3 * sp + 1) * N;
+          const double k0 = aux[(9 + 2 * sp) * N + q], e0 = aux[(10 + 2 * sp) * N + q];
+          double out = 0.0;
+          for (d = 0; d < 3; ++d) {
+            const double* f = FN + (sp * 3 + d) * N;
+            const double* lam = LM + (sp * 3 + d) * N;
+            const double fr = holo(u, f, lam, kap, kas, q, st[d], g->dx[d]);
+            const double fl = holo(u, f, lam, kap, kas, q - st[d], st[d], g->dx[d]);
+            out -= (fr - fl) / g->dx[d];
+          }
+          C[sp] = e0 - k0 * (u[q] / m.sqrtg) / GM[sp * N + q];
+          if (stiff)
+            stiff[(12 + sp) * N + q] = alp * m.sqrtg * C[sp];
+          else
+            out += alp * m.sqrtg * C[sp];
+          rhs[(44 + sp) * N + q] = out;
+        }
+        rhs[23 * N + q] -= alp * m.sqrtg * par->m_b * (C[0] - C[1]);
+      }
+  free(FN);
+  free(LM);
+  free(GM);
+}
+
+/* After the stage's E and F_i are updated: per interior point and species,
+ * N = (N* + adt alpha eta0)/(1 + adt alpha kappa0_a/Gamma), with N* the number
+ * density on input (undensitized) and Gamma from the updated E, F_i and their
+ * closure (App. C). */
+void orc_m1n_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt) {
+  const int ng = g->ng;
+  const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
+  const int64_t N = npts(g);
+#pragma omp parallel for collapse(2) schedule(static)
+  for (int64_t k = ng; k < Nz - ng; ++k)
+    for (int64_t j = ng; j < Ny - ng; ++j)
+      for (int64_t i = ng; i < Nx - ng; ++i) {
+        const int64_t q = i + Nx * (j + Ny * k);
+        const double alp = U[18 * N + q];
+        m1_metric m;
+        int sp;
+        m1_metric_at(U, N, q, &m);
+        for (sp = 0; sp < 3; ++sp) {
+          m1_state s;
+          double Pij[3][3], J, H[3], chi, gam, Ns;
+          const double k0 = aux[(9 + 2 * sp) * N + q], e0 = aux[(10 + 2 * sp) * N + q];
+          point_state(U, P, N, q, sp, &m, &s);
+          closure(&s, Pij, &J, H, &chi, NULL);
+          gam = s.W * (s.E - s.vF) / J;
+          Ns = U[(44 + sp) * N + q] / m.sqrtg;
+          U[(44 + sp) * N + q] = m.sqrtg * (Ns + adt * alp * e0) / (1.0 + adt * alp * k0 / gam);
+        }
+      }
 }

@@ -96,6 +96,8 @@ typedef struct {
   int evolve_mhd;       /* GRMHD block on/off */
   int couple_matter;    /* matter terms in the CCZ4 block on/off */
   int evolve_m1;        /* M1 radiation (fields 32..43, aux kappa_a, kappa_s, eta) on/off */
+  int evolve_m1n;       /* with evolve_m1: neutrino number densities (fields 44..46, aux 9..14) on/off */
+  double m_b;           /* reference baryon mass of the electron-fraction source */
 } orc_par;
 
 /* ---- EoS (Sec. 2.2, hybrid piecewise polytrope + thermal ideal gas) ---- */
@@ -154,10 +156,19 @@ void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const do
 void orc_m1_rhs_split(const orc_grid* g, const orc_par* par, const double* U, const double* P,
                       const double* aux, double* rhs, double* stiff, double* max_speed);
 int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);
+/* neutrino number densities (Sec. 2.3): rhs[44..46] written (their collision
+ * sources to stiff[12..14] instead when stiff is non-NULL) and the
+ * electron-fraction source added to rhs[23]; U has 47 fields, aux 15 */
+void orc_m1n_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
+                 double* rhs, double* stiff);
+/* the analytic implicit number-density update of App. C, after E and F_i of
+ * the stage are updated */
+void orc_m1n_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);
 /* explicit part F (44 fields) and stiff radiation part R (12 fields) of L(U) */
 void orc_rhs_split(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
                    const double* aux, double* F, double* R, double* max_speed);
-/* one IMEX(4,4,2) step of Table I (44 fields, frozen ghosts); returns the number
+/* one IMEX(4,4,2) step of Table I (44 fields, 47 with the number densities, frozen
+ * ghosts); returns the number
  * of implicit point solves that did not converge */
 int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
                       double dt, int periodic);

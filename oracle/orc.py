@@ -31,7 +31,8 @@ class Par(C.Structure):
                 ("eta", C.c_double), ("beta0", C.c_double * 3), ("sigma_ko", C.c_double),
                 ("c_b", C.c_double), ("kappa_b", C.c_double), ("alpha_mp5", C.c_double),
                 ("f_beta", C.c_double), ("f_alpha_kind", C.c_int), ("evolve_st", C.c_int),
-                ("evolve_mhd", C.c_int), ("couple_matter", C.c_int), ("evolve_m1", C.c_int)]
+                ("evolve_mhd", C.c_int), ("couple_matter", C.c_int), ("evolve_m1", C.c_int),
+                ("evolve_m1n", C.c_int), ("m_b", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -117,6 +118,9 @@ def _bind(L):
         L.orc_m1_implicit.restype = C.c_int64
         L.orc_imex_step.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, C.c_double, C.c_int]
         L.orc_imex_step.restype = C.c_int64
+    if hasattr(L, "orc_m1n_rhs"):
+        L.orc_m1n_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), _dp, _dp, _dp, _dp, _dp]
+        L.orc_m1n_implicit.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_double]
     if hasattr(L, "orc_mlp_forward"):
         L.orc_bf16.argtypes = [C.c_float]
         L.orc_bf16.restype = C.c_float
@@ -179,6 +183,8 @@ def make_par(cfg):
     p.evolve_mhd = int(cfg["evolve_mhd"])
     p.couple_matter = int(cfg["couple_matter"])
     p.evolve_m1 = int(cfg.get("evolve_m1", 0))
+    p.evolve_m1n = int(cfg.get("evolve_m1n", 0))
+    p.m_b = float(cfg.get("m_b", 1.0))
     return p
 
 
@@ -404,6 +410,16 @@ def rhs_split(g, par, e, U, P, aux, F, R):
     lib().orc_rhs_split(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(P), ptr(aux), ptr(F), ptr(R),
                         C.byref(ms))
     return ms.value
+
+
+def m1n_rhs(g, par, U, P, aux, out, stiff=None):
+    """Number-density part of L(U) (47 fields, aux 15): out[44..46] written,
+    the electron-fraction source added to out[23]."""
+    lib().orc_m1n_rhs(C.byref(g), C.byref(par), ptr(U), ptr(P), ptr(aux), ptr(out), ptr(stiff))
+
+
+def m1n_implicit(g, U, P, aux, adt):
+    lib().orc_m1n_implicit(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt))
 
 
 def m1_implicit(g, U, P, aux, adt):

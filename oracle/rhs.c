@@ -61,6 +61,7 @@ void orc_rhs_full(const orc_grid* g, const orc_par* par, const orc_eos* e, const
                   const double* aux, double* rhs, double* max_speed) {
   orc_rhs(g, par, e, U, P, rhs, max_speed);
   if (par->evolve_m1) orc_m1_rhs(g, par, U, P, aux, rhs, max_speed);
+  if (par->evolve_m1 && par->evolve_m1n) orc_m1n_rhs(g, par, U, P, aux, rhs, NULL);
 }
 
 /* Explicit RK4 of Table I (c = 0, 1/2, 1/2, 1; b = 1/6, 1/3, 1/3, 1/6),
@@ -187,11 +188,12 @@ void orc_rhs_split(const orc_grid* g, const orc_par* par, const orc_eos* e, cons
                    const double* aux, double* F, double* R, double* max_speed) {
   orc_rhs(g, par, e, U, P, F, max_speed);
   orc_m1_rhs_split(g, par, U, P, aux, F, R, max_speed);
+  if (par->evolve_m1n) orc_m1n_rhs(g, par, U, P, aux, F, R);
 }
 
 int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
                       double dt, int periodic) {
-  const int ng = g->ng, nf = 44;
+  const int ng = g->ng, nf = par->evolve_m1n ? 47 : 44, nr = nf - 32;
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
   double* Un = (double*)malloc(sizeof(double) * nf * N);
@@ -204,7 +206,7 @@ int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, d
   memcpy(Un, U, sizeof(double) * nf * N);
   for (st = 0; st < 4; ++st) {
     F[st] = (double*)calloc(nf * N, sizeof(double));
-    R[st] = (double*)calloc(12 * N, sizeof(double));
+    R[st] = (double*)calloc(nr * N, sizeof(double));
   }
   for (st = 0; st < 4; ++st) {
     memcpy(Ui, Un, sizeof(double) * nf * N);
@@ -227,6 +229,7 @@ int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, d
     orc_con2prim(g, e, Ui, P, NULL, NULL);
     if (IM_AI[st][st] != 0.0) {
       bad += orc_m1_implicit(g, Ui, P, aux, IM_AI[st][st] * dt);
+      if (par->evolve_m1n) orc_m1n_implicit(g, Ui, P, aux, IM_AI[st][st] * dt);
       if (periodic) orc_fill_periodic(g, Ui, nf);
     }
     orc_rhs_split(g, par, e, Ui, P, aux, F[st], R[st], NULL);

@@ -8,7 +8,12 @@
 //                   the stage's primitives, the closure's Eddington factor
 //                   frozen at its value for V*; Newton's method with the exact
 //                   Jacobian (dual numbers), 4x4 elimination with partial
-//                   pivoting, to |dV| <= 1e-15 (E + |F|), at most 60 iterations
+//                   pivoting, at most 60 iterations; converged at
+//                   |dV| <= 1e-15 (E + |F|), or once an update no larger than
+//                   1e-9 (E + |F|) is not below half of the previous one
+//                   (Newton has stopped contracting: rounding floor); a solve
+//                   that does not converge keeps the first Newton iterate
+//                   (App. C's linearised implicit update about V*)
 #include "c2p_dev.hpp"
 #include "m1_dev.hpp"
 #include "prof.hpp"
@@ -193,6 +198,8 @@ __device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const do
     const double Vs[4] = {s0.E, s0.F[0], s0.F[1], s0.F[2]};
     double V[4] = {Vs[0], Vs[1], Vs[2], Vs[3]};
     bool ok = false;
+    double prev = HUGE_VAL;
+    double V1[4] = {Vs[0], Vs[1], Vs[2], Vs[3]};
 #pragma unroll 1
     for (int it = 0; it < 60; ++it) {
       const double scale = fabs(V[0]) + fabs(V[1]) + fabs(V[2]) + fabs(V[3]);
@@ -216,12 +223,22 @@ __device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const do
         V[r] += dV[r];
         nrm += fabs(dV[r]);
       }
-      if (nrm <= 1e-15 * scale) {
+      if (it == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) V1[r] = V[r];
+      }
+      // converged, or stopped contracting at the rounding floor
+      if (nrm <= 1e-15 * scale || (nrm <= 1e-9 * scale && nrm >= 0.5 * prev)) {
         ok = true;
         break;
       }
+      prev = nrm;
     }
-    if (!ok) ++bad;
+    if (!ok) {
+      ++bad;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) V[r] = V1[r];
+    }
     U[(int64_t)(32 + 4 * sp) * sf + q] = m.sqrtg * V[0];
 #pragma unroll
     for (int r = 0; r < 3; ++r) U[(int64_t)(33 + 4 * sp + r) * sf + q] = m.sqrtg * V[1 + r];

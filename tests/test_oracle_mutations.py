@@ -4,12 +4,15 @@ temporary directory, never over oracle/liborc.so), binds the copy and checks
 that at least one named pin fails on it.  The unmodified oracle passes the
 same pins in their own test files.
 
-The slips are the ones a reader of Sec. 2.1 (damping and gauge terms) and
-Sec. 3.3 (MP5 bounds) could make: kappa_z (2 - kappa_2) for (2 + kappa_2), a
-sign of eta, the 3/4 of the shift, the 2/3 K of the Ghat damping, a dropped
-Theta term, the 4/3 curvature weight of f^LC, the halves of f^MD, the alpha of
-f^UL, the arguments of d^M4 swapped, and the sign rule of the 4-argument
-minmod.
+The slips are the ones a reader of Sec. 2.1 (damping and gauge terms),
+Sec. 3.3 (MP5 bounds) and Sec. 2.3 / App. C (number densities) could make:
+kappa_z (2 - kappa_2) for (2 + kappa_2), a sign of eta, the 3/4 of the shift,
+the 2/3 K of the Ghat damping, a dropped Theta term, the 4/3 curvature weight
+of f^LC, the halves of f^MD, the alpha of f^UL, the arguments of d^M4 swapped,
+the sign rule of the 4-argument minmod; a sign in Gamma, the normal part of
+H^a dropped or flipped, the W on the shift, H^k without 1/J, the number
+source with Gamma multiplied or N densitized, the electron-fraction source's
+sign or baryon mass, and the lapse or emission of the implicit update.
 """
 import os
 import shutil
@@ -22,7 +25,10 @@ import pytest
 from oracle import build as obuild
 
 import test_oracle_gauge as G
+import test_oracle_m1n as NM
 import test_oracle_stencils as S
+
+NPINS = [NM.check_source_at_rest, NM.check_thick_limit, NM.check_thin_limit, NM.check_imex_relaxation]
 
 ORACLE_DIR = os.path.dirname(obuild.__file__)
 
@@ -62,6 +68,24 @@ MUTANTS = [
      "minmod4(4.0 * dm1 - d0, 4.0 * d0 - dm1, dm1, dp1)", [S.check_mp5_limited]),
     ("mp5 f^LC D-", "fd.c", "f0 + 0.5 * dminus + 4.0 / 3.0", "f0 + 0.5 * dplus + 4.0 / 3.0",
      [S.check_mp5_limited]),
+    ("N Gamma sign", "m1.c", "gam = s.W * (s.E - s.vF) / J;\n      GM[sp * N + p] = gam;",
+     "gam = s.W * (s.E + s.vF) / J;\n      GM[sp * N + p] = gam;", NPINS),
+    ("N four-vector H shift term sign", "m1.c", "Hu[d] = s.W * (J - s.E + s.vF) * U[(19 + d) * N + p] / alp;",
+     "Hu[d] = -s.W * (J - s.E + s.vF) * U[(19 + d) * N + p] / alp;", NPINS),
+    ("N H spatial projection only", "m1.c", "Hu[d] = s.W * (J - s.E + s.vF) * U[(19 + d) * N + p] / alp;",
+     "Hu[d] = 0.0;", NPINS),
+    ("N flux W on the shift", "m1.c", "(-s.W * bd + alp * s.W * s.v[d] + alp * Hu[d] / J)",
+     "(-bd + alp * s.W * s.v[d] + alp * Hu[d] / J)", NPINS),
+    ("N flux H over J", "m1.c", "(-s.W * bd + alp * s.W * s.v[d] + alp * Hu[d] / J)",
+     "(-s.W * bd + alp * s.W * s.v[d] + alp * Hu[d])", NPINS),
+    ("N source Gamma", "m1.c", "C[sp] = e0 - k0 * (u[q] / m.sqrtg) / GM[sp * N + q];",
+     "C[sp] = e0 - k0 * (u[q] / m.sqrtg) * GM[sp * N + q];", NPINS),
+    ("N source densitized N", "m1.c", "C[sp] = e0 - k0 * (u[q] / m.sqrtg) / GM[sp * N + q];",
+     "C[sp] = e0 - k0 * u[q] / GM[sp * N + q];", NPINS),
+    ("Ye source sign", "m1.c", "par->m_b * (C[0] - C[1])", "par->m_b * (C[1] - C[0])", NPINS),
+    ("Ye source m_b dropped", "m1.c", "par->m_b * (C[0] - C[1])", "(C[0] - C[1])", NPINS),
+    ("N implicit lapse", "m1.c", "(1.0 + adt * alp * k0 / gam)", "(1.0 + adt * k0 / gam)", NPINS),
+    ("N implicit emission", "m1.c", "(Ns + adt * alp * e0)", "(Ns + adt * e0)", NPINS),
 ]
 
 
