@@ -145,9 +145,11 @@ static void atmosphere(const orc_eos* e, double prim[8]) {
   prim[7] = e->ye_atm;
 }
 
-unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3],
-                       const double gdn[6], const double gup[6], double alpha,
-                       double prim[8], double mu_out[2], int* iters) {
+/* steps 1-4 and the error policy; with mu_fixed != NULL, steps 2 and 3 are
+ * skipped and the primitives are those at mu = *mu_fixed */
+static unsigned c2p_point_impl(const orc_eos* e, const double cons[6], const double B[3],
+                               const double gdn[6], const double gup[6], double alpha,
+                               const double* mu_fixed, double prim[8], double mu_out[2], int* iters) {
   c2p_ctx c;
   c2p_state s;
   double r_dn[3], r_up[3], cB[3], cB_dn[3];
@@ -182,16 +184,21 @@ unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3]
   c.B2rp2 = fmax(0.0, c.B2 * c.r2 - c.rB * c.rB);
   c.v02 = c.r2 / (c.h0 * c.h0 + c.r2);
 
-  /* step 2: mu_+ in (0, 1/h0] */
-  fa_hi = f_a(&c, 1.0 / c.h0);
-  if (fa_hi <= 0.0) mup = 1.0 / c.h0;
-  else mup = brent(f_a, &c, 0.0, 1.0 / c.h0, -1.0, fa_hi, 200, &it1, &ok1);
+  if (mu_fixed) {
+    mup = 0.0;
+    mu = *mu_fixed;
+  } else {
+    /* step 2: mu_+ in (0, 1/h0] */
+    fa_hi = f_a(&c, 1.0 / c.h0);
+    if (fa_hi <= 0.0) mup = 1.0 / c.h0;
+    else mup = brent(f_a, &c, 0.0, 1.0 / c.h0, -1.0, fa_hi, 200, &it1, &ok1);
 
-  /* step 3: mu in (0, mu_+] */
-  f_lo = f_main(&c, 0.0);
-  f_hi = f_main(&c, mup);
-  if (f_hi <= 0.0) mu = mup;
-  else mu = brent(f_main, &c, 0.0, mup, f_lo, f_hi, 200, &it2, &ok2);
+    /* step 3: mu in (0, mu_+] */
+    f_lo = f_main(&c, 0.0);
+    f_hi = f_main(&c, mup);
+    if (f_hi <= 0.0) mu = mup;
+    else mu = brent(f_main, &c, 0.0, mup, f_lo, f_hi, 200, &it2, &ok2);
+  }
   if (!(ok1 && ok2)) flags |= ORC_F_NOT_CONVERGED;
   if (iters) *iters = it1 + it2;
   if (mu_out) { mu_out[0] = mup; mu_out[1] = mu; }
@@ -255,6 +262,12 @@ unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3]
   prim[6] = W;
   prim[7] = ye;
   return flags;
+}
+
+unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3],
+                       const double gdn[6], const double gup[6], double alpha,
+                       double prim[8], double mu_out[2], int* iters) {
+  return c2p_point_impl(e, cons, B, gdn, gup, alpha, NULL, prim, mu_out, iters);
 }
 
 /* ---------- grid-level drivers ---------- */
@@ -355,6 +368,26 @@ int64_t orc_con2prim(const orc_grid* g, const orc_eos* e, double* U, double* P,
   }
   ORC_PHASE(ORC_PH_OTHER);
   return nfatal;
+}
+
+/* Primitives (step 4 and the error policy) at a given mu per padded point,
+ * mu[N] (undensitizing as orc_con2prim; U is not written).  For the tests'
+ * condition estimates: how far the primitives move when mu moves. */
+void orc_c2p_prims_at(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,
+                      double* P, uint8_t* flags) {
+  int64_t N = npts(g), p;
+#pragma omp parallel for schedule(static)
+  for (p = 0; p < N; ++p) {
+    double gdn[6], gup[6], sg, cons[6], B[3], prim[8], m = mu[p];
+    unsigned f;
+    int i;
+    metric_at(U, p, N, gdn, gup, &sg);
+    for (i = 0; i < 6; ++i) cons[i] = U[(22 + i) * N + p] / sg;
+    for (i = 0; i < 3; ++i) B[i] = U[(28 + i) * N + p] / sg;
+    f = c2p_point_impl(e, cons, B, gdn, gup, U[18 * N + p], &m, prim, NULL, NULL);
+    for (i = 0; i < 8; ++i) P[i * N + p] = prim[i];
+    if (flags) flags[p] = (uint8_t)f;
+  }
 }
 
 void orc_c2p_features(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,

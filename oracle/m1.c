@@ -445,6 +445,105 @@ static void implicit_residual(const m1_state* s0, double chi, const double V[4],
   for (a = 0; a < 3; ++a) G[1 + a] = V[1 + a] - Vs[1 + a] - adt * alp * Si[a];
 }
 
+/* dG/dV = I - adt calJ with calJ = d(alpha (S_n, S_i))/d(E, F_j) as App. C
+ * prints it: J and H_i of the Minerbo closure with the Eddington factor chi
+ * frozen, written as functions of (E, F_i), and their derivatives
+ *   dJ/dE     = W^2 + d_thin (v.fh)^2 W^2 + d_thick (3 - 2W^2)(W^2 - 1)/(1 + 2W^2)
+ *   dJ/dF_j   = 2W^2 (-1 + d_thin E (v.fh)/F + 2 d_thick (W^2-1)/(1+2W^2)) v^j
+ *               - 2 d_thin W^2 E (v.fh)^2 / F fh^j
+ *   dH_i/dE   = W^3 (-1 - d_thin (v.fh)^2 + d_thick (2W^2-3)/(1+2W^2)) v_i
+ *               - d_thin W (v.fh) fh_i
+ *   dH_i/dF_j = W (1 - d_thin E (v.fh)/F - d_thick v^2) delta_i^j
+ *               + 2W^3 [1 - d_thin E (v.fh)/F - d_thick (v^2 + 1/(2W^2 (1+2W^2)))] v_i v^j
+ *               + 2 d_thin W E (v.fh)/F fh_i fh^j + 2 d_thin W^3 E (v.fh)^2/F v_i fh^j
+ *               - d_thin W E/F fh_i v^j
+ * with F = sqrt(F_k F^k), fh_i = F_i/F, kappa_as = kappa_a + kappa_s, and
+ *   calJ_00 = -alpha W (kappa_as - kappa_s dJ/dE)
+ *   calJ_0j = alpha W (kappa_s dJ/dF_j + kappa_as v^j)
+ *   calJ_i0 = -alpha (kappa_as dH_i/dE + W kappa_a dJ/dE v_i)
+ *   calJ_ij = -alpha (kappa_as dH_i/dF_j + W kappa_a v_i dJ/dF_j).
+ * Where F_k F^k = 0 the thin terms with fh are dropped (the closure drops
+ * P^thin there). */
+static void implicit_jacobian(const m1_state* s, double chi, double adt, double alp, double ka, double ks,
+                              double Jm[4][4]) {
+  const double W = s->W, W2 = W * W, W3 = W2 * W;
+  const double dthick = 1.5 * (1.0 - chi), dthin = 1.0 - dthick;
+  const double kas = ka + ks;
+  const double F = sqrt(s->F2);
+  double fh[3] = {0.0, 0.0, 0.0}, fhu[3] = {0.0, 0.0, 0.0}, vfh = 0.0, v2 = 0.0;
+  double dJdE, dJdF[3], dHdE[3], dHdF[3][3], cal[4][4];
+  int i, j;
+  for (i = 0; i < 3; ++i) v2 += s->v[i] * s->vd[i];
+  if (F > 0.0) {
+    for (i = 0; i < 3; ++i) {
+      fh[i] = s->F[i] / F;
+      fhu[i] = s->Fu[i] / F;
+    }
+    vfh = s->vF / F;
+  }
+  {
+    const double tE = F > 0.0 ? s->E * vfh / F : 0.0;       /* E (v.fh)/F */
+    const double tE2 = F > 0.0 ? s->E * vfh * vfh / F : 0.0; /* E (v.fh)^2/F */
+    const double tE0 = F > 0.0 ? s->E / F : 0.0;             /* E/F */
+    dJdE = W2 + dthin * vfh * vfh * W2 + dthick * (3.0 - 2.0 * W2) * (W2 - 1.0) / (1.0 + 2.0 * W2);
+    for (j = 0; j < 3; ++j)
+      dJdF[j] = 2.0 * W2 * (-1.0 + dthin * tE + 2.0 * dthick * (W2 - 1.0) / (1.0 + 2.0 * W2)) * s->v[j] -
+                2.0 * dthin * W2 * tE2 * fhu[j];
+    for (i = 0; i < 3; ++i)
+      dHdE[i] = W3 * (-1.0 - dthin * vfh * vfh + dthick * (2.0 * W2 - 3.0) / (1.0 + 2.0 * W2)) * s->vd[i] -
+                dthin * W * vfh * fh[i];
+    for (i = 0; i < 3; ++i)
+      for (j = 0; j < 3; ++j)
+        dHdF[i][j] = W * (1.0 - dthin * tE - dthick * v2) * (i == j ? 1.0 : 0.0) +
+                     2.0 * W3 * (1.0 - dthin * tE - dthick * (v2 + 1.0 / (2.0 * W2 * (1.0 + 2.0 * W2)))) *
+                         s->vd[i] * s->v[j] +
+                     2.0 * dthin * W * tE * fh[i] * fhu[j] + 2.0 * dthin * W3 * tE2 * s->vd[i] * fhu[j] -
+                     dthin * W * tE0 * fh[i] * s->v[j];
+  }
+  cal[0][0] = -alp * W * (kas - ks * dJdE);
+  for (j = 0; j < 3; ++j) cal[0][1 + j] = alp * W * (ks * dJdF[j] + kas * s->v[j]);
+  for (i = 0; i < 3; ++i) {
+    cal[1 + i][0] = -alp * (kas * dHdE[i] + W * ka * dJdE * s->vd[i]);
+    for (j = 0; j < 3; ++j) cal[1 + i][1 + j] = -alp * (kas * dHdF[i][j] + W * ka * s->vd[i] * dJdF[j]);
+  }
+  for (i = 0; i < 4; ++i)
+    for (j = 0; j < 4; ++j) Jm[i][j] = (i == j ? 1.0 : 0.0) - adt * cal[i][j];
+}
+
+/* Residual and App. C Jacobian of the implicit M1 equation at one point, for
+ * the pins: metric gdn (6 components xx,xy,xz,yy,yz,zz), fluid v^i and W, the
+ * trial V = (E, F_i) and V*, the frozen Eddington factor chi. */
+void orc_m1_implicit_point(const double gd6[6], const double v[3], double W, const double V[4], const double Vs[4],
+                           double chi, double adt, double alp, double ka, double ks, double eta, double G[4],
+                           double Jac[16]) {
+  double gdn[3][3], gup[3][3], det, Jm[4][4];
+  m1_state s;
+  int i, j;
+  for (i = 0; i < 3; ++i)
+    for (j = 0; j < 3; ++j) gdn[i][j] = gd6[S6m[i][j]];
+  det = gdn[0][0] * (gdn[1][1] * gdn[2][2] - gdn[1][2] * gdn[2][1]) -
+        gdn[0][1] * (gdn[1][0] * gdn[2][2] - gdn[1][2] * gdn[2][0]) +
+        gdn[0][2] * (gdn[1][0] * gdn[2][1] - gdn[1][1] * gdn[2][0]);
+  gup[0][0] = (gdn[1][1] * gdn[2][2] - gdn[1][2] * gdn[2][1]) / det;
+  gup[0][1] = (gdn[0][2] * gdn[2][1] - gdn[0][1] * gdn[2][2]) / det;
+  gup[0][2] = (gdn[0][1] * gdn[1][2] - gdn[0][2] * gdn[1][1]) / det;
+  gup[1][1] = (gdn[0][0] * gdn[2][2] - gdn[0][2] * gdn[2][0]) / det;
+  gup[1][2] = (gdn[0][2] * gdn[1][0] - gdn[0][0] * gdn[1][2]) / det;
+  gup[2][2] = (gdn[0][0] * gdn[1][1] - gdn[0][1] * gdn[1][0]) / det;
+  gup[1][0] = gup[0][1];
+  gup[2][0] = gup[0][2];
+  gup[2][1] = gup[1][2];
+  {
+    m1_state s0;
+    state_init(&s0, Vs[0], Vs + 1, v, W, gdn, gup);
+    implicit_residual(&s0, chi, V, Vs, adt, alp, ka, ks, eta, G);
+  }
+  state_init(&s, V[0], V + 1, v, W, gdn, gup);
+  implicit_jacobian(&s, chi, adt, alp, ka, ks, Jm);
+  for (i = 0; i < 4; ++i)
+    for (j = 0; j < 4; ++j) Jac[4 * i + j] = Jm[i][j];
+}
+
 /* solve the 4x4 system A x = b by Gaussian elimination with partial pivoting */
 static int solve4(double A[4][4], double b[4], double x[4]) {
   int i, j, k;
@@ -483,8 +582,8 @@ static int solve4(double A[4][4], double b[4], double x[4]) {
  * species, V = (E, F_i) solves V = V* + adt alpha (S_n, S_i)(V) with V* the
  * radiation fields on input (densitized in U; the equations are solved
  * undensitized), the fluid state from P and the closure's Eddington factor
- * frozen at its value for V*.  Newton's method with a central-difference
- * Jacobian, at most 60 iterations.  Converged when |dV| <= 1e-15 (E + |F|), or
+ * frozen at its value for V*.  Newton's method with App. C's Jacobian
+ * (implicit_jacobian), at most 60 iterations.  Converged when |dV| <= 1e-15 (E + |F|), or
  * when an update no larger than 1e-9 (E + |F|) is not below half of the one
  * before it: Newton has stopped contracting and rounding decides the last
  * digits (App. C leaves the stopping rule open).  A solve that does not
@@ -509,7 +608,7 @@ int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const dou
           const double ka = aux[(3 * sp) * N + q], ks = aux[(3 * sp + 1) * N + q], eta = aux[(3 * sp + 2) * N + q];
           m1_state s0;
           double Pij[3][3], J, H[3], chi, Vs[4], V[4];
-          int it, a, c, ok = 0;
+          int it, a, ok = 0;
           point_state(U, P, N, q, sp, &m, &s0);
           closure(&s0, Pij, &J, H, &chi, NULL);
           Vs[0] = s0.E;
@@ -520,14 +619,10 @@ int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const dou
           for (it = 0; it < 60; ++it) {
             double G[4], Jm[4][4], dV[4], scale = fabs(V[0]) + fabs(V[1]) + fabs(V[2]) + fabs(V[3]), nrm = 0.0;
             implicit_residual(&s0, chi, V, Vs, adt, alp, ka, ks, eta, G);
-            for (c = 0; c < 4; ++c) {
-              double Vp[4], Vm[4], Gp[4], Gm[4], h = 1e-6 * scale;
-              for (a = 0; a < 4; ++a) Vp[a] = Vm[a] = V[a];
-              Vp[c] += h;
-              Vm[c] -= h;
-              implicit_residual(&s0, chi, Vp, Vs, adt, alp, ka, ks, eta, Gp);
-              implicit_residual(&s0, chi, Vm, Vs, adt, alp, ka, ks, eta, Gm);
-              for (a = 0; a < 4; ++a) Jm[a][c] = (Gp[a] - Gm[a]) / (2.0 * h);
+            {
+              m1_state sv;
+              state_init(&sv, V[0], V + 1, s0.v, s0.W, s0.gdn, s0.gup);
+              implicit_jacobian(&sv, chi, adt, alp, ka, ks, Jm);
             }
             for (a = 0; a < 4; ++a) G[a] = -G[a];
             if (!solve4(Jm, G, dV)) break;

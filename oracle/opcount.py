@@ -18,7 +18,12 @@ from one evaluation with three grey species on the same star (M1 point work
 per padded point; M1 update per interior point, without the oracle's second
 closure evaluation at the point, which the algorithmic count takes once).
 
-Usage: python oracle/opcount.py [--n 128]
+With --level-m1 N the counts are taken instead on the seeded 16-box subset
+(inputs.level_subset) of the N-box level with three grey M1 species (the
+headline level workload), summed over its boxes: every per-unit figure
+above, over the boxes' own interior and padded points.
+
+Usage: python oracle/opcount.py [--n 128] [--level-m1 803]
 """
 import argparse
 import ctypes as C
@@ -75,7 +80,11 @@ def build(outdir):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--level-m1", type=int, default=0, help="count on the 16-box subset of this level instead")
     args = ap.parse_args()
+    if args.level_m1:
+        level_m1(args.level_m1)
+        return
     from oracle import orc
     from paper_2510_13965_amd import inputs as I
 
@@ -161,6 +170,79 @@ def main():
     diag = {c: round(float(v), 2) for c, v in zip(CATS, row)}
     diag["flop"] = round(float(row[:5].sum()), 2)
     out["per_interior_point"]["constraint_monitors"] = diag
+    print(json.dumps(out, indent=1))
+
+
+def level_m1(nboxes):
+    from oracle import orc
+    from paper_2510_13965_amd import inputs as I
+
+    boxes = I.amr_level_boxes(seed=I.SEED0 + 5, nboxes=nboxes)
+    sub = I.level_subset(nboxes)
+    Ab = I.star_field_amplitude()
+    tot = np.zeros((len(PHASES), 7))
+    nint = npad = 0
+    iface_w = np.zeros(7)  # interface work of MHD and M1, weighted per box by (n+1)/(2n) per axis
+    with tempfile.TemporaryDirectory() as td:
+        so = build(td)
+        orc.use_library(so)
+        orc.set_threads(1)
+        L = C.CDLL(so)
+        buf = (C.c_longlong * (NROW * 7))()
+
+        def take():
+            L.orc_opc_read(buf)
+            L.orc_opc_reset()
+            return np.array(list(buf), dtype=np.float64).reshape(NROW, 7)[:len(PHASES)]
+
+        e = orc.make_eos(I.EOS_IDEAL2)
+        par = orc.make_par(dict(I.PARAMS, evolve_m1=1))
+        rec = {"mhd_recon": np.zeros(7), "m1_holo": np.zeros(7)}
+        for b in sub:
+            ip, U, P, EM = I.amr_box_state(boxes[b], Ab)
+            R, aux = I.m1_radiation(ip, P, I.SEED0 + 500 + b)
+            g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+            orc.prim2con(g, e, U, P, EM, 0)
+            U44 = np.concatenate([U, R])
+            L.orc_opc_reset()
+            Pr = np.zeros_like(P)
+            orc.con2prim(g, e, U44, Pr, None, None)
+            k = np.zeros_like(U44)
+            orc.rhs_full(g, par, e, U44, Pr, aux, k)
+            acc = np.zeros_like(U44)
+            Us = U44.copy()
+            for st in range(4):
+                orc.rk4_stage_interior(g, I.NU_M1, st, 0.0625, U44, k, acc, Us if st < 3 else U44.copy())
+            c = take()
+            # interfaces are counted twice by the oracle; the algorithmic count takes
+            # each once: (n+1)/(2n) of the counted work per axis line, the mean over axes
+            fac = np.mean([(n + 1) / (2.0 * n) for n in ip.n])
+            for ph in rec:
+                rec[ph] += c[PHASES.index(ph)] * fac
+            tot += c
+            nint += ip.ninterior
+            npad += ip.npts
+            print("box %d %s counted" % (b, ip.n), file=sys.stderr, flush=True)
+
+    def per(ph, unit, extra=None):
+        row = tot[PHASES.index(ph)] / unit
+        if extra is not None:
+            row = row + extra / unit
+        d = {c: round(float(v), 2) for c, v in zip(CATS, row)}
+        d["flop"] = round(float(row[:5].sum()), 2)
+        return d
+
+    out = {
+        "workload": "16-box seeded subset of the %d-box level with three grey M1 species (44 fields), one "
+                    "evaluation of each step per box, summed" % nboxes,
+        "boxes": sub, "interior_points": nint, "padded_points": npad,
+        "per_padded_point": {"con2prim": per("con2prim", npad), "mhd_point_3axes": per("mhd_point", npad),
+                             "m1_point_3species_3axes": per("m1_point", npad)},
+        "per_interior_point": {"ccz4": per("ccz4", nint), "mhd_update_algorithmic": per("mhd_update", nint,
+                                                                                       rec["mhd_recon"]),
+                               "m1_update_algorithmic": per("m1_update", nint, rec["m1_holo"])},
+        "per_interior_point_and_field": {"rk_stage": per("rk", nint * I.NU_M1 * 4)},
+    }
     print(json.dumps(out, indent=1))
 
 

@@ -126,6 +126,10 @@ int64_t orc_con2prim(const orc_grid* g, const orc_eos* e, double* U, double* P,
 unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3],
                        const double gdn[6], const double gup[6], double alpha,
                        double prim[8], double mu[2], int* iters);
+/* primitives and error-policy flags at a given mu[N] per padded point (no
+ * root solve; U is only read) */
+void orc_c2p_prims_at(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,
+                      double* P, uint8_t* flags);
 
 /* ---- learned con2prim starting guess (MLP 8 -> 64 -> 64 -> 2) ---- */
 #define ORC_MLP_NPARAM 4866
@@ -155,7 +159,14 @@ void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const do
                 double* rhs, double* max_speed);
 void orc_m1_rhs_split(const orc_grid* g, const orc_par* par, const double* U, const double* P,
                       const double* aux, double* rhs, double* stiff, double* max_speed);
+/* threads of the oracle's OpenMP loops (timing) */
+void orc_set_threads(int n);
 int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);
+/* residual G and App. C Jacobian dG/dV (row-major 4x4) of the implicit M1
+ * equation of one species at one point (undensitized; gd6 the physical metric) */
+void orc_m1_implicit_point(const double gd6[6], const double v[3], double W, const double V[4], const double Vs[4],
+                           double chi, double adt, double alp, double ka, double ks, double eta, double G[4],
+                           double Jac[16]);
 /* neutrino number densities (Sec. 2.3): rhs[44..46] written (their collision
  * sources to stiff[12..14] instead when stiff is non-NULL) and the
  * electron-fraction source added to rhs[23]; U has 47 fields, aux 15 */
@@ -172,6 +183,12 @@ void orc_rhs_split(const orc_grid* g, const orc_par* par, const orc_eos* e, cons
  * of implicit point solves that did not converge */
 int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
                       double dt, int periodic);
+/* the same for scheme 0 (IMEX(4,4,2)) or 1 (IMEX(3,3,2): SSP-RK(3,3) with the
+ * re-derived L-stable I32L); orc_imex_tableau returns a scheme's tableaux
+ * (4x4 row-major, stages in *stages) */
+int64_t orc_imex_step_scheme(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
+                             double dt, int periodic, int scheme);
+void orc_imex_tableau(int scheme, double AE[16], double AI[16], double BE[4], double BI[4], int* stages);
 /* orc_rhs plus, if par->evolve_m1, the M1 part (U has 44 fields) */
 void orc_rhs_full(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
                   const double* aux, double* rhs, double* max_speed);

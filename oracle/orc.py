@@ -82,6 +82,17 @@ def _bind(L):
     L.orc_prim2con.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp, C.c_int]
     L.orc_con2prim.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _u8p, _dp]
     L.orc_con2prim.restype = C.c_int64
+    L.orc_imex_step_scheme.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, C.c_double,
+                                       C.c_int, C.c_int]
+    L.orc_imex_step_scheme.restype = C.c_int64
+    L.orc_imex_tableau.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
+    L.orc_imex_tableau.restype = None
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_set_threads.restype = None
+    L.orc_m1_implicit_point.argtypes = [_dp, _dp, C.c_double, _dp, _dp] + [C.c_double] * 6 + [_dp, _dp]
+    L.orc_m1_implicit_point.restype = None
+    L.orc_c2p_prims_at.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp, _u8p]
+    L.orc_c2p_prims_at.restype = None
     L.orc_c2p_point.argtypes = [C.POINTER(Eos), _dp, _dp, _dp, _dp, C.c_double, _dp, _dp,
                                 C.POINTER(C.c_int)]
     L.orc_c2p_point.restype = C.c_uint
@@ -275,6 +286,12 @@ def constraints(g, U):
     return out, sums
 
 
+def c2p_prims_at(g, e, U, mu, P, flags=None):
+    """Primitives and flags at the given mu (one value per padded point)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    lib().orc_c2p_prims_at(C.byref(g), C.byref(e), ptr(U), ptr(mu), ptr(P), ptr(flags))
+
+
 def c2p_point(e, cons, B, gdn, gup, alpha):
     cons = np.ascontiguousarray(cons, dtype=np.float64)
     B = np.ascontiguousarray(B, dtype=np.float64)
@@ -422,12 +439,36 @@ def m1n_implicit(g, U, P, aux, adt):
     lib().orc_m1n_implicit(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt))
 
 
+def set_threads(n):
+    """Threads of the oracle's parallel loops (for timing on n cores)."""
+    lib().orc_set_threads(int(n))
+
+
+def m1_implicit_point(gd6, v, W, V, Vs, chi, adt, alp, ka, ks, eta):
+    """(G, dG/dV) of the implicit M1 equation at one point (App. C Jacobian)."""
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (gd6, v, V, Vs)]
+    G = np.zeros(4)
+    Jac = np.zeros(16)
+    lib().orc_m1_implicit_point(ptr(a[0]), ptr(a[1]), float(W), ptr(a[2]), ptr(a[3]), float(chi), float(adt),
+                                float(alp), float(ka), float(ks), float(eta), ptr(G), ptr(Jac))
+    return G, Jac.reshape(4, 4)
+
+
 def m1_implicit(g, U, P, aux, adt):
     return int(lib().orc_m1_implicit(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt)))
 
 
-def imex_step(g, par, e, U, aux, dt, periodic=False):
-    """One IMEX(4,4,2) step in place on U (44 fields); returns the count of
-    implicit solves that did not converge."""
-    return int(lib().orc_imex_step(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(aux), float(dt),
-                                   int(bool(periodic))))
+def imex_step(g, par, e, U, aux, dt, periodic=False, scheme=0):
+    """One IMEX step in place on U (44 or 47 fields): scheme 0 IMEX(4,4,2),
+    1 IMEX(3,3,2); returns the count of implicit solves that did not converge."""
+    return int(lib().orc_imex_step_scheme(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(aux), float(dt),
+                                          int(bool(periodic)), int(scheme)))
+
+
+def imex_tableau(scheme):
+    """(AE, AI, BE, BI) of an IMEX scheme as numpy arrays (stages x stages)."""
+    AE, AI, BE, BI = np.zeros(16), np.zeros(16), np.zeros(4), np.zeros(4)
+    ns = C.c_int(0)
+    lib().orc_imex_tableau(int(scheme), ptr(AE), ptr(AI), ptr(BE), ptr(BI), C.byref(ns))
+    n = ns.value
+    return AE.reshape(4, 4)[:n, :n], AI.reshape(4, 4)[:n, :n], BE[:n], BI[:n]

@@ -7,6 +7,18 @@
 #include <stdlib.h>
 #include <string.h>
 #include "orc.h"
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* threads of the oracle's parallel loops (for timing it on a given core count) */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
 
 void orc_ccz4_point(const orc_par* par, const double* U, const double* P, int64_t N,
                     int64_t p, const int64_t st[3], const double h[3], double out[22]);
@@ -191,11 +203,83 @@ void orc_rhs_split(const orc_grid* g, const orc_par* par, const orc_eos* e, cons
   if (par->evolve_m1n) orc_m1n_rhs(g, par, U, P, aux, F, R);
 }
 
-int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
-                      double dt, int periodic) {
+/* ---------------------------------------------------------------- IMEX(3,3,2)
+ * Table II pairs the explicit SSP-RK(3,3) of Shu and Osher (c = (0, 1, 1/2),
+ * A = ((0), (1), (1/4, 1/4)), b = (1/6, 1/6, 2/3)) with an L-stable implicit
+ * I32L.  As printed, the implicit rows sum to (0, 1, 1) while its c column is
+ * (0, 1, 1/2); with c the row sums (Sec. 3.1 defines c that way) the
+ * printed tableau fails the second-order condition sum_i b_i c_i = 1/2
+ * (it gives 5/6).  The tableau used here is re-derived from Sec. 3.1's
+ * conditions keeping the printed structure: an explicit first stage (first
+ * row 0), the printed c = (0, 1, 1/2) (equal to the explicit c, so every
+ * coupling condition of order 2 holds with b equal to the explicit b) and the
+ * printed b = (1/6, 1/6, 2/3).  Rows 2 and 3 then sum to 1 and 1/2, and
+ * the stability function R(z) = 1 + z b^T (I - z A)^{-1} 1 is a cubic over
+ * 6 (1 - a22 z)(1 - a33 z); L-stability (R bounded and R -> 0 as z -> -inf)
+ * makes its z^3 and z^2 coefficients vanish:
+ *   6 a22 a33 - 2 a22 + 4 a32 - a33 = 0,   (1 - a22)(1 - a33) = 1/2.
+ * With equal diagonal entries a22 = a33 = gamma, gamma = 1 - 1/sqrt(2) (the
+ * root in (0, 1)), a32 = 3 gamma (1 - 2 gamma)/4, a31 = 1/2 - gamma - a32,
+ * a21 = 1 - gamma; then R(z) = (1 + (1 - 2 gamma) z)/(1 - gamma z)^2 and
+ * |R(iy)|^2 <= 1 (A-stable).  (The printed second row (1/2, 1/2) admits no
+ * L-stable completion: with a22 = 1/2 the second condition forces a33 = 0.) */
+static void imex332_tableau(double AE[4][4], double AI[4][4], double BE[4], double BI[4]) {
+  const double gam = 1.0 - sqrt(0.5);
+  const double a32 = 3.0 * gam * (1.0 - 2.0 * gam) / 4.0;
+  int i, j;
+  for (i = 0; i < 4; ++i) {
+    BE[i] = BI[i] = 0.0;
+    for (j = 0; j < 4; ++j) AE[i][j] = AI[i][j] = 0.0;
+  }
+  AE[1][0] = 1.0;
+  AE[2][0] = 0.25;
+  AE[2][1] = 0.25;
+  AI[1][0] = 1.0 - gam;
+  AI[1][1] = gam;
+  AI[2][0] = 0.5 - gam - a32;
+  AI[2][1] = a32;
+  AI[2][2] = gam;
+  BE[0] = BI[0] = 1.0 / 6.0;
+  BE[1] = BI[1] = 1.0 / 6.0;
+  BE[2] = BI[2] = 2.0 / 3.0;
+}
+
+void orc_imex_tableau(int scheme, double AE[16], double AI[16], double BE[4], double BI[4], int* stages) {
+  double ae[4][4], ai[4][4], be[4], bi[4];
+  int i, j;
+  if (scheme == 1) {
+    imex332_tableau(ae, ai, be, bi);
+    *stages = 3;
+  } else {
+    for (i = 0; i < 4; ++i) {
+      be[i] = IM_BE[i];
+      bi[i] = IM_BI[i];
+      for (j = 0; j < 4; ++j) {
+        ae[i][j] = IM_AE[i][j];
+        ai[i][j] = IM_AI[i][j];
+      }
+    }
+    *stages = 4;
+  }
+  for (i = 0; i < 4; ++i) {
+    BE[i] = be[i];
+    BI[i] = bi[i];
+    for (j = 0; j < 4; ++j) {
+      AE[4 * i + j] = ae[i][j];
+      AI[4 * i + j] = ai[i][j];
+    }
+  }
+}
+
+/* one IMEX step of `scheme` (0: IMEX(4,4,2) of Table I, 1: IMEX(3,3,2) with
+ * the re-derived I32L above) */
+int64_t orc_imex_step_scheme(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
+                             double dt, int periodic, int scheme) {
   const int ng = g->ng, nf = par->evolve_m1n ? 47 : 44, nr = nf - 32;
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
+  double AE[16], AI[16], BE[4], BI[4];
+  int ns;
   double* Un = (double*)malloc(sizeof(double) * nf * N);
   double* Ui = (double*)malloc(sizeof(double) * nf * N);
   double* P = (double*)calloc(8 * N, sizeof(double));
@@ -203,12 +287,13 @@ int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, d
   double* R[4];
   int64_t bad = 0;
   int st, f;
+  orc_imex_tableau(scheme, AE, AI, BE, BI, &ns);
   memcpy(Un, U, sizeof(double) * nf * N);
-  for (st = 0; st < 4; ++st) {
+  for (st = 0; st < ns; ++st) {
     F[st] = (double*)calloc(nf * N, sizeof(double));
     R[st] = (double*)calloc(nr * N, sizeof(double));
   }
-  for (st = 0; st < 4; ++st) {
+  for (st = 0; st < ns; ++st) {
     memcpy(Ui, Un, sizeof(double) * nf * N);
     for (f = 0; f < nf; ++f) {
       int64_t k;
@@ -219,17 +304,17 @@ int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, d
             const int64_t p = f * N + i + Nx * (j + Ny * k);
             double v = Un[p];
             int jj;
-            for (jj = 0; jj < st; ++jj) v += dt * IM_AE[st][jj] * F[jj][p];
+            for (jj = 0; jj < st; ++jj) v += dt * AE[4 * st + jj] * F[jj][p];
             if (f >= 32)
-              for (jj = 0; jj < st; ++jj) v += dt * IM_AI[st][jj] * R[jj][(f - 32) * N + (p - f * N)];
+              for (jj = 0; jj < st; ++jj) v += dt * AI[4 * st + jj] * R[jj][(f - 32) * N + (p - f * N)];
             Ui[p] = v;
           }
     }
     if (periodic) orc_fill_periodic(g, Ui, nf);
     orc_con2prim(g, e, Ui, P, NULL, NULL);
-    if (IM_AI[st][st] != 0.0) {
-      bad += orc_m1_implicit(g, Ui, P, aux, IM_AI[st][st] * dt);
-      if (par->evolve_m1n) orc_m1n_implicit(g, Ui, P, aux, IM_AI[st][st] * dt);
+    if (AI[4 * st + st] != 0.0) {
+      bad += orc_m1_implicit(g, Ui, P, aux, AI[4 * st + st] * dt);
+      if (par->evolve_m1n) orc_m1n_implicit(g, Ui, P, aux, AI[4 * st + st] * dt);
       if (periodic) orc_fill_periodic(g, Ui, nf);
     }
     orc_rhs_split(g, par, e, Ui, P, aux, F[st], R[st], NULL);
@@ -242,14 +327,14 @@ int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, d
         for (int64_t i = ng; i < Nx - ng; ++i) {
           const int64_t p = f * N + i + Nx * (j + Ny * k);
           double v = Un[p];
-          for (st = 0; st < 4; ++st) v += dt * IM_BE[st] * F[st][p];
+          for (st = 0; st < ns; ++st) v += dt * BE[st] * F[st][p];
           if (f >= 32)
-            for (st = 0; st < 4; ++st) v += dt * IM_BI[st] * R[st][(f - 32) * N + (p - f * N)];
+            for (st = 0; st < ns; ++st) v += dt * BI[st] * R[st][(f - 32) * N + (p - f * N)];
           U[p] = v;
         }
   }
   if (periodic) orc_fill_periodic(g, U, nf);
-  for (st = 0; st < 4; ++st) {
+  for (st = 0; st < ns; ++st) {
     free(F[st]);
     free(R[st]);
   }
@@ -257,4 +342,9 @@ int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, d
   free(Ui);
   free(P);
   return bad;
+}
+
+int64_t orc_imex_step(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
+                      double dt, int periodic) {
+  return orc_imex_step_scheme(g, par, e, U, aux, dt, periodic, 0);
 }

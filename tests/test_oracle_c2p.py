@@ -245,3 +245,39 @@ def test_corrected_cons_rewritten(orc, eos_ideal):
     assert flags.ravel().tolist() == [FL["ATMO"], 0]
     assert U[I.DBAR].ravel()[0] == 1e-12 and U[I.TAUBAR].ravel()[0] == 0.0
     assert U[I.DBAR].ravel()[1] == 1e-3
+
+
+def test_prims_at_given_mu(orc, eos_pwp):
+    """The fixed-mu evaluation used for condition estimates: at the solver's
+    own root it reproduces the solver's primitives and flags bit for bit, and
+    at the mu of the state that generated the conserved data (mu = 1/(h W)
+    of App. D's construction) it returns that state's rho, W and v."""
+    ip, U, P, EM = I.c2p_cells(ncell=1 << 10, seed=1234, log_sigma=(-4.0, -2.0))
+    g = orc.make_grid(ip.n, ip.dx, ng=0)
+    orc.prim2con(g, eos_pwp, U, P, EM, 1)
+    Uo = U.copy()
+    Po = np.zeros_like(P)
+    fl = np.zeros(ip.shape, dtype=np.uint8)
+    mu = np.zeros((2,) + ip.shape)
+    orc.con2prim(g, eos_pwp, Uo, Po, fl, mu)
+    P1 = np.zeros_like(P)
+    f1 = np.zeros_like(fl)
+    orc.c2p_prims_at(g, eos_pwp, U, mu[1], P1, f1)
+    ok = fl == 0
+    assert ok.sum() > 900
+    assert np.array_equal(P1[:, ok], Po[:, ok]) and np.array_equal(f1[ok], fl[ok])
+    # mu = 1/(h W), h = 1 + eps + p/rho the specific enthalpy of the generating
+    # state (the variable of App. D's recovery), computed from that state alone
+    h = 1.0 + P[I.EPS] + P[I.PRESS] / P[I.RHO]
+    Pm = np.zeros_like(P)
+    orc.c2p_prims_at(g, eos_pwp, U, 1.0 / (h * P[I.WLOR]), Pm)
+    for c in (I.RHO, I.WLOR):
+        rel = np.abs(Pm[c][ok] - P[c][ok]) / np.abs(P[c][ok])
+        assert rel.max() <= 1e-12, (c, rel.max())
+    # eps is a difference of terms of the size of the energy per unit rest mass
+    # q = tau/D (App. D); it is pinned in that unit
+    q = U[24][ok] / U[22][ok]
+    rel = np.abs(Pm[I.EPS][ok] - P[I.EPS][ok]) / (1.0 + q)
+    assert rel.max() <= 1e-12, rel.max()
+    vs = np.abs(P[3:6][:, ok]).max(0)
+    assert (np.abs(Pm[3:6][:, ok] - P[3:6][:, ok]).max(0) / vs).max() <= 1e-12

@@ -110,3 +110,45 @@ def test_implicit_solves_converge_on_rough_fields():
     par = orc.make_par(dict(I.PARAMS, evolve_m1=1))
     assert orc.imex_step(g, par, e, U44, aux, 0.25 * ip.dx[0]) == 0
     assert np.isfinite(U44).all()
+
+
+def check_implicit_jacobian(orc):
+    """App. C's printed Jacobian of the implicit M1 equation (closure frozen)
+    is the derivative of its residual G: central differences approach it to
+    1e-6, at second order where truncation dominates (the error drops by ~100
+    from step h to h/10), on random
+    states with W up to 5, flux factors 0..0.99, any Eddington factor and
+    opacities up to 10."""
+    r = np.random.default_rng(5)
+    for t in range(200):
+        A = np.eye(3) * r.uniform(1, 2) + r.uniform(-0.1, 0.1, (3, 3))
+        A = 0.5 * (A + A.T)
+        gd6 = np.array([A[0, 0], A[0, 1], A[0, 2], A[1, 1], A[1, 2], A[2, 2]])
+        W = r.uniform(1.0, 5.0)
+        d = r.normal(size=3)
+        vu = d / np.sqrt(d @ A @ d) * np.sqrt(1 - 1 / W ** 2)
+        E = 10 ** r.uniform(-6, -2)
+        fd = r.normal(size=3)
+        F = fd / np.sqrt(fd @ np.linalg.inv(A) @ fd) * E * r.uniform(0.0, 0.99)
+        V = np.concatenate([[E], F])
+        Vs = V * (1 + r.uniform(-0.1, 0.1, 4))
+        args = (r.uniform(1 / 3, 1.0), r.uniform(0.01, 1.0), r.uniform(0.5, 1), r.uniform(0, 10), r.uniform(0, 10),
+                r.uniform(0, 1e-3))
+        _, Jp = orc.m1_implicit_point(gd6, vu, W, V, Vs, *args)
+        err = []
+        for h in (1e-5, 1e-6):
+            Jf = np.zeros((4, 4))
+            for c in range(4):
+                dv = np.zeros(4)
+                dv[c] = h * np.abs(V).sum()
+                Jf[:, c] = (orc.m1_implicit_point(gd6, vu, W, V + dv, Vs, *args)[0]
+                            - orc.m1_implicit_point(gd6, vu, W, V - dv, Vs, *args)[0]) / (2 * dv[c])
+            err.append(np.abs(Jp - Jf).max() / np.abs(Jf).max())
+        # rounding dominates below ~1e-8; above it the error is truncation
+        assert min(err) <= 1e-6, (t, err)
+        if err[0] > 1e-7:
+            assert err[1] <= 0.05 * err[0], (t, err)
+
+
+def test_implicit_jacobian_is_the_derivative():
+    check_implicit_jacobian(orc)

@@ -12,7 +12,8 @@ of f^LC, the halves of f^MD, the alpha of f^UL, the arguments of d^M4 swapped,
 the sign rule of the 4-argument minmod; a sign in Gamma, the normal part of
 H^a dropped or flipped, the W on the shift, H^k without 1/J, the number
 source with Gamma multiplied or N densitized, the electron-fraction source's
-sign or baryon mass, and the lapse or emission of the implicit update.
+sign or baryon mass, and the lapse or emission of the implicit update; a
+factor or sign of App. C's printed Jacobian of the implicit M1 equation.
 """
 import os
 import shutil
@@ -25,6 +26,7 @@ import pytest
 from oracle import build as obuild
 
 import test_oracle_gauge as G
+import test_oracle_imex as IM
 import test_oracle_m1n as NM
 import test_oracle_stencils as S
 
@@ -86,6 +88,12 @@ MUTANTS = [
     ("Ye source m_b dropped", "m1.c", "par->m_b * (C[0] - C[1])", "(C[0] - C[1])", NPINS),
     ("N implicit lapse", "m1.c", "(1.0 + adt * alp * k0 / gam)", "(1.0 + adt * k0 / gam)", NPINS),
     ("N implicit emission", "m1.c", "(Ns + adt * alp * e0)", "(Ns + adt * e0)", NPINS),
+    ("App. C dJ/dE thick factor", "m1.c", "dthick * (3.0 - 2.0 * W2) * (W2 - 1.0)",
+     "dthick * (3.0 - 2.0 * W2) * (W2 + 1.0)", [IM.check_implicit_jacobian]),
+    ("App. C dH/dF last term sign", "m1.c", "dthin * W * tE0 * fh[i] * s->v[j];",
+     "(-dthin) * W * tE0 * fh[i] * s->v[j];", [IM.check_implicit_jacobian]),
+    ("App. C calJ_0j advection sign", "m1.c", "(ks * dJdF[j] + kas * s->v[j])", "(ks * dJdF[j] - kas * s->v[j])",
+     [IM.check_implicit_jacobian]),
 ]
 
 
