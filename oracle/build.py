@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c"]
-EXTRA = ["m1.c", "mlp.c", "amr.c", "diag.c"]
+EXTRA = ["m1.c", "mlp.c", "amr.c", "diag.c", "les.c"]
 
 
 def build(verbose=False):

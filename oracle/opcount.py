@@ -39,7 +39,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 sys.path.insert(0, ROOT)
 
-SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c", "m1.c", "mlp.c", "diag.c"]
+SOURCES = ["eos.c", "fd.c", "c2p.c", "ccz4.c", "grmhd.c", "rhs.c", "m1.c", "mlp.c", "diag.c", "les.c"]
 PHASES = ["other", "ccz4", "mhd_point", "mhd_recon", "mhd_update", "con2prim", "rk", "prim2con",
           "m1_point", "m1_holo", "m1_update", "m1_reclosure"]
 NROW = 16

@@ -98,6 +98,7 @@ typedef struct {
   int evolve_m1;        /* M1 radiation (fields 32..43, aux kappa_a, kappa_s, eta) on/off */
   int evolve_m1n;       /* with evolve_m1: neutrino number densities (fields 44..46, aux 9..14) on/off */
   double m_b;           /* reference baryon mass of the electron-fraction source */
+  double les_cm;        /* C_M of the gradient SGS term of the induction equation (App. A); 0: off */
 } orc_par;
 
 /* ---- EoS (Sec. 2.2, hybrid piecewise polytrope + thermal ideal gas) ---- */
@@ -159,6 +160,13 @@ void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const do
                 double* rhs, double* max_speed);
 void orc_m1_rhs_split(const orc_grid* g, const orc_par* par, const double* U, const double* P,
                       const double* aux, double* rhs, double* stiff, double* max_speed);
+/* gradient SGS (LES) term of the induction equation (App. A): rhs[28..30] +=
+ * d_k (alpha G_B^{ki}) at interior points (called by orc_rhs when les_cm != 0) */
+void orc_les_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
+                 double* rhs);
+/* H_v^i and H_M^{xy,xz,yz} at every point two or more from the patch edge
+ * (6 fields; for the pins) */
+void orc_les_point_fields(const orc_grid* g, const orc_eos* e, const double* U, const double* P, double* out);
 /* threads of the oracle's OpenMP loops (timing) */
 void orc_set_threads(int n);
 int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);

@@ -32,7 +32,7 @@ class Par(C.Structure):
                 ("c_b", C.c_double), ("kappa_b", C.c_double), ("alpha_mp5", C.c_double),
                 ("f_beta", C.c_double), ("f_alpha_kind", C.c_int), ("evolve_st", C.c_int),
                 ("evolve_mhd", C.c_int), ("couple_matter", C.c_int), ("evolve_m1", C.c_int),
-                ("evolve_m1n", C.c_int), ("m_b", C.c_double)]
+                ("evolve_m1n", C.c_int), ("m_b", C.c_double), ("les_cm", C.c_double)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -87,6 +87,10 @@ def _bind(L):
     L.orc_imex_step_scheme.restype = C.c_int64
     L.orc_imex_tableau.argtypes = [C.c_int, _dp, _dp, _dp, _dp, C.POINTER(C.c_int)]
     L.orc_imex_tableau.restype = None
+    L.orc_les_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp]
+    L.orc_les_rhs.restype = None
+    L.orc_les_point_fields.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp]
+    L.orc_les_point_fields.restype = None
     L.orc_set_threads.argtypes = [C.c_int]
     L.orc_set_threads.restype = None
     L.orc_m1_implicit_point.argtypes = [_dp, _dp, C.c_double, _dp, _dp] + [C.c_double] * 6 + [_dp, _dp]
@@ -196,6 +200,7 @@ def make_par(cfg):
     p.evolve_m1 = int(cfg.get("evolve_m1", 0))
     p.evolve_m1n = int(cfg.get("evolve_m1n", 0))
     p.m_b = float(cfg.get("m_b", 1.0))
+    p.les_cm = float(cfg.get("les_cm", 0.0))
     return p
 
 
@@ -437,6 +442,19 @@ def m1n_rhs(g, par, U, P, aux, out, stiff=None):
 
 def m1n_implicit(g, U, P, aux, adt):
     lib().orc_m1n_implicit(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt))
+
+
+def les_rhs(g, par, e, U, P, out):
+    """Adds the gradient SGS term of the induction equation to out[28..30]."""
+    lib().orc_les_rhs(C.byref(g), C.byref(par), C.byref(e), ptr(U), ptr(P), ptr(out))
+
+
+def les_point_fields(g, e, U, P):
+    """(H_v^i, H_M^xy, H_M^xz, H_M^yz): 6 fields at the points two or more from
+    the patch edge (zero elsewhere)."""
+    out = np.zeros((6,) + U.shape[1:])
+    lib().orc_les_point_fields(C.byref(g), C.byref(e), ptr(U), ptr(P), ptr(out))
+    return out
 
 
 def set_threads(n):

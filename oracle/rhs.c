@@ -56,6 +56,7 @@ void orc_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const doub
   ORC_PHASE(ORC_PH_OTHER);
   if (par->evolve_mhd) {
     orc_grmhd_rhs(g, par, e, U, P, rhs, max_speed);
+    if (par->les_cm != 0.0) orc_les_rhs(g, par, e, U, P, rhs);
   } else {
 #pragma omp parallel for schedule(static)
     for (k = ng; k < Nz - ng; ++k)

@@ -13,7 +13,9 @@ the sign rule of the 4-argument minmod; a sign in Gamma, the normal part of
 H^a dropped or flipped, the W on the shift, H^k without 1/J, the number
 source with Gamma multiplied or N densitized, the electron-fraction source's
 sign or baryon mass, and the lapse or emission of the implicit update; a
-factor or sign of App. C's printed Jacobian of the implicit M1 equation.
+factor or sign of App. C's printed Jacobian of the implicit M1 equation;
+the LES term's product part, second-derivative factor, index order, xi and
+divergence assembly (App. A).
 """
 import os
 import shutil
@@ -27,6 +29,7 @@ from oracle import build as obuild
 
 import test_oracle_gauge as G
 import test_oracle_imex as IM
+import test_oracle_les as LES
 import test_oracle_m1n as NM
 import test_oracle_stencils as S
 
@@ -94,6 +97,14 @@ MUTANTS = [
      "(-dthin) * W * tE0 * fh[i] * s->v[j];", [IM.check_implicit_jacobian]),
     ("App. C calJ_0j advection sign", "m1.c", "(ks * dJdF[j] + kas * s->v[j])", "(ks * dJdF[j] - kas * s->v[j])",
      [IM.check_implicit_jacobian]),
+    ("LES product term sign", "les.c", "+ 2.0 * (bv - vb);", "- 2.0 * (bv - vb);", [LES.check_filter_expansion]),
+    ("LES second derivative factor", "les.c", "rhs[c] += 2.0 * Cj[c].a2;", "rhs[c] += Cj[c].a2;",
+     [LES.check_filter_expansion]),
+    ("LES B index of H_v term", "les.c", "HM[c] = Pv[5 + ii] * Hv[kk] - Pv[5 + kk] * Hv[ii]",
+     "HM[c] = Pv[5 + kk] * Hv[kk] - Pv[5 + ii] * Hv[ii]", [LES.check_filter_expansion]),
+    ("LES xi 24", "les.c", "xi = cbrt(m.det) * D2 / 24.0;", "xi = cbrt(m.det) * D2 / 12.0;", [LES.check_assembly]),
+    ("LES divergence sign", "les.c", "rhs[30 * N + p] += (gxz[p + st[0]] - gxz[p - st[0]]) / dx2 + ",
+     "rhs[30 * N + p] += (gxz[p + st[0]] - gxz[p - st[0]]) / dx2 - ", [LES.check_assembly]),
 ]
 
 
