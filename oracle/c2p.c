@@ -145,6 +145,30 @@ static void atmosphere(const orc_eos* e, double prim[8]) {
   prim[7] = e->ye_atm;
 }
 
+/* step 1: the quantities fixed during the iterations; r^i and calB^i kept for step 4 */
+static void setup_ctx(const orc_eos* e, const double cons[6], const double B[3], const double gdn[6],
+                      const double gup[6], c2p_ctx* c, double r_up[3], double cB[3]) {
+  double r_dn[3], cB_dn[3];
+  int i;
+  c->e = e;
+  c->D = cons[0];
+  c->h0 = e->h0;
+  c->q = cons[2] / cons[0];
+  for (i = 0; i < 3; ++i) {
+    r_dn[i] = cons[3 + i] / cons[0];
+    cB[i] = B[i] / sqrt(cons[0]);
+  }
+  r_up[0] = gup[0] * r_dn[0] + gup[1] * r_dn[1] + gup[2] * r_dn[2];
+  r_up[1] = gup[1] * r_dn[0] + gup[3] * r_dn[1] + gup[4] * r_dn[2];
+  r_up[2] = gup[2] * r_dn[0] + gup[4] * r_dn[1] + gup[5] * r_dn[2];
+  lower(gdn, cB, cB_dn);
+  c->r2 = r_up[0] * r_dn[0] + r_up[1] * r_dn[1] + r_up[2] * r_dn[2];
+  c->B2 = cB[0] * cB_dn[0] + cB[1] * cB_dn[1] + cB[2] * cB_dn[2];
+  c->rB = r_dn[0] * cB[0] + r_dn[1] * cB[1] + r_dn[2] * cB[2];
+  c->B2rp2 = fmax(0.0, c->B2 * c->r2 - c->rB * c->rB);
+  c->v02 = c->r2 / (c->h0 * c->h0 + c->r2);
+}
+
 /* steps 1-4 and the error policy; with mu_fixed != NULL, steps 2 and 3 are
  * skipped and the primitives are those at mu = *mu_fixed */
 static unsigned c2p_point_impl(const orc_eos* e, const double cons[6], const double B[3],
@@ -152,7 +176,7 @@ static unsigned c2p_point_impl(const orc_eos* e, const double cons[6], const dou
                                const double* mu_fixed, double prim[8], double mu_out[2], int* iters) {
   c2p_ctx c;
   c2p_state s;
-  double r_dn[3], r_up[3], cB[3], cB_dn[3];
+  double r_up[3], cB[3];
   double mup, mu, fa_hi, f_lo, f_hi;
   int it1 = 0, it2 = 0, ok1 = 1, ok2 = 1, i;
   unsigned flags = 0;
@@ -166,23 +190,7 @@ static unsigned c2p_point_impl(const orc_eos* e, const double cons[6], const dou
     atmosphere(e, prim);
     return ORC_F_ATMO;
   }
-  c.e = e;
-  c.D = cons[0];
-  c.h0 = e->h0;
-  c.q = cons[2] / cons[0];
-  for (i = 0; i < 3; ++i) {
-    r_dn[i] = cons[3 + i] / cons[0];
-    cB[i] = B[i] / sqrt(cons[0]);
-  }
-  r_up[0] = gup[0] * r_dn[0] + gup[1] * r_dn[1] + gup[2] * r_dn[2];
-  r_up[1] = gup[1] * r_dn[0] + gup[3] * r_dn[1] + gup[4] * r_dn[2];
-  r_up[2] = gup[2] * r_dn[0] + gup[4] * r_dn[1] + gup[5] * r_dn[2];
-  lower(gdn, cB, cB_dn);
-  c.r2 = r_up[0] * r_dn[0] + r_up[1] * r_dn[1] + r_up[2] * r_dn[2];
-  c.B2 = cB[0] * cB_dn[0] + cB[1] * cB_dn[1] + cB[2] * cB_dn[2];
-  c.rB = r_dn[0] * cB[0] + r_dn[1] * cB[1] + r_dn[2] * cB[2];
-  c.B2rp2 = fmax(0.0, c.B2 * c.r2 - c.rB * c.rB);
-  c.v02 = c.r2 / (c.h0 * c.h0 + c.r2);
+  setup_ctx(e, cons, B, gdn, gup, &c, r_up, cB);
 
   if (mu_fixed) {
     mup = 0.0;
@@ -387,6 +395,30 @@ void orc_c2p_prims_at(const orc_grid* g, const orc_eos* e, const double* U, cons
     f = c2p_point_impl(e, cons, B, gdn, gup, U[18 * N + p], &m, prim, NULL, NULL);
     for (i = 0; i < 8; ++i) P[i * N + p] = prim[i];
     if (flags) flags[p] = (uint8_t)f;
+  }
+}
+
+/* f_a and f (steps 2 and 3) at a given mu per padded point, fa[N] and f[N]
+ * (undensitizing as orc_con2prim).  For the tests: whether a mu found by
+ * another solver is a root of the same functions. */
+void orc_c2p_f_at(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,
+                  double* fa, double* f) {
+  int64_t N = npts(g), p;
+#pragma omp parallel for schedule(static)
+  for (p = 0; p < N; ++p) {
+    double gdn[6], gup[6], sg, cons[6], B[3], r_up[3], cB[3];
+    c2p_ctx c;
+    int i;
+    metric_at(U, p, N, gdn, gup, &sg);
+    for (i = 0; i < 6; ++i) cons[i] = U[(22 + i) * N + p] / sg;
+    for (i = 0; i < 3; ++i) B[i] = U[(28 + i) * N + p] / sg;
+    if (!(cons[0] >= e->rho_min)) {
+      fa[p] = f[p] = NAN;
+      continue;
+    }
+    setup_ctx(e, cons, B, gdn, gup, &c, r_up, cB);
+    fa[p] = f_a(&c, mu[p]);
+    f[p] = f_main(&c, mu[p]);
   }
 }
 

@@ -131,6 +131,9 @@ unsigned orc_c2p_point(const orc_eos* e, const double cons[6], const double B[3]
  * root solve; U is only read) */
 void orc_c2p_prims_at(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,
                       double* P, uint8_t* flags);
+/* f_a and f (steps 2 and 3 of the recovery) at a given mu[N] per padded point */
+void orc_c2p_f_at(const orc_grid* g, const orc_eos* e, const double* U, const double* mu,
+                  double* fa, double* f);
 
 /* ---- learned con2prim starting guess (MLP 8 -> 64 -> 64 -> 2) ---- */
 #define ORC_MLP_NPARAM 4866

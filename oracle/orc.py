@@ -97,6 +97,8 @@ def _bind(L):
     L.orc_m1_implicit_point.restype = None
     L.orc_c2p_prims_at.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp, _u8p]
     L.orc_c2p_prims_at.restype = None
+    L.orc_c2p_f_at.argtypes = [C.POINTER(Grid), C.POINTER(Eos), _dp, _dp, _dp, _dp]
+    L.orc_c2p_f_at.restype = None
     L.orc_c2p_point.argtypes = [C.POINTER(Eos), _dp, _dp, _dp, _dp, C.c_double, _dp, _dp,
                                 C.POINTER(C.c_int)]
     L.orc_c2p_point.restype = C.c_uint
@@ -295,6 +297,16 @@ def c2p_prims_at(g, e, U, mu, P, flags=None):
     """Primitives and flags at the given mu (one value per padded point)."""
     mu = np.ascontiguousarray(mu, dtype=np.float64)
     lib().orc_c2p_prims_at(C.byref(g), C.byref(e), ptr(U), ptr(mu), ptr(P), ptr(flags))
+
+
+def c2p_f_at(g, e, U, mu):
+    """f_a and f at the given mu (one value per padded point; NaN where the
+    point is atmosphere)."""
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    fa = np.zeros_like(mu)
+    f = np.zeros_like(mu)
+    lib().orc_c2p_f_at(C.byref(g), C.byref(e), ptr(U), ptr(mu), ptr(fa), ptr(f))
+    return fa, f
 
 
 def c2p_point(e, cons, B, gdn, gup, alpha):
