@@ -1,17 +1,22 @@
 #!/usr/bin/env python3
 """Zone-update throughput of the MoL right-hand side on one MI355X.
 
-Workload: one 128^3 FP64 patch (dx = 0.25, [-16,16]^3) holding the K=100,
-Gamma=2, rho_c=1.28e-3 TOV star with a poloidal field (max b^2/rho = 1e-3) and
-an atmosphere of rho = 1e-12; full CCZ4 + GRMHD right-hand side, con2prim on
-the padded patch and the RK4 stage update.  One step = one RK4 step = four
-right-hand-side evaluations; one zone update = one interior point through one
-evaluation (con2prim + rhs + stage).  Inputs are synthetic and built on the
-device (the prim->cons map runs in the library); the timed region starts with
-everything resident in HBM.
+Headline workload: a batched AMR level of 803 uneven boxes (edges from
+{16,24,32,48,64} per axis, three 2:1 levels dx = 1, 1/2, 1/4, 40.9 M interior
+points) sampled from the K=100, Gamma=2, rho_c=1.28e-3 TOV star with its
+poloidal field, evolving CCZ4 + GRMHD + three grey M1 species (44 fields),
+one RK4 step = four right-hand-side evaluations.  One zone update = one
+interior point through one evaluation (con2prim on the padded boxes + right-
+hand side + stage update).  `value` is the chosen form: the learned con2prim
+guess with the batched, autotuned persistent launches; beside it the plain
+form (per-box launches, bracketed con2prim) and the batched graph replays are
+timed on the same level.  Secondary workloads (the 128^3 star patch, the
+192-box level without radiation, random con2prim states, IMEX, the glue and
+the monitors) follow under `paths`.  Inputs are synthetic and built on the
+device (the prim->cons map runs in the library); every timed region starts
+with everything resident in HBM.
 
-Prints one JSON line (see the keys below); --gpus N > 1 is refused: the build
-targets one GPU.
+Prints one JSON line; --gpus N > 1 is refused: the build targets one GPU.
 """
 import argparse
 import json
@@ -49,6 +54,8 @@ def parse():
     ap.add_argument("--no-c2p-cells", action="store_true", help="skip con2prim on random states")
     ap.add_argument("--c2p-log2", type=int, default=24, help="log2 of the number of random con2prim states")
     ap.add_argument("--level-steps", type=int, default=5)
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of the headline's per-box plain form")
+    ap.add_argument("--headline-only", action="store_true", help="only the headline level (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (3 times): the reference for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters to bytes")
@@ -86,18 +93,9 @@ def time_steps(torch, step, steps, warmup):
     return e0.elapsed_time(e1) / steps
 
 
-def learned_path(torch, mhd, I, run, step, args, nint):
-    """Same patch and steps with the learned con2prim guess.  The network is
-    trained here (own kernels) on 2^18 random states of the star workloads'
-    distribution; training time is reported, not part of the step."""
-    from paper_2510_13965_amd import learned
-
-    t0 = time.perf_counter()
-    X, T = learned.training_set(1 << 18, seed=I.SEED0 + 50, eos_cfg=I.EOS_IDEAL2, **learned.STAR_SAMPLING)
-    prm, hist = learned.train(X, T, seed=7, epochs=24, batch=4096)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    say("learned path: trained in %.1f s, loss %.3e -> %.3e" % (t_train, hist[0], hist[-1]))
+def learned_path(torch, mhd, I, run, step, args, nint, prm):
+    """Same patch and steps with the learned con2prim guess (the network
+    trained on the star workloads' distribution)."""
     run.use_learned(prm)
     step()
     run.stats.zero_()
@@ -107,9 +105,7 @@ def learned_path(torch, mhd, I, run, step, args, nint):
     nev = 4 * args.steps * run.ip.npts
     say("learned path: %.3f ms/step, fallback %.4f" % (ms, st[2] / nev))
     return {"zone_updates_per_s": round(nint * 4 / (ms * 1e-3), 1), "ms_per_step": round(ms, 4),
-            "fallback_rate": round(float(st[2]) / nev, 6), "root_evals_per_point": round(float(st[3]) / nev, 3),
-            "train_s": round(t_train, 2), "train_loss_first_last": [hist[0], hist[-1]], "train_states": 1 << 18,
-            "_mlp": prm}
+            "fallback_rate": round(float(st[2]) / nev, 6), "root_evals_per_point": round(float(st[3]) / nev, 3)}
 
 
 def m1_path(torch, mhd, I, ip, U, P, EM, args):
@@ -177,24 +173,28 @@ def c2p_cells_path(torch, mhd, I, args):
         once(st)  # the counted call, on the untouched states
         torch.cuda.synchronize()
         ms = time_steps(torch, once, 3, 1)
+        mhd.profile_start()
+        once()
+        torch.cuda.synchronize()
+        kern = {k: round(t / n, 4) for k, (n, t) in mhd.profile_stop().items()}
         res[mode] = (mu.clone(), fl.clone(), st.cpu().numpy())
         out[mode] = {"states_per_s": round(n / (ms * 1e-3), 1), "ms": round(ms, 3),
-                     "root_evals_per_state": round(float(res[mode][2][3]) / n, 3)}
+                     "root_evals_per_state": round(float(res[mode][2][3]) / n, 3), "kernels_ms": kern}
         say("c2p cells %s: %.3f ms" % (mode, ms))
         del Ud, Pd
     mup, flp, _ = res["plain"]
     mul, fll, stl = res["learned"]
     solved = (mup[1] > 0) & ((fll & 32) == 0)
-    rel = ((mul - mup).abs() / mup.abs().clamp_min(1e-300))[:, solved]
+    rel = ((mul[1] - mup[1]).abs() / mup[1].abs().clamp_min(1e-300))[solved]
     # Where the root function has more than one root in (0, mu_+] (possible once
     # the density and energy are clamped to the EoS range), Newton from the
     # learned guess and the bracketing solver may converge to different roots:
     # counted separately; the maximum difference is taken over the other states.
-    other = rel[1] > 1e-6
+    # (The learned path does not solve for mu_+: only mu is compared.)
+    other = rel > 1e-6
     out["learned"]["fallback_rate"] = round(float(stl[2]) / n, 6)
     out["learned"]["states_other_root"] = int(other.sum().item())
-    same = rel[:, ~other]
-    out["learned"]["max_rel_root_difference"] = [float(same[0].max().item()), float(same[1].max().item())]
+    out["learned"]["max_rel_root_difference"] = float(rel[~other].max().item())
     out["learned"]["flags_differ"] = int(((fll & ~32) != flp).sum().item())
     return out
 
@@ -305,18 +305,14 @@ class _Units:
         self.ninterior, self.npts = ninterior, npts
 
 
-def level_m1_path(torch, mhd, I, args, mlp):
-    """The coupled system with three grey M1 species (44 fields) on a batched
-    level of ~800 uneven boxes (~40 M interior points) of the star: per-box
-    launches with the bracketed con2prim against the autotuned batched level
-    replayed as a hipGraph, with the bracketed and with the learned con2prim."""
-    from paper_2510_13965_amd.step import LevelRun
-
+def build_level_m1(torch, mhd, I, nboxes):
+    """The boxes of the level with radiation, built on the host in threads and
+    moved to the device; returns (LevelRun, box list)."""
     from concurrent.futures import ThreadPoolExecutor
 
-    torch.cuda.empty_cache()
-    t0 = time.perf_counter()
-    boxes = I.amr_level_boxes(seed=I.SEED0 + 5, nboxes=args.level_m1_boxes)
+    from paper_2510_13965_amd.step import LevelRun
+
+    boxes = I.amr_level_boxes(seed=I.SEED0 + 5, nboxes=nboxes)
     Ab = I.star_field_amplitude()
     eos = mhd.make_eos(I.EOS_IDEAL2)
 
@@ -337,16 +333,30 @@ def level_m1_path(torch, mhd, I, args, mlp):
             ips.append(ip)
             states.append(Ud)
             auxs.append(torch.as_tensor(aux).cuda())
-    par = dict(I.PARAMS, evolve_m1=1)
-    lr = LevelRun(ips, states, I.EOS_IDEAL2, par, auxs=auxs)
+    lr = LevelRun(ips, states, I.EOS_IDEAL2, dict(I.PARAMS, evolve_m1=1), auxs=auxs)
     del states, auxs
     torch.cuda.synchronize()
-    say("level M1: %d boxes, %d interior points, built in %.1f s" % (len(ips), lr.ninterior, time.perf_counter() - t0))
-    dt = 0.25 * min(ip.dx[0] for ip in ips)
+    return lr, boxes
+
+
+def headline_level_m1(torch, mhd, I, args, mlp):
+    """The headline: the coupled system with three grey M1 species (44 fields)
+    on a batched level of ~800 uneven boxes (~40 M interior points) of the
+    star.  Plain form: per-box launches with the bracketed con2prim.  Chosen
+    form (`value`): the learned con2prim guess with the batched, autotuned
+    persistent launches, timed over exactly `steps` steps after `warmup`
+    untimed ones, with per-kernel HIP events on the launch stream.  Also
+    timed: the batched level with the bracketed con2prim, and both batched
+    forms replayed as hipGraphs."""
+    torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    lr, boxes = build_level_m1(torch, mhd, I, args.level_m1_boxes)
+    say("headline level: %d boxes, %d interior points, built in %.1f s"
+        % (len(lr.boxes), lr.ninterior, time.perf_counter() - t0))
+    dt = 0.25 * min(b["ip"].dx[0] for b in lr.boxes)
     nzu = lr.ninterior * 4
-    res = {"workload": "%d boxes, edges from {16,24,32,48,64}, 3 levels dx=1,1/2,1/4 of the TOV star, CCZ4+GRMHD+3 "
-                       "grey M1 species (44 fields); dt=%.4g" % (len(ips), dt),
-           "interior_points": lr.ninterior, "padded_points": lr.npts, "evolved_fields": I.NU_M1}
+    res = {"interior_points": lr.ninterior, "padded_points": lr.npts, "boxes": len(lr.boxes), "dt": dt,
+           "evolved_fields": I.NU_M1}
 
     def per_box_step():
         for s in range(4):
@@ -356,41 +366,58 @@ def level_m1_path(torch, mhd, I, args, mlp):
                 mhd.rhs(b["patch"], lr.par, lr.eos, Ux, b["P"], b["k"], None, b["ws"], aux=b["aux"])
                 mhd.rk_stage(b["patch"], I.NU_M1, s, dt, b["U"], b["k"], b["acc"], b["Us"] if s < 3 else b["U"])
 
-    ms = time_steps(torch, per_box_step, 1, 1)
-    res["per_box"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
-    say("level M1 per-box: %.2f ms/step" % ms)
+    nplain = max(1, min(args.steps, args.plain_steps))
+    ms = time_steps(torch, per_box_step, nplain, 1)
+    res["plain_per_box"] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3),
+                            "steps": nplain}
+    say("headline plain (per box, bracketed con2prim): %.2f ms/step" % ms)
     t1 = time.perf_counter()
+    lr.level.set_learned(mlp)
     res["autotuned"] = lr.level.autotune(dt)
     res["autotune_s"] = round(time.perf_counter() - t1, 2)
+    # the chosen form, eager, with per-kernel events: the value
+    for _ in range(args.warmup):
+        lr.level.rk4_step(dt)
+    torch.cuda.synchronize()
+    mhd.profile_start()
+    ms_value = time_steps(torch, lambda: lr.level.rk4_step(dt), args.steps, 0)
+    prof = mhd.profile_stop()
+    res["learned_batched"] = {"zone_updates_per_s": round(nzu / (ms_value * 1e-3), 1),
+                              "ms_per_step": round(ms_value, 3), "steps": args.steps}
+    say("headline learned + batched: %.2f ms/step" % ms_value)
+    st = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device="cuda")
+    lr.level.rhs(0, None, st)
+    st = st.cpu().numpy()
+    res["c2p_learned"] = {"fallback_rate": round(float(st[2]) / lr.npts, 6),
+                          "root_evals_per_point": round(float(st[3]) / lr.npts, 3)}
     stream = torch.cuda.Stream()
-    units = _Units(lr.ninterior, lr.npts)
-    for tag, m in (("batched_graph", None), ("batched_graph_learned", mlp)):
-        if tag == "batched_graph_learned" and m is None:
-            continue
+    nrep = max(2, min(args.steps, 5))
+    for tag, m in (("learned_batched_graph", mlp), ("plain_batched_graph", None)):
         lr.level.set_learned(m)
         stream.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(stream):
             lr.level.rk4_step(dt, use_graph=True, stream=stream)   # capture + warm-up
-            ms = time_steps(torch, lambda: lr.level.rk4_step(dt, use_graph=True, stream=stream),
-                            args.level_steps, 0)
-        res[tag] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3)}
-        say("level M1 %s (%s): %.2f ms/step" % (tag, res["autotuned"], ms))
-    # per-kernel times of one eager step (graph replays are not event-timed)
-    lr.level.set_learned(mlp)
-    mhd.profile_start()
-    lr.level.rk4_step(dt)
-    prof = mhd.profile_stop()
-    res["kernels"] = kernel_table(prof, units, 1, nfields=I.NU_M1)
+            ms = time_steps(torch, lambda: lr.level.rk4_step(dt, use_graph=True, stream=stream), nrep, 0)
+        res[tag] = {"zone_updates_per_s": round(nzu / (ms * 1e-3), 1), "ms_per_step": round(ms, 3), "steps": nrep}
+        say("headline %s: %.2f ms/step" % (tag, ms))
     st = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device="cuda")
     lr.level.rhs(0, None, st)
     st = st.cpu().numpy()
-    res["c2p_learned" if mlp is not None else "c2p_plain"] = {
-        "fallback_rate": round(float(st[2]) / lr.npts, 6), "root_evals_per_point": round(float(st[3]) / lr.npts, 3)}
+    res["c2p_plain"] = {"root_evals_per_point": round(float(st[3]) / lr.npts, 3)}
+    # per-kernel times of one eager step with the bracketed con2prim (the
+    # con2prim phases of the two forms side by side)
+    mhd.profile_start()
+    lr.level.rk4_step(dt)
+    prof_plain = mhd.profile_stop()
+    res["kernels_plain_one_step"] = {k: round(t / n, 4) for k, (n, t) in prof_plain.items()}
     res["finite"] = all(bool(torch.isfinite(b["U"]).all().item()) for b in lr.boxes)
+    units = _Units(lr.ninterior, lr.npts)
+    res["kernels"] = kernel_table(prof, units, args.steps, nfields=I.NU_M1, flops=FLOP_PER_UNIT_LEVEL_M1)
+    res["roofline"] = roofline(prof, units, FLOP_PER_UNIT_LEVEL_M1, TRAFFIC_LEVEL_M1, nfields=I.NU_M1)
     lr.level.close()
     del lr
     torch.cuda.empty_cache()
-    return res
+    return ms_value, res
 
 
 def level_imex_path(torch, mhd, I, args):
@@ -528,31 +555,16 @@ def diag_path(torch, mhd, I, run, ip):
     return res
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration()
-        return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
-              file=sys.stderr)
-        sys.exit(2)
-    import numpy as np
-    import torch
-
-    from paper_2510_13965_amd import inputs as I
-    from paper_2510_13965_amd import mhd
+def star_patch_paths(torch, mhd, I, args, mlp):
+    """The 128^3 star patch (CCZ4 + GRMHD, plain con2prim and RK4 stage):
+    per-kernel events, its own roofline entry and the learned variant."""
     from paper_2510_13965_amd.step import PatchRun
 
-    assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    mhd.lib()
     ip, U, P, EM = I.tov_star_state(n=args.n)
-    dev = "cuda"
     say("building the %d^3 star patch" % args.n)
-    run = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS, periodic=False, device=dev)
-    # prim -> cons on the device
-    Pd = torch.as_tensor(P).to(dev).contiguous()
-    EMd = torch.as_tensor(EM).to(dev).contiguous()
+    run = PatchRun(ip, U, I.EOS_IDEAL2, I.PARAMS, periodic=False, device="cuda")
+    Pd = torch.as_tensor(P).to("cuda").contiguous()
+    EMd = torch.as_tensor(EM).to("cuda").contiguous()
     mhd.prim2con(run.patch, run.eos, run.Un, Pd, EMd, 0)
     run.Us.copy_(run.Un)
     dt = 0.25 * ip.dx[0]
@@ -562,79 +574,171 @@ def main():
     def step():
         run.step(dt)
 
-    sweep = None
-    if args.sweep_strip:
-        sweep = {}
-        for sh in (1, 2, 4, 8, 16, 32):
-            mhd.set_tuning(sh)
-            sweep[sh] = time_steps(torch, step, 3, 1)
-        best = min(sweep, key=sweep.get)
-        mhd.set_tuning(best)
-        sweep = {"ms_per_step": {k: round(v, 3) for k, v in sweep.items()}, "chosen": best}
-    say("plain path: warmup")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed region: whole steps only, per-kernel events recorded by the library
-    w0 = time.perf_counter()
     mhd.profile_start()
     ms_step = time_steps(torch, step, args.steps, 0)
     prof = mhd.profile_stop()
-    wall = time.perf_counter() - w0
     nint = ip.ninterior
-    zu_s = nint * 4 / (ms_step * 1e-3)
-    fin = bool(torch.isfinite(run.Un).all().item())
-    kern = kernel_table(prof, ip, args.steps)
-    roof = roofline(prof, ip, args.n)
-    say("plain path: %.3f ms/step" % ms_step)
+    res = {"workload": "TOV star K=100 Gamma=2 rho_c=1.28e-3, %d^3 interior, dx=%.4g, full CCZ4+GRMHD RHS + plain "
+                       "con2prim + RK4 stage" % (args.n, ip.dx[0]),
+           "interior_points": nint, "padded_points": ip.npts,
+           "zone_updates_per_s": round(nint * 4 / (ms_step * 1e-3), 1), "ms_per_step": round(ms_step, 4),
+           "kernels": kernel_table(prof, ip, args.steps),
+           "roofline": roofline(prof, ip, FLOP_PER_UNIT_STAR, TRAFFIC_STAR),
+           "finite": bool(torch.isfinite(run.Un).all().item()), "tuning": mhd.get_tuning()}
+    say("star patch plain: %.3f ms/step" % ms_step)
+    if mlp is not None:
+        res["learned"] = learned_path(torch, mhd, I, run, step, args, nint, mlp)
+    return run, ip, (U, P, EM), res
 
-    paths = {"plain": {"zone_updates_per_s": round(zu_s, 1), "ms_per_step": round(ms_step, 4)}}
-    level = None
-    if not args.no_learned:
-        paths["learned"] = learned_path(torch, mhd, I, run, step, args, nint)
-    if not args.no_c2p_cells:
-        paths["c2p_cells"] = c2p_cells_path(torch, mhd, I, args)
-    if not args.no_m1:
-        paths["m1"] = m1_path(torch, mhd, I, ip, U, P, EM, args)
-        paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
-    if not args.no_level:
-        level = level_paths(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
-    if not args.no_diag:
-        paths["constraints"] = diag_path(torch, mhd, I, run, ip)
-    if not args.no_glue:
-        paths["glue"] = glue_path(torch, mhd, I, args)
-    if not args.no_level_imex:
-        paths["level_imex"] = level_imex_path(torch, mhd, I, args)
-    if not args.no_level_m1:
-        paths["level_m1"] = level_m1_path(torch, mhd, I, args, paths.get("learned", {}).get("_mlp"))
-    if "learned" in paths:
-        paths["learned"].pop("_mlp", None)
 
-    out = {"metric": METRIC, "value": round(zu_s, 1), "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
-           "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2510_13965_amd import inputs as I
+    from paper_2510_13965_amd import mhd
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    mhd.lib()
+    w0 = time.perf_counter()
+    mlp, train = train_star_mlp(torch, I)
+    ms_value, head = headline_level_m1(torch, mhd, I, args, mlp)
+    paths = {}
+    if not args.headline_only:
+        run, ip, (U, P, EM), paths["star128"] = star_patch_paths(torch, mhd, I, args, mlp)
+        if not args.no_diag:
+            paths["constraints"] = diag_path(torch, mhd, I, run, ip)
+        del run
+        torch.cuda.empty_cache()
+        if not args.no_c2p_cells:
+            paths["c2p_cells"] = c2p_cells_path(torch, mhd, I, args)
+        if not args.no_m1:
+            paths["m1"] = m1_path(torch, mhd, I, ip, U, P, EM, args)
+            paths["imex"] = imex_path(torch, mhd, I, ip, U, P, EM, args)
+        if not args.no_level:
+            paths["level192"] = level_paths(torch, mhd, I, args, mlp)
+        if not args.no_glue:
+            paths["glue"] = glue_path(torch, mhd, I, args)
+        if not args.no_level_imex:
+            paths["level_imex"] = level_imex_path(torch, mhd, I, args)
+    nzu = head["interior_points"] * 4
+    value = nzu / (ms_value * 1e-3)
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "zone-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_value, 4), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "TOV star K=100 Gamma=2 rho_c=1.28e-3, %d^3 interior, dx=%.4g, full CCZ4+GRMHD "
-                                  "RHS + plain con2prim + RK4 stage" % (args.n, ip.dx[0]),
-                      "interior_points": nint, "padded_points": ip.npts, "rhs_evals_per_step": 4, "path": "plain"},
-           "paths": paths, "level": level,
-           "kernels": kern,
-           "wall_s": round(wall, 3), "finite": fin, "tuning": mhd.get_tuning(), "strip_sweep": sweep,
-           "roofline": roof}
-
+           "config": {"workload": "batched AMR level of %d boxes (edges from {16,24,32,48,64}, three 2:1 levels "
+                                  "dx=1,1/2,1/4) of the TOV star K=100 Gamma=2 rho_c=1.28e-3 with poloidal B, CCZ4 + "
+                                  "GRMHD + 3 grey M1 species (44 fields), RK4 dt=%.4g; chosen form: learned "
+                                  "con2prim guess + batched autotuned persistent launches. Radiation opacities "
+                                  "kappa_a, kappa_s = 10^U(-3,0) * rho/1e-3 (proportional to density, up to 1 at "
+                                  "the centre), not log-uniform [1e-8,1e-2]: density-independent opacities drive the "
+                                  "1e-12 atmosphere to the velocity cap within a step"
+                                  % (head["boxes"], head["dt"]),
+                      "interior_points": head["interior_points"], "padded_points": head["padded_points"],
+                      "rhs_evals_per_step": 4, "path": "learned+batched",
+                      "plain_zone_updates_per_s": head["plain_per_box"]["zone_updates_per_s"],
+                      "learned_batched_vs_plain": round(value / head["plain_per_box"]["zone_updates_per_s"], 3)},
+           "headline": head, "train": train, "paths": paths, "roofline": head["roofline"]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(ip, U, P, EM, args.cpu_evals)
+        out["cpu_baseline"] = cpu_baseline_level_m1(args)
+    out["wall_s"] = round(time.perf_counter() - w0, 1)
     print(json.dumps(out), flush=True)
 
 
-# Algorithmic work per unit, counted on this workload by oracle/opcount.py
-# (the oracle's own evaluation with an op-counting scalar type; add/sub, mul,
-# div, sqrt and pow/exp/log count one flop each).  Units: interior points for
-# the RHS kernels, padded points for con2prim and the point fluxes, interior
+def train_star_mlp(torch, I):
+    """The network of the learned con2prim guess, trained here (own kernels) on
+    2^18 random states of the star workloads' distribution; training time is
+    reported, not part of any step."""
+    from paper_2510_13965_amd import learned
+
+    t0 = time.perf_counter()
+    X, T = learned.training_set(1 << 18, seed=I.SEED0 + 50, eos_cfg=I.EOS_IDEAL2, **learned.STAR_SAMPLING)
+    prm, hist = learned.train(X, T, seed=7, epochs=24, batch=4096)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    say("network trained in %.1f s, loss %.3e -> %.3e" % (t_train, hist[0], hist[-1]))
+    return prm, {"states": 1 << 18, "epochs": 24, "train_s": round(t_train, 2),
+                 "loss_first_last": [hist[0], hist[-1]]}
+
+
+def cpu_baseline_level_m1(args):
+    """The FP64 oracle on the host cores: one evaluation (con2prim + right-hand
+    side with radiation + RK4 stage) of each box of the seeded 16-box subset
+    of the headline level, from the level's initial data; on all cores the
+    process may use and on one core, median of 3 each."""
+    import numpy as np
+
+    from oracle import orc
+    from paper_2510_13965_amd import inputs as I
+
+    boxes = I.amr_level_boxes(seed=I.SEED0 + 5, nboxes=args.level_m1_boxes)
+    sub = I.level_subset(len(boxes))
+    Ab = I.star_field_amplitude()
+    e = orc.make_eos(I.EOS_IDEAL2)
+    par = orc.make_par(dict(I.PARAMS, evolve_m1=1))
+    states = []
+    for b in sub:
+        ip, U, P, EM = I.amr_box_state(boxes[b], Ab)
+        R, aux = I.m1_radiation(ip, P, I.SEED0 + 500 + b)
+        g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+        orc.prim2con(g, e, U, P, EM, 0)
+        states.append((ip, g, np.concatenate([U, R]), aux))
+    nint = sum(ip.ninterior for ip, _, _, _ in states)
+    dt = 0.25 * min(b["dx"][0] for b in boxes)
+
+    def once(sample):
+        t0 = time.perf_counter()
+        for ip, g, U0, aux in sample:
+            U = U0.copy()
+            Pr = np.zeros((I.NP,) + ip.shape)
+            k = np.zeros_like(U)
+            acc = np.zeros_like(U)
+            Us = U.copy()
+            orc.con2prim(g, e, U, Pr, None, None)
+            orc.rhs_full(g, par, e, U, Pr, aux, k)
+            orc.rk4_stage_interior(g, I.NU_M1, 0, dt, U, k, acc, Us)
+        return time.perf_counter() - t0
+
+    cores = len(os.sched_getaffinity(0))
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp:
+        cores = min(cores, int(omp))
+    orc.set_threads(cores)
+    t_all = sorted(once(states) for _ in range(3))[1]
+    # one thread: the first box of the subset only (the whole subset would take minutes)
+    one = states[:1]
+    n_one = one[0][0].ninterior
+    orc.set_threads(1)
+    t_one = sorted(once(one) for _ in range(3))[1]
+    orc.set_threads(cores)
+    return {"value": round(nint / t_all, 1), "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
+            "sample": "one evaluation (con2prim + RHS with 3 grey M1 species + RK4 stage) of each of the %d boxes "
+                      "of the seeded subset of the headline level (%d interior points) from its initial data, "
+                      "median of 3: %.2f s on %d threads. On 1 thread, the subset's first box (%s, %d interior "
+                      "points), median of 3: %.2f s"
+                      % (len(states), nint, t_all, cores, "x".join(str(v) for v in one[0][0].n), n_one, t_one),
+            "one_core": {"value": round(n_one / t_one, 1), "unit": "zone-updates/s", "cores": 1}}
+
+
+# Algorithmic work per unit, counted by oracle/opcount.py (the oracle's own
+# evaluation with an op-counting scalar type; add/sub, mul, div, sqrt and
+# pow/exp/log count one flop each).  Units: interior points for the RHS
+# kernels, padded points for con2prim and the point fluxes, interior
 # point-fields for the RK stage.  The MHD and M1 updates count every interface
-# once; the M1 point kernel (closure root, point fluxes and speeds of three
-# species on three axes) and the M1 update were counted with three grey species
-# on the same star.
-FLOP_PER_UNIT = {
+# once.  Star patch: the 128^3 star (M1 rows: three grey species on the same
+# star).  Level with radiation: the 16-box subset of the 803-box level
+# (inputs.level_subset), three grey species, summed over the boxes.
+FLOP_PER_UNIT_STAR = {
     "k_con2prim": 188.85,
     "k_mhd_point": 1608.0,
     "k_mhd_update": 5136.11,
@@ -643,11 +747,25 @@ FLOP_PER_UNIT = {
     "k_m1_point": 15301.03,
     "k_m1_update": 2855.5,
 }
-# HBM bytes per launch of the dominant kernel from rocprofv3 --pmc (FETCH_SIZE x 2
-# + WRITE_SIZE x 1, the factors that make a plain 1 GiB copy read and write 1 GiB),
+FLOP_PER_UNIT_LEVEL_M1 = {
+    "k_con2prim": 188.85,
+    "k_mhd_point": 1608.0,
+    "k_mhd_update": 5136.11,
+    "ccz4 (4 kernels)": 10396.0,
+    "k_rk4_stage": 4.75,
+    "k_m1_point": 15301.03,
+    "k_m1_update": 2855.5,
+}
+# HBM bytes per launch of a kernel from rocprofv3 --pmc (FETCH_SIZE and
+# WRITE_SIZE, each scaled by what the counter reads for a plain 1 GiB copy),
 # valid only for the kernel sources they were taken on (sha256 of these files).
-TRAFFIC = {"k_mhd_update": (2698185360.0, "6d780a4bcdb13c60")}
-TRAFFIC_SOURCES = {"k_mhd_update": ["paper_2510_13965_amd/csrc/grmhd.hip", "paper_2510_13965_amd/csrc/dev_common.hpp"]}
+TRAFFIC_STAR = {"k_mhd_update": (2698185360.0, "6d780a4bcdb13c60")}
+TRAFFIC_LEVEL_M1 = {}
+TRAFFIC_SOURCES = {
+    "k_mhd_update": ["paper_2510_13965_amd/csrc/grmhd.hip", "paper_2510_13965_amd/csrc/dev_common.hpp"],
+    "k_m1_point": ["paper_2510_13965_amd/csrc/m1.hip", "paper_2510_13965_amd/csrc/m1_dev.hpp",
+                   "paper_2510_13965_amd/csrc/dev_common.hpp"],
+}
 
 
 def sources_sha(files):
@@ -660,38 +778,41 @@ def sources_sha(files):
     return h.hexdigest()[:16]
 
 
-def kernel_table(prof, ip, steps, nfields=32):
+def kernel_table(prof, ip, steps, nfields=32, flops=None):
     """Per-kernel launches and event-timed durations, with the achieved FP64
     rate of the algorithmic flops where the count exists."""
+    flops = FLOP_PER_UNIT_STAR if flops is None else flops
     units = {"k_con2prim": ip.npts, "k_mhd_point": ip.npts, "k_mhd_update": ip.ninterior,
              "k_rk4_stage": ip.ninterior * nfields, "k_m1_point": ip.npts, "k_m1_update": ip.ninterior}
     tab = {}
     for k, (n, t) in prof.items():
         e = {"launches": n, "ms_per_launch": round(t / n, 4), "ms_per_step": round(t / steps, 4)}
         if k in units:
-            e["fp64_tflops"] = round(FLOP_PER_UNIT[k] * units[k] / (t / n * 1e-3) / 1e12, 3)
+            e["fp64_tflops"] = round(flops[k] * units[k] / (t / n * 1e-3) / 1e12, 3)
         tab[k] = e
     cz = [k for k in prof if k.startswith("k_ccz4_")]
     if cz:
         t = sum(prof[k][1] for k in cz) / prof[cz[0]][0]
         tab["ccz4 (4 kernels)"] = {"ms_per_launch": round(t, 4),
-                                   "fp64_tflops": round(FLOP_PER_UNIT["ccz4 (4 kernels)"] * ip.ninterior
+                                   "fp64_tflops": round(flops["ccz4 (4 kernels)"] * ip.ninterior
                                                         / (t * 1e-3) / 1e12, 3)}
     return tab
 
 
-def kernel_work(ip):
-    """Bound and algorithmic work of one launch of each kernel on this patch:
-    FP64 flops (oracle op counts) for the arithmetic-bound kernels, minimum HBM
-    bytes for the streaming ones (every input value read once, every output
-    written once)."""
+def kernel_work(ip, flops, nfields):
+    """Bound and algorithmic work of one launch of each kernel on this patch
+    or level: FP64 flops (oracle op counts) for the arithmetic-bound kernels,
+    minimum HBM bytes for the streaming ones (every input value read once,
+    every output written once)."""
     nint, npad = ip.ninterior, ip.npts
     return {
-        "k_mhd_update": ("alu", FLOP_PER_UNIT["k_mhd_update"] * nint),
-        "k_mhd_point": ("alu", FLOP_PER_UNIT["k_mhd_point"] * npad),
-        "k_con2prim": ("alu", FLOP_PER_UNIT["k_con2prim"] * npad),
+        "k_mhd_update": ("alu", flops["k_mhd_update"] * nint),
+        "k_mhd_point": ("alu", flops["k_mhd_point"] * npad),
+        "k_con2prim": ("alu", flops["k_con2prim"] * npad),
+        "k_m1_point": ("alu", flops["k_m1_point"] * npad),
+        "k_m1_update": ("alu", flops["k_m1_update"] * nint),
         # stages 0-2 read Un, k, acc and write acc, Unext; stage 3 reads Un, k, acc and writes Un
-        "k_rk4_stage": ("hbm", nint * 32 * 8 * 4.75),
+        "k_rk4_stage": ("hbm", nint * nfields * 8 * 4.75),
         # 22 CCZ4 fields read on the padded patch, 22 right-hand sides written
         "k_ccz4_stencil": ("hbm", 22 * 8 * (npad + nint)),
         # 11 fields read on the padded patch, 24 second-derivative fields written
@@ -699,12 +820,12 @@ def kernel_work(ip):
     }
 
 
-def roofline(prof, ip, n):
-    """Roofline entry of the kernel with the largest share of the step (among
-    those with an algorithmic work figure; the kernel with the largest share
-    overall is named beside it).  Achieved = algorithmic work of one launch /
-    its average event-timed duration."""
-    work = kernel_work(ip)
+def roofline(prof, ip, flops, traffic, nfields=32):
+    """Roofline entry of the kernel with the largest share of the timed region
+    (among those with an algorithmic work figure; the kernel with the largest
+    share overall is named beside it).  Achieved = algorithmic work of one
+    launch / its average event-timed duration."""
+    work = kernel_work(ip, flops, nfields)
     top = max(prof, key=lambda k: prof[k][1])
     dom = max((k for k in prof if k in work), key=lambda k: prof[k][1])
     launches, tot = prof[dom]
@@ -721,7 +842,7 @@ def roofline(prof, ip, n):
         ach = w / (ms * 1e-3) / 1e9
         out.update({"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(ach / HBM_PEAK_GBS, 4), "bytes_per_launch": w})
-    t = TRAFFIC.get(dom)
+    t = traffic.get(dom)
     out["traffic"] = t[0] if t and dom in TRAFFIC_SOURCES and t[1] == sources_sha(TRAFFIC_SOURCES[dom]) else None
     return out
 

@@ -29,7 +29,12 @@
  *   densitized by sqrt(gamma) (Sec. 2.2).  With MHD_EVOLVE_M1, 12 more fields:
  *   per species s = 0, 1, 2 the densitized neutrino energy and flux Ebar,
  *   Fbar_x,y,z at 32 + 4 s (Sec. 2.3), and an aux array of MHD_NAUX fields
- *   (kappa_a, kappa_s, eta of species s at 3 s, 3 s + 1, 3 s + 2).
+ *   (kappa_a, kappa_s, eta of species s at 3 s, 3 s + 1, 3 s + 2).  With
+ *   MHD_EVOLVE_M1N as well, 3 more: the densitized neutrino number density
+ *   Nbar of species s at 44 + s (Sec. 2.3; MHD_NU_M1N fields), and the aux
+ *   array has MHD_NAUX_N fields: after the 9 above, the number absorption
+ *   opacity kappa0_a and emissivity eta0 of species s at 9 + 2 s, 10 + 2 s.
+ *   Species 0 is the electron neutrino, 1 its antineutrino.
  * Primitive fields P (MHD_NP = 8): rho, eps, p, v^x, v^y, v^z, W, Ye.
  * Errors: 0 on success; a negative MHD_E* code otherwise, with a message
  *   available from mhd_last_error() (per host thread).  Argument errors are
@@ -45,13 +50,15 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 4
+#define MHD_ABI_VERSION 5
 
 #define MHD_NST 22
 #define MHD_NMHD 10
 #define MHD_NU 32
 #define MHD_NU_M1 44 /* with three grey M1 species (MHD_EVOLVE_M1) */
 #define MHD_NAUX 9   /* per species kappa_a, kappa_s, eta */
+#define MHD_NU_M1N 47 /* with the three number densities as well (MHD_EVOLVE_M1N) */
+#define MHD_NAUX_N 15 /* and per species kappa0_a, eta0 */
 #define MHD_NP 8
 #define MHD_NEM 4
 
@@ -83,6 +90,7 @@ extern "C" {
 #define MHD_EVOLVE_MHD 2u
 #define MHD_COUPLE_MATTER 4u
 #define MHD_EVOLVE_M1 8u /* grey M1 radiation, three species (Sec. 2.3): U has MHD_NU_M1 fields */
+#define MHD_EVOLVE_M1N 16u /* with MHD_EVOLVE_M1: the number densities too (Sec. 2.3): MHD_NU_M1N fields */
 
 /* f_alpha_kind: the slicing function f_alpha(alpha) of the lapse equation */
 #define MHD_FALPHA_ONE 0      /* 1+log slicing, f_alpha = 1 (the paper's standard) */
@@ -125,7 +133,10 @@ typedef struct {
   double beta0[3];
   double sigma_ko, c_b, kappa_b, alpha_mp5, f_beta;
   int32_t f_alpha_kind;
-  uint32_t flags; /* MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER */
+  uint32_t flags; /* MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER | MHD_EVOLVE_M1 | MHD_EVOLVE_M1N */
+  double m_b;     /* reference baryon mass of the electron-fraction source (Sec. 2.2), with MHD_EVOLVE_M1N */
+  double les_cm;  /* C_M of the gradient SGS (LES) term of the induction equation (App. A; the paper uses 8);
+                     0 switches the term off.  Single patches only (mhd_level_create rejects it). */
 } mhd_params_t;
 
 /* Launch tuning.  The results never depend on it (bitwise).
@@ -237,15 +248,15 @@ int mhd_con2prim_learned(const mhd_patch_t* patch, const mhd_eos_t* eos, const f
 /* Allocation-free variant of mhd_con2prim_learned, for callers that cannot
  * allocate device memory (code under stream or graph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  Same kernels, arguments, outputs
- * and results as mhd_con2prim_learned, without the workspace: the fallback
- * queue is a file-scope device array of the library, 256 + 4 * 2^22 bytes
- * (16 MiB) per device, held from the first call on a device until the process
- * ends.  The padded patch must have at most 2^22 points (4 194 304; a 155^3
+ * and results as mhd_con2prim_learned, without the workspace: the two queues
+ * and the network's rows live in a file-scope device array of the library,
+ * 512 + 40 * 2^22 bytes (160 MiB) per device, held from the first call on a
+ * device until the process ends.  The padded patch must have at most 2^22 points (4 194 304; a 155^3
  * padded patch fits), else MHD_EINVAL.  The call allocates nothing; its first
  * call on a device looks up the array's address (MHD_EHIP if that fails) with
  * that device current, and the stream must belong to the current device.
- * Every call on a device shares that device's queue, whose count the call
- * clears by a kernel on `stream` before use: calls that overlap on one device
+ * Every call on a device shares that device's array, whose queue counts the
+ * call clears by a kernel on `stream` before use: calls that overlap on one device
  * (different streams, or threads without ordering between their streams)
  * race and give wrong answers. */
 int mhd_con2prim_learned_noalloc(const mhd_patch_t* patch, const mhd_eos_t* eos, const float* mlp, double* U,
@@ -288,20 +299,25 @@ int mhd_mlp_adam(float* mlp, const float* grad, float* m, float* v, int step, fl
  * also evolves the three grey M1 species (Sec. 2.3, 3.4): U, Us, k and acc then
  * hold MHD_NU_M1 fields, aux is required and the workspace is
  * mhd_rhs_workspace_size_m1() bytes; the results are bitwise those of per-box
- * mhd_rhs with MHD_EVOLVE_M1 and mhd_rk_stage over 44 fields.
+ * mhd_rhs with MHD_EVOLVE_M1 and mhd_rk_stage over 44 fields.  With
+ * MHD_EVOLVE_M1N too, the three number densities as well (Sec. 2.3): MHD_NU_M1N
+ * fields, MHD_NAUX_N aux fields, mhd_rhs_workspace_size_m1n() bytes, and
+ * params->m_b finite.  The LES term (les_cm != 0) is rejected: single patches
+ * only.
  * mhd_level_create copies the descriptors to the device (the only allocation,
  * with a capture stream); the arrays stay the caller's and must outlive it. */
 typedef struct {
   mhd_patch_t patch;
-  double* U;        /* state at t^n (32 or 44 fields); the RK4 step updates it in place */
-  double* Us;       /* stage state (32 or 44 fields) */
+  double* U;        /* state at t^n (32, 44 or 47 fields); the RK4 step updates it in place */
+  double* Us;       /* stage state (as U) */
   double* P;        /* primitives (8 fields) */
-  double* k;        /* right-hand side (32 or 44 fields) */
-  double* acc;      /* RK4 accumulator (32 or 44 fields) */
-  void* workspace;  /* mhd_rhs_workspace_size(&patch) bytes or more (_m1 with M1) */
+  double* k;        /* right-hand side (as U) */
+  double* acc;      /* RK4 accumulator (as U) */
+  void* workspace;  /* mhd_rhs_workspace_size(&patch) bytes or more (_m1 with M1, _m1n with M1N) */
   size_t workspace_bytes;
   uint8_t* flags;   /* con2prim flags, may be NULL */
-  const double* aux; /* MHD_NAUX fields (kappa_a, kappa_s, eta per species) with MHD_EVOLVE_M1, else NULL */
+  const double* aux; /* MHD_NAUX fields (kappa_a, kappa_s, eta per species) with MHD_EVOLVE_M1, MHD_NAUX_N
+                        with MHD_EVOLVE_M1N, else NULL */
 } mhd_box_t;
 
 typedef struct mhd_level mhd_level_t;
@@ -337,7 +353,8 @@ int mhd_level_set_learned(mhd_level_t* level, const float* mlp, void* workspace,
 
 /* IMEX(4,4,2) on a batched level (Table I; App. C), for a level that evolves M1.
  * mhd_level_set_imex: per box (same order as at creation), the explicit parts
- *   F[s] (MHD_NU_M1 fields) and stiff parts R[s] (12 fields) of the four
+ *   F[s] (MHD_NU_M1 fields, MHD_NU_M1N with the number densities) and stiff
+ *   parts R[s] (12 fields, 15 with the number densities) of the four
  *   stages, device arrays in the box's patch layout, caller-owned, outliving
  *   their use; boxes = NULL detaches them.  Waits for the device.
  * mhd_level_imex_step: one step of size dt of every box, per box and stage the
@@ -364,13 +381,35 @@ size_t mhd_rhs_workspace_size(const mhd_patch_t* patch);
 /* Workspace of mhd_rhs with MHD_EVOLVE_M1 (closure, point fluxes, speeds). */
 size_t mhd_rhs_workspace_size_m1(const mhd_patch_t* patch);
 
+/* Workspace of mhd_rhs with MHD_EVOLVE_M1 | MHD_EVOLVE_M1N (as _m1, plus the
+ * number densities' point fluxes and the factors Gamma). */
+size_t mhd_rhs_workspace_size_m1n(const mhd_patch_t* patch);
+
 /* L(U) at the interior points (Sec. 2.1, 2.2, 2.3, 3.2, 3.3, 3.4, App. B).
- * In: U (32 fields incl. ghosts, 44 with MHD_EVOLVE_M1), P (8 fields incl.
- *   ghosts; from con2prim), aux (MHD_NAUX fields, required with
- *   MHD_EVOLVE_M1, else ignored and may be NULL).
- * Out: rhs (32 or 44 fields, interior points only; ghost entries untouched).
+ * In: U (32 fields incl. ghosts, 44 with MHD_EVOLVE_M1, 47 with
+ *   MHD_EVOLVE_M1N too), P (8 fields incl. ghosts; from con2prim), aux
+ *   (MHD_NAUX fields with MHD_EVOLVE_M1, MHD_NAUX_N with MHD_EVOLVE_M1N;
+ *   else ignored and may be NULL).
+ * Out: rhs (32, 44 or 47 fields, interior points only; ghost entries untouched).
  *   With MHD_EVOLVE_M1 the radiation also enters the CCZ4 matter terms (if
  *   MHD_COUPLE_MATTER) and exchanges energy and momentum with the fluid.
+ *   With MHD_EVOLVE_M1N the number densities are evolved (Sec. 2.3): number
+ *   current N^a = n (u^a + H^a/J) of the closure's J and H^a, so the d_k-flux
+ *   of Nbar is (-W beta^k + alpha W v^k + alpha H^k/J) Nbar/Gamma with
+ *   Gamma = W (E - F_i v^i)/J and H^k = gamma^kj H_j + W (J - E + F_i v^i)
+ *   beta^k/alpha; HO/LO interfaces as the energy moments' (Sec. 3.4, the
+ *   species' speed and kappa_a + kappa_s); source alpha sqrt(gamma) C with
+ *   C = eta0 - kappa0_a N/Gamma; and the electron fraction's DYebar gains
+ *   -alpha sqrt(gamma) m_b (C_0 - C_1) (Sec. 2.2).
+ *   With params->les_cm != 0 (and MHD_EVOLVE_MHD) the gradient SGS term of
+ *   App. A enters the induction equation: the flux of Bbar^i along k gains
+ *   -alpha G_B^{ki}, G_B^{ki} = -C_M xi sqrt(gamma) H_M^{ki}, xi = gamma^(1/3)
+ *   Delta^2/24 with Delta^2 = (dx dy dz)^(2/3), H_M^{ki} = B^i H_v^k - B^k H_v^i
+ *   + 2 (grad B^i . grad v^k - grad B^k . grad v^i) (dot products with
+ *   gamma^jl), H_v the velocity part of the primitives' second-order response
+ *   to filtering the conserved fields (the quantity App. A's closed forms
+ *   abbreviate); first derivatives of the primitives by 4th-order centred
+ *   differences, the divergence by 2nd-order centred ones.
  * max_speed: device double, max over interior points and axes of the point
  *   speed (fast magnetosonic bound and cleaning mode, and the M1 speed);
  *   updated with an atomic max, the caller initialises it (to 0).  May be NULL.
@@ -383,15 +422,27 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
 /* ---- IMEX(4,4,2) of Table I for the stiff radiation collisions (App. C) -----
  * mhd_rhs_split: as mhd_rhs with MHD_EVOLVE_M1, but the radiation's collision
  *   terms alpha sqrt(gamma) (S_n, S_i) (the stiff part) go to `stiff` (12
- *   fields, species-major, patch layout) instead of rhs; the fluid's opposite
- *   exchange stays in rhs (explicit).
- * mhd_imex_combine: at the interior points of all 44 fields, stage s = 0..3:
- *   Uout = Un + dt sum_{j<s} AE[s][j] F[j], and on the radiation fields also
- *   + dt sum_{j<s} AI[s][j] R[j] (the explicit state V* of the stage); s = 4:
- *   Uout = Un + dt sum_i (BE[i] F[i] + BI[i] R[i]) (radiation) and
- *   Un + dt sum_i BE[i] F[i] (other fields).  F, R: host arrays of 4 device
- *   pointers to stage explicit (44 fields) and stiff (12 fields) parts; only
- *   the entries the stage reads must be set.  Uout may alias Un only at s = 4.
+ *   fields, species-major, patch layout; with MHD_EVOLVE_M1N 15, the number
+ *   densities' alpha sqrt(gamma) C at 12 + s) instead of rhs; the fluid's
+ *   opposite exchange and the electron fraction's source stay in rhs
+ *   (explicit).
+ * mhd_imex_combine: for scheme MHD_IMEX_442 (Table I: explicit RK4 with the
+ *   L-stable I42L, ns = 4 stages) or MHD_IMEX_332 (Table II's SSP-RK(3,3)
+ *   with an L-stable I32L re-derived from Sec. 3.1's order and L-stability
+ *   conditions, ns = 3: the printed implicit half is first order, its rows
+ *   summing to (0, 1, 1) against its c = (0, 1, 1/2); the re-derived one keeps
+ *   the printed first row, c and b, with diagonal gamma = 1 - 1/sqrt(2): rows
+ *   (0,0,0), (1 - gamma, gamma, 0), (1/2 - gamma - a32, a32, gamma),
+ *   a32 = 3 gamma (1 - 2 gamma)/4), at the interior points of all nfields
+ *   fields (44, or 47 with the number densities), stage s = 0..ns-1:
+ *   Uout = Un + dt sum_{j<s} AE[s][j] F[j], and on the radiation fields (32
+ *   and up) also + dt sum_{j<s} AI[s][j] R[j] (the explicit state V* of the
+ *   stage); s = ns: Uout = Un + dt sum_i (BE[i] F[i] + BI[i] R[i]) (radiation)
+ *   and Un + dt sum_i BE[i] F[i] (other fields).  F, R: host arrays of 4
+ *   device pointers to stage explicit (nfields fields) and stiff (nfields - 32
+ *   fields) parts; only the entries the stage reads must be set.  Uout may
+ *   alias Un only at s = ns.  The implicit solve of stage s takes
+ *   adt = AI[s][s] dt.
  * mhd_m1_implicit: at the interior points, per species, replaces the radiation
  *   fields V* of U by the solution V of V = V* + adt alpha (S_n, S_i)(V)
  *   (undensitized), the fluid state from P, the closure's Eddington factor
@@ -401,14 +452,20 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
  *   rounding floor: App. C leaves the stopping rule open).  A solve that does
  *   not converge (singular Jacobian, or 60 iterations) keeps the first Newton
  *   iterate, App. C's linearised implicit update about V*; nfail (device
- *   uint64, may be NULL) is incremented per such species solve. */
+ *   uint64, may be NULL) is incremented per such species solve.  With
+ *   evolve_n != 0 (U of 47 fields, aux of MHD_NAUX_N) each species' number
+ *   density then takes App. C's closed-form implicit update
+ *   N = (N* + adt alpha eta0)/(1 + adt alpha kappa0_a/Gamma), Gamma from the
+ *   updated E, F_i and their closure. */
 int mhd_rhs_split(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
                   const double* P, const double* aux, double* rhs, double* stiff, double* max_speed, void* workspace,
                   size_t workspace_bytes, void* stream);
-int mhd_imex_combine(const mhd_patch_t* patch, int stage, double dt, const double* Un, const double* const* F,
-                     const double* const* R, double* Uout, void* stream);
+#define MHD_IMEX_442 0
+#define MHD_IMEX_332 1
+int mhd_imex_combine(const mhd_patch_t* patch, int scheme, int nfields, int stage, double dt, const double* Un,
+                     const double* const* F, const double* const* R, double* Uout, void* stream);
 int mhd_m1_implicit(const mhd_patch_t* patch, const double* aux, double* U, const double* P, double adt,
-                    uint64_t* nfail, void* stream);
+                    int evolve_n, uint64_t* nfail, void* stream);
 
 /* Explicit RK4 stage of Table I at the interior points of `nfields` fields:
  *   stage s (0..3): acc = (s ? acc : 0) + b_s k;  s < 3: Unext = Un + dt a_{s+1,s} k;

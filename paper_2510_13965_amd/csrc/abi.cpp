@@ -15,13 +15,17 @@
 namespace mhd {
 int launch_ccz4(const Geom& g, const mhd_params_t& par, const double* U, const double* P, double* rhs, double* ws,
                 int strip, const double* m1P, hipStream_t s);
-int m1_workspace_fields();
-int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, hipStream_t s);
+int m1_workspace_fields(bool nd);
+int les_workspace_fields();
+int launch_les(const Geom& g, const mhd_eos_t& eos, double cm, const double* U, const double* P, double* ws,
+               double* rhs, hipStream_t s);
+int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, int nd,
+                    hipStream_t s);
 int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
-                     double* max_speed, double* stiff, hipStream_t s);
-int launch_imex_combine(const Geom& g, int stage, double dt, const double* Un, const double* const* F,
-                        const double* const* R, double* Uout, hipStream_t s);
-int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt,
+                     double* max_speed, double* stiff, int nd, double m_b, hipStream_t s);
+int launch_imex_combine(const Geom& g, int scheme, int nfields, int stage, double dt, const double* Un,
+                        const double* const* F, const double* const* R, double* Uout, hipStream_t s);
+int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt, int nd,
                        unsigned long long* nfail, hipStream_t s);
 int ccz4_workspace_fields();
 int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,
@@ -207,7 +211,9 @@ static int64_t padded_points(const mhd_patch_t* p) {
 
 size_t mhd_con2prim_learned_workspace_size(const mhd_patch_t* patch) {
   if (!patch) return 0;
-  return 256 + 4 * (size_t)padded_points(patch);
+  // counts, two 4-byte queues, then (256-byte aligned) one 8-float row per point
+  const size_t n = (size_t)padded_points(patch);
+  return ((256 + 8 * n + 255) / 256) * 256 + 32 * n;
 }
 
 int mhd_con2prim_learned(const mhd_patch_t* patch, const mhd_eos_t* eos, const float* mlp, double* U, double* P,
@@ -285,15 +291,25 @@ int mhd_mlp_adam(float* mlp, const float* grad, float* m, float* v, int step, fl
                    "mhd_mlp_adam");
 }
 
+// fields of the base workspace: 33 of point fluxes and speeds (GRMHD), the CCZ4
+// second derivatives, then the LES term's B^i and alpha G_B (6)
+static int64_t base_workspace_fields() {
+  return 33 + (int64_t)mhd::ccz4_workspace_fields() + (int64_t)mhd::les_workspace_fields();
+}
+
 size_t mhd_rhs_workspace_size(const mhd_patch_t* patch) {
   if (!patch) return 0;
-  // 33 fields of point fluxes and speeds (GRMHD), then the CCZ4 second derivatives
-  return (size_t)(33 + mhd::ccz4_workspace_fields()) * (size_t)patch->sf * sizeof(double);
+  return (size_t)base_workspace_fields() * (size_t)patch->sf * sizeof(double);
 }
 
 size_t mhd_rhs_workspace_size_m1(const mhd_patch_t* patch) {
   if (!patch) return 0;
-  return mhd_rhs_workspace_size(patch) + (size_t)mhd::m1_workspace_fields() * (size_t)patch->sf * sizeof(double);
+  return mhd_rhs_workspace_size(patch) + (size_t)mhd::m1_workspace_fields(false) * (size_t)patch->sf * sizeof(double);
+}
+
+size_t mhd_rhs_workspace_size_m1n(const mhd_patch_t* patch) {
+  if (!patch) return 0;
+  return mhd_rhs_workspace_size(patch) + (size_t)mhd::m1_workspace_fields(true) * (size_t)patch->sf * sizeof(double);
 }
 
 static int rhs_impl(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
@@ -305,13 +321,18 @@ static int rhs_impl(const mhd_patch_t* patch, const mhd_params_t* params, const 
   if (!U || !rhs) return fail(MHD_EINVAL, "mhd_rhs: U and rhs must be non-NULL");
   const uint32_t fl = params->flags;
   const bool m1 = (fl & MHD_EVOLVE_M1) != 0;
+  const bool nd = m1 && (fl & MHD_EVOLVE_M1N) != 0;
+  if ((fl & MHD_EVOLVE_M1N) && !m1) return fail(MHD_EINVAL, "mhd_rhs: MHD_EVOLVE_M1N needs MHD_EVOLVE_M1");
+  if (nd && !std::isfinite(params->m_b)) return fail(MHD_EINVAL, "mhd_rhs: m_b must be finite");
   if ((fl & (MHD_EVOLVE_MHD | MHD_COUPLE_MATTER)) && !P)
     return fail(MHD_EINVAL, "mhd_rhs: P is required when the fluid is evolved or coupled");
   if (m1 && (!P || !aux)) return fail(MHD_EINVAL, "mhd_rhs: P and aux are required with MHD_EVOLVE_M1");
   if ((fl & MHD_EVOLVE_MHD) && !(params->c_b > 0.0)) return fail(MHD_EINVAL, "mhd_rhs: c_b must be > 0");
+  if (!std::isfinite(params->les_cm)) return fail(MHD_EINVAL, "mhd_rhs: les_cm must be finite");
   if (params->f_alpha_kind != MHD_FALPHA_ONE && params->f_alpha_kind != MHD_FALPHA_HARMONIC)
     return fail(MHD_EINVAL, "mhd_rhs: unknown f_alpha_kind %d", params->f_alpha_kind);
-  const size_t need = m1 ? mhd_rhs_workspace_size_m1(patch) : mhd_rhs_workspace_size(patch);
+  const size_t need = nd ? mhd_rhs_workspace_size_m1n(patch)
+                        : (m1 ? mhd_rhs_workspace_size_m1(patch) : mhd_rhs_workspace_size(patch));
   if (!workspace || workspace_bytes < need)
     return fail(MHD_EWORKSPACE, "mhd_rhs: workspace of %zu bytes needed (got %zu)", need, workspace_bytes);
   if (patch->sf > (int64_t)(INT32_MAX / 8))
@@ -320,8 +341,9 @@ static int rhs_impl(const mhd_patch_t* patch, const mhd_params_t* params, const 
   const mhd::Geom g = geom_of(patch);
   hipStream_t s = (hipStream_t)stream;
   double* ws = (double*)workspace;
-  double* ws_m1 = ws + (int64_t)(33 + mhd::ccz4_workspace_fields()) * patch->sf;
-  if (m1 && (rc = hip_check(mhd::launch_m1_point(g, U, P, aux, ws_m1, s), "mhd_rhs/m1 point"))) return rc;
+  double* ws_les = ws + (int64_t)(33 + mhd::ccz4_workspace_fields()) * patch->sf;
+  double* ws_m1 = ws + base_workspace_fields() * patch->sf;
+  if (m1 && (rc = hip_check(mhd::launch_m1_point(g, U, P, aux, ws_m1, nd ? 1 : 0, s), "mhd_rhs/m1 point"))) return rc;
   const bool radiation_matter = m1 && (fl & MHD_COUPLE_MATTER);
   if (fl & MHD_EVOLVE_SPACETIME) {
     if ((rc = hip_check(mhd::launch_ccz4(g, *params, U, P, rhs, ws + 33 * patch->sf, g_strip,
@@ -335,10 +357,15 @@ static int rhs_impl(const mhd_patch_t* patch, const mhd_params_t* params, const 
   if (fl & MHD_EVOLVE_MHD) {
     if ((rc = hip_check(mhd::launch_mhd(g, *params, *eos, U, P, ws, rhs, max_speed, g_strip, s), "mhd_rhs/grmhd")))
       return rc;
+    if (params->les_cm != 0.0 &&
+        (rc = hip_check(mhd::launch_les(g, *eos, params->les_cm, U, P, ws_les, rhs, s), "mhd_rhs/les")))
+      return rc;
   } else {
     if ((rc = hip_check(mhd::launch_zero_interior(g, MHD_NST, MHD_NMHD, rhs, s), "mhd_rhs/zero"))) return rc;
   }
-  if (m1 && (rc = hip_check(mhd::launch_m1_update(g, U, P, aux, ws_m1, rhs, max_speed, stiff, s), "mhd_rhs/m1 update")))
+  if (m1 && (rc = hip_check(mhd::launch_m1_update(g, U, P, aux, ws_m1, rhs, max_speed, stiff, nd ? 1 : 0, params->m_b,
+                                                  s),
+                            "mhd_rhs/m1 update")))
     return rc;
   return MHD_OK;
 }
@@ -357,14 +384,19 @@ int mhd_rhs_split(const mhd_patch_t* patch, const mhd_params_t* params, const mh
   return rhs_impl(patch, params, eos, U, P, aux, rhs, stiff, max_speed, workspace, workspace_bytes, stream);
 }
 
-int mhd_imex_combine(const mhd_patch_t* patch, int stage, double dt, const double* Un, const double* const* F,
-                     const double* const* R, double* Uout, void* stream) {
+int mhd_imex_combine(const mhd_patch_t* patch, int scheme, int nfields, int stage, double dt, const double* Un,
+                     const double* const* F, const double* const* R, double* Uout, void* stream) {
   int rc;
-  if ((rc = check_patch(patch, -1, MHD_NU_M1, "mhd_imex_combine"))) return rc;
-  if (stage < 0 || stage > 4) return fail(MHD_EINVAL, "mhd_imex_combine: stage must be 0..4");
+  if (scheme != MHD_IMEX_442 && scheme != MHD_IMEX_332)
+    return fail(MHD_EINVAL, "mhd_imex_combine: scheme must be MHD_IMEX_442 or MHD_IMEX_332");
+  const int ns = scheme == MHD_IMEX_442 ? 4 : 3;
+  if (nfields != MHD_NU_M1 && nfields != MHD_NU_M1N)
+    return fail(MHD_EINVAL, "mhd_imex_combine: nfields must be %d or %d", MHD_NU_M1, MHD_NU_M1N);
+  if ((rc = check_patch(patch, -1, nfields, "mhd_imex_combine"))) return rc;
+  if (stage < 0 || stage > ns) return fail(MHD_EINVAL, "mhd_imex_combine: stage must be 0..%d", ns);
   if (!Un || !Uout || !F || !R) return fail(MHD_EINVAL, "mhd_imex_combine: NULL array");
   if (!std::isfinite(dt)) return fail(MHD_EINVAL, "mhd_imex_combine: dt must be finite");
-  const int nread = stage < 4 ? stage : 4;
+  const int nread = stage < ns ? stage : ns;
   const double* f4[4] = {nullptr, nullptr, nullptr, nullptr};
   const double* r4[4] = {nullptr, nullptr, nullptr, nullptr};
   for (int j = 0; j < nread; ++j) {
@@ -372,18 +404,19 @@ int mhd_imex_combine(const mhd_patch_t* patch, int stage, double dt, const doubl
     f4[j] = F[j];
     r4[j] = R[j];
   }
-  if (Uout == Un && stage < 4) return fail(MHD_EINVAL, "mhd_imex_combine: Uout may alias Un only at stage 4");
-  return hip_check(mhd::launch_imex_combine(geom_of(patch), stage, dt, Un, f4, r4, Uout, (hipStream_t)stream),
-                   "mhd_imex_combine");
+  if (Uout == Un && stage < ns) return fail(MHD_EINVAL, "mhd_imex_combine: Uout may alias Un only at the final stage");
+  return hip_check(
+      mhd::launch_imex_combine(geom_of(patch), scheme, nfields, stage, dt, Un, f4, r4, Uout, (hipStream_t)stream),
+      "mhd_imex_combine");
 }
 
 int mhd_m1_implicit(const mhd_patch_t* patch, const double* aux, double* U, const double* P, double adt,
-                    uint64_t* nfail, void* stream) {
+                    int evolve_n, uint64_t* nfail, void* stream) {
   int rc;
   if ((rc = check_patch(patch, -1, 1, "mhd_m1_implicit"))) return rc;
   if (!aux || !U || !P) return fail(MHD_EINVAL, "mhd_m1_implicit: aux, U and P are required");
   if (!(adt >= 0.0) || !std::isfinite(adt)) return fail(MHD_EINVAL, "mhd_m1_implicit: adt must be finite and >= 0");
-  return hip_check(mhd::launch_m1_implicit(geom_of(patch), U, P, aux, adt,
+  return hip_check(mhd::launch_m1_implicit(geom_of(patch), U, P, aux, adt, evolve_n ? 1 : 0,
                                            reinterpret_cast<unsigned long long*>(nfail), (hipStream_t)stream),
                    "mhd_m1_implicit");
 }

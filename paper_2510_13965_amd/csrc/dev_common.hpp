@@ -126,8 +126,8 @@ struct BoxDev {
   uint8_t* flags;
   const double* aux;  // M1 opacities and emissivities (levels evolving radiation), else null
   double* ws_m1;      // M1 part of the RHS workspace, else null
-  double* F[4];       // IMEX: explicit parts of the four stages (44 fields), else null
-  double* R[4];       // IMEX: stiff parts of the four stages (12 fields), else null
+  double* F[4];       // IMEX: explicit parts of the four stages (44 or 47 fields), else null
+  double* R[4];       // IMEX: stiff parts of the four stages (12 or 15 fields), else null
   int cpp_int, cpp_pad;    // chunks per interior / padded z plane
   int64_t t0_int, t0_pad;  // first global tile id of the box in each space
   int ntx_lds, nty_lds, nzc_lds;  // LDS-staged kernels: (x, y) tiles and z chunks of the box
@@ -140,8 +140,9 @@ struct LevelArgs {
   int strip;
   int src;  // 0: evaluate at U, 1: at Us
   int stage;
-  int nfields;  // evolved fields: 32, or 44 with three M1 species
+  int nfields;  // evolved fields: 32, 44 with three M1 species, 47 with their number densities
   int m1;       // nonzero: the boxes evolve the M1 radiation
+  int nd;       // nonzero: and the three number densities (15 aux fields, 75 M1 workspace fields)
   int slot;     // right-hand side into k (-1) or, in an IMEX stage, into F[slot] with the stiff part in R[slot]
   double adt;   // IMEX: implicit step a_ii dt of the collision solve
   unsigned long long* nfail;  // IMEX: count of collision solves that did not converge (may be null)
@@ -153,8 +154,10 @@ struct LevelArgs {
   int64_t* stats;
   // con2prim with the learned guess (mlp == nullptr: the bracketed solver)
   const float* mlp;
-  uint32_t* qcount;
-  uint64_t* queue;
+  uint32_t* qcount;  // [0]: points to solve, [1]: points for the bracketed solver
+  uint64_t* queue;   // (box << 32) | padded point of the points to solve
+  uint64_t* fqueue;  // the same for the rejected points
+  float* feat;       // per solve-queue slot: 8 network inputs, then its 2 outputs in place
 };
 
 // where the right-hand-side kernels of a level write: k (RK), or an IMEX

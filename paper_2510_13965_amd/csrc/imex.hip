@@ -13,7 +13,11 @@
 //                   1e-9 (E + |F|) is not below half of the previous one
 //                   (Newton has stopped contracting: rounding floor); a solve
 //                   that does not converge keeps the first Newton iterate
-//                   (App. C's linearised implicit update about V*)
+//                   (App. C's linearised implicit update about V*); with the
+//                   number densities, each species' N then takes App. C's
+//                   closed-form update N = (N* + adt alpha eta0) /
+//                   (1 + adt alpha kappa0_a/Gamma), Gamma from the updated
+//                   E, F_i and their closure
 #include "c2p_dev.hpp"
 #include "m1_dev.hpp"
 #include "prof.hpp"
@@ -22,36 +26,54 @@ namespace mhd {
 
 #pragma clang fp contract(off)
 
-__constant__ double kImAE[4][4] = {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1.0, 0}};
-__constant__ double kImAI[4][4] = {
-    {0, 0, 0, 0}, {0.25, 0.25, 0, 0}, {0, 1.0 / 6.0, 1.0 / 3.0, 0}, {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}};
-__constant__ double kImB[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+// Tableaux, [scheme][stage][j]: scheme 0 is Table I's IMEX(4,4,2) (explicit
+// RK4 with I42L); scheme 1 is IMEX(3,3,2): Table II's explicit SSP-RK(3,3)
+// with an L-stable I32L re-derived from Sec. 3.1's conditions (the printed one
+// is first order: its rows sum to (0, 1, 1) against its c = (0, 1, 1/2)).
+// The re-derived I32L keeps the printed explicit first stage, c and b and has
+// equal diagonal entries gamma = 1 - 1/sqrt(2): rows (0, 0, 0),
+// (1 - gamma, gamma, 0), (1/2 - gamma - a32, a32, gamma) with
+// a32 = 3 gamma (1 - 2 gamma)/4 (the values below are those expressions
+// evaluated in double).  In both schemes b is the same for the two halves.
+__constant__ double kImAE[2][4][4] = {
+    {{0, 0, 0, 0}, {0.5, 0, 0, 0}, {0, 0.5, 0, 0}, {0, 0, 1.0, 0}},
+    {{0, 0, 0, 0}, {1.0, 0, 0, 0}, {0.25, 0.25, 0, 0}, {0, 0, 0, 0}}};
+__constant__ double kImAI[2][4][4] = {
+    {{0, 0, 0, 0}, {0.25, 0.25, 0, 0}, {0, 1.0 / 6.0, 1.0 / 3.0, 0}, {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}},
+    {{0, 0, 0, 0},
+     {0.7071067811865476, 0.2928932188134524, 0, 0},
+     {0.11611652351681563, 0.09099025766973194, 0.2928932188134524, 0},
+     {0, 0, 0, 0}}};
+__constant__ double kImB[2][4] = {{1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}, {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0, 0}};
+__constant__ int kImStages[2] = {4, 3};
 
 struct ImexArgs {
   Geom g;
+  int scheme;  // 0: IMEX(4,4,2), 1: IMEX(3,3,2)
   int stage;
   double dt;
   const double* Un;
-  const double* F[4];  // explicit parts of the earlier stages (44 fields)
-  const double* R[4];  // stiff parts (12 fields)
+  const double* F[4];  // explicit parts of the earlier stages (44 or 47 fields)
+  const double* R[4];  // stiff parts (12 or 15 fields)
   double* Uout;
 };
 
-// block 64x4, grid z = nz * 44 (field-major)
-// one element of stage `s` of Table I's IMEX combination: field f (0..43) at
+// block 64x4, grid z = nz * nfields (field-major)
+// one element of stage `s` of Table I's IMEX combination: field f (0..46) at
 // point pt; the stiff parts exist for the radiation fields (f >= 32) only
-__device__ __forceinline__ void imex_element(int s, double dt, const double* Un, const double* const* F,
+__device__ __forceinline__ void imex_element(int sc, int s, double dt, const double* Un, const double* const* F,
                                              const double* const* R, double* Uout, int f, int64_t pt, int64_t sf) {
   const int64_t p = (int64_t)f * sf + pt;
+  const int ns = kImStages[sc];
   double v = Un[p];
-  if (s < 4) {
-    for (int jj = 0; jj < s; ++jj) v += dt * kImAE[s][jj] * F[jj][p];
+  if (s < ns) {
+    for (int jj = 0; jj < s; ++jj) v += dt * kImAE[sc][s][jj] * F[jj][p];
     if (f >= 32)
-      for (int jj = 0; jj < s; ++jj) v += dt * kImAI[s][jj] * R[jj][(int64_t)(f - 32) * sf + pt];
+      for (int jj = 0; jj < s; ++jj) v += dt * kImAI[sc][s][jj] * R[jj][(int64_t)(f - 32) * sf + pt];
   } else {
-    for (int st = 0; st < 4; ++st) v += dt * kImB[st] * F[st][p];
+    for (int st = 0; st < ns; ++st) v += dt * kImB[sc][st] * F[st][p];
     if (f >= 32)
-      for (int st = 0; st < 4; ++st) v += dt * kImB[st] * R[st][(int64_t)(f - 32) * sf + pt];
+      for (int st = 0; st < ns; ++st) v += dt * kImB[sc][st] * R[st][(int64_t)(f - 32) * sf + pt];
   }
   Uout[p] = v;
 }
@@ -63,7 +85,7 @@ __global__ void __launch_bounds__(256) k_imex_combine(ImexArgs a) {
   const int kz = blockIdx.z % g.nz;
   const int f = blockIdx.z / g.nz;
   if (i >= g.nx || j >= g.ny) return;
-  imex_element(a.stage, a.dt, a.Un, a.F, a.R, a.Uout, f, g.at(i + g.ng, j + g.ng, kz + g.ng), g.sf);
+  imex_element(a.scheme, a.stage, a.dt, a.Un, a.F, a.R, a.Uout, f, g.at(i + g.ng, j + g.ng, kz + g.ng), g.sf);
 }
 
 // every field of every interior point of a level's boxes; stage 4 writes U
@@ -75,7 +97,7 @@ __global__ void __launch_bounds__(256) k_imex_combine_lv(LevelArgs L) {
     const double* const* F = B.F;
     const double* const* R = B.R;
 #pragma unroll 4
-    for (int f = 0; f < MHD_NU_M1; ++f) imex_element(L.stage, L.dt, B.U, F, R, out, f, pt, B.g.sf);
+    for (int f = 0; f < L.nfields; ++f) imex_element(0, L.stage, L.dt, B.U, F, R, out, f, pt, B.g.sf);
   });
 }
 
@@ -177,13 +199,14 @@ struct ImplArgs {
   const double* __restrict__ aux;
   double adt;
   unsigned long long* nfail;
+  int nd;  // nonzero: the number densities (U fields 44..46, aux 9..14) follow
 };
 
 // the implicit collision solve of the three species at interior point q (padded
 // index); returns the number of species solves that did not converge
 __device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const double* __restrict__ P,
                                                            const double* __restrict__ aux, int64_t sf, int64_t q,
-                                                           double adt) {
+                                                           double adt, int nd = 0) {
   MetricR m;
   m1_metric(U, sf, q, m);
   const double alp = U[18 * sf + q];
@@ -242,6 +265,19 @@ __device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const do
     U[(int64_t)(32 + 4 * sp) * sf + q] = m.sqrtg * V[0];
 #pragma unroll
     for (int r = 0; r < 3; ++r) U[(int64_t)(33 + 4 * sp + r) * sf + q] = m.sqrtg * V[1 + r];
+    if (nd) {
+      // the number density, from the moments just stored (read back as the
+      // densitized fields they now are) and their closure
+      M1State s1;
+      m1_load_state(U, P, sf, q, sp, m, s1);
+      const double chi1 = m1_closure_chi(s1, m.gd, m.gu);
+      double Pij[6], J, H[3], HH;
+      m1_closure_eval(s1, m.gd, m.gu, chi1, Pij, J, H, HH);
+      const double gam = s1.W * (s1.E - s1.vF) / J;
+      const double k0 = aux[(int64_t)(9 + 2 * sp) * sf + q], e0 = aux[(int64_t)(10 + 2 * sp) * sf + q];
+      const double Ns = U[(int64_t)(44 + sp) * sf + q] / m.sqrtg;
+      U[(int64_t)(44 + sp) * sf + q] = m.sqrtg * (Ns + adt * alp * e0) / (1.0 + adt * alp * k0 / gam);
+    }
   }
   return bad;
 }
@@ -252,7 +288,7 @@ __global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
-  const unsigned long long bad = m1_implicit_at(a.U, a.P, a.aux, g.sf, g.at(i + g.ng, j + g.ng, k + g.ng), a.adt);
+  const unsigned long long bad = m1_implicit_at(a.U, a.P, a.aux, g.sf, g.at(i + g.ng, j + g.ng, k + g.ng), a.adt, a.nd);
   if (bad && a.nfail) atomicAdd(a.nfail, bad);
 }
 
@@ -262,15 +298,16 @@ __global__ void __launch_bounds__(256) k_m1_implicit_lv(LevelArgs L) {
   unsigned long long bad = 0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    bad += m1_implicit_at(B.Us, B.P, B.aux, B.g.sf, B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng), L.adt);
+    bad += m1_implicit_at(B.Us, B.P, B.aux, B.g.sf, B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng), L.adt, L.nd);
   });
   if (bad && L.nfail) atomicAdd(L.nfail, bad);
 }
 
-int launch_imex_combine(const Geom& g, int stage, double dt, const double* Un, const double* const* F,
-                        const double* const* R, double* Uout, hipStream_t s) {
+int launch_imex_combine(const Geom& g, int scheme, int nfields, int stage, double dt, const double* Un,
+                        const double* const* F, const double* const* R, double* Uout, hipStream_t s) {
   ImexArgs a;
   a.g = g;
+  a.scheme = scheme;
   a.stage = stage;
   a.dt = dt;
   a.Un = Un;
@@ -279,7 +316,7 @@ int launch_imex_combine(const Geom& g, int stage, double dt, const double* Un, c
     a.R[st] = R[st];
   }
   a.Uout = Uout;
-  dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * 44);
+  dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz * nfields);
   MHD_LAUNCH(KID_IMEX_COMBINE, k_imex_combine, grd, dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
@@ -294,9 +331,9 @@ int launch_m1_implicit_level(const LevelArgs& L, int grid, int block, hipStream_
   return (int)hipGetLastError();
 }
 
-int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt,
+int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt, int nd,
                        unsigned long long* nfail, hipStream_t s) {
-  ImplArgs a{g, U, P, aux, adt, nfail};
+  ImplArgs a{g, U, P, aux, adt, nfail, nd};
   MHD_LAUNCH(KID_M1_IMPLICIT, k_m1_implicit, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }

@@ -5,12 +5,16 @@
 // (8 -> 64 -> 64 -> 2, ReLU) maps 8 metric-invariant scalars of the state
 // (log D, log q, log r^2, log calB^2, (r.calB)^2/(r^2 calB^2), log(1+q),
 // log r^2/(1+q)^2, log calB^2/(1+q)) to corrections of closed-form
-// approximations of log(mu_+ h0) and log(mu/mu_+) (c2p_baseline);
-// Newton's method in FP64 polishes each guess for at most three iterations,
-// and a point is accepted only if the residual falls below 1e-12 (f_a
-// absolute, f relative to mu) with 0 < mu <= mu_+.  Every other point goes to
-// a queue that the bracketed solver then finishes, so the plain solver
-// decides and the answer is the root either way.
+// approximations of log(mu_+ h0) and log(mu/mu_+) (c2p_baseline); their sum
+// is a guess for mu itself.  Newton's method in FP64 polishes it for at most
+// three updates, and a point is accepted only if the residual of f falls below
+// 1e-12 mu, one evaluation on the far side of the corrected root shows a sign
+// change within 1e-12 of it, and f_a <= 0 there.  f_a is strictly increasing
+// (mu^2 (h0^2 + rbar^2) is a sum of products of nonnegative increasing
+// functions of mu), so that last check places the root in (0, mu_+] without
+// solving for mu_+.  Every other point goes to a queue that the bracketed
+// solver then finishes, so the plain solver decides and the answer is the
+// root either way.
 //
 // Network arithmetic: the two hidden layers run on the bf16 matrix cores
 // (v_mfma_f32_32x32x16_bf16, FP32 accumulation) with inputs, weights and
@@ -167,30 +171,94 @@ __device__ __forceinline__ void mlp_forward(const MlpLds& s, const float z[8], M
   }
 }
 
+// The same network for inference only: identical operations in the same
+// order (so the same outputs bit for bit), without keeping the layers'
+// pre-activations for a backward pass: layer 2 is formed one 32-unit tile at
+// a time and folded into the output sums at once, which keeps the register
+// footprint small enough for several waves per SIMD.
+__device__ __forceinline__ void mlp_infer(const MlpLds& s, const float z[8], float y[2]) {
+#pragma clang fp contract(off)
+  const int l = lane_id(), g = l >> 5, c = l & 31;
+  float part[2][2] = {{0.0f, 0.0f}, {0.0f, 0.0f}};
+  // one 32-point tile (mt) at a time: layer 1 for both 32-unit halves of the
+  // hidden layer, then layer 2 half by half, folded into the output sums
+#pragma unroll 1
+  for (int mt = 0; mt < 2; ++mt) {
+    bf16x8 xb;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const float v = __shfl(z[j], c + 32 * mt, 64);
+      xb[j] = to_bf16(g ? 0.0f : v);
+    }
+    bf16x8 hb[4];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      const bf16x8 aw = lds8(&s.w1[(32 * nt + c) * 16 + 8 * g]);
+      const f32x16 zero = {};
+      const f32x16 a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, xb, zero, 0, 0, 0);
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const float v = a1[i] + s.b1[acc_row(nt, i, g)];
+        // accumulator slot 16 nt + i is B-operand entry (ks, j) = ((16 nt + i) / 8, (16 nt + i) % 8)
+        hb[(16 * nt + i) >> 3][(16 * nt + i) & 7] = to_bf16(v > 0.0f ? v : 0.0f);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+      f32x16 acc = {};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        const bf16x8 aw = lds8(&s.w2p[(32 * nt + c) * kLd + 16 * ks + 8 * g]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aw, hb[ks], acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        float sacc = part[o][mt];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const float h = acc[i] + s.b2[acc_row(nt, i, g)];
+          sacc += s.w3[o * 64 + acc_row(nt, i, g)] * (h > 0.0f ? h : 0.0f);
+        }
+        part[o][mt] = sacc;
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    const float mine = g ? part[o][1] : part[o][0];
+    const float send = g ? part[o][0] : part[o][1];
+    y[o] = mine + __shfl_xor(send, 32, 64) + s.b3[o];
+  }
+}
+
 // --------------------------------------------------------------- features
 
-__device__ __forceinline__ void c2p_features(const C2pInv& c, double x[8]) {
+// The network's inputs are binary32 (then bf16 on the matrix cores), so the
+// logarithms are taken in binary32 of the FP64 quantities rounded to it; the
+// ratio x4 is formed in FP64 (its tiny guard would underflow in binary32).
+__device__ __forceinline__ void c2p_features(const C2pInv& c, float x[8]) {
 #pragma clang fp contract(off)
   const double onep = 1.0 + c.q;
-  x[0] = log10(c.D);
-  x[1] = log10(fmax(c.q, 1e-30));
-  x[2] = log10(c.r2 + 1e-30);
-  x[3] = log10(c.B2 + 1e-30);
-  x[4] = c.rB * c.rB / (c.r2 * c.B2 + 1e-300);
-  x[5] = log10(onep);
-  x[6] = log10(c.r2 / (onep * onep) + 1e-30);
-  x[7] = log10(c.B2 / onep + 1e-30);
+  x[0] = log10f((float)c.D);
+  x[1] = log10f((float)fmax(c.q, 1e-30));
+  x[2] = log10f((float)(c.r2 + 1e-30));
+  x[3] = log10f((float)(c.B2 + 1e-30));
+  x[4] = (float)(c.rB * c.rB / (c.r2 * c.B2 + 1e-300));
+  x[5] = log10f((float)onep);
+  x[6] = log10f((float)(c.r2 / (onep * onep) + 1e-30));
+  x[7] = log10f((float)(c.B2 / onep + 1e-30));
 }
 
 // Closed-form approximations of the two log fractions, corrected by the
 // network: exact for the auxiliary root without magnetic field (rbar = r, so
 // mu_+ = 1/sqrt(h0^2 + r^2)); mu ~ 1/(1 + q) for the second root (D (1 + q)
 // is the energy density, about rho h W^2 for a cold, weakly magnetised fluid).
-__device__ __forceinline__ void c2p_baseline(const C2pInv& c, double h0, double b[2]) {
+// In binary32: they only place the starting guesses.
+__device__ __forceinline__ void c2p_baseline(const C2pInv& c, double h0, float b[2]) {
 #pragma clang fp contract(off)
-  const double l = 0.5 * log(h0 * h0 + c.r2);
-  b[0] = log(h0) - l;
-  b[1] = -log(1.0 + c.q) + l;
+  const float l = 0.5f * logf((float)(h0 * h0 + c.r2));
+  b[0] = logf((float)h0) - l;
+  b[1] = -logf((float)(1.0 + c.q)) + l;
 }
 
 __device__ __forceinline__ void standardize(const MlpLds& s, const float x[8], float z[8]) {
@@ -228,16 +296,16 @@ __global__ void __launch_bounds__(256) k_mlp_features(FeatArgs a) {
     if (a.T) a.T[t * 2] = a.T[t * 2 + 1] = nan;
     return;
   }
-  double x[8];
+  float x[8];
   c2p_features(c, x);
 #pragma unroll
-  for (int q = 0; q < 8; ++q) a.X[t * 8 + q] = (float)x[q];
+  for (int q = 0; q < 8; ++q) a.X[t * 8 + q] = x[q];
   if (a.T && a.mu) {
     const double mup = a.mu[p], mu = a.mu[a.g.sf + p];
-    double b[2];
+    float b[2];
     c2p_baseline(c, a.eos.h0, b);
-    a.T[t * 2] = (float)(log(mup * a.eos.h0) - b[0]);
-    a.T[t * 2 + 1] = (float)(log(mu / mup) - b[1]);
+    a.T[t * 2] = (float)(log(mup * a.eos.h0) - (double)b[0]);
+    a.T[t * 2 + 1] = (float)(log(mu / mup) - (double)b[1]);
   }
 }
 
@@ -533,52 +601,88 @@ struct LearnedArgs {
   uint8_t* __restrict__ flags;
   double* __restrict__ mu;
   int64_t* __restrict__ stats;
-  uint32_t* __restrict__ qcount;
-  uint32_t* __restrict__ queue;
+  uint32_t* __restrict__ qcount;  // [0]: points to solve, [1]: points for the bracketed solver
+  uint32_t* __restrict__ queue;   // linear padded indices of the points to solve
+  uint32_t* __restrict__ fqueue;  // linear padded indices of the rejected points
+  float* __restrict__ feat;        // per solve-queue slot: 8 raw features, then the 2 network outputs in place
   int Nx, Ny;
   int64_t npts;
 };
 
 constexpr int kNewtonIt = 3;
 
-// Newton on F from x0 with at most kNewtonIt updates (iterates clamped to hi).
-// A point x is accepted when |F(x)| <= tol(x) and F has the opposite sign at
-// x (1 -+ 5e-13) on the side where the root lies (F increases through its
-// only root in the bracket; F(hi) > 0 is known): the root is then within
-// 5e-13 relative of x, and the result is the Newton correction of x kept
-// inside that interval.  nev counts the function evaluations.
-template <class FnD, class Fn>
-__device__ __forceinline__ bool newton_polish(const FnD& F, const Fn& Fv, double x, double hi, bool rel, double& out,
-                                              int& nev) {
+// mu_+ (App. D): the root of f_a on (0, hi], hi = 1/h0, or hi itself where
+// f_a(hi) <= 0.  Newton on f_a from x0 with at most kNewtonIt updates, iterates
+// kept in (0, hi]; accepted once |f_a(x)| <= 1e-12, returning the Newton
+// correction of x.  f_a costs one division and one square root: no EoS.
+__device__ __forceinline__ bool newton_mup(const C2pInv& c, double x, double hi, double& out, int& nev) {
 #pragma clang fp contract(off)
   for (int it = 0; it <= kNewtonIt; ++it) {
-    const Dual r = F(Dual{x, 1.0});
+    const Dual r = fa_t<Dual>(c, Dual{x, 1.0});
     ++nev;
-    const double tol = rel ? 1e-12 * x : 1e-12;
-    if (fabs(r.v) <= tol) {
-      if (r.d != 0.0) x = x - r.v / r.d;
-      x = fmin(x, hi);
-      if (!(x > 0.0)) return false;
-      const double lo = x * (1.0 - 5e-13), up = fmin(x * (1.0 + 5e-13), hi);
-      const double flo = Fv(lo), fup = up < hi ? Fv(up) : 1.0;  // F(hi) > 0 is known
-      nev += up < hi ? 2 : 1;
-      if (!(flo <= 0.0 && fup >= 0.0)) return false;
-      out = x;
+    if (x == hi && r.v <= 0.0) {  // f_a(hi) <= 0: the bracket's end itself
+      out = hi;
       return true;
     }
-    if (it == kNewtonIt || !(r.d != 0.0)) return false;
-    // an update past the bracket's upper end restarts from that end, where F
-    // is known to be positive (roots close to it are common)
-    x = fmin(x - r.v / r.d, hi);
+    if (!(r.d > 0.0)) return false;
+    const double x1 = x - r.v / r.d;
+    if (fabs(r.v) <= 1e-12) {
+      out = fmin(x1, hi);
+      return out > 0.0;
+    }
+    if (it == kNewtonIt) return false;
+    x = fmin(x1, hi);
     if (!(x > 0.0)) return false;
   }
   return false;
 }
 
-struct FaDual {
-  const C2pInv& c;
-  __device__ Dual operator()(Dual mu) const { return fa_t<Dual>(c, mu); }
-};
+// Newton on f from x0 with at most kNewtonIt updates, iterates kept in
+// (0, mup] (an update past mup restarts from it: roots close to mup are
+// common, and above it the velocity clamp of App. D changes f's branch).
+// At an iterate x with |f(x)| <= 1e-12 x the Newton correction x1 is taken;
+// one more evaluation at y, 5e-13 x1 beyond x1 on the side away from x, must
+// have the sign opposite to f(x), and |y - x| <= 1e-12 x1: a root of f then
+// lies between x and y, within 1e-12 x1 of x1.  That interval must lie below
+// f_a's root (f_a is increasing): taken as shown when its upper end is below
+// mup (1 - 1e-9), mup being f_a's root to ~1e-12, else checked by f_a <= 0
+// there.  nev counts the root-function evaluations, f_a's included.
+template <class FnD, class Fn>
+__device__ __forceinline__ bool newton_mu(const FnD& F, const Fn& Fv, const C2pInv& c, double x, double mup,
+                                          double& out, int& nev) {
+#pragma clang fp contract(off)
+  for (int it = 0; it <= kNewtonIt; ++it) {
+    const Dual r = F(Dual{x, 1.0});
+    ++nev;
+    if (!(r.d != 0.0)) return false;
+    const double x1 = x - r.v / r.d;
+    if (fabs(r.v) <= 1e-12 * x) {
+      double up = x;
+      if (r.v != 0.0) {
+        const double dir = (r.v < 0.0) == (r.d > 0.0) ? 1.0 : -1.0;
+        const double y = x1 + dir * 5e-13 * x1;
+        const double fy = Fv(y);
+        ++nev;
+        if (!((fy > 0.0) != (r.v > 0.0) || fy == 0.0)) return false;
+        if (!(fabs(y - x) <= 1e-12 * x1)) return false;
+        up = fmax(x, y);
+      }
+      if (!(up < mup * (1.0 - 1e-9))) {
+        const double fa = fa_t<double>(c, up);
+        ++nev;
+        if (!(fa <= 0.0)) return false;
+      }
+      if (!(x1 > 0.0)) return false;
+      out = r.v != 0.0 ? x1 : x;
+      return true;
+    }
+    if (it == kNewtonIt) return false;
+    x = fmin(x1, mup);
+    if (!(x > 0.0)) return false;
+  }
+  return false;
+}
+
 struct FDual {
   const mhd_eos_t& e;
   const C2pInv& c;
@@ -586,118 +690,194 @@ struct FDual {
 };
 
 // log fraction (baseline + network output) -> fraction of the bracket's upper end, in (0, 1]
-__device__ __forceinline__ double frac_of(double y) { return exp(fmin(y, 0.0)); }
+__device__ __forceinline__ double frac_of(float y) { return (double)expf(fminf(y, 0.0f)); }
 
 struct LearnedOut {
   bool fallback;
   int64_t nfatal, ncorr, nit;
 };
 
-// con2prim of padded point (i, j, k) with the learned guess; every lane of the
-// wavefront calls this (the network runs on the whole wavefront), lanes
-// without a point with inside = false.  Returns whether the point needs the
-// bracketed solver (then nothing is stored for it).
-__device__ __forceinline__ LearnedOut learned_point(const MlpLds& s, const mhd_eos_t& eos, const Geom& g, double* U,
-                                                    double* P, uint8_t* flags, double* mu, int i, int j, int k,
-                                                    bool inside) {
+// con2prim of padded point (i, j, k), one that needs a root solve, from the
+// network's two outputs y: Newton for mu_+ and then mu (no matrix cores here,
+// so the kernel is not held to the network's register budget).  Returns
+// whether the point needs the bracketed solver (then nothing is stored).
+__device__ __forceinline__ LearnedOut newton_point(const mhd_eos_t& eos, const Geom& g, double* U, double* P,
+                                                   uint8_t* flags, double* mu, int i, int j, int k, float y0,
+                                                   float y1) {
   LearnedOut r{false, 0, 0, 0};
-  int64_t p = 0;
+  const int64_t p = g.at(i, j, k);
   C2pPoint pt;
+  load_point(U, g.sf, p, pt);
   C2pInv c;
-  bool solve = false;
-  if (inside) {
-    p = g.at(i, j, k);
-    load_point(U, g.sf, p, pt);
-    solve = c2p_setup(eos, pt, c);
+  if (!c2p_setup(eos, pt, c)) {  // not reached for queued points
+    r.fallback = true;
+    return r;
   }
-  // network guess (whole wave, dead lanes with zero inputs); skipped by
-  // wavefronts without a state to solve (atmosphere, padding)
-  float y[2] = {0.0f, 0.0f};
-  if (__any(solve)) {
-    float z[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    if (solve) {
-      double x[8];
-      c2p_features(c, x);
-      float xf[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) xf[q] = (float)x[q];
-      standardize(s, xf, z);
-    }
-    MlpFwd f;
-    mlp_forward(s, z, f, y);
-  }
-  if (!inside) return r;
   C2pOut o;
   o.flags = 0;
   o.iters = 0;
-  o.mup = o.mu = 0.0;
-  if (!solve) {
-    atmosphere_prims(eos, o.prim);
-    o.flags = MHD_FLAG_ATMO;
-    double Wn;
-    const double zv[3] = {0.0, 0.0, 0.0};
-    prim_to_cons(pt.gd, o.prim[0], o.prim[1], o.prim[2], zv, o.prim[7], pt.B, o.cons, Wn);
-  } else {
-    int nev = 0;
-    double b[2];
-    c2p_baseline(c, c.h0, b);
-    const double hi = 1.0 / c.h0;
-    const double fhi = fa_t<double>(c, hi);
-    double mup = hi;
-    bool ok = true;
-    if (fhi > 0.0) ok = newton_polish(FaDual{c}, FaFn{c}, frac_of(b[0] + (double)y[0]) * hi, hi, false, mup, nev);
-    double m = mup;
-    if (ok) {
-      const FFn fp{eos, c};
-      const double f1 = fp(mup);
-      ++nev;
-      if (f1 > 0.0) ok = newton_polish(FDual{eos, c}, fp, frac_of(b[1] + (double)y[1]) * mup, mup, true, m, nev);
-    }
-    r.nit = nev + 1;  // root-function evaluations, f_a(1/h0) included
-    if (!ok) {
-      r.fallback = true;
-      return r;
-    }
-    o.mup = mup;
-    o.mu = m;
-    c2p_finish(eos, pt, c, m, o);
+  int nev = 0;
+  float b[2];
+  c2p_baseline(c, c.h0, b);
+  const double hi = 1.0 / c.h0;
+  double mup = hi, m = hi;
+  bool ok = newton_mup(c, frac_of(b[0] + y0) * hi, hi, mup, nev);
+  if (ok) ok = newton_mu(FDual{eos, c}, FFn{eos, c}, c, frac_of(b[1] + y1) * mup, mup, m, nev);
+  r.nit = nev;
+  if (!ok) {
+    r.fallback = true;
+    return r;
   }
+  o.mup = mup;
+  o.mu = m;
+  c2p_finish(eos, pt, c, m, o);
   store_point(U, P, flags, mu, g.sf, p, pt, o);
   r.nfatal = (o.flags & MHD_FLAG_FATAL) ? 1 : 0;
   r.ncorr = (o.flags & C2P_CORRECTED) ? 1 : 0;
   return r;
 }
 
-// wave-aggregated append of `entry` for the lanes with `take` set
+// First pass: every padded point is loaded once; points below the density
+// threshold get the atmosphere (as in the bracketed path); for the others the
+// network's 8 raw features are computed (binary32).  No network here: the
+// pass runs at full occupancy.  Returns whether the point needs a solve.
+__device__ __forceinline__ bool classify_point(const mhd_eos_t& eos, const Geom& g, double* U, double* P,
+                                               uint8_t* flags, double* mu, int i, int j, int k, float x[8]) {
+  const int64_t p = g.at(i, j, k);
+  C2pPoint pt;
+  load_point(U, g.sf, p, pt);
+  C2pInv c;
+  if (!c2p_setup(eos, pt, c)) {
+    C2pOut o;
+    o.iters = 0;
+    o.mup = o.mu = 0.0;
+    atmosphere_prims(eos, o.prim);
+    o.flags = MHD_FLAG_ATMO;
+    double Wn;
+    const double zv[3] = {0.0, 0.0, 0.0};
+    prim_to_cons(pt.gd, o.prim[0], o.prim[1], o.prim[2], zv, o.prim[7], pt.B, o.cons, Wn);
+    store_point(U, P, flags, mu, g.sf, p, pt, o);
+    return false;
+  }
+  c2p_features(c, x);
+  return true;
+}
+
+// wave-aggregated append of `entry` for the lanes with `take` set; returns the
+// lane's slot (meaningful where take is set)
 template <class T>
-__device__ __forceinline__ void queue_append(bool take, T entry, uint32_t* count, T* queue) {
+__device__ __forceinline__ uint32_t queue_append(bool take, T entry, uint32_t* count, T* queue) {
   const uint64_t mask = __ballot(take);
-  if (!mask) return;
+  if (!mask) return 0u;
   const int l = lane_id();
   const int leader = __ffsll((unsigned long long)mask) - 1;
   uint32_t base = 0;
   if (l == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
   base = __shfl(base, leader, 64);
-  if (take) queue[base + __popcll(mask & ((1ull << l) - 1ull))] = entry;
+  const uint32_t slot = base + (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
+  if (take) queue[slot] = entry;
+  return slot;
 }
 
-// blocks stride over chunks of 256 padded points (the trip count is uniform
-// over the block: the network runs on whole wavefronts).  Two waves per SIMD:
-// left alone, the matrix-core accumulators (AGPRs) come on top of ~230 VGPRs
-// and the kernel runs one wave per SIMD, which leaves the root-function
-// evaluations' latency unhidden
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_c2p_learned(LearnedArgs a) {
-  __shared__ MlpLds s;
-  mlp_stage(a.prm, s);
+// block-aggregated append (every thread of the block calls it, with a
+// block-uniform trip count): one atomic per block and call instead of one per
+// wavefront, since appends from every wavefront to one counter serialise in
+// L2 when most points are queued.  Returns the lane's slot where take is set.
+template <class T>
+__device__ __forceinline__ uint32_t block_queue_append(bool take, T entry, uint32_t* count, T* queue) {
+  __shared__ uint32_t wsum[4], bbase;
+  const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+  const int w = tid >> 6, l = tid & 63;
+  const uint64_t mask = __ballot(take);
+  if (l == 0) wsum[w] = (uint32_t)__popcll(mask);
   __syncthreads();
-  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
+  if (tid == 0) {
+    const int nw = (int)((blockDim.x * blockDim.y + 63) / 64);
+    uint32_t tot = 0;
+    for (int v = 0; v < nw; ++v) {
+      const uint32_t c = wsum[v];
+      wsum[v] = tot;
+      tot += c;
+    }
+    bbase = tot ? atomicAdd(count, tot) : 0u;
+  }
+  __syncthreads();
+  const uint32_t slot = bbase + wsum[w] + (uint32_t)__popcll(mask & ((1ull << l) - 1ull));
+  if (take) queue[slot] = entry;
+  __syncthreads();  // wsum and bbase are reused by the next call
+  return slot;
+}
+
+__device__ __forceinline__ void store_features(float* feat, uint32_t slot, const float x[8]) {
+  float4* f = reinterpret_cast<float4*>(feat + (int64_t)slot * 8);
+  f[0] = make_float4(x[0], x[1], x[2], x[3]);
+  f[1] = make_float4(x[4], x[5], x[6], x[7]);
+}
+
+__global__ void __launch_bounds__(256) k_c2p_classify(LearnedArgs a) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(a.eos, seos);
+  int64_t ncorr = 0;
+  // block-uniform trip count (the append synchronises the block)
   for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < a.npts; base += (int64_t)gridDim.x * blockDim.x) {
     const int64_t t = base + threadIdx.x;
-    const bool inside = t < a.npts;
-    const int i = inside ? (int)(t % a.Nx) : 0, j = inside ? (int)((t / a.Nx) % a.Ny) : 0;
-    const int k = inside ? (int)(t / ((int64_t)a.Nx * a.Ny)) : 0;
-    const LearnedOut r = learned_point(s, a.eos, a.g, a.U, a.P, a.flags, a.mu, i, j, k, inside);
-    queue_append<uint32_t>(r.fallback, (uint32_t)t, a.qcount, a.queue);
+    float x[8];
+    bool solve = false;
+    if (t < a.npts) {
+      const int i = (int)(t % a.Nx), j = (int)((t / a.Nx) % a.Ny), k = (int)(t / ((int64_t)a.Nx * a.Ny));
+      solve = classify_point(eos, a.g, a.U, a.P, a.flags, a.mu, i, j, k, x);
+      ncorr += solve ? 0 : 1;
+    }
+    const uint32_t slot = block_queue_append<uint32_t>(solve, (uint32_t)t, &a.qcount[0], a.queue);
+    if (solve) store_features(a.feat, slot, x);
+  }
+  if (a.stats) block_add_stats(a.stats, 0, ncorr, 0, 0);
+}
+
+// Second pass: the network on the queued feature rows, whole wavefronts of
+// them (blocks stride over chunks of 256 rows, so the trip count is uniform
+// over the block); the two outputs overwrite the row's first two features.
+__global__ void __launch_bounds__(256) k_c2p_mlp(const float* __restrict__ prm, const uint32_t* __restrict__ qcount,
+                                                 float* __restrict__ feat) {
+  const int64_t nq = qcount[0];
+  if ((int64_t)blockIdx.x * blockDim.x >= nq) return;  // whole block: no work
+  __shared__ MlpLds s;
+  mlp_stage(prm, s);
+  __syncthreads();
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nq; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = base + threadIdx.x;
+    const bool live = q < nq;
+    float x[8] = {0, 0, 0, 0, 0, 0, 0, 0}, z[8] = {0, 0, 0, 0, 0, 0, 0, 0}, y[2];
+    if (live) {
+      const float4* f = reinterpret_cast<const float4*>(feat + q * 8);
+      const float4 f0 = f[0], f1 = f[1];
+      x[0] = f0.x, x[1] = f0.y, x[2] = f0.z, x[3] = f0.w, x[4] = f1.x, x[5] = f1.y, x[6] = f1.z, x[7] = f1.w;
+      standardize(s, x, z);
+    }
+    mlp_infer(s, z, y);
+    if (live) *reinterpret_cast<float2*>(feat + q * 8) = make_float2(y[0], y[1]);
+  }
+}
+
+// Third pass: Newton from the network's guesses on the queued points;
+// rejected points go to the fallback queue
+__global__ void __launch_bounds__(256) k_c2p_newton(LearnedArgs a) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(a.eos, seos);
+  const int64_t nq = a.qcount[0];
+  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nq; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = base + threadIdx.x;
+    const bool live = q < nq;
+    LearnedOut r{false, 0, 0, 0};
+    int64_t t = 0;
+    if (live) {
+      t = (int64_t)a.queue[q];
+      const int i = (int)(t % a.Nx), j = (int)((t / a.Nx) % a.Ny), k = (int)(t / ((int64_t)a.Nx * a.Ny));
+      const float2 y = *reinterpret_cast<const float2*>(a.feat + q * 8);
+      r = newton_point(eos, a.g, a.U, a.P, a.flags, a.mu, i, j, k, y.x, y.y);
+    }
+    queue_append<uint32_t>(r.fallback, (uint32_t)t, &a.qcount[1], a.fqueue);
     nfatal += r.nfatal;
     ncorr += r.ncorr;
     nfb += r.fallback ? 1 : 0;
@@ -706,37 +886,71 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   if (a.stats) block_add_stats(a.stats, nfatal, ncorr, nfb, nit);
 }
 
-// level version: queue entries are (box << 32) | linear padded point of the box
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_c2p_learned_lv(LevelArgs L) {
-  __shared__ MlpLds s;
-  mlp_stage(L.mlp, s);
-  __syncthreads();
-  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
+// level versions: queue entries are (box << 32) | linear padded point of the box
+__device__ __forceinline__ uint64_t level_entry(const LevelArgs& L, const BoxDev& B, int i, int j, int k) {
+  const int Nx = B.g.nx + 2 * B.g.ng, Ny = B.g.ny + 2 * B.g.ng;
+  const uint64_t box = (uint64_t)(&B - L.boxes);
+  return (box << 32) | (uint64_t)((int64_t)i + (int64_t)Nx * ((int64_t)j + (int64_t)Ny * k));
+}
+__device__ __forceinline__ const BoxDev& level_point(const LevelArgs& L, uint64_t e, int& i, int& j, int& k) {
+  const BoxDev& B = L.boxes[(int)(e >> 32)];
+  const int64_t t = (int64_t)(e & 0xffffffffull);
+  const int Nx = B.g.nx + 2 * B.g.ng, Ny = B.g.ny + 2 * B.g.ng;
+  i = (int)(t % Nx);
+  j = (int)((t / Nx) % Ny);
+  k = (int)(t / ((int64_t)Nx * Ny));
+  return B;
+}
+
+__global__ void __launch_bounds__(256) k_c2p_classify_lv(LevelArgs L) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(L.eos, seos);
+  int64_t ncorr = 0;
   for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    const LearnedOut r = learned_point(s, L.eos, B.g, L.src ? B.Us : B.U, B.P, B.flags, nullptr, i, j, k, live);
-    const int Nx = B.g.nx + 2 * B.g.ng, Ny = B.g.ny + 2 * B.g.ng;
-    const uint64_t box = (uint64_t)(&B - L.boxes);
-    const uint64_t entry = (box << 32) | (uint64_t)((int64_t)i + (int64_t)Nx * ((int64_t)j + (int64_t)Ny * k));
-    queue_append<uint64_t>(r.fallback, entry, L.qcount, L.queue);
+    float x[8];
+    const bool solve = live && classify_point(eos, B.g, L.src ? B.Us : B.U, B.P, B.flags, nullptr, i, j, k, x);
+    ncorr += (live && !solve) ? 1 : 0;
+    const uint32_t slot =
+        block_queue_append<uint64_t>(solve, solve ? level_entry(L, B, i, j, k) : 0ull, &L.qcount[0], L.queue);
+    if (solve) store_features(L.feat, slot, x);
+  });
+  if (L.stats) block_add_stats(L.stats, 0, ncorr, 0, 0);
+}
+
+__global__ void __launch_bounds__(256) k_c2p_newton_lv(LevelArgs L) {
+  __shared__ mhd_eos_t seos;
+  const mhd_eos_t& eos = stage_eos(L.eos, seos);
+  const int64_t nq = L.qcount[0];
+  int64_t nfatal = 0, ncorr = 0, nfb = 0, nit = 0;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < nq; base += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t q = base + threadIdx.x;
+    const bool live = q < nq;
+    LearnedOut r{false, 0, 0, 0};
+    uint64_t e = 0;
+    if (live) {
+      e = L.queue[q];
+      int i, j, k;
+      const BoxDev& B = level_point(L, e, i, j, k);
+      const float2 y = *reinterpret_cast<const float2*>(L.feat + q * 8);
+      r = newton_point(eos, B.g, L.src ? B.Us : B.U, B.P, B.flags, nullptr, i, j, k, y.x, y.y);
+    }
+    queue_append<uint64_t>(r.fallback, e, &L.qcount[1], L.fqueue);
     nfatal += r.nfatal;
     ncorr += r.ncorr;
     nfb += r.fallback ? 1 : 0;
     nit += r.nit;
-  });
+  }
   if (L.stats) block_add_stats(L.stats, nfatal, ncorr, nfb, nit);
 }
 
 __global__ void __launch_bounds__(256) k_c2p_fallback_lv(LevelArgs L) {
   __shared__ mhd_eos_t seos;
   const mhd_eos_t& eos = stage_eos(L.eos, seos);
-  const uint32_t nq = *L.qcount;
+  const uint32_t nq = L.qcount[1];
   int64_t nfatal = 0, ncorr = 0, nit = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
-    const uint64_t e = L.queue[q];
-    const BoxDev& B = L.boxes[(int)(e >> 32)];
-    const int64_t t = (int64_t)(e & 0xffffffffull);
-    const int Nx = B.g.nx + 2 * B.g.ng, Ny = B.g.ny + 2 * B.g.ng;
-    const int i = (int)(t % Nx), j = (int)((t / Nx) % Ny), k = (int)(t / ((int64_t)Nx * Ny));
+    int i, j, k;
+    const BoxDev& B = level_point(L, L.fqueue[q], i, j, k);
     const int64_t p = B.g.at(i, j, k);
     double* U = L.src ? B.Us : B.U;
     C2pPoint pt;
@@ -756,10 +970,10 @@ __global__ void __launch_bounds__(256) k_c2p_fallback_lv(LevelArgs L) {
 __global__ void __launch_bounds__(256) k_c2p_fallback(LearnedArgs a) {
   __shared__ mhd_eos_t seos;
   const mhd_eos_t& eos = stage_eos(a.eos, seos);
-  const uint32_t nq = *a.qcount;
+  const uint32_t nq = a.qcount[1];
   int64_t nfatal = 0, ncorr = 0, nit = 0;
   for (uint32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nq; q += gridDim.x * blockDim.x) {
-    const int64_t t = a.queue[q];
+    const int64_t t = a.fqueue[q];
     const int i = (int)(t % a.Nx), j = (int)((t / a.Nx) % a.Ny), k = (int)(t / ((int64_t)a.Nx * a.Ny));
     const int64_t p = a.g.at(i, j, k);
     C2pPoint pt;
@@ -775,7 +989,10 @@ __global__ void __launch_bounds__(256) k_c2p_fallback(LearnedArgs a) {
   if (a.stats) block_add_stats(a.stats, nfatal, ncorr, 0, nit);
 }
 
-__global__ void k_zero_u32(uint32_t* p) { *p = 0u; }
+__global__ void k_zero_u32(uint32_t* p) {
+  p[0] = 0u;
+  p[1] = 0u;
+}
 
 // ------------------------------------------------------------------ launchers
 
@@ -824,29 +1041,37 @@ int launch_mlp_adam(float* prm, const float* grad, float* m, float* v, int step,
 int launch_con2prim_learned(const Geom& g, const mhd_eos_t& eos, const float* prm, double* U, double* P,
                             uint8_t* flags, double* mu, int64_t* stats, void* ws, hipStream_t s) {
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
+  const int64_t npts = (int64_t)Nx * Ny * Nz;
   uint32_t* qcount = reinterpret_cast<uint32_t*>(ws);
   uint32_t* queue = qcount + 64;  // 256-byte offset
-  LearnedArgs a{g, eos, prm, U, P, flags, mu, stats, qcount, queue, Nx, Ny, (int64_t)Nx * Ny * Nz};
+  // the feature rows start on the next 256-byte boundary after the two queues
+  const uintptr_t fb = (reinterpret_cast<uintptr_t>(queue + 2 * npts) + 255u) & ~uintptr_t(255u);
+  float* feat = reinterpret_cast<float*>(fb);
+  LearnedArgs a{g, eos, prm, U, P, flags, mu, stats, qcount, queue, queue + npts, feat, Nx, Ny, npts};
   MHD_LAUNCH(KID_ZERO, k_zero_u32, dim3(1), dim3(1), 0, s, qcount);
-  const int64_t fb_blocks = (a.npts + 255) / 256;
-  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_learned, dim3((unsigned)(fb_blocks < 2048 ? fb_blocks : 2048)), dim3(256), 0, s,
-             a);
-  MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback, dim3((unsigned)(fb_blocks < 2048 ? fb_blocks : 2048)), dim3(256), 0, s,
-             a);
+  const int64_t nblk = (a.npts + 255) / 256;
+  const unsigned grid = (unsigned)(nblk < 2048 ? nblk : 2048);
+  MHD_LAUNCH(KID_C2P_CLASSIFY, k_c2p_classify, dim3(grid), dim3(256), 0, s, a);
+  MHD_LAUNCH(KID_MLP_FORWARD, k_c2p_mlp, dim3(grid), dim3(256), 0, s, prm, qcount, feat);
+  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_newton, dim3(grid), dim3(256), 0, s, a);
+  MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback, dim3(grid), dim3(256), 0, s, a);
   return (int)hipGetLastError();
 }
 
 // ---------------------------------------------- allocation-free entry point
-// The fallback queue of mhd_con2prim_learned_noalloc lives in this file-scope
-// device array: a count word padded to 256 bytes, then one 4-byte slot per
-// padded point for patches of at most kNoAllocMaxPoints padded points
-// (16 MiB + 256 B per device, held until the process ends).  In host code the
-// array's name is not a device address: the address comes from
-// hipGetSymbolAddress, taken once per device with that device current, and
-// only that address is passed to kernels.  Every call on a device shares its
-// array; calls that overlap on one device race.
+// The queues and network rows of mhd_con2prim_learned_noalloc live in this
+// file-scope device array, laid out as the workspace of mhd_con2prim_learned:
+// the two count words padded to 256 bytes, the solve queue and the fallback
+// queue (4 bytes per padded point each), then from the next 256-byte boundary
+// an 8-float row per padded point (features, then the network's outputs).
+// 512 B + 40 B per point covers patches of at most kNoAllocMaxPoints padded
+// points (160 MiB per device, held until the process ends).  In host code the array's name is not a device
+// address: the address comes from hipGetSymbolAddress, taken once per device
+// with that device current, and only that address is passed to kernels.
+// Every call on a device shares its array; calls that overlap on one device
+// race.
 constexpr int64_t kNoAllocMaxPoints = int64_t(1) << 22;
-static __device__ __align__(256) uint32_t scratch[64 + kNoAllocMaxPoints];
+static __device__ __align__(256) uint32_t scratch[128 + 10 * kNoAllocMaxPoints];
 
 namespace {
 constexpr int kMaxDevices = 64;
@@ -883,10 +1108,12 @@ int launch_con2prim_learned_noalloc(const Geom& g, const mhd_eos_t& eos, const f
   return launch_con2prim_learned(g, eos, prm, U, P, flags, mu, stats, ws, s);
 }
 
-int launch_con2prim_learned_level(const LevelArgs& L, int grid, int block, int grid_fb, hipStream_t s) {
+int launch_con2prim_learned_level(const LevelArgs& L, int grid, int block, int grid_q, hipStream_t s) {
   MHD_LAUNCH(KID_ZERO, k_zero_u32, dim3(1), dim3(1), 0, s, L.qcount);
-  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_learned_lv, dim3(grid), dim3(block), 0, s, L);
-  MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback_lv, dim3(grid_fb), dim3(256), 0, s, L);
+  MHD_LAUNCH(KID_C2P_CLASSIFY, k_c2p_classify_lv, dim3(grid), dim3(block), 0, s, L);
+  MHD_LAUNCH(KID_MLP_FORWARD, k_c2p_mlp, dim3(grid_q), dim3(256), 0, s, L.mlp, L.qcount, L.feat);
+  MHD_LAUNCH(KID_C2P_LEARNED, k_c2p_newton_lv, dim3(grid_q), dim3(256), 0, s, L);
+  MHD_LAUNCH(KID_C2P_FALLBACK, k_c2p_fallback_lv, dim3(grid_q), dim3(256), 0, s, L);
   return (int)hipGetLastError();
 }
 

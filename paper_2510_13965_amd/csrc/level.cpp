@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cmath>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -24,6 +25,7 @@ int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t 
 int launch_imex_combine_level(const LevelArgs& L, int grid, int block, hipStream_t s);
 int launch_m1_implicit_level(const LevelArgs& L, int grid, int block, hipStream_t s);
 int ccz4_workspace_fields();
+int les_workspace_fields();
 int abi_fail(int code, const char* msg);
 int abi_hip(int rc, const char* what);
 Geom abi_geom(const mhd_patch_t* p);
@@ -124,7 +126,8 @@ mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, dou
   L.adt = 0.0;
   L.nfail = nullptr;
   L.m1 = (lv->par.flags & MHD_EVOLVE_M1) ? 1 : 0;
-  L.nfields = L.m1 ? MHD_NU_M1 : MHD_NU;
+  L.nd = (L.m1 && (lv->par.flags & MHD_EVOLVE_M1N)) ? 1 : 0;
+  L.nfields = L.nd ? MHD_NU_M1N : (L.m1 ? MHD_NU_M1 : MHD_NU);
   L.ntile_int = lv->ntile_int;
   L.ntile_pad = lv->ntile_pad;
   L.ntile_lds = lv->ntile_lds;
@@ -136,6 +139,8 @@ mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, dou
   L.mlp = lv->mlp;
   L.qcount = static_cast<uint32_t*>(lv->lws);
   L.queue = lv->lws ? reinterpret_cast<uint64_t*>(static_cast<char*>(lv->lws) + 256) : nullptr;
+  L.fqueue = lv->lws ? L.queue + lv->npad : nullptr;
+  L.feat = lv->lws ? reinterpret_cast<float*>(L.fqueue + lv->npad) : nullptr;
   return L;
 }
 
@@ -266,8 +271,14 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
   const uint32_t need = MHD_EVOLVE_SPACETIME | MHD_EVOLVE_MHD | MHD_COUPLE_MATTER;
   if ((par->flags & need) != need)
     return abi_fail(MHD_EINVAL, "mhd_level_create: a level evolves the full coupled system (all flags set)");
-  if (par->flags & ~(need | MHD_EVOLVE_M1)) return abi_fail(MHD_EINVAL, "mhd_level_create: unknown params flags");
+  if (par->les_cm != 0.0)
+    return abi_fail(MHD_EINVAL, "mhd_level_create: the LES term (les_cm != 0) is evolved on single patches only");
+  if (par->flags & ~(need | MHD_EVOLVE_M1 | MHD_EVOLVE_M1N))
+    return abi_fail(MHD_EINVAL, "mhd_level_create: unknown params flags");
   const bool m1 = (par->flags & MHD_EVOLVE_M1) != 0;
+  const bool nd = (par->flags & MHD_EVOLVE_M1N) != 0;
+  if (nd && !m1) return abi_fail(MHD_EINVAL, "mhd_level_create: MHD_EVOLVE_M1N needs MHD_EVOLVE_M1");
+  if (nd && !std::isfinite(par->m_b)) return abi_fail(MHD_EINVAL, "mhd_level_create: m_b must be finite");
   if (par->f_alpha_kind != MHD_FALPHA_ONE && par->f_alpha_kind != MHD_FALPHA_HARMONIC)
     return abi_fail(MHD_EINVAL, "mhd_level_create: unknown f_alpha_kind");
   if (!(par->c_b > 0.0)) return abi_fail(MHD_EINVAL, "mhd_level_create: c_b must be > 0");
@@ -278,7 +289,8 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
     if ((rc = mhd::abi_check_patch(&B.patch, 3, "mhd_level_create"))) return rc;
     if (!B.U || !B.Us || !B.P || !B.k || !B.acc || !B.workspace)
       return abi_fail(MHD_EINVAL, "mhd_level_create: box arrays must be non-NULL (flags may be NULL)");
-    if (B.workspace_bytes < (m1 ? mhd_rhs_workspace_size_m1(&B.patch) : mhd_rhs_workspace_size(&B.patch)))
+    if (B.workspace_bytes < (nd ? mhd_rhs_workspace_size_m1n(&B.patch)
+                                : (m1 ? mhd_rhs_workspace_size_m1(&B.patch) : mhd_rhs_workspace_size(&B.patch))))
       return abi_fail(MHD_EWORKSPACE, "mhd_level_create: box workspace too small");
     if (m1 && !B.aux) return abi_fail(MHD_EINVAL, "mhd_level_create: aux is required with MHD_EVOLVE_M1");
     if (B.patch.sf > (int64_t)(INT32_MAX / 8))
@@ -300,7 +312,8 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
     D.ws = static_cast<double*>(B.workspace);
     D.flags = B.flags;
     D.aux = m1 ? B.aux : nullptr;
-    D.ws_m1 = m1 ? D.ws + (int64_t)(33 + mhd::ccz4_workspace_fields()) * B.patch.sf : nullptr;
+    D.ws_m1 = m1 ? D.ws + (int64_t)(33 + mhd::ccz4_workspace_fields() + mhd::les_workspace_fields()) * B.patch.sf
+                 : nullptr;
     lv->npad += (int64_t)(B.patch.nx + 6) * (B.patch.ny + 6) * (B.patch.nz + 6);
   }
   lv->par = *par;
@@ -348,7 +361,8 @@ int mhd_level_get_tuning(const mhd_level_t* lv, mhd_tuning_t* t) {
 
 size_t mhd_level_learned_workspace_size(const mhd_level_t* lv) {
   if (!lv) return 0;
-  return 256 + 8 * (size_t)lv->npad;
+  // counts, two 8-byte queues, then one 8-float row per padded point
+  return 256 + 16 * (size_t)lv->npad + 32 * (size_t)lv->npad;
 }
 
 int mhd_level_set_learned(mhd_level_t* lv, const float* mlp, void* workspace, size_t workspace_bytes) {

@@ -13,6 +13,14 @@
 //                conservative difference, the geometric sources, the
 //                collision sources alpha sqrt(gamma) (S_n, S_i) and their
 //                opposite on the fluid's taubar, Sbar_i
+// With the number densities Nbar (U fields 44 + s), k_m1_point also stores
+// each species' number flux along each axis, (-W beta^k + alpha W v^k +
+// alpha H^k/J) Nbar/Gamma, with H^k the spatial part of the four-vector H^a
+// (gamma^kj H_j + W (J - E + F_i v^i) beta^k/alpha) and Gamma = W (E - F_i
+// v^i)/J, the number current N^a = n (u^a + H^a/J) of Sec. 2.3; k_m1_update
+// takes their HO/LO interfaces with the energy moments' speed and opacity
+// switch, the source alpha sqrt(gamma) (eta0 - kappa0_a N/Gamma), and adds
+// -alpha sqrt(gamma) m_b (C_0 - C_1) to the electron fraction's DYebar.
 // The CCZ4 kernels read the closure P_ij from the same workspace for the
 // radiation part of the matter terms.
 //
@@ -38,7 +46,9 @@ struct M1Args {
   double* __restrict__ W;  // M1 workspace (kM1Fields fields)
   double* __restrict__ rhs;
   unsigned long long* max_speed;
-  double* __restrict__ stiff;  // IMEX split: the radiation's collision terms (12 fields), or null
+  double* __restrict__ stiff;  // IMEX split: the radiation's collision terms (12 or 15 fields), or null
+  int nd;                      // nonzero: the number densities are evolved (47 fields, 15 aux, 75 workspace fields)
+  double m_b;                  // reference baryon mass of the electron-fraction source
 };
 
 // padded indices
@@ -71,6 +81,20 @@ __device__ __forceinline__ void m1_point_at(const M1Args& a, int i, int j, int k
         f[(1 + c) * sf] = -bd * a.U[(33 + 4 * sp + c) * sf + p] + alp * m.sqrtg * Pdc;
       }
       f[4 * sf] = m1_speed(s, m.gu, chi, alp, bd, d);
+    }
+    if (a.nd) {
+      const double gam = s.W * (s.E - s.vF) / J;
+      a.W[(int64_t)(kM1Gamma + sp) * sf + p] = gam;
+      const double Hn = s.W * (J - s.E + s.vF);
+      const double Nb = a.U[(int64_t)(44 + sp) * sf + p];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double bd = a.U[(19 + d) * sf + p];
+        double Hu = Hn * bd / alp;
+#pragma unroll
+        for (int e = 0; e < 3; ++e) Hu += m.gu[sym(d, e)] * H[e];
+        a.W[(int64_t)(kM1NFlux + 3 * sp + d) * sf + p] = (-s.W * bd + alp * s.W * s.v[d] + alp * Hu / J) * Nb / gam;
+      }
     }
   }
 }
@@ -129,7 +153,7 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
     // flux differences of the three species first (the metric derivatives of
     // the sources are not live meanwhile); each output then gets its
     // geometric and collision terms in the same order as before
-    double outs[3][4];
+    double outs[3][4], outN[3] = {0.0, 0.0, 0.0};
     const double hx = g.h[0], hy = g.h[1], hz = g.h[2];
     const double ihx = g.idx[0], ihy = g.idx[1], ihz = g.idx[2];
 #pragma unroll 1
@@ -151,6 +175,16 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
           const double fr = m1_holo(u, f, wr, q, st);
           const double fl = m1_holo(u, f, wl, q - st, st);
           out[c] -= div_rn(fr - fl, h, ih);
+        }
+        if (a.nd) {
+          const double* u = U + (int64_t)(44 + sp) * sf;
+          const double* f = a.W + (int64_t)(kM1NFlux + 3 * sp + d) * sf;
+          const double fr = m1_holo(u, f, wr, q, st);
+          const double fl = m1_holo(u, f, wl, q - st, st);
+          const double dN = div_rn(fr - fl, h, ih);
+          if (sp == 0) outN[0] -= dN;
+          else if (sp == 1) outN[1] -= dN;
+          else outN[2] -= dN;
         }
       }
 #pragma unroll
@@ -266,6 +300,26 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
 #pragma unroll
       for (int c = 0; c < 4; ++c) a.rhs[(int64_t)(32 + 4 * sp + c) * sf + q] = out[c];
     }
+    if (a.nd) {
+      // number densities: emission and absorption, and the electron fraction's source
+      double C[3];
+#pragma unroll 1
+      for (int sp = 0; sp < 3; ++sp) {
+        const double k0 = a.aux[(int64_t)(9 + 2 * sp) * sf + q], e0 = a.aux[(int64_t)(10 + 2 * sp) * sf + q];
+        const double gam = a.W[(int64_t)(kM1Gamma + sp) * sf + q];
+        const double Cs = e0 - k0 * (U[(int64_t)(44 + sp) * sf + q] / m.sqrtg) / gam;
+        double o = sp == 0 ? outN[0] : (sp == 1 ? outN[1] : outN[2]);
+        if (a.stiff)
+          a.stiff[(int64_t)(12 + sp) * sf + q] = alp * m.sqrtg * Cs;
+        else
+          o += alp * m.sqrtg * Cs;
+        a.rhs[(int64_t)(44 + sp) * sf + q] = o;
+        if (sp == 0) C[0] = Cs;
+        else if (sp == 1) C[1] = Cs;
+        else C[2] = Cs;
+      }
+      a.rhs[23 * sf + q] -= alp * m.sqrtg * a.m_b * (C[0] - C[1]);
+    }
   }
   return vmax;
 }
@@ -283,7 +337,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 __global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
   for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr};
+    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr, L.nd, L.par.m_b};
     m1_point_at(a, i, j, k);
   });
 }
@@ -292,13 +346,14 @@ template <bool IMEX>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update_lv(LevelArgs L) {
   double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
-    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs<IMEX>(B, L), L.max_speed, level_stiff<IMEX>(B, L)};
+    const M1Args a{B.g,      L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs<IMEX>(B, L), L.max_speed,
+                   level_stiff<IMEX>(B, L), L.nd, L.par.m_b};
     vmax = fmax(vmax, m1_update_at(a, i, j, k, live));
   });
   if (L.max_speed) block_max_to(L.max_speed, vmax);
 }
 
-int m1_workspace_fields() { return kM1Fields; }
+int m1_workspace_fields(bool nd) { return nd ? kM1NFields : kM1Fields; }
 
 int launch_m1_point_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
   MHD_LAUNCH(KID_M1_POINT, k_m1_point_lv, dim3(grid), dim3(block), 0, s, L);
@@ -313,16 +368,17 @@ int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t 
   return (int)hipGetLastError();
 }
 
-int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, hipStream_t s) {
-  M1Args a{g, U, P, aux, ws, nullptr, nullptr, nullptr};
+int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, int nd,
+                    hipStream_t s) {
+  M1Args a{g, U, P, aux, ws, nullptr, nullptr, nullptr, nd, 0.0};
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
   MHD_LAUNCH(KID_M1_POINT, k_m1_point, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 
 int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
-                     double* max_speed, double* stiff, hipStream_t s) {
-  M1Args a{g, U, P, aux, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed), stiff};
+                     double* max_speed, double* stiff, int nd, double m_b, hipStream_t s) {
+  M1Args a{g, U, P, aux, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed), stiff, nd, m_b};
   MHD_LAUNCH(KID_M1_UPDATE, k_m1_update, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }

@@ -13,6 +13,11 @@ namespace mhd {
 constexpr int kM1Closure = 0;  // workspace: P_ij of species s at 6 s + c
 constexpr int kM1Flux = 18;    // fluxes and speed of (species s, axis d): 18 + 5 (3 s + d) + c, c = 4 speed
 constexpr int kM1Fields = 63;
+// with the number densities: their point fluxes (species s, axis d) at
+// 63 + 3 s + d, and Gamma = W (E - F_i v^i)/J of species s at 72 + s
+constexpr int kM1NFlux = 63;
+constexpr int kM1Gamma = 72;
+constexpr int kM1NFields = 75;
 
 struct M1State {
   double E, F[3], Fu[3], F2, v[3], vd[3], W, vF;

@@ -18,7 +18,7 @@ const char* const kNames[KID_COUNT] = {"k_ccz4_stencil", "k_ccz4_d2",  "k_ccz4_c
                                        "k_mlp_adam", "k_c2p_learned", "k_c2p_fallback", "k_m1_point",
                                        "k_m1_update", "k_imex_combine", "k_m1_implicit", "k_prolong",
                                        "k_restrict", "k_dense_output", "k_ssprk3_stage", "k_constraints",
-                                       "k_constraint_planes", "k_constraint_total"};
+                                       "k_constraint_planes", "k_constraint_total", "k_c2p_classify", "k_les"};
 
 struct Rec {
   int kid;

@@ -41,6 +41,8 @@ enum KernelId : int {
   KID_CONSTRAINTS,
   KID_CONSTRAINT_PLANES,
   KID_CONSTRAINT_TOTAL,
+  KID_C2P_CLASSIFY,
+  KID_LES,
   KID_COUNT
 };
 

@@ -95,7 +95,8 @@ __device__ __forceinline__ void rk4_level_point(const LevelArgs& L) {
 }
 
 __global__ void __launch_bounds__(256) k_rk4_stage_lv(LevelArgs L) {
-  if (L.nfields == MHD_NU_M1) rk4_level_point<MHD_NU_M1>(L);
+  if (L.nfields == MHD_NU_M1N) rk4_level_point<MHD_NU_M1N>(L);
+  else if (L.nfields == MHD_NU_M1) rk4_level_point<MHD_NU_M1>(L);
   else rk4_level_point<MHD_NU>(L);
 }
 

@@ -338,6 +338,14 @@ def amr_level_boxes(seed=SEED0 + 3, nboxes=192, edges=(16, 24, 32, 48, 64)):
     return boxes
 
 
+def level_subset(nboxes, k=16, seed=SEED0 + 6):
+    """Seeded subset of k box indices (sorted) of a level of nboxes boxes: the
+    boxes the oracle runs for the level workloads' CPU figures and sampled
+    parity checks."""
+    r = rng(seed)
+    return sorted(int(i) for i in r.choice(nboxes, size=min(k, nboxes), replace=False))
+
+
 def amr_box_state(box, Ab):
     patch = Patch(box["n"], box["dx"], box["x0"])
     U, P, EM, _ = star_fields(patch, Ab=Ab)
@@ -427,6 +435,8 @@ def c2p_cells(seed=SEED0 + 4, ncell=1 << 24, shape=None, log_rho=(-12.0, -3.0), 
 
 NU_M1 = 44       # evolved fields with three M1 species
 NAUX = 9         # kappa_a, kappa_s, eta per species
+NU_M1N = 47      # with the three neutrino number densities Nbar (fields 44..46)
+NAUX_N = 15      # and per species the number opacity kappa0_a (9 + 2 s) and emissivity eta0 (10 + 2 s)
 
 
 def _smooth01(r, patch, X, Y, Z, count=4):
@@ -487,3 +497,29 @@ def m1_radiation(patch, P, seed):
         aux[3 * s + 1] = ks
         aux[3 * s + 2] = ka * 1e-2 * P[RHO] * P[EPS]
     return R, aux
+
+
+def m1n_fields(patch, U44, aux9, seed):
+    """The three neutrino number densities on top of m1_fields' radiation:
+    returns U with 47 fields (Nbar of species s at 44 + s) and 15 aux fields
+    (kappa0_a at 9 + 2 s, eta0 at 10 + 2 s after the 9 energy ones).
+
+    Nbar = Ebar / e_mean with a smooth mean neutrino energy e_mean =
+    10^(-1.5 + s(x)) (s smooth in [0, 1]); kappa0_a = kappa_a 10^u with u
+    uniform in [-0.5, 0.5] per point; eta0 = kappa0_a E_eq / e_mean with the
+    energy moments' E_eq = eta / kappa_a (where kappa_a = 0, eta0 = 0)."""
+    r = rng(seed)
+    Z, Y, X = patch.coords()
+    U = np.empty((NU_M1N,) + patch.shape)
+    U[:NU_M1] = U44[:NU_M1]
+    aux = np.zeros((NAUX_N,) + patch.shape)
+    aux[:NAUX] = aux9[:NAUX]
+    for sp in range(3):
+        emean = 10.0 ** (-1.5 + _smooth01(r, patch, X, Y, Z))
+        U[NU_M1 + sp] = U44[32 + 4 * sp] / emean
+        ka, eta = aux9[3 * sp], aux9[3 * sp + 2]
+        k0 = ka * 10.0 ** r.uniform(-0.5, 0.5, patch.shape)
+        Eeq = np.divide(eta, ka, out=np.zeros_like(eta), where=ka > 0)
+        aux[9 + 2 * sp] = k0
+        aux[10 + 2 * sp] = k0 * Eeq / emean
+    return U, aux

@@ -14,8 +14,10 @@ LIBPATH = os.path.join(HERE, "libmhd.so")
 
 MHD_NST, MHD_NMHD, MHD_NU, MHD_NP, MHD_NEM = 22, 10, 32, 8, 4
 MHD_NU_M1, MHD_NAUX = 44, 9
+MHD_NU_M1N, MHD_NAUX_N = 47, 15
 MHD_NSTAT = 8
-EVOLVE_SPACETIME, EVOLVE_MHD, COUPLE_MATTER, EVOLVE_M1 = 1, 2, 4, 8
+EVOLVE_SPACETIME, EVOLVE_MHD, COUPLE_MATTER, EVOLVE_M1, EVOLVE_M1N = 1, 2, 4, 8, 16
+IMEX_442, IMEX_332 = 0, 1
 FLAG = dict(ATMO=1, EPS_LO=2, EPS_HI=4, VEL_LIMIT=8, YE_RESET=16, FALLBACK=32, NOT_CONVERGED=64, FATAL=128)
 STAT_FATAL, STAT_CORRECTED, STAT_FALLBACK, STAT_ITERATIONS = 0, 1, 2, 3
 
@@ -40,7 +42,8 @@ class Params(C.Structure):
     _fields_ = [("kappa_z", C.c_double), ("kappa_c", C.c_double), ("kappa_2", C.c_double),
                 ("eta", C.c_double), ("beta0", C.c_double * 3), ("sigma_ko", C.c_double),
                 ("c_b", C.c_double), ("kappa_b", C.c_double), ("alpha_mp5", C.c_double),
-                ("f_beta", C.c_double), ("f_alpha_kind", C.c_int32), ("flags", C.c_uint32)]
+                ("f_beta", C.c_double), ("f_alpha_kind", C.c_int32), ("flags", C.c_uint32), ("m_b", C.c_double),
+                ("les_cm", C.c_double)]
 
 
 class Tuning(C.Structure):
@@ -74,6 +77,7 @@ SIGNATURES = {
     "mhd_con2prim": (C.c_int, [C.POINTER(Patch), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp]),
     "mhd_rhs_workspace_size": (C.c_size_t, [C.POINTER(Patch)]),
     "mhd_rhs_workspace_size_m1": (C.c_size_t, [C.POINTER(Patch)]),
+    "mhd_rhs_workspace_size_m1n": (C.c_size_t, [C.POINTER(Patch)]),
     "mhd_rhs": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
                           C.c_size_t, _vp]),
     "mhd_rk_stage": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_double, _vp, _vp, _vp, _vp, _vp]),
@@ -110,9 +114,9 @@ SIGNATURES = {
     "mhd_level_imex_step": (C.c_int, [_vp, C.c_double, _vp, _vp, C.c_int, _vp]),
     "mhd_rhs_split": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, C.c_size_t, _vp]),
-    "mhd_imex_combine": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_double, _vp, C.POINTER(C.c_void_p),
-                                   C.POINTER(C.c_void_p), _vp, _vp]),
-    "mhd_m1_implicit": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, C.c_double, _vp, _vp]),
+    "mhd_imex_combine": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_int, C.c_double, _vp,
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _vp, _vp]),
+    "mhd_m1_implicit": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, C.c_double, C.c_int, _vp, _vp]),
     "mhd_constraints": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, _vp]),
     "mhd_profile_start": (C.c_int, []),
     "mhd_profile_stop": (C.c_int, [C.POINTER(KernelTime), C.c_int, C.POINTER(C.c_int)]),
@@ -211,7 +215,11 @@ def make_params(cfg):
         fl |= COUPLE_MATTER
     if cfg.get("evolve_m1", 0):
         fl |= EVOLVE_M1
+    if cfg.get("evolve_m1n", 0):
+        fl |= EVOLVE_M1N
     p.flags = fl
+    p.m_b = float(cfg.get("m_b", 1.0))
+    p.les_cm = float(cfg.get("les_cm", 0.0))
     return p
 
 
@@ -310,17 +318,17 @@ def rhs_split(patch, params, eos, U, P, aux, out, stiff, max_speed=None, workspa
                                _ptr(stiff), _ptr(max_speed), _ptr(workspace), nbytes, _stream(stream)))
 
 
-def imex_combine(patch, stage, dt, Un, F, R, Uout, stream=None):
+def imex_combine(patch, stage, dt, Un, F, R, Uout, stream=None, nfields=MHD_NU_M1, scheme=IMEX_442):
     """F, R: lists of up to 4 device tensors (stage explicit and stiff parts)."""
     fa = (C.c_void_p * 4)(*[(_ptr(F[j]) if j < len(F) and F[j] is not None else None) for j in range(4)])
     ra = (C.c_void_p * 4)(*[(_ptr(R[j]) if j < len(R) and R[j] is not None else None) for j in range(4)])
-    _check(lib().mhd_imex_combine(C.byref(patch), int(stage), float(dt), _ptr(Un), fa, ra, _ptr(Uout),
-                                  _stream(stream)))
+    _check(lib().mhd_imex_combine(C.byref(patch), int(scheme), int(nfields), int(stage), float(dt), _ptr(Un), fa, ra,
+                                  _ptr(Uout), _stream(stream)))
 
 
-def m1_implicit(patch, aux, U, P, adt, nfail=None, stream=None):
-    _check(lib().mhd_m1_implicit(C.byref(patch), _ptr(aux), _ptr(U), _ptr(P), float(adt), _ptr(nfail),
-                                 _stream(stream)))
+def m1_implicit(patch, aux, U, P, adt, nfail=None, stream=None, evolve_n=False):
+    _check(lib().mhd_m1_implicit(C.byref(patch), _ptr(aux), _ptr(U), _ptr(P), float(adt), int(bool(evolve_n)),
+                                 _ptr(nfail), _stream(stream)))
 
 
 def set_tuning(strip):
@@ -488,9 +496,14 @@ def profile_stop():
     return {out[i].name.decode(): (int(out[i].launches), float(out[i].total_ms)) for i in range(min(n.value, 32))}
 
 
-def workspace_for(patch, device="cuda", m1=False):
+def workspace_for(patch, device="cuda", m1=False, m1n=False):
     import torch
 
-    size = int(lib().mhd_rhs_workspace_size_m1(C.byref(patch))) if m1 else rhs_workspace_size(patch)
+    if m1n:
+        size = int(lib().mhd_rhs_workspace_size_m1n(C.byref(patch)))
+    elif m1:
+        size = int(lib().mhd_rhs_workspace_size_m1(C.byref(patch)))
+    else:
+        size = rhs_workspace_size(patch)
     n = (size + 7) // 8
     return torch.empty(n, dtype=torch.float64, device=device)

@@ -4,6 +4,8 @@ A ``PatchRun`` owns the device buffers of one patch and issues, per RK4 stage,
 the sequence (ghost fill) -> con2prim -> rhs -> rk_stage, all stream-ordered on
 one HIP stream with no host synchronisation inside a step.
 """
+import math
+
 import torch
 
 from . import inputs as I
@@ -42,9 +44,10 @@ class PatchRun:
         self.P = torch.zeros((I.NP,) + tuple(ipatch.shape), dtype=torch.float64, device=device)
         self.flags = torch.zeros(tuple(ipatch.shape), dtype=torch.uint8, device=device)
         self.m1 = bool(par_cfg.get("evolve_m1", 0))
-        self.nfields = I.NU_M1 if self.m1 else I.NU
+        self.nd = self.m1 and bool(par_cfg.get("evolve_m1n", 0))
+        self.nfields = I.NU_M1N if self.nd else (I.NU_M1 if self.m1 else I.NU)
         self.aux = None if aux is None else t(aux)
-        self.ws = mhd.workspace_for(self.patch, device, m1=self.m1)
+        self.ws = mhd.workspace_for(self.patch, device, m1=self.m1, m1n=self.nd)
         self.vmax = torch.zeros(1, dtype=torch.float64, device=device)
         self.stats = torch.zeros(mhd.MHD_NSTAT, dtype=torch.int64, device=device)
         self.mlp = None
@@ -103,14 +106,15 @@ class LevelRun:
         self.eos = mhd.make_eos(eos_cfg)
         self.par = mhd.make_params(par_cfg)
         self.m1 = bool(par_cfg.get("evolve_m1", 0))
-        self.nfields = I.NU_M1 if self.m1 else I.NU
+        self.nd = self.m1 and bool(par_cfg.get("evolve_m1n", 0))
+        self.nfields = I.NU_M1N if self.nd else (I.NU_M1 if self.m1 else I.NU)
         self.boxes = []
         for b, (ip, U0) in enumerate(zip(ipatches, states)):
             pt = mhd.patch_of(ip)
             U = torch.as_tensor(U0, dtype=torch.float64).to(device).contiguous()
             d = dict(patch=pt, ip=ip, U=U, Us=U.clone(), k=torch.zeros_like(U), acc=torch.zeros_like(U),
                      P=torch.zeros((I.NP,) + tuple(ip.shape), dtype=torch.float64, device=device),
-                     ws=mhd.workspace_for(pt, device, m1=self.m1))
+                     ws=mhd.workspace_for(pt, device, m1=self.m1, m1n=self.nd))
             if flags:
                 d["flags"] = torch.zeros(tuple(ip.shape), dtype=torch.uint8, device=device)
             if auxs is not None and auxs[b] is not None:
@@ -118,7 +122,8 @@ class LevelRun:
             if imex:
                 shp = tuple(ip.shape)
                 d["F"] = [torch.zeros_like(U) for _ in range(4)]
-                d["R"] = [torch.zeros((12,) + shp, dtype=torch.float64, device=device) for _ in range(4)]
+                d["R"] = [torch.zeros((self.nfields - I.NU,) + shp, dtype=torch.float64, device=device)
+                          for _ in range(4)]
             self.boxes.append(d)
         self.level = mhd.Level(self.boxes, self.par, self.eos)
         if imex:
@@ -138,49 +143,63 @@ class LevelRun:
         return sum(b["ip"].npts for b in self.boxes)
 
 
-# implicit diagonal of Table I's I42L tableau
-IMEX_AII = (0.0, 0.25, 1.0 / 3.0, 1.0 / 6.0)
+# implicit diagonals: Table I's I42L, and the I32L paired with SSP-RK(3,3)
+# (gamma = 1 - 1/sqrt(2), as the library's tableau evaluates it)
+IMEX_AII = {mhd.IMEX_442: (0.0, 0.25, 1.0 / 3.0, 1.0 / 6.0),
+            mhd.IMEX_332: (0.0, 1.0 - math.sqrt(0.5), 1.0 - math.sqrt(0.5))}
 
 
 class ImexRun:
     """One patch with three M1 species stepped by IMEX(4,4,2) (Table I): the
     radiation's collision terms implicit (mhd_m1_implicit), everything else
     explicit.  Per stage: combine -> (ghost fill) -> con2prim -> implicit solve
-    -> (ghost fill) -> split RHS."""
+    -> (ghost fill) -> split RHS.  With evolve_m1n in par_cfg the three number
+    densities (47 fields, 15 aux) are evolved too, their collision sources
+    implicit.  scheme: mhd.IMEX_442 (Table I) or mhd.IMEX_332 (SSP-RK(3,3)
+    with the re-derived L-stable I32L)."""
 
-    def __init__(self, ipatch, U0, aux, eos_cfg, par_cfg, periodic=False, device="cuda", stream=None):
+    def __init__(self, ipatch, U0, aux, eos_cfg, par_cfg, periodic=False, device="cuda", stream=None,
+                 scheme=mhd.IMEX_442):
+        self.scheme = scheme
+        self.aii = IMEX_AII[scheme]
         self.ip = ipatch
         self.patch = mhd.patch_of(ipatch)
         self.eos = mhd.make_eos(eos_cfg)
         self.par = mhd.make_params(dict(par_cfg, evolve_m1=1))
+        self.nd = bool(par_cfg.get("evolve_m1n", 0))
+        self.nfields = I.NU_M1N if self.nd else I.NU_M1
         self.periodic = periodic
         self.stream = stream
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
         self.Un = t(U0)
+        assert self.Un.shape[0] == self.nfields
         self.Ust = self.Un.clone()
         self.aux = t(aux)
         shp = tuple(ipatch.shape)
         self.F = [torch.zeros_like(self.Un) for _ in range(4)]
-        self.R = [torch.zeros((12,) + shp, dtype=torch.float64, device=device) for _ in range(4)]
+        self.R = [torch.zeros((self.nfields - I.NU,) + shp, dtype=torch.float64, device=device) for _ in range(4)]
         self.P = torch.zeros((I.NP,) + shp, dtype=torch.float64, device=device)
         self.flags = torch.zeros(shp, dtype=torch.uint8, device=device)
-        self.ws = mhd.workspace_for(self.patch, device, m1=True)
+        self.ws = mhd.workspace_for(self.patch, device, m1=True, m1n=self.nd)
         self.vmax = torch.zeros(1, dtype=torch.float64, device=device)
         self.nfail = torch.zeros(1, dtype=torch.int64, device=device)
 
     def step(self, dt):
         s_ = self.stream
-        for s in range(4):
-            mhd.imex_combine(self.patch, s, dt, self.Un, self.F, self.R, self.Ust, s_)
+        nf = self.nfields
+        ns = len(self.aii)
+        for s in range(ns):
+            mhd.imex_combine(self.patch, s, dt, self.Un, self.F, self.R, self.Ust, s_, nfields=nf, scheme=self.scheme)
             if self.periodic:
-                mhd.fill_ghosts_periodic(self.patch, self.Ust, I.NU_M1, s_)
+                mhd.fill_ghosts_periodic(self.patch, self.Ust, nf, s_)
             mhd.con2prim(self.patch, self.eos, self.Ust, self.P, self.flags, None, None, s_)
-            if IMEX_AII[s] != 0.0:
-                mhd.m1_implicit(self.patch, self.aux, self.Ust, self.P, IMEX_AII[s] * dt, self.nfail, s_)
+            if self.aii[s] != 0.0:
+                mhd.m1_implicit(self.patch, self.aux, self.Ust, self.P, self.aii[s] * dt, self.nfail, s_,
+                                evolve_n=self.nd)
                 if self.periodic:
-                    mhd.fill_ghosts_periodic(self.patch, self.Ust, I.NU_M1, s_)
+                    mhd.fill_ghosts_periodic(self.patch, self.Ust, nf, s_)
             mhd.rhs_split(self.patch, self.par, self.eos, self.Ust, self.P, self.aux, self.F[s], self.R[s], self.vmax,
                           self.ws, s_)
-        mhd.imex_combine(self.patch, 4, dt, self.Un, self.F, self.R, self.Un, s_)
+        mhd.imex_combine(self.patch, ns, dt, self.Un, self.F, self.R, self.Un, s_, nfields=nf, scheme=self.scheme)
         if self.periodic:
-            mhd.fill_ghosts_periodic(self.patch, self.Un, I.NU_M1, s_)
+            mhd.fill_ghosts_periodic(self.patch, self.Un, nf, s_)

@@ -4,12 +4,15 @@ The network is checked against the oracle's FP64 network with the same bf16
 roundings; agreement is to the arithmetic the two sides do differently (FP32
 accumulation on the matrix cores vs exact sums), which can flip a bf16
 rounding of a hidden activation now and then.  The con2prim answer with the
-learned guess is checked against the plain bracketed solver, which stays the
-judge: mu and mu_+ to 1e-12 relative (on all but a rare set of cells where the
-root function is flat to rounding around its root, where both answers must
+learned guess is checked against the oracle's bracketed solver on the same
+states (rejected guesses bitwise against the GPU's bracketed solver, which
+decides them): mu and mu_+ to 1e-12 relative (on all but a rare set of cells
+where the clamped root function has several roots, where both answers must
 reproduce the conserved state to 1e-12), flags equal apart from the fallback
 bit (and the eps-floor decision of the plain test), primitives to 1e-12 on
-well-conditioned cells, and a backward error of 1e-12 on every cell.
+the cells whose predicted error (condition in the data, and sensitivity to
+mu times the two roots' difference) is below 1e-13, within 16 times the
+prediction elsewhere, and a backward error of 1e-12 on every cell.
 """
 import sys
 
@@ -183,21 +186,113 @@ def c2p_both(ip, U, prm, eos_cfg):
     return out
 
 
-def check_learned_against_plain(orc, ip, U, P, EM, out, eos_cfg):
+def condition_estimate(orc, g, e, U, Po, flo):
+    """Relative condition number of each cell's primitives in its input data:
+    the oracle's answer is recomputed from the conserved and metric fields
+    perturbed by 16 ulp (relative, random signs, two draws); kappa is the
+    largest relative change of rho, eps, p, W (v relative to its largest
+    component) over 16 * 2^-52.  A cell whose flags change gets kappa = inf."""
+    r = np.random.default_rng(99)
+    delta = 16.0 * 2.0 ** -52
+    kap = np.zeros(Po.shape[1:])
+    for _ in range(2):
+        Up = U * (1.0 + delta * r.choice([-1.0, 1.0], size=U.shape))
+        Pp = np.zeros_like(Po)
+        fp = np.zeros_like(flo)
+        orc.con2prim(g, e, Up, Pp, fp, None)
+        vs = np.maximum(np.abs(Po[3:6]).max(0), 1e-300)
+        ch = [np.abs(Pp[c] - Po[c]) / np.maximum(np.abs(Po[c]), 1e-300) for c in (I.RHO, I.EPS, I.PRESS, I.WLOR)]
+        ch.append(np.abs(Pp[3:6] - Po[3:6]).max(0) / vs)
+        k = np.max(ch, axis=0) / delta
+        k[fp != flo] = np.inf
+        kap = np.maximum(kap, k)
+    return kap
+
+
+def mu_sensitivity(orc, g, e, U, mu):
+    """|dx/dmu| mu/|x| of the primitives at the root (central difference of
+    the oracle's primitives at mu (1 -+ 1e-8)), the largest over rho, eps,
+    p, W and v (relative to its largest component)."""
+    d = 1e-8
+    Pa = np.zeros((I.NP,) + mu.shape)
+    Pb = np.zeros_like(Pa)
+    P0 = np.zeros_like(Pa)
+    orc.c2p_prims_at(g, e, U, mu * (1.0 + d), Pa)
+    orc.c2p_prims_at(g, e, U, mu * (1.0 - d), Pb)
+    orc.c2p_prims_at(g, e, U, mu, P0)
+    ks = [np.abs(Pa[c] - Pb[c]) / (2 * d * np.maximum(np.abs(P0[c]), 1e-300))
+          for c in (I.RHO, I.EPS, I.PRESS, I.WLOR)]
+    vs = np.maximum(np.abs(P0[3:6]).max(0), 1e-300)
+    ks.append(np.abs(Pa[3:6] - Pb[3:6]).max(0) / (2 * d * vs))
+    return np.max(ks, axis=0)
+
+
+def ulp_response(orc, g, e, U, mu):
+    """The primitives' largest relative change (rho, eps, p, W; v relative to
+    its largest component) when mu moves by one to three ulp either way: the
+    rounding noise of evaluating them at a root, which a second evaluation in
+    another operation order may show (large where eps comes out of a
+    cancellation)."""
+    P0 = np.zeros((I.NP,) + mu.shape)
+    orc.c2p_prims_at(g, e, U, mu, P0)
+    vs = np.maximum(np.abs(P0[3:6]).max(0), 1e-300)
+    worst = np.zeros(mu.shape)
+    for j in (-3, -2, -1, 1, 2, 3):
+        Pj = np.zeros_like(P0)
+        orc.c2p_prims_at(g, e, U, mu * (1.0 + j * 2.0 ** -52), Pj)
+        ch = [np.abs(Pj[c] - P0[c]) / np.maximum(np.abs(P0[c]), 1e-300) for c in (I.RHO, I.EPS, I.PRESS, I.WLOR)]
+        ch.append(np.abs(Pj[3:6] - P0[3:6]).max(0) / vs)
+        worst = np.maximum(worst, np.max(ch, axis=0))
+    return worst
+
+
+def is_root(orc, g, e, U, mu, mup):
+    """Whether each mu is a root of the recovery's f below mu_+ within the
+    solvers' acceptance: |f(mu)| <= 1e-12 mu, or f changes sign within
+    1e-12 mu of it, or mu = mu_+ with f(mu_+) <= 0 (the end of the bracket)."""
+    _, f0 = orc.c2p_f_at(g, e, U, mu)
+    _, fl = orc.c2p_f_at(g, e, U, mu * (1.0 - 1e-12))
+    _, fh = orc.c2p_f_at(g, e, U, mu * (1.0 + 1e-12))
+    _, fp = orc.c2p_f_at(g, e, U, mup)
+    return (np.abs(f0) <= 1e-12 * mu) | (fl * fh <= 0.0) | ((mu >= mup * (1.0 - 1e-12)) & (fp <= 0.0))
+
+
+def check_learned(orc, ip, U, P, EM, out, eos_cfg):
+    """The learned answer against the oracle's bracketed solver on the same
+    states (and, where the network's guess was rejected, bitwise against the
+    GPU's bracketed solver, which takes the oracle's steps)."""
     Up, Pp, flp, mup, stp = out["plain"]
     Ul, Pl, fll, mul, stl = out["learned"]
-    FB = np.uint8(32)
-    fb = (fll & FB) != 0
-    # fallback points were solved by the plain solver: bitwise identical
-    assert np.array_equal(Pl[:, fb], Pp[:, fb])
-    assert np.array_equal(mul[:, fb], mup[:, fb])
-    flg = fll & ~FB
-    same = flg == flp
-    diff = ~same
-    assert diff.mean() < 1e-3
-    assert np.all(((flg ^ flp)[diff] & ~np.uint8(2)) == 0)
     g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
     e = orc.make_eos(eos_cfg)
+    Uo = U.copy()
+    Po = np.zeros_like(P)
+    flo = np.zeros(ip.shape, dtype=np.uint8)
+    muo = np.zeros((2,) + ip.shape)
+    orc.con2prim(g, e, Uo, Po, flo, muo)
+    FB = np.uint8(32)
+    fb = (fll & FB) != 0
+    # rejected guesses: the bracketed solver decided, bit for bit
+    assert np.array_equal(Pl[:, fb], Pp[:, fb]) and np.array_equal(mul[:, fb], mup[:, fb])
+    acc = ~fb & (mul[1] > 0)
+    # mu_+ (Newton on f_a) to 1e-12 of the oracle's, and mu below it
+    relp = np.abs(mul[0][acc] - muo[0][acc]) / muo[0][acc]
+    assert relp.max() <= 1e-12, relp.max()
+    assert np.all(mul[1][acc] <= muo[0][acc] * (1.0 + 1e-12))
+    rel = np.zeros(ip.shape)
+    rel[acc] = np.abs(mul[1][acc] - muo[1][acc]) / muo[1][acc]
+    other = acc & (rel > 1e-12)
+    say("accepted %d of %d solved; mu_+ to %.1e; roots differing by more than 1e-12: %d (max %.1e); max elsewhere %.1e"
+        % (acc.sum(), (muo[1] > 0).sum(), relp.max(), other.sum(), rel.max(), rel[acc & ~other].max()))
+    # f need not be monotone where rho or eps is clamped into the EoS range, so a
+    # guess can lead to another root of it than the bracketed solver's: every
+    # such root must be a root (within the acceptance) of the oracle's f
+    if other.any():
+        assert np.all(is_root(orc, g, e, U, mul[1], mul[0])[other])
+    flg = fll & ~FB
+    diff = flg != flo
+    assert diff.mean() < 1e-3
+    assert np.all(((flg ^ flo)[diff] & ~np.uint8(2)) == 0)
 
     def backward_error(Pside, mask):
         U2 = U.copy()
@@ -207,41 +302,45 @@ def check_learned_against_plain(orc, ip, U, P, EM, out, eos_cfg):
         scale = np.abs(C0[0]) + np.abs(C0[2]) + np.sqrt((C0[3:6] ** 2).sum(0))
         return np.abs(C2 - C0).max(0) / scale
 
-    # the roots agree to 1e-12 except where f is flat to rounding around its
-    # root (several answers are correct there): those must stay rare, and both
-    # answers must reproduce the conserved state to 1e-12
-    solved = same & (mup[1] > 0)
-    wc = same & (flp == 0) & (P[I.WLOR] < 2.0) & ((EM[0:3] ** 2).sum(0) < 0.1 * P[I.RHO])
-    off = np.zeros_like(solved)
-    for c in range(2):
-        rel = np.zeros(solved.shape)
-        rel[solved] = np.abs(mul[c][solved] - mup[c][solved]) / mup[c][solved]
-        assert rel[wc].max() <= 1e-12, (c, rel[wc].max())
-        off |= rel > 1e-12
-    relmu = np.abs(mul[1][solved] - mup[1][solved]) / mup[1][solved]
-    say("roots differing by more than 1e-12: %d of %d (max %.1e)" % (off.sum(), solved.sum(), relmu.max()))
-    assert off.mean() <= 1e-3
-    clean = off & (flp == 0) & (flg == 0)
+    # where several roots exist (R15-type clamped states) both answers must
+    # give back the conserved state
+    clean = other & (flo == 0) & (flg == 0)
     if clean.any():
         assert backward_error(Pl, clean).max() <= 1e-12
-        assert backward_error(Pp, clean).max() <= 1e-12
-    # forward error on the well-conditioned cells.  rho, v, W follow the root
-    # to 1e-12 relative; eps is a difference of terms of the size of the
-    # conserved energy per unit D (and p follows eps), so a root that agrees
-    # to 1e-14 can move a small eps by much more than 1e-12 of itself: those
-    # two are bounded in units of that energy scale
-    C0 = U[22:28][:, wc]
-    escale = (np.abs(C0[0]) + np.abs(C0[2]) + np.sqrt((C0[3:6] ** 2).sum(0))) / np.abs(C0[0])
+    # forward error.  Both roots are correct to the solvers' tolerances, and the
+    # primitives follow a root difference dmu with their sensitivity kmu to mu;
+    # the data's own conditioning kd adds kd 2^-52, and evaluating them at the
+    # root adds its rounding noise (ulp_response).  Where the predicted error
+    # is below 1e-13 (well-conditioned cells, with the root difference taken
+    # into account) the primitives must agree to 1e-12; elsewhere within 16
+    # times the prediction.
+    kd = condition_estimate(orc, g, e, U, Po, flo)
+    kmu = mu_sensitivity(orc, g, e, U, muo[1])
+    pred = kmu * rel + kd * 2.0 ** -52 + ulp_response(orc, g, e, U, muo[1])
+    clean_acc = acc & ~other & (flo == 0) & (flg == 0)
+    wc = clean_acc & (pred < 1e-13)
+    ill = clean_acc & ~wc & np.isfinite(pred)
+    worst, ratio = 0.0, 0.0
+
+    def worst_cell(dm):
+        q = np.unravel_index(np.argmax(dm), dm.shape)
+        return dict(rel_mu=rel[q], kd=kd[q], kmu=kmu[q], pred=pred[q], mu=(muo[:, q[0], q[1], q[2]], mul[:, q[0], q[1], q[2]]),
+                    oracle=Po[(slice(None),) + q], learned=Pl[(slice(None),) + q], plain=Pp[(slice(None),) + q])
+
     for c in range(I.NP):
-        d = np.abs(Pl[c][wc] - Pp[c][wc])
-        if c == I.EPS:
-            rel = d / escale
-        elif c == I.PRESS:
-            rel = d / (escale * Pp[I.RHO][wc])
+        if c in (3, 4, 5):
+            sc = np.maximum(np.abs(Po[3:6]).max(0), 1e-300)
         else:
-            rel = d / np.maximum(np.abs(Pp[c][wc]), 1e-300)
-        assert rel.max() <= 1e-12, (c, rel.max())
-    assert backward_error(Pl, flg == 0).max() <= 1e-12
+            sc = np.maximum(np.abs(Po[c]), 1e-300)
+        d = np.abs(Pl[c] - Po[c]) / sc
+        assert d[wc].max() <= 1e-12, (c, d[wc].max(), worst_cell(np.where(wc, d, -1.0)))
+        if ill.any():
+            worst = max(worst, d[ill].max())
+            ratio = max(ratio, (d[ill] / (pred[ill] + 1e-16)).max())
+    say("cells with predicted error < 1e-13: %d of %d accepted (primitives to 1e-12); others %d, max relative "
+        "error there %.1e, at most %.1f times the prediction" % (wc.sum(), acc.sum(), ill.sum(), worst, ratio))
+    assert ratio <= 16.0
+    assert backward_error(Pl, acc & (flg == 0)).max() <= 1e-12
     assert stl[2] == fb.sum()
     return fb.mean(), stp[3], stl[3]
 
@@ -257,17 +356,17 @@ def test_learned_c2p_untrained_is_plain(orc, dev):
     orc.prim2con(g, orc.make_eos(I.EOS_PWP3), U, P, EM, 1)
     prm = torch.as_tensor(rand_params(8, scale=0.05)).cuda()
     out = c2p_both(ip, U, prm, I.EOS_PWP3)
-    rate, itp, itl = check_learned_against_plain(orc, ip, U, P, EM, out, I.EOS_PWP3)
+    rate, itp, itl = check_learned(orc, ip, U, P, EM, out, I.EOS_PWP3)
     say("fallback rate with random weights %.3f" % rate)
 
 
 def test_learned_c2p_trained_parity_and_gain(orc, dev):
     """Train on 2^16 states (own seed), test on 2^16 fresh states spanning nine
     decades of density, W up to 10 and magnetisations up to 10: the answer
-    matches the plain solver and most points are accepted after Newton.  The
-    root-function evaluations of both paths are reported (three Newton updates
-    from a guess good to ~1e-3 cost about as many evaluations as Brent's method;
-    the time per point is what the benchmark measures)."""
+    matches the oracle's bracketed solver and most points are accepted after
+    Newton.  The gain: the learned path needs fewer root-function evaluations
+    per state than the bracketed solver (its Newton iterations, one sign check
+    and one f_a evaluation, against two Brent solves and their bracket ends)."""
     from paper_2510_13965_amd import learned
 
     say("case learned c2p, trained 2^16 -> 2^16")
@@ -279,8 +378,9 @@ def test_learned_c2p_trained_parity_and_gain(orc, dev):
     g = orc.make_grid(ip.n, ip.dx, ng=0)
     orc.prim2con(g, orc.make_eos(I.EOS_PWP3), U, P, EM, 1)
     out = c2p_both(ip, U, prm, I.EOS_PWP3)
-    rate, itp, itl = check_learned_against_plain(orc, ip, U, P, EM, out, I.EOS_PWP3)
+    rate, itp, itl = check_learned(orc, ip, U, P, EM, out, I.EOS_PWP3)
     n = ip.npts
     say("fallback rate %.4f; root-function evaluations per point: plain %.2f learned %.2f"
         % (rate, itp / n, itl / n))
     assert rate < 0.2
+    assert itl < 0.85 * itp

@@ -100,6 +100,18 @@ def test_m1_rhs_parity_star(orc, dev):
     assert msg == pytest.approx(mso, rel=1e-12)
 
 
+def test_m1_rhs_parity_star_64(orc, dev):
+    """The star at the benchmark's patch size (64^3 interior, three species),
+    every interior point of all 44 fields against the oracle."""
+    say("case m1 rhs, star 64^3")
+    ip, U, P, EM = I.tov_star_state(n=64)
+    U44, aux = with_m1(orc, ip, U, P, EM, seed=I.SEED0 + 63)
+    O, mso = oracle_full(orc, ip, U44, aux)
+    G, msg = gpu_full(ip, U44, aux)
+    compare(ip, G, O, "star64+m1")
+    assert msg == pytest.approx(mso, rel=1e-12)
+
+
 def test_m1_rk4_step_parity(orc, dev):
     """One RK4 step with 44 fields, frozen ghosts, against the oracle's step."""
     import torch
