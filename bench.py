@@ -737,7 +737,10 @@ def cpu_baseline_level_m1(args):
 # point-fields for the RK stage.  The MHD and M1 updates count every interface
 # once.  Star patch: the 128^3 star (M1 rows: three grey species on the same
 # star).  Level with radiation: the 16-box subset of the 803-box level
-# (inputs.level_subset), three grey species, summed over the boxes.
+# (inputs.level_subset), three grey species, summed over the boxes
+# (python oracle/opcount.py --level-m1 803); its CCZ4 row includes the
+# radiation's matter terms, while the closure they use is counted with the M1
+# point step, where the kernels evaluate it.
 FLOP_PER_UNIT_STAR = {
     "k_con2prim": 188.85,
     "k_mhd_point": 1608.0,
@@ -748,13 +751,13 @@ FLOP_PER_UNIT_STAR = {
     "k_m1_update": 2855.5,
 }
 FLOP_PER_UNIT_LEVEL_M1 = {
-    "k_con2prim": 188.85,
+    "k_con2prim": 233.58,
     "k_mhd_point": 1608.0,
-    "k_mhd_update": 5136.11,
-    "ccz4 (4 kernels)": 10396.0,
+    "k_mhd_update": 5048.19,
+    "ccz4 (4 kernels)": 10651.0,
     "k_rk4_stage": 4.75,
-    "k_m1_point": 15301.03,
-    "k_m1_update": 2855.5,
+    "k_m1_point": 11941.59,
+    "k_m1_update": 2873.4,
 }
 # HBM bytes per launch of a kernel from rocprofv3 --pmc (FETCH_SIZE and
 # WRITE_SIZE, each scaled by what the counter reads for a plain 1 GiB copy),

@@ -268,7 +268,9 @@ void orc_m1_matter(const double* U, const double* P, int64_t N, int64_t p, doubl
     m1_state s;
     double Pij[3][3], J, H[3], chi;
     point_state(U, P, N, p, sp, &m, &s);
+    ORC_PHASE(ORC_PH_M1_RECL); /* the closure itself belongs to the M1 point step */
     closure(&s, Pij, &J, H, &chi, NULL);
+    ORC_PHASE(ORC_PH_CCZ4);
     *E += s.E;
     for (i = 0; i < 3; ++i) {
       S[i] += s.F[i];

@@ -52,6 +52,7 @@ struct M1Args {
 };
 
 // padded indices
+template <bool ND>
 __device__ __forceinline__ void m1_point_at(const M1Args& a, int i, int j, int k) {
   const Geom& g = a.g;
   const int64_t sf = g.sf, p = g.at(i, j, k);
@@ -82,7 +83,7 @@ __device__ __forceinline__ void m1_point_at(const M1Args& a, int i, int j, int k
       }
       f[4 * sf] = m1_speed(s, m.gu, chi, alp, bd, d);
     }
-    if (a.nd) {
+    if (ND) {
       const double gam = s.W * (s.E - s.vF) / J;
       a.W[(int64_t)(kM1Gamma + sp) * sf + p] = gam;
       const double Hn = s.W * (J - s.E + s.vF);
@@ -99,13 +100,16 @@ __device__ __forceinline__ void m1_point_at(const M1Args& a, int i, int j, int k
   }
 }
 
+// ND: the number densities too (a compile-time switch, so the kernels without
+// them carry none of their registers)
+template <bool ND>
 __global__ void __launch_bounds__(256) k_m1_point(M1Args a) {
   const Geom& g = a.g;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= g.nx + 2 * g.ng || j >= g.ny + 2 * g.ng) return;
-  m1_point_at(a, i, j, k);
+  m1_point_at<ND>(a, i, j, k);
 }
 
 // Lax-Friedrichs speed and the thick-limit weight A = tanh(1/(kappa h)) at the
@@ -138,6 +142,7 @@ __device__ __forceinline__ double m1_holo(const double* __restrict__ u, const do
 }
 
 // interior indices; returns the largest M1 point speed at the point (0 if not live)
+template <bool ND>
 __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, int k, bool live) {
   const Geom& g = a.g;
   const int64_t sf = g.sf;
@@ -176,7 +181,7 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
           const double fl = m1_holo(u, f, wl, q - st, st);
           out[c] -= div_rn(fr - fl, h, ih);
         }
-        if (a.nd) {
+        if (ND) {
           const double* u = U + (int64_t)(44 + sp) * sf;
           const double* f = a.W + (int64_t)(kM1NFlux + 3 * sp + d) * sf;
           const double fr = m1_holo(u, f, wr, q, st);
@@ -300,7 +305,7 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
 #pragma unroll
       for (int c = 0; c < 4; ++c) a.rhs[(int64_t)(32 + 4 * sp + c) * sf + q] = out[c];
     }
-    if (a.nd) {
+    if (ND) {
       // number densities: emission and absorption, and the electron fraction's source
       double C[3];
 #pragma unroll 1
@@ -324,31 +329,33 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
   return vmax;
 }
 
+template <bool ND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update(M1Args a) {
   const Geom& g = a.g;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z;
-  const double vmax = m1_update_at(a, i, j, k, i < g.nx && j < g.ny);
+  const double vmax = m1_update_at<ND>(a, i, j, k, i < g.nx && j < g.ny);
   if (a.max_speed) block_max_to(a.max_speed, vmax);
 }
 
 // levels: the same point functions over every box, one persistent launch each
+template <bool ND>
 __global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
   for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr, L.nd, L.par.m_b};
-    m1_point_at(a, i, j, k);
+    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr, ND, L.par.m_b};
+    m1_point_at<ND>(a, i, j, k);
   });
 }
 
-template <bool IMEX>
+template <bool IMEX, bool ND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update_lv(LevelArgs L) {
   double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     const M1Args a{B.g,      L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs<IMEX>(B, L), L.max_speed,
-                   level_stiff<IMEX>(B, L), L.nd, L.par.m_b};
-    vmax = fmax(vmax, m1_update_at(a, i, j, k, live));
+                   level_stiff<IMEX>(B, L), ND, L.par.m_b};
+    vmax = fmax(vmax, m1_update_at<ND>(a, i, j, k, live));
   });
   if (L.max_speed) block_max_to(L.max_speed, vmax);
 }
@@ -356,15 +363,25 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 int m1_workspace_fields(bool nd) { return nd ? kM1NFields : kM1Fields; }
 
 int launch_m1_point_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
-  MHD_LAUNCH(KID_M1_POINT, k_m1_point_lv, dim3(grid), dim3(block), 0, s, L);
+  if (L.nd)
+    MHD_LAUNCH(KID_M1_POINT, k_m1_point_lv<true>, dim3(grid), dim3(block), 0, s, L);
+  else
+    MHD_LAUNCH(KID_M1_POINT, k_m1_point_lv<false>, dim3(grid), dim3(block), 0, s, L);
   return (int)hipGetLastError();
 }
 
 int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t s) {
-  if (L.slot >= 0)
-    MHD_LAUNCH(KID_M1_UPDATE, k_m1_update_lv<true>, dim3(grid), dim3(block), 0, s, L);
-  else
-    MHD_LAUNCH(KID_M1_UPDATE, k_m1_update_lv<false>, dim3(grid), dim3(block), 0, s, L);
+  if (L.slot >= 0) {
+    if (L.nd)
+      MHD_LAUNCH(KID_M1_UPDATE, (k_m1_update_lv<true, true>), dim3(grid), dim3(block), 0, s, L);
+    else
+      MHD_LAUNCH(KID_M1_UPDATE, (k_m1_update_lv<true, false>), dim3(grid), dim3(block), 0, s, L);
+  } else {
+    if (L.nd)
+      MHD_LAUNCH(KID_M1_UPDATE, (k_m1_update_lv<false, true>), dim3(grid), dim3(block), 0, s, L);
+    else
+      MHD_LAUNCH(KID_M1_UPDATE, (k_m1_update_lv<false, false>), dim3(grid), dim3(block), 0, s, L);
+  }
   return (int)hipGetLastError();
 }
 
@@ -372,14 +389,22 @@ int launch_m1_point(const Geom& g, const double* U, const double* P, const doubl
                     hipStream_t s) {
   M1Args a{g, U, P, aux, ws, nullptr, nullptr, nullptr, nd, 0.0};
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
-  MHD_LAUNCH(KID_M1_POINT, k_m1_point, dim3((Nx + 63) / 64, (Ny + 3) / 4, Nz), dim3(64, 4, 1), 0, s, a);
+  const dim3 grd((Nx + 63) / 64, (Ny + 3) / 4, Nz);
+  if (nd)
+    MHD_LAUNCH(KID_M1_POINT, k_m1_point<true>, grd, dim3(64, 4, 1), 0, s, a);
+  else
+    MHD_LAUNCH(KID_M1_POINT, k_m1_point<false>, grd, dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 
 int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
                      double* max_speed, double* stiff, int nd, double m_b, hipStream_t s) {
   M1Args a{g, U, P, aux, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed), stiff, nd, m_b};
-  MHD_LAUNCH(KID_M1_UPDATE, k_m1_update, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), dim3(64, 4, 1), 0, s, a);
+  const dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
+  if (nd)
+    MHD_LAUNCH(KID_M1_UPDATE, k_m1_update<true>, grd, dim3(64, 4, 1), 0, s, a);
+  else
+    MHD_LAUNCH(KID_M1_UPDATE, k_m1_update<false>, grd, dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }
 
