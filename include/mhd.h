@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define MHD_ABI_VERSION 5
+#define MHD_ABI_VERSION 6
 
 #define MHD_NST 22
 #define MHD_NMHD 10
@@ -91,6 +91,9 @@ extern "C" {
 #define MHD_COUPLE_MATTER 4u
 #define MHD_EVOLVE_M1 8u /* grey M1 radiation, three species (Sec. 2.3): U has MHD_NU_M1 fields */
 #define MHD_EVOLVE_M1N 16u /* with MHD_EVOLVE_M1: the number densities too (Sec. 2.3): MHD_NU_M1N fields */
+/* with MHD_EVOLVE_M1, for mhd_rhs_split: the fluid's share of the collision
+ * exchange is stiff too (see mhd_rhs_split); single patches only */
+#define MHD_COUPLE_EXCHANGE 32u
 
 /* f_alpha_kind: the slicing function f_alpha(alpha) of the lapse equation */
 #define MHD_FALPHA_ONE 0      /* 1+log slicing, f_alpha = 1 (the paper's standard) */
@@ -425,7 +428,15 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
  *   fields, species-major, patch layout; with MHD_EVOLVE_M1N 15, the number
  *   densities' alpha sqrt(gamma) C at 12 + s) instead of rhs; the fluid's
  *   opposite exchange and the electron fraction's source stay in rhs
- *   (explicit).
+ *   (explicit).  With MHD_COUPLE_EXCHANGE in params->flags they go to
+ *   `stiff` too, after the radiation's: the fluid's share at 12 (15 with
+ *   MHD_EVOLVE_M1N) + 0 (taubar) and + 1..3 (Sbar_i), summed over the
+ *   species, and the electron fraction's at 15 + 4; mhd_imex_stiff_fields()
+ *   gives the count (12, 15, 16 or 20).  Taken with mhd_imex_combine's
+ *   coupled and mhd_m1_implicit's MHD_IMPLICIT_COUPLED, the exchange is then
+ *   implicit for both sides and conserves energy, momentum and lepton number
+ *   at every stage (the fluid's primitives are held during the solve, as App.
+ *   C holds them).
  * mhd_imex_combine: for scheme MHD_IMEX_442 (Table I: explicit RK4 with the
  *   L-stable I42L, ns = 4 stages) or MHD_IMEX_332 (Table II's SSP-RK(3,3)
  *   with an L-stable I32L re-derived from Sec. 3.1's order and L-stability
@@ -438,9 +449,12 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
  *   Uout = Un + dt sum_{j<s} AE[s][j] F[j], and on the radiation fields (32
  *   and up) also + dt sum_{j<s} AI[s][j] R[j] (the explicit state V* of the
  *   stage); s = ns: Uout = Un + dt sum_i (BE[i] F[i] + BI[i] R[i]) (radiation)
- *   and Un + dt sum_i BE[i] F[i] (other fields).  F, R: host arrays of 4
- *   device pointers to stage explicit (nfields fields) and stiff (nfields - 32
- *   fields) parts; only the entries the stage reads must be set.  Uout may
+ *   and Un + dt sum_i BE[i] F[i] (other fields).  With coupled != 0 the
+ *   fluid's taubar, Sbar_i (and DYe with the number densities) take their
+ *   stiff slots as the radiation does.  F, R: host arrays of 4 device pointers
+ *   to stage explicit (nfields fields) and stiff
+ *   (mhd_imex_stiff_fields(nfields, coupled) fields) parts; only the entries
+ *   the stage reads must be set.  Uout may
  *   alias Un only at s = ns.  The implicit solve of stage s takes
  *   adt = AI[s][s] dt.
  * mhd_m1_implicit: at the interior points, per species, replaces the radiation
@@ -452,20 +466,26 @@ int mhd_rhs(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_
  *   rounding floor: App. C leaves the stopping rule open).  A solve that does
  *   not converge (singular Jacobian, or 60 iterations) keeps the first Newton
  *   iterate, App. C's linearised implicit update about V*; nfail (device
- *   uint64, may be NULL) is incremented per such species solve.  With
- *   evolve_n != 0 (U of 47 fields, aux of MHD_NAUX_N) each species' number
+ *   uint64, may be NULL) is incremented per such species solve.  flags:
+ *   MHD_IMPLICIT_N (U of 47 fields, aux of MHD_NAUX_N): each species' number
  *   density then takes App. C's closed-form implicit update
  *   N = (N* + adt alpha eta0)/(1 + adt alpha kappa0_a/Gamma), Gamma from the
- *   updated E, F_i and their closure. */
+ *   updated E, F_i and their closure; MHD_IMPLICIT_COUPLED: the fluid's taubar
+ *   and Sbar_i then lose what each species' Ebar and Fbar_i gained, and DYe
+ *   (with MHD_IMPLICIT_N) loses m_b times the gain of (Nbar_nue -
+ *   Nbar_nuebar).  m_b is read only then; it must be finite. */
 int mhd_rhs_split(const mhd_patch_t* patch, const mhd_params_t* params, const mhd_eos_t* eos, const double* U,
                   const double* P, const double* aux, double* rhs, double* stiff, double* max_speed, void* workspace,
                   size_t workspace_bytes, void* stream);
 #define MHD_IMEX_442 0
 #define MHD_IMEX_332 1
-int mhd_imex_combine(const mhd_patch_t* patch, int scheme, int nfields, int stage, double dt, const double* Un,
-                     const double* const* F, const double* const* R, double* Uout, void* stream);
+int mhd_imex_stiff_fields(int nfields, int coupled);
+int mhd_imex_combine(const mhd_patch_t* patch, int scheme, int nfields, int coupled, int stage, double dt,
+                     const double* Un, const double* const* F, const double* const* R, double* Uout, void* stream);
+#define MHD_IMPLICIT_N 1u
+#define MHD_IMPLICIT_COUPLED 2u
 int mhd_m1_implicit(const mhd_patch_t* patch, const double* aux, double* U, const double* P, double adt,
-                    int evolve_n, uint64_t* nfail, void* stream);
+                    unsigned flags, double m_b, uint64_t* nfail, void* stream);
 
 /* Explicit RK4 stage of Table I at the interior points of `nfields` fields:
  *   stage s (0..3): acc = (s ? acc : 0) + b_s k;  s < 3: Unext = Un + dt a_{s+1,s} k;

@@ -286,6 +286,7 @@ void orc_m1_matter(const double* U, const double* P, int64_t N, int64_t p, doubl
 static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, const double* P,
                         const double* aux, double* rhs, double* stiff, double* max_speed) {
   const int ng = g->ng;
+  const int nrad = par->evolve_m1n ? 15 : 12; /* stiff slots of the radiation (and number densities) */
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
   const int64_t st[3] = {1, Nx, Nx * Ny};
@@ -407,8 +408,15 @@ static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, 
             out[0] += alp * m.sqrtg * Sn;
             for (a = 0; a < 3; ++a) out[1 + a] += alp * m.sqrtg * Si[a];
           }
-          rhs[24 * N + q] -= alp * m.sqrtg * Sn;
-          for (a = 0; a < 3; ++a) rhs[(25 + a) * N + q] -= alp * m.sqrtg * Si[a];
+          if (stiff && par->couple_exchange) {
+            /* the fluid's share in the stiff part too: slots nrad (tau), nrad + 1..3 (S_i) */
+            double* fs = stiff + (int64_t)nrad * N + q;
+            fs[0] = (sp == 0 ? 0.0 : fs[0]) - alp * m.sqrtg * Sn;
+            for (a = 0; a < 3; ++a) fs[(1 + a) * N] = (sp == 0 ? 0.0 : fs[(1 + a) * N]) - alp * m.sqrtg * Si[a];
+          } else {
+            rhs[24 * N + q] -= alp * m.sqrtg * Sn;
+            for (a = 0; a < 3; ++a) rhs[(25 + a) * N + q] -= alp * m.sqrtg * Si[a];
+          }
           for (c = 0; c < 4; ++c) rhs[(32 + 4 * sp + c) * N + q] = out[c];
         }
       }
@@ -416,7 +424,6 @@ static void m1_rhs_impl(const orc_grid* g, const orc_par* par, const double* U, 
   free(FL);
   free(LM);
   if (max_speed) *max_speed = fmax(*max_speed, vmax);
-  (void)par;
 }
 
 void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const double* P, const double* aux,
@@ -426,7 +433,8 @@ void orc_m1_rhs(const orc_grid* g, const orc_par* par, const double* U, const do
 
 /* as orc_m1_rhs, but the radiation's collision terms (the stiff part of the
  * IMEX splitting) go to stiff (12 fields) instead of rhs; the fluid's opposite
- * exchange stays in rhs (explicit) */
+ * exchange stays in rhs (explicit), or with par->couple_exchange goes to the
+ * stiff slots after the radiation's (tau, then S_i; orc_imex_stiff_fields) */
 void orc_m1_rhs_split(const orc_grid* g, const orc_par* par, const double* U, const double* P,
                       const double* aux, double* rhs, double* stiff, double* max_speed) {
   m1_rhs_impl(g, par, U, P, aux, rhs, stiff, max_speed);
@@ -593,6 +601,15 @@ static int solve4(double A[4][4], double b[4], double x[4]) {
  * implicit update about V' = V* (one solve with the Jacobian at V*).  Returns
  * the number of solves that did not converge. */
 int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt) {
+  return orc_m1_implicit_x(g, U, P, aux, adt, 0);
+}
+
+/* as orc_m1_implicit; with couple != 0 the fluid's taubar and Sbar_i then lose
+ * what each species' Ebar and Fbar_i gained in its solve (the stiff exchange
+ * taken implicitly by both sides, as it is evaluated in the stiff slots of
+ * the split right-hand side) */
+int64_t orc_m1_implicit_x(const orc_grid* g, double* U, const double* P, const double* aux, double adt,
+                          int couple) {
   const int ng = g->ng;
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
@@ -644,8 +661,16 @@ int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const dou
             bad += 1;
             for (a = 0; a < 4; ++a) V[a] = V1[a];
           }
-          U[(32 + 4 * sp) * N + q] = m.sqrtg * V[0];
-          for (a = 0; a < 3; ++a) U[(33 + 4 * sp + a) * N + q] = m.sqrtg * V[1 + a];
+          {
+            const double E0 = U[(32 + 4 * sp) * N + q];
+            U[(32 + 4 * sp) * N + q] = m.sqrtg * V[0];
+            if (couple) U[24 * N + q] -= U[(32 + 4 * sp) * N + q] - E0;
+          }
+          for (a = 0; a < 3; ++a) {
+            const double F0 = U[(33 + 4 * sp + a) * N + q];
+            U[(33 + 4 * sp + a) * N + q] = m.sqrtg * V[1 + a];
+            if (couple) U[(25 + a) * N + q] -= U[(33 + 4 * sp + a) * N + q] - F0;
+          }
         }
       }
   return bad;
@@ -739,7 +764,10 @@ void orc_m1n_rhs(const orc_grid* g, const orc_par* par, const double* U, const d
             out += alp * m.sqrtg * C[sp];
           rhs[(44 + sp) * N + q] = out;
         }
-        rhs[23 * N + q] -= alp * m.sqrtg * par->m_b * (C[0] - C[1]);
+        if (stiff && par->couple_exchange)
+          stiff[(15 + 4) * N + q] = -alp * m.sqrtg * par->m_b * (C[0] - C[1]);
+        else
+          rhs[23 * N + q] -= alp * m.sqrtg * par->m_b * (C[0] - C[1]);
       }
   free(FN);
   free(LM);
@@ -751,6 +779,14 @@ void orc_m1n_rhs(const orc_grid* g, const orc_par* par, const double* U, const d
  * density on input (undensitized) and Gamma from the updated E, F_i and their
  * closure (App. C). */
 void orc_m1n_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt) {
+  orc_m1n_implicit_x(g, U, P, aux, adt, 0, 0.0);
+}
+
+/* as orc_m1n_implicit; with couple != 0, DYebar then changes by -m_b times
+ * the change of (Nbar_nue - Nbar_nuebar), the electron fraction's stiff source
+ * taken implicitly with the number densities */
+void orc_m1n_implicit_x(const orc_grid* g, double* U, const double* P, const double* aux, double adt, int couple,
+                        double m_b) {
   const int ng = g->ng;
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
@@ -761,6 +797,7 @@ void orc_m1n_implicit(const orc_grid* g, double* U, const double* P, const doubl
         const int64_t q = i + Nx * (j + Ny * k);
         const double alp = U[18 * N + q];
         m1_metric m;
+        double dN[3];
         int sp;
         m1_metric_at(U, N, q, &m);
         for (sp = 0; sp < 3; ++sp) {
@@ -771,7 +808,10 @@ void orc_m1n_implicit(const orc_grid* g, double* U, const double* P, const doubl
           closure(&s, Pij, &J, H, &chi, NULL);
           gam = s.W * (s.E - s.vF) / J;
           Ns = U[(44 + sp) * N + q] / m.sqrtg;
+          dN[sp] = -U[(44 + sp) * N + q];
           U[(44 + sp) * N + q] = m.sqrtg * (Ns + adt * alp * e0) / (1.0 + adt * alp * k0 / gam);
+          dN[sp] += U[(44 + sp) * N + q];
         }
+        if (couple) U[23 * N + q] -= m_b * (dN[0] - dN[1]);
       }
 }

@@ -99,6 +99,9 @@ typedef struct {
   int evolve_m1n;       /* with evolve_m1: neutrino number densities (fields 44..46, aux 9..14) on/off */
   double m_b;           /* reference baryon mass of the electron-fraction source */
   double les_cm;        /* C_M of the gradient SGS term of the induction equation (App. A); 0: off */
+  int couple_exchange;  /* IMEX: the fluid's share of the collision exchange is stiff too (fluid slots of R,
+                           and the implicit solve moves the exchanged energy, momentum and lepton number
+                           out of the fluid); 0: it stays explicit */
 } orc_par;
 
 /* ---- EoS (Sec. 2.2, hybrid piecewise polytrope + thermal ideal gas) ---- */
@@ -172,7 +175,11 @@ void orc_les_rhs(const orc_grid* g, const orc_par* par, const orc_eos* e, const 
 void orc_les_point_fields(const orc_grid* g, const orc_eos* e, const double* U, const double* P, double* out);
 /* threads of the oracle's OpenMP loops (timing) */
 void orc_set_threads(int n);
+/* stiff fields of the split right-hand side for these parameters */
+int orc_imex_stiff_fields(const orc_par* par);
 int64_t orc_m1_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);
+int64_t orc_m1_implicit_x(const orc_grid* g, double* U, const double* P, const double* aux, double adt,
+                          int couple);
 /* residual G and App. C Jacobian dG/dV (row-major 4x4) of the implicit M1
  * equation of one species at one point (undensitized; gd6 the physical metric) */
 void orc_m1_implicit_point(const double gd6[6], const double v[3], double W, const double V[4], const double Vs[4],
@@ -186,6 +193,8 @@ void orc_m1n_rhs(const orc_grid* g, const orc_par* par, const double* U, const d
 /* the analytic implicit number-density update of App. C, after E and F_i of
  * the stage are updated */
 void orc_m1n_implicit(const orc_grid* g, double* U, const double* P, const double* aux, double adt);
+void orc_m1n_implicit_x(const orc_grid* g, double* U, const double* P, const double* aux, double adt, int couple,
+                        double m_b);
 /* explicit part F (44 fields) and stiff radiation part R (12 fields) of L(U) */
 void orc_rhs_split(const orc_grid* g, const orc_par* par, const orc_eos* e, const double* U, const double* P,
                    const double* aux, double* F, double* R, double* max_speed);

@@ -32,7 +32,8 @@ class Par(C.Structure):
                 ("c_b", C.c_double), ("kappa_b", C.c_double), ("alpha_mp5", C.c_double),
                 ("f_beta", C.c_double), ("f_alpha_kind", C.c_int), ("evolve_st", C.c_int),
                 ("evolve_mhd", C.c_int), ("couple_matter", C.c_int), ("evolve_m1", C.c_int),
-                ("evolve_m1n", C.c_int), ("m_b", C.c_double), ("les_cm", C.c_double)]
+                ("evolve_m1n", C.c_int), ("m_b", C.c_double), ("les_cm", C.c_double),
+                ("couple_exchange", C.c_int)]
 
 
 _dp = C.POINTER(C.c_double)
@@ -133,11 +134,16 @@ def _bind(L):
         L.orc_rhs_split.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, _dp, _dp, _dp, _dp]
         L.orc_m1_implicit.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_double]
         L.orc_m1_implicit.restype = C.c_int64
+        L.orc_m1_implicit_x.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_double, C.c_int]
+        L.orc_m1_implicit_x.restype = C.c_int64
+        L.orc_imex_stiff_fields.argtypes = [C.POINTER(Par)]
+        L.orc_imex_stiff_fields.restype = C.c_int
         L.orc_imex_step.argtypes = [C.POINTER(Grid), C.POINTER(Par), C.POINTER(Eos), _dp, _dp, C.c_double, C.c_int]
         L.orc_imex_step.restype = C.c_int64
     if hasattr(L, "orc_m1n_rhs"):
         L.orc_m1n_rhs.argtypes = [C.POINTER(Grid), C.POINTER(Par), _dp, _dp, _dp, _dp, _dp]
         L.orc_m1n_implicit.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_double]
+        L.orc_m1n_implicit_x.argtypes = [C.POINTER(Grid), _dp, _dp, _dp, C.c_double, C.c_int, C.c_double]
     if hasattr(L, "orc_mlp_forward"):
         L.orc_bf16.argtypes = [C.c_float]
         L.orc_bf16.restype = C.c_float
@@ -203,6 +209,7 @@ def make_par(cfg):
     p.evolve_m1n = int(cfg.get("evolve_m1n", 0))
     p.m_b = float(cfg.get("m_b", 1.0))
     p.les_cm = float(cfg.get("les_cm", 0.0))
+    p.couple_exchange = int(cfg.get("couple_exchange", 0))
     return p
 
 
@@ -484,8 +491,20 @@ def m1_implicit_point(gd6, v, W, V, Vs, chi, adt, alp, ka, ks, eta):
     return G, Jac.reshape(4, 4)
 
 
-def m1_implicit(g, U, P, aux, adt):
-    return int(lib().orc_m1_implicit(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt)))
+def m1_implicit(g, U, P, aux, adt, couple=0):
+    """Implicit collision solve of the three species in place on U; with
+    couple, the fluid's taubar and Sbar_i lose what the radiation gained.
+    Returns the count of solves that did not converge."""
+    return int(lib().orc_m1_implicit_x(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt), int(couple)))
+
+
+def m1n_implicit_x(g, U, P, aux, adt, couple=0, m_b=1.0):
+    lib().orc_m1n_implicit_x(C.byref(g), ptr(U), ptr(P), ptr(aux), float(adt), int(couple), float(m_b))
+
+
+def imex_stiff_fields(par):
+    """Stiff fields of the split right-hand side for these parameters."""
+    return int(lib().orc_imex_stiff_fields(C.byref(par)))
 
 
 def imex_step(g, par, e, U, aux, dt, periodic=False, scheme=0):

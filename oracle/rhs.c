@@ -274,9 +274,27 @@ void orc_imex_tableau(int scheme, double AE[16], double AI[16], double BE[4], do
 
 /* one IMEX step of `scheme` (0: IMEX(4,4,2) of Table I, 1: IMEX(3,3,2) with
  * the re-derived I32L above) */
+/* stiff fields of the split right-hand side: the radiation's 12 (15 with the
+ * number densities), then with par->couple_exchange the fluid's share of the
+ * exchange, tau and S_i (and DYe with the number densities) */
+int orc_imex_stiff_fields(const orc_par* par) {
+  const int nrad = par->evolve_m1n ? 15 : 12;
+  return par->couple_exchange ? nrad + 4 + (par->evolve_m1n ? 1 : 0) : nrad;
+}
+
+/* stiff slot of evolved field f, or -1 */
+static int stiff_slot(const orc_par* par, int f) {
+  const int nrad = par->evolve_m1n ? 15 : 12;
+  if (f >= 32) return f - 32;
+  if (!par->couple_exchange) return -1;
+  if (f >= 24 && f <= 27) return nrad + f - 24;
+  if (f == 23 && par->evolve_m1n) return nrad + 4;
+  return -1;
+}
+
 int64_t orc_imex_step_scheme(const orc_grid* g, const orc_par* par, const orc_eos* e, double* U, const double* aux,
                              double dt, int periodic, int scheme) {
-  const int ng = g->ng, nf = par->evolve_m1n ? 47 : 44, nr = nf - 32;
+  const int ng = g->ng, nf = par->evolve_m1n ? 47 : 44, nr = orc_imex_stiff_fields(par);
   const int64_t Nx = g->n[0] + 2 * ng, Ny = g->n[1] + 2 * ng, Nz = g->n[2] + 2 * ng;
   const int64_t N = npts(g);
   double AE[16], AI[16], BE[4], BI[4];
@@ -297,6 +315,7 @@ int64_t orc_imex_step_scheme(const orc_grid* g, const orc_par* par, const orc_eo
   for (st = 0; st < ns; ++st) {
     memcpy(Ui, Un, sizeof(double) * nf * N);
     for (f = 0; f < nf; ++f) {
+      const int rs = stiff_slot(par, f);
       int64_t k;
 #pragma omp parallel for schedule(static)
       for (k = ng; k < Nz - ng; ++k)
@@ -306,31 +325,33 @@ int64_t orc_imex_step_scheme(const orc_grid* g, const orc_par* par, const orc_eo
             double v = Un[p];
             int jj;
             for (jj = 0; jj < st; ++jj) v += dt * AE[4 * st + jj] * F[jj][p];
-            if (f >= 32)
-              for (jj = 0; jj < st; ++jj) v += dt * AI[4 * st + jj] * R[jj][(f - 32) * N + (p - f * N)];
+            if (rs >= 0)
+              for (jj = 0; jj < st; ++jj) v += dt * AI[4 * st + jj] * R[jj][rs * N + (p - f * N)];
             Ui[p] = v;
           }
     }
     if (periodic) orc_fill_periodic(g, Ui, nf);
     orc_con2prim(g, e, Ui, P, NULL, NULL);
     if (AI[4 * st + st] != 0.0) {
-      bad += orc_m1_implicit(g, Ui, P, aux, AI[4 * st + st] * dt);
-      if (par->evolve_m1n) orc_m1n_implicit(g, Ui, P, aux, AI[4 * st + st] * dt);
+      bad += orc_m1_implicit_x(g, Ui, P, aux, AI[4 * st + st] * dt, par->couple_exchange);
+      if (par->evolve_m1n)
+        orc_m1n_implicit_x(g, Ui, P, aux, AI[4 * st + st] * dt, par->couple_exchange, par->m_b);
       if (periodic) orc_fill_periodic(g, Ui, nf);
     }
     orc_rhs_split(g, par, e, Ui, P, aux, F[st], R[st], NULL);
   }
   for (f = 0; f < nf; ++f) {
+    const int rs = stiff_slot(par, f);
     int64_t k;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) private(st)
     for (k = ng; k < Nz - ng; ++k)
       for (int64_t j = ng; j < Ny - ng; ++j)
         for (int64_t i = ng; i < Nx - ng; ++i) {
           const int64_t p = f * N + i + Nx * (j + Ny * k);
           double v = Un[p];
           for (st = 0; st < ns; ++st) v += dt * BE[st] * F[st][p];
-          if (f >= 32)
-            for (st = 0; st < ns; ++st) v += dt * BI[st] * R[st][(f - 32) * N + (p - f * N)];
+          if (rs >= 0)
+            for (st = 0; st < ns; ++st) v += dt * BI[st] * R[st][rs * N + (p - f * N)];
           U[p] = v;
         }
   }

@@ -22,11 +22,11 @@ int launch_les(const Geom& g, const mhd_eos_t& eos, double cm, const double* U, 
 int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, int nd,
                     hipStream_t s);
 int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
-                     double* max_speed, double* stiff, int nd, double m_b, hipStream_t s);
-int launch_imex_combine(const Geom& g, int scheme, int nfields, int stage, double dt, const double* Un,
+                     double* max_speed, double* stiff, int nd, double m_b, int coupled, hipStream_t s);
+int launch_imex_combine(const Geom& g, int scheme, int nfields, int coupled, int stage, double dt, const double* Un,
                         const double* const* F, const double* const* R, double* Uout, hipStream_t s);
-int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt, int nd,
-                       unsigned long long* nfail, hipStream_t s);
+int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt, int nd, int coupled,
+                       double m_b, unsigned long long* nfail, hipStream_t s);
 int ccz4_workspace_fields();
 int launch_mhd(const Geom& g, const mhd_params_t& par, const mhd_eos_t& eos, const double* U, const double* P,
                double* ws, double* rhs, double* max_speed, int strip, hipStream_t s);
@@ -363,8 +363,9 @@ static int rhs_impl(const mhd_patch_t* patch, const mhd_params_t* params, const 
   } else {
     if ((rc = hip_check(mhd::launch_zero_interior(g, MHD_NST, MHD_NMHD, rhs, s), "mhd_rhs/zero"))) return rc;
   }
+  const int coupled = (stiff && (fl & MHD_COUPLE_EXCHANGE)) ? 1 : 0;
   if (m1 && (rc = hip_check(mhd::launch_m1_update(g, U, P, aux, ws_m1, rhs, max_speed, stiff, nd ? 1 : 0, params->m_b,
-                                                  s),
+                                                  coupled, s),
                             "mhd_rhs/m1 update")))
     return rc;
   return MHD_OK;
@@ -384,8 +385,15 @@ int mhd_rhs_split(const mhd_patch_t* patch, const mhd_params_t* params, const mh
   return rhs_impl(patch, params, eos, U, P, aux, rhs, stiff, max_speed, workspace, workspace_bytes, stream);
 }
 
-int mhd_imex_combine(const mhd_patch_t* patch, int scheme, int nfields, int stage, double dt, const double* Un,
-                     const double* const* F, const double* const* R, double* Uout, void* stream) {
+int mhd_imex_stiff_fields(int nfields, int coupled) {
+  if (nfields != MHD_NU_M1 && nfields != MHD_NU_M1N)
+    return fail(MHD_EINVAL, "mhd_imex_stiff_fields: nfields must be %d or %d", MHD_NU_M1, MHD_NU_M1N);
+  const int nrad = nfields - 32;
+  return coupled ? nrad + 4 + (nfields == MHD_NU_M1N ? 1 : 0) : nrad;
+}
+
+int mhd_imex_combine(const mhd_patch_t* patch, int scheme, int nfields, int coupled, int stage, double dt,
+                     const double* Un, const double* const* F, const double* const* R, double* Uout, void* stream) {
   int rc;
   if (scheme != MHD_IMEX_442 && scheme != MHD_IMEX_332)
     return fail(MHD_EINVAL, "mhd_imex_combine: scheme must be MHD_IMEX_442 or MHD_IMEX_332");
@@ -406,17 +414,21 @@ int mhd_imex_combine(const mhd_patch_t* patch, int scheme, int nfields, int stag
   }
   if (Uout == Un && stage < ns) return fail(MHD_EINVAL, "mhd_imex_combine: Uout may alias Un only at the final stage");
   return hip_check(
-      mhd::launch_imex_combine(geom_of(patch), scheme, nfields, stage, dt, Un, f4, r4, Uout, (hipStream_t)stream),
+      mhd::launch_imex_combine(geom_of(patch), scheme, nfields, coupled ? 1 : 0, stage, dt, Un, f4, r4, Uout,
+                               (hipStream_t)stream),
       "mhd_imex_combine");
 }
 
 int mhd_m1_implicit(const mhd_patch_t* patch, const double* aux, double* U, const double* P, double adt,
-                    int evolve_n, uint64_t* nfail, void* stream) {
+                    unsigned flags, double m_b, uint64_t* nfail, void* stream) {
   int rc;
   if ((rc = check_patch(patch, -1, 1, "mhd_m1_implicit"))) return rc;
   if (!aux || !U || !P) return fail(MHD_EINVAL, "mhd_m1_implicit: aux, U and P are required");
   if (!(adt >= 0.0) || !std::isfinite(adt)) return fail(MHD_EINVAL, "mhd_m1_implicit: adt must be finite and >= 0");
-  return hip_check(mhd::launch_m1_implicit(geom_of(patch), U, P, aux, adt, evolve_n ? 1 : 0,
+  if (flags & ~(MHD_IMPLICIT_N | MHD_IMPLICIT_COUPLED)) return fail(MHD_EINVAL, "mhd_m1_implicit: unknown flags");
+  if (!std::isfinite(m_b)) return fail(MHD_EINVAL, "mhd_m1_implicit: m_b must be finite");
+  return hip_check(mhd::launch_m1_implicit(geom_of(patch), U, P, aux, adt, (flags & MHD_IMPLICIT_N) ? 1 : 0,
+                                           (flags & MHD_IMPLICIT_COUPLED) ? 1 : 0, m_b,
                                            reinterpret_cast<unsigned long long*>(nfail), (hipStream_t)stream),
                    "mhd_m1_implicit");
 }

@@ -54,26 +54,41 @@ struct ImexArgs {
   double dt;
   const double* Un;
   const double* F[4];  // explicit parts of the earlier stages (44 or 47 fields)
-  const double* R[4];  // stiff parts (12 or 15 fields)
+  const double* R[4];  // stiff parts (12 or 15 fields; 16 or 20 with the coupled exchange)
   double* Uout;
+  int nfields;
+  int coupled;  // the fluid's share of the exchange is in R too
 };
 
 // block 64x4, grid z = nz * nfields (field-major)
-// one element of stage `s` of Table I's IMEX combination: field f (0..46) at
-// point pt; the stiff parts exist for the radiation fields (f >= 32) only
+// stiff slot of evolved field f (nfields 44 or 47), or -1: the radiation's
+// fields (32 and up) in order, then with the coupled exchange the fluid's
+// tau and S_i, and DYe with the number densities
+__device__ __forceinline__ int stiff_slot(int f, int nfields, int coupled) {
+  const int nrad = nfields - 32;
+  if (f >= 32) return f - 32;
+  if (!coupled) return -1;
+  if (f >= 24 && f <= 27) return nrad + f - 24;
+  if (f == 23 && nfields == MHD_NU_M1N) return nrad + 4;
+  return -1;
+}
+
+// one element of stage `s` of the IMEX combination: field f (0..46) at point
+// pt, with stiff slot rs (-1: the field has no stiff part)
 __device__ __forceinline__ void imex_element(int sc, int s, double dt, const double* Un, const double* const* F,
-                                             const double* const* R, double* Uout, int f, int64_t pt, int64_t sf) {
+                                             const double* const* R, double* Uout, int f, int64_t pt, int64_t sf,
+                                             int rs) {
   const int64_t p = (int64_t)f * sf + pt;
   const int ns = kImStages[sc];
   double v = Un[p];
   if (s < ns) {
     for (int jj = 0; jj < s; ++jj) v += dt * kImAE[sc][s][jj] * F[jj][p];
-    if (f >= 32)
-      for (int jj = 0; jj < s; ++jj) v += dt * kImAI[sc][s][jj] * R[jj][(int64_t)(f - 32) * sf + pt];
+    if (rs >= 0)
+      for (int jj = 0; jj < s; ++jj) v += dt * kImAI[sc][s][jj] * R[jj][(int64_t)rs * sf + pt];
   } else {
     for (int st = 0; st < ns; ++st) v += dt * kImB[sc][st] * F[st][p];
-    if (f >= 32)
-      for (int st = 0; st < ns; ++st) v += dt * kImB[sc][st] * R[st][(int64_t)(f - 32) * sf + pt];
+    if (rs >= 0)
+      for (int st = 0; st < ns; ++st) v += dt * kImB[sc][st] * R[st][(int64_t)rs * sf + pt];
   }
   Uout[p] = v;
 }
@@ -85,7 +100,8 @@ __global__ void __launch_bounds__(256) k_imex_combine(ImexArgs a) {
   const int kz = blockIdx.z % g.nz;
   const int f = blockIdx.z / g.nz;
   if (i >= g.nx || j >= g.ny) return;
-  imex_element(a.scheme, a.stage, a.dt, a.Un, a.F, a.R, a.Uout, f, g.at(i + g.ng, j + g.ng, kz + g.ng), g.sf);
+  imex_element(a.scheme, a.stage, a.dt, a.Un, a.F, a.R, a.Uout, f, g.at(i + g.ng, j + g.ng, kz + g.ng), g.sf,
+               stiff_slot(f, a.nfields, a.coupled));
 }
 
 // every field of every interior point of a level's boxes; stage 4 writes U
@@ -97,7 +113,8 @@ __global__ void __launch_bounds__(256) k_imex_combine_lv(LevelArgs L) {
     const double* const* F = B.F;
     const double* const* R = B.R;
 #pragma unroll 4
-    for (int f = 0; f < L.nfields; ++f) imex_element(0, L.stage, L.dt, B.U, F, R, out, f, pt, B.g.sf);
+    for (int f = 0; f < L.nfields; ++f)
+      imex_element(0, L.stage, L.dt, B.U, F, R, out, f, pt, B.g.sf, stiff_slot(f, L.nfields, 0));
   });
 }
 
@@ -199,18 +216,24 @@ struct ImplArgs {
   const double* __restrict__ aux;
   double adt;
   unsigned long long* nfail;
-  int nd;  // nonzero: the number densities (U fields 44..46, aux 9..14) follow
+  int nd;       // nonzero: the number densities (U fields 44..46, aux 9..14) follow
+  int coupled;  // nonzero: the fluid's taubar, Sbar_i (and DYe) give up what the radiation gains
+  double m_b;   // baryon mass of the electron fraction's exchange
 };
 
 // the implicit collision solve of the three species at interior point q (padded
-// index); returns the number of species solves that did not converge
+// index); returns the number of species solves that did not converge.  With
+// coupled, the fluid's taubar and Sbar_i lose what each species' Ebar and
+// Fbar_i gain, and DYe loses m_b times the gain of (Nbar_nue - Nbar_nuebar).
 __device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const double* __restrict__ P,
                                                            const double* __restrict__ aux, int64_t sf, int64_t q,
-                                                           double adt, int nd = 0) {
+                                                           double adt, int nd = 0, int coupled = 0,
+                                                           double m_b = 0.0) {
   MetricR m;
   m1_metric(U, sf, q, m);
   const double alp = U[18 * sf + q];
   unsigned long long bad = 0;
+  double dN[3] = {0.0, 0.0, 0.0};
 #pragma unroll 1
   for (int sp = 0; sp < 3; ++sp) {
     const double ka = aux[(int64_t)(3 * sp) * sf + q], ks = aux[(int64_t)(3 * sp + 1) * sf + q];
@@ -262,9 +285,17 @@ __device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const do
 #pragma unroll
       for (int r = 0; r < 4; ++r) V[r] = V1[r];
     }
-    U[(int64_t)(32 + 4 * sp) * sf + q] = m.sqrtg * V[0];
+    {
+      const double E0 = U[(int64_t)(32 + 4 * sp) * sf + q];
+      U[(int64_t)(32 + 4 * sp) * sf + q] = m.sqrtg * V[0];
+      if (coupled) U[24 * sf + q] -= U[(int64_t)(32 + 4 * sp) * sf + q] - E0;
+    }
 #pragma unroll
-    for (int r = 0; r < 3; ++r) U[(int64_t)(33 + 4 * sp + r) * sf + q] = m.sqrtg * V[1 + r];
+    for (int r = 0; r < 3; ++r) {
+      const double F0 = U[(int64_t)(33 + 4 * sp + r) * sf + q];
+      U[(int64_t)(33 + 4 * sp + r) * sf + q] = m.sqrtg * V[1 + r];
+      if (coupled) U[(25 + r) * sf + q] -= U[(int64_t)(33 + 4 * sp + r) * sf + q] - F0;
+    }
     if (nd) {
       // the number density, from the moments just stored (read back as the
       // densitized fields they now are) and their closure
@@ -276,9 +307,14 @@ __device__ __forceinline__ unsigned long long m1_implicit_at(double* U, const do
       const double gam = s1.W * (s1.E - s1.vF) / J;
       const double k0 = aux[(int64_t)(9 + 2 * sp) * sf + q], e0 = aux[(int64_t)(10 + 2 * sp) * sf + q];
       const double Ns = U[(int64_t)(44 + sp) * sf + q] / m.sqrtg;
+      double d = -U[(int64_t)(44 + sp) * sf + q];
       U[(int64_t)(44 + sp) * sf + q] = m.sqrtg * (Ns + adt * alp * e0) / (1.0 + adt * alp * k0 / gam);
+      d += U[(int64_t)(44 + sp) * sf + q];
+      if (sp == 0) dN[0] = d;
+      else if (sp == 1) dN[1] = d;
     }
   }
+  if (nd && coupled) U[23 * sf + q] -= m_b * (dN[0] - dN[1]);
   return bad;
 }
 
@@ -288,7 +324,8 @@ __global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z;
   if (i >= g.nx || j >= g.ny) return;
-  const unsigned long long bad = m1_implicit_at(a.U, a.P, a.aux, g.sf, g.at(i + g.ng, j + g.ng, k + g.ng), a.adt, a.nd);
+  const unsigned long long bad =
+      m1_implicit_at(a.U, a.P, a.aux, g.sf, g.at(i + g.ng, j + g.ng, k + g.ng), a.adt, a.nd, a.coupled, a.m_b);
   if (bad && a.nfail) atomicAdd(a.nfail, bad);
 }
 
@@ -303,10 +340,12 @@ __global__ void __launch_bounds__(256) k_m1_implicit_lv(LevelArgs L) {
   if (bad && L.nfail) atomicAdd(L.nfail, bad);
 }
 
-int launch_imex_combine(const Geom& g, int scheme, int nfields, int stage, double dt, const double* Un,
+int launch_imex_combine(const Geom& g, int scheme, int nfields, int coupled, int stage, double dt, const double* Un,
                         const double* const* F, const double* const* R, double* Uout, hipStream_t s) {
   ImexArgs a;
   a.g = g;
+  a.nfields = nfields;
+  a.coupled = coupled;
   a.scheme = scheme;
   a.stage = stage;
   a.dt = dt;
@@ -331,9 +370,10 @@ int launch_m1_implicit_level(const LevelArgs& L, int grid, int block, hipStream_
   return (int)hipGetLastError();
 }
 
-int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt, int nd,
+int launch_m1_implicit(const Geom& g, double* U, const double* P, const double* aux, double adt, int nd, int coupled,
+                       double m_b,
                        unsigned long long* nfail, hipStream_t s) {
-  ImplArgs a{g, U, P, aux, adt, nfail, nd};
+  ImplArgs a{g, U, P, aux, adt, nfail, nd, coupled, m_b};
   MHD_LAUNCH(KID_M1_IMPLICIT, k_m1_implicit, dim3((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz), dim3(64, 4, 1), 0, s, a);
   return (int)hipGetLastError();
 }

@@ -273,6 +273,8 @@ int mhd_level_create(const mhd_box_t* boxes, int nboxes, const mhd_params_t* par
     return abi_fail(MHD_EINVAL, "mhd_level_create: a level evolves the full coupled system (all flags set)");
   if (par->les_cm != 0.0)
     return abi_fail(MHD_EINVAL, "mhd_level_create: the LES term (les_cm != 0) is evolved on single patches only");
+  if (par->flags & MHD_COUPLE_EXCHANGE)
+    return abi_fail(MHD_EINVAL, "mhd_level_create: the coupled exchange (MHD_COUPLE_EXCHANGE) runs on single patches only");
   if (par->flags & ~(need | MHD_EVOLVE_M1 | MHD_EVOLVE_M1N))
     return abi_fail(MHD_EINVAL, "mhd_level_create: unknown params flags");
   const bool m1 = (par->flags & MHD_EVOLVE_M1) != 0;

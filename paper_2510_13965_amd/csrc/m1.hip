@@ -49,6 +49,7 @@ struct M1Args {
   double* __restrict__ stiff;  // IMEX split: the radiation's collision terms (12 or 15 fields), or null
   int nd;                      // nonzero: the number densities are evolved (47 fields, 15 aux, 75 workspace fields)
   double m_b;                  // reference baryon mass of the electron-fraction source
+  int coupled;                 // with stiff: the fluid's share of the exchange goes to stiff too (after the radiation's)
 };
 
 // padded indices
@@ -299,9 +300,17 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
 #pragma unroll
         for (int r = 0; r < 3; ++r) out[1 + r] += alp * m.sqrtg * Si[r];
       }
-      a.rhs[24 * sf + q] -= alp * m.sqrtg * Sn;
+      if (a.stiff && a.coupled) {
+        // the fluid's share in the stiff part too: slots (12 or 15) + 0 (tau), + 1..3 (S_i)
+        double* fs = a.stiff + (int64_t)(ND ? 15 : 12) * sf + q;
+        fs[0] = (sp == 0 ? 0.0 : fs[0]) - alp * m.sqrtg * Sn;
 #pragma unroll
-      for (int r = 0; r < 3; ++r) a.rhs[(25 + r) * sf + q] -= alp * m.sqrtg * Si[r];
+        for (int r = 0; r < 3; ++r) fs[(1 + r) * sf] = (sp == 0 ? 0.0 : fs[(1 + r) * sf]) - alp * m.sqrtg * Si[r];
+      } else {
+        a.rhs[24 * sf + q] -= alp * m.sqrtg * Sn;
+#pragma unroll
+        for (int r = 0; r < 3; ++r) a.rhs[(25 + r) * sf + q] -= alp * m.sqrtg * Si[r];
+      }
 #pragma unroll
       for (int c = 0; c < 4; ++c) a.rhs[(int64_t)(32 + 4 * sp + c) * sf + q] = out[c];
     }
@@ -323,7 +332,10 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
         else if (sp == 1) C[1] = Cs;
         else C[2] = Cs;
       }
-      a.rhs[23 * sf + q] -= alp * m.sqrtg * a.m_b * (C[0] - C[1]);
+      if (a.stiff && a.coupled)
+        a.stiff[(int64_t)(15 + 4) * sf + q] = -alp * m.sqrtg * a.m_b * (C[0] - C[1]);
+      else
+        a.rhs[23 * sf + q] -= alp * m.sqrtg * a.m_b * (C[0] - C[1]);
     }
   }
   return vmax;
@@ -344,7 +356,7 @@ template <bool ND>
 __global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
   for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
-    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr, ND, L.par.m_b};
+    const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr, ND, L.par.m_b, 0};
     m1_point_at<ND>(a, i, j, k);
   });
 }
@@ -354,7 +366,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   double vmax = 0.0;
   for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
     const M1Args a{B.g,      L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs<IMEX>(B, L), L.max_speed,
-                   level_stiff<IMEX>(B, L), ND, L.par.m_b};
+                   level_stiff<IMEX>(B, L), ND, L.par.m_b, 0};
     vmax = fmax(vmax, m1_update_at<ND>(a, i, j, k, live));
   });
   if (L.max_speed) block_max_to(L.max_speed, vmax);
@@ -387,7 +399,7 @@ int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t 
 
 int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, int nd,
                     hipStream_t s) {
-  M1Args a{g, U, P, aux, ws, nullptr, nullptr, nullptr, nd, 0.0};
+  M1Args a{g, U, P, aux, ws, nullptr, nullptr, nullptr, nd, 0.0, 0};
   const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
   const dim3 grd((Nx + 63) / 64, (Ny + 3) / 4, Nz);
   if (nd)
@@ -398,8 +410,8 @@ int launch_m1_point(const Geom& g, const double* U, const double* P, const doubl
 }
 
 int launch_m1_update(const Geom& g, const double* U, const double* P, const double* aux, double* ws, double* rhs,
-                     double* max_speed, double* stiff, int nd, double m_b, hipStream_t s) {
-  M1Args a{g, U, P, aux, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed), stiff, nd, m_b};
+                     double* max_speed, double* stiff, int nd, double m_b, int coupled, hipStream_t s) {
+  M1Args a{g, U, P, aux, ws, rhs, reinterpret_cast<unsigned long long*>(max_speed), stiff, nd, m_b, coupled};
   const dim3 grd((g.nx + 63) / 64, (g.ny + 3) / 4, g.nz);
   if (nd)
     MHD_LAUNCH(KID_M1_UPDATE, k_m1_update<true>, grd, dim3(64, 4, 1), 0, s, a);

@@ -16,7 +16,8 @@ MHD_NST, MHD_NMHD, MHD_NU, MHD_NP, MHD_NEM = 22, 10, 32, 8, 4
 MHD_NU_M1, MHD_NAUX = 44, 9
 MHD_NU_M1N, MHD_NAUX_N = 47, 15
 MHD_NSTAT = 8
-EVOLVE_SPACETIME, EVOLVE_MHD, COUPLE_MATTER, EVOLVE_M1, EVOLVE_M1N = 1, 2, 4, 8, 16
+EVOLVE_SPACETIME, EVOLVE_MHD, COUPLE_MATTER, EVOLVE_M1, EVOLVE_M1N, COUPLE_EXCHANGE = 1, 2, 4, 8, 16, 32
+IMPLICIT_N, IMPLICIT_COUPLED = 1, 2
 IMEX_442, IMEX_332 = 0, 1
 FLAG = dict(ATMO=1, EPS_LO=2, EPS_HI=4, VEL_LIMIT=8, YE_RESET=16, FALLBACK=32, NOT_CONVERGED=64, FATAL=128)
 STAT_FATAL, STAT_CORRECTED, STAT_FALLBACK, STAT_ITERATIONS = 0, 1, 2, 3
@@ -114,9 +115,10 @@ SIGNATURES = {
     "mhd_level_imex_step": (C.c_int, [_vp, C.c_double, _vp, _vp, C.c_int, _vp]),
     "mhd_rhs_split": (C.c_int, [C.POINTER(Patch), C.POINTER(Params), C.POINTER(Eos), _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, C.c_size_t, _vp]),
-    "mhd_imex_combine": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_int, C.c_double, _vp,
+    "mhd_imex_stiff_fields": (C.c_int, [C.c_int, C.c_int]),
+    "mhd_imex_combine": (C.c_int, [C.POINTER(Patch), C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, _vp,
                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), _vp, _vp]),
-    "mhd_m1_implicit": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, C.c_double, C.c_int, _vp, _vp]),
+    "mhd_m1_implicit": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, C.c_double, C.c_uint, C.c_double, _vp, _vp]),
     "mhd_constraints": (C.c_int, [C.POINTER(Patch), _vp, _vp, _vp, _vp]),
     "mhd_profile_start": (C.c_int, []),
     "mhd_profile_stop": (C.c_int, [C.POINTER(KernelTime), C.c_int, C.POINTER(C.c_int)]),
@@ -217,6 +219,8 @@ def make_params(cfg):
         fl |= EVOLVE_M1
     if cfg.get("evolve_m1n", 0):
         fl |= EVOLVE_M1N
+    if cfg.get("couple_exchange", 0):
+        fl |= COUPLE_EXCHANGE
     p.flags = fl
     p.m_b = float(cfg.get("m_b", 1.0))
     p.les_cm = float(cfg.get("les_cm", 0.0))
@@ -318,16 +322,24 @@ def rhs_split(patch, params, eos, U, P, aux, out, stiff, max_speed=None, workspa
                                _ptr(stiff), _ptr(max_speed), _ptr(workspace), nbytes, _stream(stream)))
 
 
-def imex_combine(patch, stage, dt, Un, F, R, Uout, stream=None, nfields=MHD_NU_M1, scheme=IMEX_442):
+def imex_stiff_fields(nfields, coupled=False):
+    n = int(lib().mhd_imex_stiff_fields(int(nfields), int(bool(coupled))))
+    if n < 0:
+        _check(n)
+    return n
+
+
+def imex_combine(patch, stage, dt, Un, F, R, Uout, stream=None, nfields=MHD_NU_M1, scheme=IMEX_442, coupled=False):
     """F, R: lists of up to 4 device tensors (stage explicit and stiff parts)."""
     fa = (C.c_void_p * 4)(*[(_ptr(F[j]) if j < len(F) and F[j] is not None else None) for j in range(4)])
     ra = (C.c_void_p * 4)(*[(_ptr(R[j]) if j < len(R) and R[j] is not None else None) for j in range(4)])
-    _check(lib().mhd_imex_combine(C.byref(patch), int(scheme), int(nfields), int(stage), float(dt), _ptr(Un), fa, ra,
-                                  _ptr(Uout), _stream(stream)))
+    _check(lib().mhd_imex_combine(C.byref(patch), int(scheme), int(nfields), int(bool(coupled)), int(stage),
+                                  float(dt), _ptr(Un), fa, ra, _ptr(Uout), _stream(stream)))
 
 
-def m1_implicit(patch, aux, U, P, adt, nfail=None, stream=None, evolve_n=False):
-    _check(lib().mhd_m1_implicit(C.byref(patch), _ptr(aux), _ptr(U), _ptr(P), float(adt), int(bool(evolve_n)),
+def m1_implicit(patch, aux, U, P, adt, nfail=None, stream=None, evolve_n=False, coupled=False, m_b=1.0):
+    flags = (IMPLICIT_N if evolve_n else 0) | (IMPLICIT_COUPLED if coupled else 0)
+    _check(lib().mhd_m1_implicit(C.byref(patch), _ptr(aux), _ptr(U), _ptr(P), float(adt), flags, float(m_b),
                                  _ptr(nfail), _stream(stream)))
 
 

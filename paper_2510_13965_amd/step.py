@@ -156,7 +156,9 @@ class ImexRun:
     -> (ghost fill) -> split RHS.  With evolve_m1n in par_cfg the three number
     densities (47 fields, 15 aux) are evolved too, their collision sources
     implicit.  scheme: mhd.IMEX_442 (Table I) or mhd.IMEX_332 (SSP-RK(3,3)
-    with the re-derived L-stable I32L)."""
+    with the re-derived L-stable I32L).  With couple_exchange in par_cfg the
+    fluid's share of the exchange is implicit too (its stiff slots, and the
+    implicit solve moves what the radiation gains out of the fluid)."""
 
     def __init__(self, ipatch, U0, aux, eos_cfg, par_cfg, periodic=False, device="cuda", stream=None,
                  scheme=mhd.IMEX_442):
@@ -168,6 +170,9 @@ class ImexRun:
         self.par = mhd.make_params(dict(par_cfg, evolve_m1=1))
         self.nd = bool(par_cfg.get("evolve_m1n", 0))
         self.nfields = I.NU_M1N if self.nd else I.NU_M1
+        self.coupled = bool(par_cfg.get("couple_exchange", 0))
+        self.m_b = float(par_cfg.get("m_b", 1.0))
+        self.nstiff = mhd.imex_stiff_fields(self.nfields, self.coupled)
         self.periodic = periodic
         self.stream = stream
         t = lambda a: torch.as_tensor(a, dtype=torch.float64).to(device).contiguous()
@@ -177,7 +182,7 @@ class ImexRun:
         self.aux = t(aux)
         shp = tuple(ipatch.shape)
         self.F = [torch.zeros_like(self.Un) for _ in range(4)]
-        self.R = [torch.zeros((self.nfields - I.NU,) + shp, dtype=torch.float64, device=device) for _ in range(4)]
+        self.R = [torch.zeros((self.nstiff,) + shp, dtype=torch.float64, device=device) for _ in range(4)]
         self.P = torch.zeros((I.NP,) + shp, dtype=torch.float64, device=device)
         self.flags = torch.zeros(shp, dtype=torch.uint8, device=device)
         self.ws = mhd.workspace_for(self.patch, device, m1=True, m1n=self.nd)
@@ -189,17 +194,19 @@ class ImexRun:
         nf = self.nfields
         ns = len(self.aii)
         for s in range(ns):
-            mhd.imex_combine(self.patch, s, dt, self.Un, self.F, self.R, self.Ust, s_, nfields=nf, scheme=self.scheme)
+            mhd.imex_combine(self.patch, s, dt, self.Un, self.F, self.R, self.Ust, s_, nfields=nf, scheme=self.scheme,
+                             coupled=self.coupled)
             if self.periodic:
                 mhd.fill_ghosts_periodic(self.patch, self.Ust, nf, s_)
             mhd.con2prim(self.patch, self.eos, self.Ust, self.P, self.flags, None, None, s_)
             if self.aii[s] != 0.0:
                 mhd.m1_implicit(self.patch, self.aux, self.Ust, self.P, self.aii[s] * dt, self.nfail, s_,
-                                evolve_n=self.nd)
+                                evolve_n=self.nd, coupled=self.coupled, m_b=self.m_b)
                 if self.periodic:
                     mhd.fill_ghosts_periodic(self.patch, self.Ust, nf, s_)
             mhd.rhs_split(self.patch, self.par, self.eos, self.Ust, self.P, self.aux, self.F[s], self.R[s], self.vmax,
                           self.ws, s_)
-        mhd.imex_combine(self.patch, ns, dt, self.Un, self.F, self.R, self.Un, s_, nfields=nf, scheme=self.scheme)
+        mhd.imex_combine(self.patch, ns, dt, self.Un, self.F, self.R, self.Un, s_, nfields=nf, scheme=self.scheme,
+                         coupled=self.coupled)
         if self.periodic:
             mhd.fill_ghosts_periodic(self.patch, self.Un, nf, s_)

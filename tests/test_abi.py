@@ -43,7 +43,7 @@ def test_binding_covers_header(lib):
 
 
 def test_abi_version(lib):
-    assert lib.mhd_abi_version() == 5
+    assert lib.mhd_abi_version() == 6
 
 
 def test_eos_init_matches_oracle(lib, orc):

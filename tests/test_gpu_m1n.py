@@ -321,3 +321,123 @@ def test_m1n_level_rk4_and_imex_bitwise(level_n_states):
             assert np.array_equal(ref, ie.boxes[b]["U"].cpu().numpy()), ("imex eager", step, b)
             assert np.array_equal(ref, ig.boxes[b]["U"].cpu().numpy()), ("imex graph", step, b)
         assert int(nf_e.item()) == int(nf_g.item()) == sum(int(r.nfail.item()) for r in ibox)
+
+
+# ---------------------------------------------------------------- coupled exchange
+
+@pytest.mark.parametrize("case", ["star", "star+N"])
+def test_coupled_exchange_imex_step_parity(orc, dev, case):
+    """IMEX(4,4,2) with the fluid's share of the exchange implicit too
+    (MHD_COUPLE_EXCHANGE): the 28^3 star at opacities x100, with and without
+    the number densities, against the oracle's step; the split right-hand
+    side's stiff fluid slots against the oracle's."""
+    import torch
+    from paper_2510_13965_amd import mhd
+    from paper_2510_13965_amd.step import ImexRun
+
+    nd = case.endswith("N")
+    say("case coupled exchange imex step,", case, "28^3, opacities x100")
+    ip, U, P, EM = I.tov_star_state(n=28)
+    if nd:
+        U0, aux = with_n(orc, ip, U, P, EM, I.SEED0 + 171)
+        par = dict(PAR_N, couple_exchange=1)
+    else:
+        g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+        orc.prim2con(g, orc.make_eos(I.EOS_IDEAL2), U, P, EM, 0)
+        U0, aux = I.m1_fields(ip, U, P, I.SEED0 + 171)
+        par = dict(I.PARAMS, evolve_m1=1, couple_exchange=1)
+    aux = aux * 100.0
+    nf = U0.shape[0]
+    dt = 0.25 * ip.dx[0]
+    g = orc.make_grid(ip.n, ip.dx, ng=ip.ng)
+    e = orc.make_eos(I.EOS_IDEAL2)
+    # split right-hand side at the initial state
+    op = orc.make_par(par)
+    nr = orc.imex_stiff_fields(op)
+    assert nr == mhd.imex_stiff_fields(nf, True) == (20 if nd else 16)
+    Uo = U0.copy()
+    Po = np.zeros((I.NP,) + ip.shape)
+    orc.con2prim(g, e, Uo, Po, None, None)
+    Fo, Ro = np.zeros_like(U0), np.zeros((nr,) + ip.shape)
+    orc.rhs_split(g, op, e, Uo, Po, aux, Fo, Ro)
+    pt = mhd.patch_of(ip)
+    F = torch.zeros((nf,) + ip.shape, dtype=torch.float64, device="cuda")
+    R = torch.zeros((nr,) + ip.shape, dtype=torch.float64, device="cuda")
+    mhd.rhs_split(pt, mhd.make_params(par), mhd.make_eos(I.EOS_IDEAL2), torch.as_tensor(Uo).cuda(),
+                  torch.as_tensor(Po).cuda(), torch.as_tensor(aux).cuda(), F, R, None,
+                  mhd.workspace_for(pt, m1=True, m1n=nd))
+    torch.cuda.synchronize()
+    compare(ip, F.cpu().numpy(), Fo, "split explicit", nf=nf)
+    compare(ip, R.cpu().numpy(), Ro, "split stiff", nf=nr)
+    # one step
+    Uo = U0.copy()
+    nf_o = orc.imex_step(g, op, e, Uo, aux, dt)
+    r = ImexRun(ip, U0, aux, I.EOS_IDEAL2, par)
+    r.step(dt)
+    torch.cuda.synchronize()
+    assert nf_o == 0 and int(r.nfail.item()) == 0
+    compare_step_n(ip, U0, r.Un.cpu().numpy(), Uo, case, nf)
+
+
+def compare_step_n(ip, U0, G, O, tag, nf):
+    sl = (slice(None),) + ip.interior()
+    worst = 0.0
+    for f in range(nf):
+        d = np.abs(G[sl][f] - O[sl][f]).max()
+        scale = np.abs(O[sl][f] - U0[sl][f]).max()
+        bound = 4e-10 * scale + 8 * np.finfo(float).eps * np.abs(O[sl][f]).max()
+        if scale > 0:
+            worst = max(worst, d / scale)
+        assert d <= bound, (tag, f, d, scale)
+    say(tag, "worst |G-O| / max|dU| = %.1e" % worst)
+
+
+def test_coupled_exchange_conserves_on_gpu(dev):
+    """Uniform fluid and radiation at rest on a flat periodic patch, no
+    gravity response, kappa_a dt = 10, 20, 30 and an equilibrium below the
+    radiation: one GPU IMEX step with the coupled exchange relaxes Ebar by
+    R(z) of Table I's implicit tableau and conserves taubar + sum Ebar to
+    rounding, while the fluid takes most of the radiation's energy."""
+    import torch
+    from paper_2510_13965_amd import mhd
+    from paper_2510_13965_amd.step import ImexRun
+
+    say("case coupled exchange, uniform relaxation on the GPU")
+    ip = I.Patch((8, 8, 8), (0.1,) * 3, (0.0,) * 3)
+    U = np.zeros((44,) + ip.shape)
+    P = np.zeros((I.NP,) + ip.shape)
+    I.flat_spacetime(U)
+    P[I.RHO] = 1e-3
+    P[I.EPS] = 0.1
+    P[I.WLOR] = 1.0
+    P[I.YE] = 0.1
+    pt = mhd.patch_of(ip)
+    Ud = torch.as_tensor(U).cuda()
+    mhd.prim2con(pt, mhd.make_eos(I.EOS_IDEAL2), Ud, torch.as_tensor(P).cuda(),
+                 torch.zeros((4,) + ip.shape, dtype=torch.float64, device="cuda"), 0)
+    U = Ud.cpu().numpy()
+    aux = np.zeros((9,) + ip.shape)
+    dt = 0.025
+    E0 = [1e-5, 2e-5, 3e-5]
+    for s in range(3):
+        U[32 + 4 * s] = E0[s]
+        aux[3 * s] = 10.0 * (s + 1) / dt
+        aux[3 * s + 2] = 1e-7 * aux[3 * s]
+    r = ImexRun(ip, U, aux, I.EOS_IDEAL2, dict(I.PARAMS, couple_matter=0, couple_exchange=1), periodic=True)
+    r.step(dt)
+    torch.cuda.synchronize()
+    X = r.Un.cpu().numpy()[(slice(None),) + ip.interior()]
+    a = U[(slice(None),) + ip.interior()]
+    from oracle import orc
+
+    _, A, _, b = orc.imex_tableau(0)
+    for s in range(3):
+        z = -10.0 * (s + 1)
+        Rz = 1.0 + z * b @ np.linalg.solve(np.eye(len(b)) - z * A, np.ones(len(b)))
+        want = 1e-7 + Rz * (E0[s] - 1e-7)
+        tol = 64 * np.finfo(float).eps * (1.0 + abs(z)) * E0[s]
+        assert np.abs(X[32 + 4 * s] - want).max() <= tol
+    tot = lambda x: x[24] + sum(x[32 + 4 * s] for s in range(3))
+    scale = np.abs(a[24]).max() + sum(E0)
+    assert np.abs(X[24] - a[24]).max() > 0.5 * sum(E0)
+    assert np.abs(tot(X) - tot(a)).max() <= 64 * np.finfo(float).eps * 31.0 * scale

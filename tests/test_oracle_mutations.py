@@ -15,7 +15,8 @@ source with Gamma multiplied or N densitized, the electron-fraction source's
 sign or baryon mass, and the lapse or emission of the implicit update; a
 factor or sign of App. C's printed Jacobian of the implicit M1 equation;
 the LES term's product part, second-derivative factor, index order, xi and
-divergence assembly (App. A).
+divergence assembly (App. A); the coupled exchange's fluid update (sign,
+momentum index, the m_b of the lepton number) and its stiff slot's sign.
 """
 import os
 import shutil
@@ -27,6 +28,7 @@ import pytest
 
 from oracle import build as obuild
 
+import test_oracle_coupled as CP
 import test_oracle_gauge as G
 import test_oracle_imex as IM
 import test_oracle_les as LES
@@ -87,8 +89,10 @@ MUTANTS = [
      "C[sp] = e0 - k0 * (u[q] / m.sqrtg) * GM[sp * N + q];", NPINS),
     ("N source densitized N", "m1.c", "C[sp] = e0 - k0 * (u[q] / m.sqrtg) / GM[sp * N + q];",
      "C[sp] = e0 - k0 * u[q] / GM[sp * N + q];", NPINS),
-    ("Ye source sign", "m1.c", "par->m_b * (C[0] - C[1])", "par->m_b * (C[1] - C[0])", NPINS),
-    ("Ye source m_b dropped", "m1.c", "par->m_b * (C[0] - C[1])", "(C[0] - C[1])", NPINS),
+    ("Ye source sign", "m1.c", "rhs[23 * N + q] -= alp * m.sqrtg * par->m_b * (C[0] - C[1])",
+     "rhs[23 * N + q] -= alp * m.sqrtg * par->m_b * (C[1] - C[0])", NPINS),
+    ("Ye source m_b dropped", "m1.c", "rhs[23 * N + q] -= alp * m.sqrtg * par->m_b * (C[0] - C[1])",
+     "rhs[23 * N + q] -= alp * m.sqrtg * (C[0] - C[1])", NPINS),
     ("N implicit lapse", "m1.c", "(1.0 + adt * alp * k0 / gam)", "(1.0 + adt * k0 / gam)", NPINS),
     ("N implicit emission", "m1.c", "(Ns + adt * alp * e0)", "(Ns + adt * e0)", NPINS),
     ("App. C dJ/dE thick factor", "m1.c", "dthick * (3.0 - 2.0 * W2) * (W2 - 1.0)",
@@ -97,6 +101,14 @@ MUTANTS = [
      "(-dthin) * W * tE0 * fh[i] * s->v[j];", [IM.check_implicit_jacobian]),
     ("App. C calJ_0j advection sign", "m1.c", "(ks * dJdF[j] + kas * s->v[j])", "(ks * dJdF[j] - kas * s->v[j])",
      [IM.check_implicit_jacobian]),
+    ("coupled exchange: fluid energy gains", "m1.c", "if (couple) U[24 * N + q] -= U[(32 + 4 * sp) * N + q] - E0;",
+     "if (couple) U[24 * N + q] += U[(32 + 4 * sp) * N + q] - E0;", [CP.check_implicit_conserves]),
+    ("coupled exchange: momentum index", "m1.c", "if (couple) U[(25 + a) * N + q] -= U[(33 + 4 * sp + a) * N + q] - F0;",
+     "if (couple) U[(25 + a) * N + q] -= U[(33 + 4 * sp + (2 - a)) * N + q] - F0;", [CP.check_implicit_conserves]),
+    ("coupled exchange: lepton number m_b", "m1.c", "if (couple) U[23 * N + q] -= m_b * (dN[0] - dN[1]);",
+     "if (couple) U[23 * N + q] -= (dN[0] - dN[1]);", [CP.check_number_update_conserves_lepton_number]),
+    ("coupled exchange: stiff slot sign", "m1.c", "fs[0] = (sp == 0 ? 0.0 : fs[0]) - alp * m.sqrtg * Sn;",
+     "fs[0] = (sp == 0 ? 0.0 : fs[0]) + alp * m.sqrtg * Sn;", [CP.check_split_slots]),
     ("LES product term sign", "les.c", "+ 2.0 * (bv - vb);", "- 2.0 * (bv - vb);", [LES.check_filter_expansion]),
     ("LES second derivative factor", "les.c", "rhs[c] += 2.0 * Cj[c].a2;", "rhs[c] += Cj[c].a2;",
      [LES.check_filter_expansion]),
