@@ -344,18 +344,42 @@ __device__ __forceinline__ double ldf(const double* fb, uint32_t voff) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, 0, 0));
 }
 
+// One buffer resource per field and stencil: based at the stencil's lowest
+// point (uniform), with the per-lane byte offset voff of the centre point and
+// the position along the axis as the scalar offset (a multiple of s8 = 8 s),
+// so a stencil's points share one resource and every field along an axis
+// shares the scalar offsets.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_at(const double* base) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, 0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ double ld_at(__amdgpu_buffer_rsrc_t r, uint32_t voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, soff, 0));
+}
+
+// the N points fb[p + (m - lo) st], m = 0 .. N-1, into v (s8 = 8 st)
+template <int N>
+__device__ __forceinline__ void ld_col(const double* fb, int64_t st, int lo, uint32_t voff, int s8, double (&v)[N]) {
+  const __amdgpu_buffer_rsrc_t r = rsrc_at(fb - lo * st);
+#pragma unroll
+  for (int m = 0; m < N; ++m) v[m] = ld_at(r, voff, m * s8);
+}
+
 // fb: field base (uniform); s: element stride along the axis (uniform);
 // voff: byte offset of the centre point; ih12 = 1/(12h), ih2_12 = 1/(12h^2)
 __device__ __forceinline__ double fd1(const double* fb, int64_t s, uint32_t voff, double ih12) {
 #pragma clang fp contract(off)
-  return (8.0 * (ldf(fb + s, voff) - ldf(fb - s, voff)) - (ldf(fb + 2 * s, voff) - ldf(fb - 2 * s, voff))) * ih12;
+  const int s8 = (int)(s * 8);
+  const __amdgpu_buffer_rsrc_t r = rsrc_at(fb - 2 * s);
+  const double m2 = ld_at(r, voff, 0), m1 = ld_at(r, voff, s8), p1 = ld_at(r, voff, 3 * s8),
+               p2 = ld_at(r, voff, 4 * s8);
+  return (8.0 * (p1 - m1) - (p2 - m2)) * ih12;
 }
 
 __device__ __forceinline__ double fd2(const double* fb, int64_t s, uint32_t voff, double ih2_12) {
 #pragma clang fp contract(off)
-  return (16.0 * (ldf(fb + s, voff) + ldf(fb - s, voff)) - (ldf(fb + 2 * s, voff) + ldf(fb - 2 * s, voff)) -
-          30.0 * ldf(fb, voff)) *
-         ih2_12;
+  double v[5];
+  ld_col(fb, s, 2, voff, (int)(s * 8), v);
+  return (16.0 * (v[3] + v[1]) - (v[4] + v[0]) - 30.0 * v[2]) * ih2_12;
 }
 
 // D_b(D_a u): the centred operator along a applied at the four b-neighbours,
@@ -373,23 +397,27 @@ __device__ __forceinline__ double fd11(const double* fb, int64_t sa, int64_t sb,
 // beta * D^upwind u with the one-sided 4th-order stencils of Sec. 3.2:
 //   beta >= 0: ( u_{+3} - 6u_{+2} + 18u_{+1} - 10u_0 - 3u_{-1})/(12h)
 //   beta <  0: (-u_{-3} + 6u_{-2} - 18u_{-1} + 10u_0 + 3u_{+1})/(12h)
+// (scalar offsets k s8 address u_{k-3})
 __device__ __forceinline__ double fdadv(const double* fb, int64_t s, uint32_t voff, double ih12, double beta) {
 #pragma clang fp contract(off)
+  const int s8 = (int)(s * 8);
+  const __amdgpu_buffer_rsrc_t r = rsrc_at(fb - 3 * s);
   double d;
   if (beta >= 0.0)
-    d = ldf(fb + 3 * s, voff) - 6.0 * ldf(fb + 2 * s, voff) + 18.0 * ldf(fb + s, voff) - 10.0 * ldf(fb, voff) -
-        3.0 * ldf(fb - s, voff);
+    d = ld_at(r, voff, 6 * s8) - 6.0 * ld_at(r, voff, 5 * s8) + 18.0 * ld_at(r, voff, 4 * s8) -
+        10.0 * ld_at(r, voff, 3 * s8) - 3.0 * ld_at(r, voff, 2 * s8);
   else
-    d = -ldf(fb - 3 * s, voff) + 6.0 * ldf(fb - 2 * s, voff) - 18.0 * ldf(fb - s, voff) + 10.0 * ldf(fb, voff) +
-        3.0 * ldf(fb + s, voff);
+    d = -ld_at(r, voff, 0) + 6.0 * ld_at(r, voff, s8) - 18.0 * ld_at(r, voff, 2 * s8) +
+        10.0 * ld_at(r, voff, 3 * s8) + 3.0 * ld_at(r, voff, 4 * s8);
   return beta * (d * ih12);
 }
 
 // Kreiss-Oliger dissipation along one axis, sigma/(64h) * 6th difference
 __device__ __forceinline__ double fdko(const double* fb, int64_t s, uint32_t voff, double sig_ih64) {
 #pragma clang fp contract(off)
-  const double q = (ldf(fb + 3 * s, voff) + ldf(fb - 3 * s, voff)) - 6.0 * (ldf(fb + 2 * s, voff) + ldf(fb - 2 * s, voff)) +
-                   15.0 * (ldf(fb + s, voff) + ldf(fb - s, voff)) - 20.0 * ldf(fb, voff);
+  double v[7];
+  ld_col(fb, s, 3, voff, (int)(s * 8), v);
+  const double q = (v[6] + v[0]) - 6.0 * (v[5] + v[1]) + 15.0 * (v[4] + v[2]) - 20.0 * v[3];
   return sig_ih64 * q;
 }
 

@@ -234,10 +234,9 @@ __device__ __forceinline__ double mhd_update_at(const MhdUpdArgs& a, int i, int 
 #pragma unroll 1
   for (int d = 0; d < 3; ++d) {
     const int64_t s = g.stride(d);
-    const double* __restrict__ lam = a.W + (int64_t)(d * 11 + 10) * sf + p;
+    const int s8 = (int)(s * 8);
     double l[7];
-#pragma unroll
-    for (int m = 0; m < 7; ++m) l[m] = lam[(m - 3) * s];
+    ld_col(a.W + (int64_t)(d * 11 + 10) * sf, s, 3, voff, s8, l);
     vmax = fmax(vmax, l[3]);
     double lL = 0.0, lR = 0.0;
 #pragma unroll
@@ -249,14 +248,9 @@ __device__ __forceinline__ double mhd_update_at(const MhdUpdArgs& a, int i, int 
     const double ihd = d == 0 ? ihx : (d == 1 ? ihy : ihz);
 #pragma unroll
     for (int f = 0; f < 10; ++f) {
-      const double* __restrict__ Fp = a.W + (int64_t)(d * 11 + f) * sf + p;
-      const double* __restrict__ Up = U + (int64_t)(22 + f) * sf + p;
       double F[7], u[7];
-#pragma unroll
-      for (int m = 0; m < 7; ++m) {
-        F[m] = Fp[(m - 3) * s];
-        u[m] = Up[(m - 3) * s];
-      }
+      ld_col(a.W + (int64_t)(d * 11 + f) * sf, s, 3, voff, s8, F);
+      ld_col(U + (int64_t)(22 + f) * sf, s, 3, voff, s8, u);
       // 2 F^+ and 2 F^- (MP5 is homogeneous, so the factor 1/2 is applied once at the end)
       double pR[7], mR[7], pL[7], mL[7];
 #pragma unroll

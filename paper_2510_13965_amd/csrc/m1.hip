@@ -114,32 +114,51 @@ __global__ void __launch_bounds__(256) k_m1_point(M1Args a) {
 }
 
 // Lax-Friedrichs speed and the thick-limit weight A = tanh(1/(kappa h)) at the
-// interface between p and p + st; both are shared by the four fields of a
-// species, so they are evaluated once per interface
+// interface between points 0 and 1 of the three-point columns (lam, kappa_a,
+// kappa_s at p - st, p, p + st: o = 0 for the interface below p, 1 above);
+// both are shared by the four fields of a species, so they are evaluated once
+// per interface
 struct M1Iface {
   double lh, A;
 };
-__device__ __forceinline__ M1Iface m1_iface(const double* __restrict__ lam, const double* __restrict__ ka,
-                                            const double* __restrict__ ks, int64_t p, int64_t st, double h) {
+__device__ __forceinline__ M1Iface m1_iface(const double (&lam)[3], const double (&ka)[3], const double (&ks)[3],
+                                            int o, double h) {
   M1Iface r;
-  r.lh = fmax(lam[p], lam[p + st]);
-  const double kap = 0.5 * (ka[p] + ka[p + st] + ks[p] + ks[p + st]);
+  r.lh = fmax(lam[o], lam[o + 1]);
+  const double kap = 0.5 * (ka[o] + ka[o + 1] + ks[o] + ks[o + 1]);
   r.A = kap > 0.0 ? tanh(1.0 / (kap * h)) : 1.0;
   return r;
 }
 
-// interface value between p and p + st of one field
-__device__ __forceinline__ double m1_holo(const double* __restrict__ u, const double* __restrict__ f, const M1Iface& w,
-                                          int64_t p, int64_t st) {
-  const double um = u[p - st], u0 = u[p], u1 = u[p + st], u2 = u[p + 2 * st];
-  const double fho = 0.5 * (f[p] + f[p + st]);
+// interface value of one field between u0 and u1 (um, u2 the next points out;
+// f0, f1 the point fluxes at u0 and u1)
+__device__ __forceinline__ double m1_holo(double um, double u0, double u1, double u2, double f0, double f1,
+                                          const M1Iface& w) {
+  const double fho = 0.5 * (f0 + f1);
   const double flo = fho - 0.5 * w.lh * (u1 - u0);
   const double du = u1 - u0;
   double phi = 0.0;
-  if (du != 0.0) phi = fmax(0.0, fmin(1.0, fmin(2.0 * (u0 - um) / du, 2.0 * (u2 - u1) / du)));
+  // min(2 (u0 - um) / du, 2 (u2 - u1) / du) with one division: rounding is
+  // monotone, so the smaller quotient is the quotient of the smaller numerator
+  // for du > 0 and of the larger one for du < 0 (same bits, NaNs included)
+  if (du != 0.0) {
+    const double a = u0 - um, b = u2 - u1;
+    phi = fmax(0.0, fmin(1.0, 2.0 * (du > 0.0 ? fmin(a, b) : fmax(a, b)) / du));
+  }
   double A = w.A;
   if ((u0 - um) * du < 0.0 && du * (u2 - u1) < 0.0) A = 1.0;
   return fho - A * (1.0 - phi) * (fho - flo);
+}
+
+// flux difference -(F_{p+1/2} - F_{p-1/2}) / h of one field along st
+__device__ __forceinline__ double m1_fdiff(const double* u, const double* f, const M1Iface& wl, const M1Iface& wr,
+                                           int64_t st, uint32_t voff, int s8, double h, double ih) {
+  double v[5], fv[3];
+  ld_col(u, st, 2, voff, s8, v);
+  ld_col(f, st, 1, voff, s8, fv);
+  const double fr = m1_holo(v[1], v[2], v[3], v[4], fv[1], fv[2], wr);
+  const double fl = m1_holo(v[0], v[1], v[2], v[3], fv[0], fv[1], wl);
+  return div_rn(fr - fl, h, ih);
 }
 
 // interior indices; returns the largest M1 point speed at the point (0 if not live)
@@ -173,21 +192,19 @@ __device__ __forceinline__ double m1_update_at(const M1Args& a, int i, int j, in
         const double* lam = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + 4) * sf;
         vmax = fmax(vmax, lam[q]);
         const double h = d == 0 ? hx : (d == 1 ? hy : hz), ih = d == 0 ? ihx : (d == 1 ? ihy : ihz);
-        const M1Iface wr = m1_iface(lam, ka, ks, q, st, h), wl = m1_iface(lam, ka, ks, q - st, st, h);
+        const int s8 = (int)(st * 8);
+        double lv[3], kav[3], ksv[3];
+        ld_col(lam, st, 1, voff, s8, lv);
+        ld_col(ka, st, 1, voff, s8, kav);
+        ld_col(ks, st, 1, voff, s8, ksv);
+        const M1Iface wr = m1_iface(lv, kav, ksv, 1, h), wl = m1_iface(lv, kav, ksv, 0, h);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const double* u = U + (int64_t)(32 + 4 * sp + c) * sf;
-          const double* f = a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + c) * sf;
-          const double fr = m1_holo(u, f, wr, q, st);
-          const double fl = m1_holo(u, f, wl, q - st, st);
-          out[c] -= div_rn(fr - fl, h, ih);
-        }
+        for (int c = 0; c < 4; ++c)
+          out[c] -= m1_fdiff(U + (int64_t)(32 + 4 * sp + c) * sf, a.W + (int64_t)(kM1Flux + 5 * (3 * sp + d) + c) * sf,
+                             wl, wr, st, voff, s8, h, ih);
         if (ND) {
-          const double* u = U + (int64_t)(44 + sp) * sf;
-          const double* f = a.W + (int64_t)(kM1NFlux + 3 * sp + d) * sf;
-          const double fr = m1_holo(u, f, wr, q, st);
-          const double fl = m1_holo(u, f, wl, q - st, st);
-          const double dN = div_rn(fr - fl, h, ih);
+          const double dN = m1_fdiff(U + (int64_t)(44 + sp) * sf, a.W + (int64_t)(kM1NFlux + 3 * sp + d) * sf, wl, wr,
+                                     st, voff, s8, h, ih);
           if (sp == 0) outN[0] -= dN;
           else if (sp == 1) outN[1] -= dN;
           else outN[2] -= dN;
