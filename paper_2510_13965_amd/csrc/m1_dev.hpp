@@ -94,15 +94,82 @@ __device__ __forceinline__ void m1_closure_eval(const M1State& s, const double g
   HH = hh - Hn * Hn;
 }
 
-__device__ __forceinline__ double m1_R(const M1State& s, const double gd[6], const double gu[6], double xi) {
-  double P[6], J, H[3], HH;
-  m1_closure_eval(s, gd, gu, m1_eddington(xi), P, J, H, HH);
-  return (xi * xi * J * J - HH) / (s.E * s.E);
+// The root function of the closure, R(xi) = (xi^2 J^2 - H_a H^a)/E^2 with J
+// and H of the closure at chi(xi), in closed form: P_ij is affine in d_thick
+// (P = P^thin + d_thick (P^thick - P^thin)), and so are J, H_i and H_n, so
+// J = Ja + d Jb and H_a H^a = c0 + c1 d + c2 d^2 with d = 3/2 (1 - chi(xi)).
+// The coefficients are formed once per state; each evaluation is then a few
+// operations instead of a closure evaluation (the same function up to
+// rounding).
+struct M1RCoef {
+  double Ja, Jb, c0, c1, c2, E2;
+};
+
+__device__ __forceinline__ M1RCoef m1_rcoef(const M1State& s, const double gd[6], const double gu[6]) {
+  const double W = s.W, W2 = W * W;
+  const double Jth = 3.0 / (2.0 * W2 + 1.0) * ((2.0 * W2 - 1.0) * s.E - 2.0 * W2 * s.vF);
+  double Hth[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    Hth[i] = s.F[i] / W + W * s.vd[i] / (2.0 * W2 + 1.0) * ((4.0 * W2 + 1.0) * s.vF - 4.0 * W2 * s.E);
+  double Pa[6], Pb[6];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) {
+      const double thin = s.F2 > 0.0 ? s.E * s.F[i] * s.F[j] / s.F2 : 0.0;
+      const double thick = 4.0 / 3.0 * Jth * W2 * s.vd[i] * s.vd[j] + W * (Hth[i] * s.vd[j] + Hth[j] * s.vd[i]) +
+                           1.0 / 3.0 * Jth * gd[sym(i, j)];
+      Pa[sym(i, j)] = thin;
+      Pb[sym(i, j)] = thick - thin;
+    }
+  double Pva[3], Pvb[3], vPva = 0.0, vPvb = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Pva[i] = 0.0;
+    Pvb[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      Pva[i] += Pa[sym(i, j)] * s.v[j];
+      Pvb[i] += Pb[sym(i, j)] * s.v[j];
+    }
+    vPva += s.v[i] * Pva[i];
+    vPvb += s.v[i] * Pvb[i];
+  }
+  M1RCoef c;
+  c.Ja = W2 * (s.E - 2.0 * s.vF + vPva);
+  c.Jb = W2 * vPvb;
+  double Ha[3], Hb[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    Ha[i] = W * (s.F[i] - Pva[i] - c.Ja * s.vd[i]);
+    Hb[i] = -W * (Pvb[i] + c.Jb * s.vd[i]);
+  }
+  const double Hna = W * (c.Ja - s.E + s.vF), Hnb = W * c.Jb;
+  double aa = 0.0, ab = 0.0, bb = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      aa += gu[sym(i, j)] * Ha[i] * Ha[j];
+      ab += gu[sym(i, j)] * Ha[i] * Hb[j];
+      bb += gu[sym(i, j)] * Hb[i] * Hb[j];
+    }
+  c.c0 = aa - Hna * Hna;
+  c.c1 = 2.0 * (ab - Hna * Hnb);
+  c.c2 = bb - Hnb * Hnb;
+  c.E2 = s.E * s.E;
+  return c;
+}
+
+__device__ __forceinline__ double m1_R(const M1RCoef& c, double xi) {
+  const double d = 1.5 * (1.0 - m1_eddington(xi));
+  const double J = c.Ja + d * c.Jb;
+  return (xi * xi * J * J - (c.c0 + d * (c.c1 + d * c.c2))) / c.E2;
 }
 
 // Brent's method on [a, b] with R(a) < 0 < R(b), to a bracket of a few ulp
-__device__ double m1_brent(const M1State& s, const double gd[6], const double gu[6], double a, double b, double fa,
-                           double fb) {
+__device__ double m1_brent(const M1RCoef& co, double a, double b, double fa, double fb) {
   double c = a, fc = fa, d = b - a, e = d;
   for (int it = 0; it < 200; ++it) {
     if ((fb > 0.0 && fc > 0.0) || (fb < 0.0 && fc < 0.0)) {
@@ -151,18 +218,19 @@ __device__ double m1_brent(const M1State& s, const double gd[6], const double gu
     fa = fb;
     if (fabs(d) > tol) b += d;
     else b += (m > 0.0 ? tol : -tol);
-    fb = m1_R(s, gd, gu, b);
+    fb = m1_R(co, b);
   }
   return b;
 }
 
 // Eddington factor of the closure at this state
 __device__ __forceinline__ double m1_closure_chi(const M1State& s, const double gd[6], const double gu[6]) {
-  const double r0 = m1_R(s, gd, gu, 0.0), r1 = m1_R(s, gd, gu, 1.0);
+  const M1RCoef co = m1_rcoef(s, gd, gu);
+  const double r0 = m1_R(co, 0.0), r1 = m1_R(co, 1.0);
   double xi;
   if (r1 <= 0.0) xi = 1.0;
   else if (r0 >= 0.0) xi = 0.0;
-  else xi = m1_brent(s, gd, gu, 0.0, 1.0, r0, r1);
+  else xi = m1_brent(co, 0.0, 1.0, r0, r1);
   return m1_eddington(xi);
 }
 
