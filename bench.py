@@ -302,10 +302,11 @@ def level_paths(torch, mhd, I, args, mlp):
 
 
 class _Units:
-    """Interior and padded point counts of a set of boxes (for kernel_table)."""
+    """Interior, padded and interior-plus-one-layer point counts of a set of
+    boxes (for kernel_table)."""
 
-    def __init__(self, ninterior, npts):
-        self.ninterior, self.npts = ninterior, npts
+    def __init__(self, ninterior, npts, nhalo1):
+        self.ninterior, self.npts, self.nhalo1 = ninterior, npts, nhalo1
 
 
 def build_level_m1(torch, mhd, I, nboxes):
@@ -443,7 +444,7 @@ def headline_level_m1(torch, mhd, I, args, mlp):
     res["kernels_plain_one_step"] = {k: round(t / n, 4) for k, (n, t) in prof_plain.items()}
     res["finite"] = all(bool(torch.isfinite(b["U"]).all().item()) for b in lr.boxes)
     del U0
-    units = _Units(lr.ninterior, lr.npts)
+    units = _Units(lr.ninterior, lr.npts, lr.nhalo1)
     res["kernels"] = kernel_table(prof, units, args.steps, nfields=I.NU_M1, flops=FLOP_PER_UNIT_LEVEL_M1)
     res["roofline"] = roofline(prof, units, FLOP_PER_UNIT_LEVEL_M1, TRAFFIC_LEVEL_M1, nfields=I.NU_M1)
     lr.level.close()
@@ -503,7 +504,7 @@ def level_imex_path(torch, mhd, I, args):
     mhd.profile_start()
     lr.level.imex_step(dt, None, nf)
     prof = mhd.profile_stop()
-    res["kernels"] = kernel_table(prof, _Units(lr.ninterior, lr.npts), 1, nfields=I.NU_M1)
+    res["kernels"] = kernel_table(prof, _Units(lr.ninterior, lr.npts, lr.nhalo1), 1, nfields=I.NU_M1)
     res["implicit_solves_not_converged"] = int(nf.item())
     res["finite"] = all(bool(torch.isfinite(b["U"]).all().item()) for b in lr.boxes)
     lr.level.close()
@@ -766,8 +767,10 @@ def cpu_baseline_level_m1(args):
 # Algorithmic work per unit, counted by oracle/opcount.py (the oracle's own
 # evaluation with an op-counting scalar type; add/sub, mul, div, sqrt and
 # pow/exp/log count one flop each).  Units: interior points for the RHS
-# kernels, padded points for con2prim and the point fluxes, interior
-# point-fields for the RK stage.  The MHD and M1 updates count every interface
+# kernels, padded points for con2prim and the GRMHD point fluxes, interior
+# point-fields for the RK stage; the M1 point pass covers the interior and one
+# ghost layer, and its row (an average over the padded points) is applied to
+# those points.  The MHD and M1 updates count every interface
 # once.  Star patch: the 128^3 star (M1 rows: three grey species on the same
 # star).  Level with radiation: the 16-box subset of the 803-box level
 # (inputs.level_subset), three grey species, summed over the boxes
@@ -823,7 +826,7 @@ def kernel_table(prof, ip, steps, nfields=32, flops=None):
     rate of the algorithmic flops where the count exists."""
     flops = FLOP_PER_UNIT_STAR if flops is None else flops
     units = {"k_con2prim": ip.npts, "k_mhd_point": ip.npts, "k_mhd_update": ip.ninterior,
-             "k_rk4_stage": ip.ninterior * nfields, "k_m1_point": ip.npts}
+             "k_rk4_stage": ip.ninterior * nfields, "k_m1_point": ip.nhalo1}
     tab = {}
     for k, (n, t) in prof.items():
         e = {"launches": n, "ms_per_launch": round(t / n, 4), "ms_per_step": round(t / steps, 4)}
@@ -849,7 +852,7 @@ def kernel_work(ip, flops, nfields):
         "k_mhd_update": ("alu", flops["k_mhd_update"] * nint),
         "k_mhd_point": ("alu", flops["k_mhd_point"] * npad),
         "k_con2prim": ("alu", flops["k_con2prim"] * npad),
-        "k_m1_point": ("alu", flops["k_m1_point"] * npad),
+        "k_m1_point": ("alu", flops["k_m1_point"] * ip.nhalo1),
         # every field read once, every output written once: U (19 metric and gauge fields, 12 radiation),
         # P (v, W), aux (9), the M1 workspace (closure 18, fluxes and speeds 45), the fluid's tau and
         # S_i read and written, 12 radiation right-hand sides written: 127 values per interior point

@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(256) k_con2prim_lv(LevelArgs L) {
   __shared__ mhd_eos_t seos;
   const mhd_eos_t& eos = stage_eos(L.eos, seos);
   int64_t nfatal = 0, ncorr = 0, nit = 0;
-  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionPadded, [&](const BoxDev& B, int i, int j, int k, bool live) {
     C2pArgs a;  // the EoS is read from LDS
     a.g = B.g;
     a.U = L.src ? B.Us : B.U;

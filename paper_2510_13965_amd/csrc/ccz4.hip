@@ -861,7 +861,7 @@ __global__ void __launch_bounds__(256) k_ccz4_curv(Ccz4Args a, const double* __r
 
 template <bool IMEX>
 __global__ void __launch_bounds__(256) k_ccz4_curv_lv(LevelArgs L) {
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionInterior, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs<IMEX>(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
     ccz4_curv_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));
@@ -876,7 +876,7 @@ __global__ void __launch_bounds__(256) k_ccz4_gauge(Ccz4Args a, const double* __
 
 template <bool IMEX>
 __global__ void __launch_bounds__(256) k_ccz4_gauge_lv(LevelArgs L) {
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionInterior, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     const Ccz4Args a{B.g, L.par, L.src ? B.Us : B.U, B.P, level_rhs<IMEX>(B, L), 0, 0, 0, 0, L.m1 ? B.ws_m1 : nullptr};
     ccz4_gauge_at(a, B.ws + 33 * B.g.sf, point_at(B.g, i, j, k));

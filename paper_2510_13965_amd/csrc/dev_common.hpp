@@ -128,8 +128,8 @@ struct BoxDev {
   double* ws_m1;      // M1 part of the RHS workspace, else null
   double* F[4];       // IMEX: explicit parts of the four stages (44 or 47 fields), else null
   double* R[4];       // IMEX: stiff parts of the four stages (12 or 15 fields), else null
-  int cpp_int, cpp_pad;    // chunks per interior / padded z plane
-  int64_t t0_int, t0_pad;  // first global tile id of the box in each space
+  int cpp_int, cpp_pad, cpp_h1;    // chunks per z plane of the interior / padded box / interior plus one layer
+  int64_t t0_int, t0_pad, t0_h1;  // first global tile id of the box in each space
   int ntx_lds, nty_lds, nzc_lds;  // LDS-staged kernels: (x, y) tiles and z chunks of the box
   int64_t t0_lds;                 // first global id of the box in the LDS tile space
 };
@@ -146,7 +146,7 @@ struct LevelArgs {
   int slot;     // right-hand side into k (-1) or, in an IMEX stage, into F[slot] with the stiff part in R[slot]
   double adt;   // IMEX: implicit step a_ii dt of the collision solve
   unsigned long long* nfail;  // IMEX: count of collision solves that did not converge (may be null)
-  int64_t ntile_int, ntile_pad, ntile_lds;
+  int64_t ntile_int, ntile_pad, ntile_h1, ntile_lds;
   double dt;
   mhd_params_t par;
   mhd_eos_t eos;
@@ -173,41 +173,49 @@ __device__ __forceinline__ double* level_stiff(const BoxDev& B, const LevelArgs&
   return IMEX ? B.R[L.slot] : nullptr;
 }
 
-__device__ __forceinline__ int find_box(const LevelArgs& L, int64_t id, bool padded) {
+// the regions a level kernel can walk: the interior, the padded box, or the
+// interior with one ghost layer (the points whose M1 point fluxes and closure
+// the update reads)
+enum LevelRegion { kRegionInterior = 0, kRegionPadded = 1, kRegionHalo1 = 2 };
+
+__device__ __forceinline__ int find_box(const LevelArgs& L, int64_t id, int region) {
   int lo = 0, hi = L.nboxes - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    const int64_t t0 = padded ? L.boxes[mid].t0_pad : L.boxes[mid].t0_int;
+    const BoxDev& M = L.boxes[mid];
+    const int64_t t0 = region == kRegionPadded ? M.t0_pad : (region == kRegionHalo1 ? M.t0_h1 : M.t0_int);
     if (t0 <= id) lo = mid;
     else hi = mid - 1;
   }
   return lo;
 }
 
-// Calls body(box, i, j, k, live) for every point of the tile space, once per
-// thread and tile (i, j, k interior indices, or padded indices if `padded`).
+// Calls body(box, i, j, k, live) for every point of the region's tile space,
+// once per thread and tile: i, j, k are interior indices for the interior and
+// padded indices otherwise (kRegionHalo1 starts at padded index ng - 1).
 template <class F>
-__device__ __forceinline__ void for_each_level_point(const LevelArgs& L, bool padded, F&& body) {
-  const int64_t total = padded ? L.ntile_pad : L.ntile_int;
+__device__ __forceinline__ void for_each_level_point(const LevelArgs& L, int region, F&& body) {
+  const bool padded = region == kRegionPadded, h1 = region == kRegionHalo1;
+  const int64_t total = padded ? L.ntile_pad : (h1 ? L.ntile_h1 : L.ntile_int);
   const int per_g = gridDim.x >> 3;  // gridDim.x is a multiple of 8
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int64_t per = (total + 7) / 8;
   const int64_t lo = xcd * per;
   const int64_t hi = lo + per < total ? lo + per : total;
   for (int64_t id = lo + slot; id < hi; id += per_g) {
-    const int b = find_box(L, id, padded);
+    const int b = find_box(L, id, region);
     const BoxDev& B = L.boxes[b];
-    const int nx = padded ? B.g.nx + 2 * B.g.ng : B.g.nx;
-    const int ny = padded ? B.g.ny + 2 * B.g.ng : B.g.ny;
-    const int nz = padded ? B.g.nz + 2 * B.g.ng : B.g.nz;
-    const int cpp = padded ? B.cpp_pad : B.cpp_int;
-    const int local = (int)(id - (padded ? B.t0_pad : B.t0_int));
+    const int ext = padded ? 2 * B.g.ng : (h1 ? 2 : 0);  // points added to each extent
+    const int nx = B.g.nx + ext, ny = B.g.ny + ext, nz = B.g.nz + ext;
+    const int cpp = padded ? B.cpp_pad : (h1 ? B.cpp_h1 : B.cpp_int);
+    const int local = (int)(id - (padded ? B.t0_pad : (h1 ? B.t0_h1 : B.t0_int)));
     const TileXYZ t = tile_of_index(local, 1, cpp, nz, L.strip);
     const int q = t.by * (int)blockDim.x + (int)threadIdx.x;
     const bool live = q < nx * ny;
     const int j = live ? q / nx : 0;
     const int i = live ? q - j * nx : 0;
-    body(B, i, j, t.bz, live);
+    const int o = h1 ? B.g.ng - 1 : 0;  // to padded indices
+    body(B, i + o, j + o, t.bz + o, live);
   }
 }
 

@@ -404,7 +404,7 @@ __global__ void __launch_bounds__(256) k_mhd_update(MhdUpdArgs a) {
 }
 
 __global__ void __launch_bounds__(256) k_mhd_point_lv(LevelArgs L) {
-  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionPadded, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     MhdPointArgs a;  // par and eos stay in the kernel arguments
     a.g = B.g;
@@ -418,7 +418,7 @@ __global__ void __launch_bounds__(256) k_mhd_point_lv(LevelArgs L) {
 template <bool IMEX>
 __global__ void __launch_bounds__(256) k_mhd_update_lv(LevelArgs L) {
   double vmax = 0.0;
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionInterior, [&](const BoxDev& B, int i, int j, int k, bool live) {
     const MhdUpdArgs a{B.g, 0, 0, 0, 0, L.par, L.src ? B.Us : B.U, B.P, B.ws, level_rhs<IMEX>(B, L), L.max_speed};
     vmax = fmax(vmax, mhd_update_at(a, i, j, k, live));
   });

@@ -106,7 +106,7 @@ __global__ void __launch_bounds__(256) k_imex_combine(ImexArgs a) {
 
 // every field of every interior point of a level's boxes; stage 4 writes U
 __global__ void __launch_bounds__(256) k_imex_combine_lv(LevelArgs L) {
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionInterior, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     const int64_t pt = B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng);
     double* out = L.stage < 4 ? B.Us : B.U;
@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(256) k_m1_implicit(ImplArgs a) {
 // per thread that has any)
 __global__ void __launch_bounds__(256) k_m1_implicit_lv(LevelArgs L) {
   unsigned long long bad = 0;
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionInterior, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     bad += m1_implicit_at(B.Us, B.P, B.aux, B.g.sf, B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng), L.adt, L.nd);
   });

@@ -906,7 +906,7 @@ __global__ void __launch_bounds__(256) k_c2p_classify_lv(LevelArgs L) {
   __shared__ mhd_eos_t seos;
   const mhd_eos_t& eos = stage_eos(L.eos, seos);
   int64_t ncorr = 0;
-  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionPadded, [&](const BoxDev& B, int i, int j, int k, bool live) {
     float x[8];
     const bool solve = live && classify_point(eos, B.g, L.src ? B.Us : B.U, B.P, B.flags, nullptr, i, j, k, x);
     ncorr += (live && !solve) ? 1 : 0;

@@ -39,7 +39,7 @@ struct mhd_level {
   mhd_params_t par;
   mhd_eos_t eos;
   mhd_tuning_t tun;
-  int64_t ntile_int = 0, ntile_pad = 0, ntile_lds = 0;
+  int64_t ntile_int = 0, ntile_pad = 0, ntile_h1 = 0, ntile_lds = 0;
   int ncu = 256;
   // graphs of one RK4 step and of one IMEX step, each valid for the arguments
   // it was captured with
@@ -78,28 +78,33 @@ int layout(mhd_level_t* lv) {
   int rc0 = abi_hip((int)hipDeviceSynchronize(), "mhd_level: synchronize");
   if (rc0) return rc0;
   const int T = block_threads(lv->tun);
-  int64_t ti = 0, tp = 0, tl = 0;
+  int64_t ti = 0, tp = 0, th = 0, tl = 0;
   for (size_t b = 0; b < lv->boxes.size(); ++b) {
     mhd::BoxDev& B = lv->host[b];
     const mhd::Geom& g = B.g;
     const int64_t plane_i = (int64_t)g.nx * g.ny;
     const int64_t plane_p = (int64_t)(g.nx + 2 * g.ng) * (g.ny + 2 * g.ng);
+    const int64_t plane_h = (int64_t)(g.nx + 2) * (g.ny + 2);
     B.cpp_int = (int)((plane_i + T - 1) / T);
     B.cpp_pad = (int)((plane_p + T - 1) / T);
+    B.cpp_h1 = (int)((plane_h + T - 1) / T);
     B.t0_int = ti;
     B.t0_pad = tp;
+    B.t0_h1 = th;
     ti += (int64_t)B.cpp_int * g.nz;
     tp += (int64_t)B.cpp_pad * (g.nz + 2 * g.ng);
+    th += (int64_t)B.cpp_h1 * (g.nz + 2);
     B.ntx_lds = (g.nx + mhd::kLevelLdsTile - 1) / mhd::kLevelLdsTile;
     B.nty_lds = (g.ny + mhd::kLevelLdsTile - 1) / mhd::kLevelLdsTile;
     B.nzc_lds = (g.nz + mhd::kLevelLdsZ - 1) / mhd::kLevelLdsZ;
     B.t0_lds = tl;
     tl += (int64_t)B.ntx_lds * B.nty_lds * B.nzc_lds;
   }
-  if (ti >= ((int64_t)1 << 31) || tp >= ((int64_t)1 << 31) || tl >= ((int64_t)1 << 31))
+  if (ti >= ((int64_t)1 << 31) || tp >= ((int64_t)1 << 31) || th >= ((int64_t)1 << 31) || tl >= ((int64_t)1 << 31))
     return abi_fail(MHD_EINVAL, "mhd_level: too many tiles for one launch");
   lv->ntile_int = ti;
   lv->ntile_pad = tp;
+  lv->ntile_h1 = th;
   lv->ntile_lds = tl;
   drop_graphs(lv);
   return abi_hip((int)hipMemcpy(lv->dev, lv->host.data(), sizeof(mhd::BoxDev) * lv->host.size(), hipMemcpyHostToDevice),
@@ -130,6 +135,7 @@ mhd::LevelArgs args_of(const mhd_level_t* lv, int src, int stage, double dt, dou
   L.nfields = L.nd ? MHD_NU_M1N : (L.m1 ? MHD_NU_M1 : MHD_NU);
   L.ntile_int = lv->ntile_int;
   L.ntile_pad = lv->ntile_pad;
+  L.ntile_h1 = lv->ntile_h1;
   L.ntile_lds = lv->ntile_lds;
   L.dt = dt;
   L.par = lv->par;
@@ -167,7 +173,7 @@ int enqueue_rhs_only(const mhd_level_t* lv, int src, double* max_speed, int slot
   // the order of mhd_rhs: M1 closure and point fluxes (the CCZ4 matter terms read
   // the closure), CCZ4, GRMHD, then the M1 update (which adds the radiation's
   // exchange to the fluid's right-hand side)
-  if (L.m1 && (rc = mhd::launch_m1_point_level(L, gp, T, s))) return rc;
+  if (L.m1 && (rc = mhd::launch_m1_point_level(L, grid_for(lv, lv->ntile_h1), T, s))) return rc;
   if ((rc = mhd::launch_ccz4_level(L, gi, T, (int)((lv->ntile_lds + 7) / 8 * 8), s))) return rc;
   if ((rc = mhd::launch_mhd_level(L, gp, gi, T, s))) return rc;
   return L.m1 ? mhd::launch_m1_update_level(L, gi, T, s) : 0;

@@ -103,14 +103,17 @@ __device__ __forceinline__ void m1_point_at(const M1Args& a, int i, int j, int k
 
 // ND: the number densities too (a compile-time switch, so the kernels without
 // them carry none of their registers)
+// The update reads the point fluxes and speeds at the interior points and
+// their first neighbours, and the closure at the interior points, so the pass
+// covers the interior and one ghost layer (grid over nx + 2, ny + 2, nz + 2).
 template <bool ND>
 __global__ void __launch_bounds__(256) k_m1_point(M1Args a) {
   const Geom& g = a.g;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int j = blockIdx.y * blockDim.y + threadIdx.y;
   const int k = blockIdx.z;
-  if (i >= g.nx + 2 * g.ng || j >= g.ny + 2 * g.ng) return;
-  m1_point_at<ND>(a, i, j, k);
+  if (i >= g.nx + 2 || j >= g.ny + 2) return;
+  m1_point_at<ND>(a, i + g.ng - 1, j + g.ng - 1, k + g.ng - 1);
 }
 
 // Lax-Friedrichs speed and the thick-limit weight A = tanh(1/(kappa h)) at the
@@ -371,7 +374,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
 // levels: the same point functions over every box, one persistent launch each
 template <bool ND>
 __global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
-  for_each_level_point(L, true, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionHalo1, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     const M1Args a{B.g, L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, nullptr, nullptr, nullptr, ND, L.par.m_b, 0};
     m1_point_at<ND>(a, i, j, k);
@@ -381,7 +384,7 @@ __global__ void __launch_bounds__(256) k_m1_point_lv(LevelArgs L) {
 template <bool IMEX, bool ND>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_m1_update_lv(LevelArgs L) {
   double vmax = 0.0;
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionInterior, [&](const BoxDev& B, int i, int j, int k, bool live) {
     const M1Args a{B.g,      L.src ? B.Us : B.U, B.P, B.aux, B.ws_m1, level_rhs<IMEX>(B, L), L.max_speed,
                    level_stiff<IMEX>(B, L), ND, L.par.m_b, 0};
     vmax = fmax(vmax, m1_update_at<ND>(a, i, j, k, live));
@@ -417,7 +420,7 @@ int launch_m1_update_level(const LevelArgs& L, int grid, int block, hipStream_t 
 int launch_m1_point(const Geom& g, const double* U, const double* P, const double* aux, double* ws, int nd,
                     hipStream_t s) {
   M1Args a{g, U, P, aux, ws, nullptr, nullptr, nullptr, nd, 0.0, 0};
-  const int Nx = g.nx + 2 * g.ng, Ny = g.ny + 2 * g.ng, Nz = g.nz + 2 * g.ng;
+  const int Nx = g.nx + 2, Ny = g.ny + 2, Nz = g.nz + 2;  // the interior and one ghost layer
   const dim3 grd((Nx + 63) / 64, (Ny + 3) / 4, Nz);
   if (nd)
     MHD_LAUNCH(KID_M1_POINT, k_m1_point<true>, grd, dim3(64, 4, 1), 0, s, a);

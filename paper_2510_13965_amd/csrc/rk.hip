@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) k_rk4_stage(RkArgs a) {
 // all evolved fields (32, or 44 with M1) of every interior point of a level's boxes
 template <int NF>
 __device__ __forceinline__ void rk4_level_point(const LevelArgs& L) {
-  for_each_level_point(L, false, [&](const BoxDev& B, int i, int j, int k, bool live) {
+  for_each_level_point(L, kRegionInterior, [&](const BoxDev& B, int i, int j, int k, bool live) {
     if (!live) return;
     const RkArgs a{B.g, L.stage, L.dt, B.U, B.k, B.acc, L.stage < 3 ? B.Us : B.U};
     const int64_t p = B.g.at(i + B.g.ng, j + B.g.ng, k + B.g.ng);

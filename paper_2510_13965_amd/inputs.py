@@ -91,6 +91,11 @@ class Patch:
     def ninterior(self):
         return self.n[0] * self.n[1] * self.n[2]
 
+    @property
+    def nhalo1(self):
+        """Points of the interior with one ghost layer."""
+        return (self.n[0] + 2) * (self.n[1] + 2) * (self.n[2] + 2)
+
     def coords(self):
         """Z, Y, X coordinate arrays of shape (Nz, Ny, Nx)."""
         ax = [self.x0[a] + (np.arange(self.n[a] + 2 * self.ng) - self.ng) * self.dx[a]

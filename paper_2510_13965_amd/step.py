@@ -142,6 +142,10 @@ class LevelRun:
     def npts(self):
         return sum(b["ip"].npts for b in self.boxes)
 
+    @property
+    def nhalo1(self):
+        return sum(b["ip"].nhalo1 for b in self.boxes)
+
 
 # implicit diagonals: Table I's I42L, and the I32L paired with SSP-RK(3,3)
 # (gamma = 1 - 1/sqrt(2), as the library's tableau evaluates it)
