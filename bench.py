@@ -799,9 +799,9 @@ FLOP_PER_UNIT_LEVEL_M1 = {
 # WRITE_SIZE, each scaled by what the counter reads for a plain 1 GiB copy),
 # valid only for the kernel sources they were taken on (sha256 of these files).
 TRAFFIC_STAR = {"k_mhd_update": (2698185360.0, "6d780a4bcdb13c60")}
-TRAFFIC_LEVEL_M1 = {"k_m1_update": (119681965798.2, "225fe3e235407bd7"),
-                    "k_m1_point": (58288660910.8, "225fe3e235407bd7"),
-                    "k_mhd_update": (68494930317.5, "d04b90aa1f89cf34")}
+TRAFFIC_LEVEL_M1 = {"k_m1_update": (119581269011.2, "c83ffef2a4ca171b"),
+                    "k_m1_point": (48873636155.1, "c83ffef2a4ca171b"),
+                    "k_mhd_update": (68506649479.9, "2a8e9605e17bbe5a")}
 TRAFFIC_SOURCES = {
     "k_mhd_update": ["paper_2510_13965_amd/csrc/grmhd.hip", "paper_2510_13965_amd/csrc/dev_common.hpp"],
     "k_m1_point": ["paper_2510_13965_amd/csrc/m1.hip", "paper_2510_13965_amd/csrc/m1_dev.hpp",
