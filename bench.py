@@ -798,7 +798,7 @@ FLOP_PER_UNIT_LEVEL_M1 = {
 # HBM bytes per launch of a kernel from rocprofv3 --pmc (FETCH_SIZE and
 # WRITE_SIZE, each scaled by what the counter reads for a plain 1 GiB copy),
 # valid only for the kernel sources they were taken on (sha256 of these files).
-TRAFFIC_STAR = {"k_mhd_update": (2698185360.0, "6d780a4bcdb13c60")}
+TRAFFIC_STAR = {"k_mhd_update": (2650625248.0, "2a8e9605e17bbe5a")}
 TRAFFIC_LEVEL_M1 = {"k_m1_update": (119581269011.2, "c83ffef2a4ca171b"),
                     "k_m1_point": (48873636155.1, "c83ffef2a4ca171b"),
                     "k_mhd_update": (68506649479.9, "2a8e9605e17bbe5a")}
